@@ -1,0 +1,449 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Each test names the passage it pins.  None of them re-types the oracle's
+formula: they use closed forms, special cases, invariants, brute force, the
+paper's printed tables, or finite differences.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2412_04459_amd import scenes as S
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+# --------------------------------------------------------------------------
+# activation: Sec. 3.1.1 eq. explin (and softplus, which it approximates)
+# --------------------------------------------------------------------------
+def test_explin_c1_at_switch():
+    # both branches meet at 1.1 with value 1.1 and slope 1
+    h = 1e-7
+    assert oracle.act(1.1) == pytest.approx(1.1, rel=1e-15)
+    left = (oracle.act(1.1) - oracle.act(1.1 - h)) / h
+    right = (oracle.act(1.1 + h) - oracle.act(1.1)) / h
+    assert left == pytest.approx(1.0, abs=1e-6)
+    assert right == pytest.approx(1.0, abs=1e-6)
+    assert oracle.act(5.0) == 5.0
+    # the init density h_geo = -10 of Sec. 4.1 activates to ~0
+    assert 0 < oracle.act(-10.0) < 1e-4
+    assert oracle.act(-10.0) == pytest.approx(4.5575e-5, rel=1e-3)
+
+
+def test_explin_positive_monotone_and_below_softplus_shape():
+    xs = np.linspace(-20, 10, 2001)
+    ys = np.array([oracle.act(x) for x in xs])
+    assert np.all(ys > 0)
+    assert np.all(np.diff(ys) > 0)
+    # explin approximates softplus: both -> x for large x, -> 0 for very negative x
+    sp = np.array([oracle.act(x, 1) for x in xs])
+    assert np.max(np.abs(ys - sp)[xs > 5]) < 0.01
+    assert np.max(np.abs(ys - sp)[xs < -10]) < 1e-4
+
+
+def test_softplus_closed_forms():
+    assert oracle.act(0.0, 1) == pytest.approx(math.log(2.0), rel=1e-15)
+    for x in (-30.0, -3.0, -0.5, 0.7, 4.0, 40.0):
+        # softplus(x) - softplus(-x) = x
+        assert oracle.act(x, 1) - oracle.act(-x, 1) == pytest.approx(x, rel=1e-12, abs=1e-12)
+    assert oracle.act(800.0, 1) == pytest.approx(800.0)
+
+
+@pytest.mark.parametrize("kind", [0, 1])
+def test_activation_derivative_matches_fd(kind):
+    for x in (-12.0, -2.0, 0.3, 1.0, 1.09, 1.2, 3.0):
+        h = 1e-6
+        fd = (oracle.act(x + h, kind) - oracle.act(x - h, kind)) / (2 * h)
+        assert oracle.act_grad(x, kind) == pytest.approx(fd, rel=1e-7, abs=1e-12)
+
+
+# --------------------------------------------------------------------------
+# spherical harmonics (Sec. 3.1.1 eq. vox_color): textbook real basis
+# --------------------------------------------------------------------------
+def _sphere_quadrature(n=24):
+    zs, wz = np.polynomial.legendre.leggauss(n)
+    phis = (np.arange(2 * n) + 0.5) * (2 * math.pi / (2 * n))
+    pts, w = [], []
+    for z, wzz in zip(zs, wz):
+        r = math.sqrt(1 - z * z)
+        for ph in phis:
+            pts.append((r * math.cos(ph), r * math.sin(ph), z))
+            w.append(wzz * 2 * math.pi / (2 * n))
+    return np.array(pts), np.array(w)
+
+
+def test_sh_orthonormal_by_quadrature():
+    pts, w = _sphere_quadrature()
+    Y = np.stack([oracle.sh_basis(3, p) for p in pts], 0)  # (P,16)
+    G = (Y * w[:, None]).T @ Y
+    assert np.allclose(G, np.eye(16), atol=1e-12)
+
+
+def test_sh_parity_addition_theorem_and_low_bands():
+    rng = np.random.default_rng(0)
+    for _ in range(50):
+        d = rng.normal(size=3)
+        d /= np.linalg.norm(d)
+        Y = oracle.sh_basis(3, d)
+        Yn = oracle.sh_basis(3, -d)
+        for l in range(4):
+            sl = slice(l * l, (l + 1) ** 2)
+            assert np.allclose(Yn[sl], (-1) ** l * Y[sl], atol=1e-14)
+            # addition theorem: sum_m Y_lm^2 = (2l+1)/(4 pi)
+            assert np.sum(Y[sl] ** 2) == pytest.approx((2 * l + 1) / (4 * math.pi), rel=1e-12)
+        assert Y[0] == pytest.approx(0.5 / math.sqrt(math.pi), rel=1e-15)
+        c1 = math.sqrt(3 / (4 * math.pi))
+        assert np.allclose(Y[1:4], c1 * np.array([d[1], d[2], d[0]]), atol=1e-14)
+    # degree-0 colour does not depend on direction, and |d| does not matter
+    assert np.allclose(oracle.sh_basis(3, [0, 0, 2.0]), oracle.sh_basis(3, [0, 0, 1.0]))
+
+
+# --------------------------------------------------------------------------
+# octree paths (Supp. A.1) and voxel geometry (Sec. 3.1.1 eq. vox_coord)
+# --------------------------------------------------------------------------
+def test_octpath_round_trip():
+    rng = np.random.default_rng(1)
+    for _ in range(500):
+        lv = int(rng.integers(1, 17))
+        i, j, k = (int(x) for x in rng.integers(0, 2 ** lv, size=3))
+        p = oracle.to_octpath(i, j, k, lv)
+        assert p < 2 ** 48
+        assert oracle.to_voxel_index(p, lv) == (i, j, k)
+        # the path's low 3*(16-lv) bits are zero (left-aligned)
+        assert p % (8 ** (16 - lv)) == 0
+
+
+def test_octpath_matches_octree_recursion():
+    # the scene builder appends child octants level by level; the listing's
+    # bit interleaving of (i, j, k) must give the same code
+    for sc in (S.scene_cfg0(), S.tiny_random_scene(3, max_level=5)):
+        for n in range(0, sc.n_voxels, max(1, sc.n_voxels // 300)):
+            i, j, k = (int(x) for x in sc.ijk[n])
+            assert oracle.to_octpath(i, j, k, int(sc.level[n])) == int(sc.octpath[n])
+
+
+def test_voxel_boxes_tile_the_cube_when_nothing_is_dropped():
+    # reading of the centre formula: centre = wc - ws/2 + s (v + 1/2); with
+    # every leaf kept the boxes are disjoint and fill the world cube
+    rng = np.random.default_rng(5)
+    ijk = np.array([[x, y, z] for x in (0, 1) for y in (0, 1) for z in (0, 1)])
+    lv = np.ones(8, np.int64)
+    leaves_ijk, leaves_lv = [], []
+    for _ in range(3):
+        sub = rng.random(len(ijk)) < 0.5
+        leaves_ijk += list(ijk[~sub])
+        leaves_lv += list(lv[~sub])
+        kids = [ijk[sub] * 2 + np.array([(c >> 2) & 1, (c >> 1) & 1, c & 1]) for c in range(8)]
+        ijk = np.concatenate(kids, 0)
+        lv = np.concatenate([lv[sub] + 1] * 8, 0)
+    leaves_ijk += list(ijk)
+    leaves_lv += list(lv)
+    sc = S.scene_from_voxels((0.5, -1.0, 2.0), 2.0, 4, np.array(leaves_ijk), np.array(leaves_lv))
+    c = sc.center.astype(np.float64).T
+    s = sc.size.astype(np.float64)
+    assert np.sum(s ** 3) == pytest.approx(8.0, rel=1e-12)
+    lo, hi = c - s[:, None] / 2, c + s[:, None] / 2
+    assert np.all(lo >= np.array([-0.5, -2.0, 1.0]) - 1e-12)
+    assert np.all(hi <= np.array([1.5, 0.0, 3.0]) + 1e-12)
+    # pairwise disjoint interiors
+    n = len(s)
+    ov = np.all((lo[:, None, :] < hi[None, :, :] - 1e-12) & (lo[None, :, :] < hi[:, None, :] - 1e-12), -1)
+    assert np.sum(ov) == n
+
+
+# --------------------------------------------------------------------------
+# direction-dependent Morton order (Supp. B.2, B.3)
+# --------------------------------------------------------------------------
+def _golden_tables():
+    rows = [l.split() for l in open(os.path.join(GOLDEN, "morton_order_tables.txt"))
+            if l.strip() and not l.startswith("#")]
+    return np.array(rows, dtype=np.int64)
+
+
+def test_child_rank_equals_printed_tables():
+    T = _golden_tables()
+    assert T.shape == (8, 8)
+    for s in range(8):
+        for t in range(8):
+            assert oracle.child_rank(s, t) == T[s, t]
+
+
+def test_morton_order_remaps_every_triplet():
+    T = _golden_tables()
+    rng = np.random.default_rng(2)
+    for _ in range(200):
+        p = int(rng.integers(0, 2 ** 48, dtype=np.uint64))
+        s = int(rng.integers(0, 8))
+        o = oracle.morton_order(p, s)
+        for n in range(16):
+            assert (o >> (3 * n)) & 7 == T[s, (p >> (3 * n)) & 7]
+
+
+def _one_pixel_camera(eye, R):
+    R = np.asarray(R, np.float64)
+    t = -R @ np.asarray(eye, np.float64)
+    return S.camera_from_pose(1, 1, 1.0, 1.0, 0.5, 0.5, R, t)
+
+
+def _random_rotation(rng):
+    q, r = np.linalg.qr(rng.normal(size=(3, 3)))
+    q = q * np.sign(np.diag(r))[None, :]
+    if np.linalg.det(q) < 0:
+        q[:, 0] = -q[:, 0]
+    return q
+
+
+def test_morton_rule_equals_entry_distance_order_brute_force():
+    """Supp. B.3: on octree-leaf voxel sets, sorting by the direction-dependent
+    Morton code equals sorting by the ray entry distance.  Checked on random
+    tiny octrees and random rays (outside and inside the cube)."""
+    rng = np.random.default_rng(7)
+    checked = 0
+    for scene_seed in range(60):
+        sc = S.tiny_random_scene(scene_seed, max_level=int(rng.integers(2, 5)))
+        for _ in range(8):
+            R = _random_rotation(rng)
+            d = R[2]  # world direction of the single pixel ray (camera z axis)
+            if rng.random() < 0.5:
+                eye = np.array([0.5, 0.5, 0.5]) - 1.5 * d + 0.2 * rng.normal(size=3)
+            else:
+                eye = rng.random(3)
+            cam = _one_pixel_camera(eye, R)
+            r = oracle.render(sc, cam, K=1, t_stop=0.0, max_seq=64)
+            if r["flags"][0] & 2:
+                continue
+            seq = [int(v) for v in r["seq"][0] if v >= 0]
+            if len(seq) < 2:
+                continue
+            dr = cam.w2c[:, :3].T @ np.array([0.0, 0.0, 1.0])
+            s = 4 * (dr[0] < 0) + 2 * (dr[1] < 0) + (dr[2] < 0)
+            by_morton = sorted(seq, key=lambda v: oracle.morton_order(int(sc.octpath[v]), int(s)))
+            assert by_morton == seq
+            checked += 1
+    assert checked > 150
+
+
+# --------------------------------------------------------------------------
+# keys and values (Supp. B.1)
+# --------------------------------------------------------------------------
+def test_compact_key_order_equals_paper_key_order():
+    rng = np.random.default_rng(3)
+    sc = S.tiny_random_scene(11, max_level=4)
+    n = 5000
+    tile = rng.integers(0, 40, size=n)
+    vid = rng.integers(0, sc.n_voxels, size=n)
+    s = rng.integers(0, 8, size=n).astype(np.uint8)
+    kp, kc, val = oracle.keys(tile, vid, s, sc.octpath, sc.max_level)
+    o1 = np.lexsort((val, kp))
+    o2 = np.lexsort((val, kc))
+    assert np.array_equal(kp[o1], kp[o2])
+    assert np.array_equal(val >> 29, s.astype(np.uint32))
+    assert np.array_equal(val & ((1 << 29) - 1), vid.astype(np.uint32))
+    assert np.array_equal(kp >> np.uint64(48), tile.astype(np.uint64))
+    # distinct (tile, voxel, s) give distinct keys when max_level <= 15
+    trip = np.unique(np.stack([tile, vid, s.astype(np.int64)], 1), axis=0)
+    kp2, kc2, _ = oracle.keys(trip[:, 0], trip[:, 1], trip[:, 2].astype(np.uint8), sc.octpath,
+                              sc.max_level)
+    assert len(np.unique(kp2)) == len(trip)
+    assert len(np.unique(kc2)) == len(trip)
+
+
+# --------------------------------------------------------------------------
+# single-voxel closed forms: Sec. 3.1.1 eq. vox_alpha, Supp. A.2 eq.
+# K_samp_pts and eq. interp, Sec. 3.1 eq. alpha_blend
+# --------------------------------------------------------------------------
+def _axis_camera(x, y, z0=-1.0):
+    """One-pixel camera at (x, y, z0) looking along +z."""
+    return S.camera_from_pose(1, 1, 1.0, 1.0, 0.5, 0.5, np.eye(3), -np.array([x, y, z0]))
+
+
+def _dc_sh(rgb):
+    y00 = 0.5 / math.sqrt(math.pi)
+    return (np.asarray(rgb, np.float64) / y00).reshape(1, 1, 3)
+
+
+@pytest.mark.parametrize("K", [1, 2, 3, 5])
+@pytest.mark.parametrize("act", [0, 1])
+def test_uniform_voxel_alpha_closed_form(K, act):
+    r = 0.7
+    sc = S.scene_from_voxels((0.5, 0.5, 0.5), 1.0, 3, [[0, 0, 0]], [1],
+                             grid_raw=lambda g: np.full(len(g), r), sh=_dc_sh([0.2, 0.5, 0.9]))
+    cam = _axis_camera(0.25, 0.25)
+    out = oracle.render(sc, cam, K=K, activation=act)
+    sigma = oracle.act(np.float32(r), act)
+    alpha = 1 - math.exp(-0.5 * sigma)  # chord length 0.5 along z
+    assert out["rgba"][0, 3] == pytest.approx(alpha, rel=1e-12)
+    assert np.allclose(out["rgba"][0, :3], alpha * np.array([0.2, 0.5, 0.9], np.float32), rtol=1e-6)
+
+
+@pytest.mark.parametrize("K", [1, 2, 4])
+def test_affine_field_orientation_and_midpoint_samples(K):
+    # raw densities affine along one axis and > 1.1 (linear branch of explin):
+    # the optical depth is the exact line integral
+    a, b = 2.0, 3.0
+    box_lo = np.zeros(3)
+    for axis, (x, y), expect in ((0, (0.125, 0.25), a + b * 0.25),   # q_x = 0.25 fixed
+                                 (1, (0.25, 0.375), a + b * 0.75),   # q_y = 0.75 fixed
+                                 (2, (0.25, 0.25), a + b * 0.5)):    # varies along the ray
+        f = (lambda ax: (lambda g: a + b * (g[:, ax] - box_lo[ax]) / 0.5))(axis)
+        sc = S.scene_from_voxels((0.5, 0.5, 0.5), 1.0, 1, [[0, 0, 0]], [1], grid_raw=f,
+                                 sh=_dc_sh([1, 1, 1]))
+        out = oracle.render(sc, _axis_camera(x, y), K=K)
+        xdepth = -math.log(1 - out["rgba"][0, 3])
+        assert xdepth == pytest.approx(0.5 * expect, rel=1e-9), axis
+
+
+def test_quadrature_converges_second_order():
+    # a non-linear field along a diagonal ray: midpoint rule error ~ K^-2
+    rng = np.random.default_rng(4)
+    sc = S.scene_from_voxels((0.5, 0.5, 0.5), 1.0, 1, [[0, 0, 0]], [1],
+                             grid_raw=lambda g: rng.normal(0.0, 2.0, size=len(g)),
+                             sh=_dc_sh([1, 1, 1]))
+    d = np.array([0.3, 0.5, 1.0])
+    d /= np.linalg.norm(d)
+    z = d
+    x = np.cross([0, 1.0, 0], z); x /= np.linalg.norm(x)
+    y = np.cross(z, x)
+    R = np.stack([x, y, z], 0)
+    cam = _one_pixel_camera(np.array([0.25, 0.25, 0.25]) - 0.8 * z, R)
+    ref = -math.log(1 - oracle.render(sc, cam, K=512)["rgba"][0, 3])
+    errs = [abs(-math.log(1 - oracle.render(sc, cam, K=k)["rgba"][0, 3]) - ref) for k in (4, 8, 16)]
+    assert errs[0] > 0
+    assert 3.0 < errs[0] / errs[1] < 5.0
+    assert 3.0 < errs[1] / errs[2] < 5.0
+
+
+def test_early_termination_closed_form():
+    # a column of 8 level-3 voxels, each with optical depth x = 2 on the ray;
+    # T_i = exp(-2 (i-1)) >= 1e-4 holds for i <= 5 only, so exactly 5 voxels
+    # are composited (the voxel taking T below the threshold is included)
+    ijk = [[1, 1, k] for k in range(8)]
+    cols = np.random.default_rng(0).random((8, 3))
+    sc = S.scene_from_voxels((0.5, 0.5, 0.5), 1.0, 3, ijk, [3] * 8,
+                             grid_raw=lambda g: np.full(len(g), 16.0),
+                             sh=np.stack([_dc_sh(c)[0] for c in cols], 0))
+    cam = _axis_camera(0.1875, 0.1875)
+    out = oracle.render(sc, cam, K=2, t_stop=1e-4, max_seq=8)
+    assert out["ncomp"][0] == 5 and out["nhit"][0] == 8
+    assert list(out["seq"][0][:5]) == [0, 1, 2, 3, 4]
+    Ts = np.exp(-2.0 * np.arange(5))
+    C = (Ts * (1 - math.exp(-2.0)))[:, None] * cols.astype(np.float32)[:5]
+    assert np.allclose(out["rgba"][0, :3], C.sum(0), rtol=1e-6)
+    assert out["rgba"][0, 3] == pytest.approx(1 - math.exp(-10.0), rel=1e-12)
+    # t_stop = 0 composites all eight
+    out = oracle.render(sc, cam, K=2, t_stop=0.0)
+    assert out["ncomp"][0] == 8
+
+
+def test_camera_inside_voxel_skips_it():
+    # Supp. A.2 listing: a hit needs a > 0, so the voxel holding the camera
+    # is not composited, the one in front is
+    sc = S.scene_from_voxels((0.5, 0.5, 0.5), 1.0, 1, [[0, 0, 0], [0, 0, 1]], [1, 1],
+                             grid_raw=lambda g: np.full(len(g), 3.0),
+                             sh=np.stack([_dc_sh([1, 0, 0])[0], _dc_sh([0, 1, 0])[0]], 0))
+    out = oracle.render(sc, _axis_camera(0.25, 0.25, 0.2), K=1, max_seq=4)
+    assert out["ncomp"][0] == 1 and out["seq"][0][0] == 1
+    assert out["rgba"][0, 0] == 0.0 and out["rgba"][0, 1] > 0
+
+
+# --------------------------------------------------------------------------
+# compositing invariants on the workload scenes
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("opaque", [False, True])
+def test_compositing_invariants_cfg0(opaque):
+    sc = S.scene_cfg0(opaque=opaque)
+    cam = S.camera_cfg0()
+    out = oracle.render(sc, cam, K=1)
+    rgba = out["rgba"]
+    assert np.all(rgba[:, :3] >= 0)
+    assert np.all((rgba[:, 3] >= 0) & (rgba[:, 3] <= 1))
+    cmax = np.max(np.maximum(0, sc.sh[:, 0, :].astype(np.float64) * 0.5 / math.sqrt(math.pi)))
+    assert np.all(rgba[:, :3] <= cmax * rgba[:, 3:4] + 1e-12)
+    assert np.all(out["ncomp"] <= out["nhit"])
+    if opaque:
+        assert np.sum(rgba[:, 3] > 0.999) > 20
+        assert np.sum(out["ncomp"] < out["nhit"]) > 0
+
+
+# --------------------------------------------------------------------------
+# the adjoint (Supp. A.2 gradient of alpha, chained through eq. alpha_blend)
+# against FP64 central finite differences
+# --------------------------------------------------------------------------
+def _loss(sc, cam, K, g, pixels, act=0, t_stop=1e-4):
+    out = oracle.render(sc, cam, K=K, pixels=pixels, activation=act, t_stop=t_stop)
+    return float(np.sum(out["rgba"] * g))
+
+
+@pytest.mark.parametrize("K,act,opaque", [(1, 0, False), (2, 0, True), (3, 1, False)])
+def test_adjoint_matches_central_differences(K, act, opaque):
+    import dataclasses
+    rng = np.random.default_rng(10 + K)
+    sc = S.tiny_random_scene(21, max_level=3, sh_degree=2,
+                             density_std=1.0 if not opaque else 0.5)
+    if opaque:
+        sc = dataclasses.replace(sc, grid_raw=(sc.grid_raw * 6.0).astype(np.float32))
+    sc = dataclasses.replace(sc, grid_raw=sc.grid_raw.astype(np.float64),
+                             sh=sc.sh.astype(np.float64))
+    cam = S.look_at(24, 24, 50.0, [1.9, 1.3, 1.1], target=(0.5, 0.5, 0.5))
+    pixels = np.arange(cam.W * cam.H)
+    g = rng.normal(size=(len(pixels), 4))
+    ref = oracle.render(sc, cam, K=K, pixels=pixels, activation=act, grad_rgba=g)
+    assert not np.any(ref["flags"] & 1)
+    gg, gs = ref["grad_grid"], ref["grad_sh"]
+    # sample grid points and sh entries with non-trivial gradients
+    cand = np.nonzero(np.abs(gg) > 1e-3 * np.abs(gg).max())[0]
+    pick = rng.choice(cand, size=min(12, len(cand)), replace=False)
+    for m in pick:
+        h = 1e-6 * max(1.0, abs(sc.grid_raw[m]))
+        up = sc.grid_raw.copy(); up[m] += h
+        dn = sc.grid_raw.copy(); dn[m] -= h
+        fd = (_loss(dataclasses.replace(sc, grid_raw=up), cam, K, g, pixels, act)
+              - _loss(dataclasses.replace(sc, grid_raw=dn), cam, K, g, pixels, act)) / (2 * h)
+        assert gg[m] == pytest.approx(fd, rel=1e-5, abs=1e-8 * np.abs(gg).max())
+    flat = np.nonzero(np.abs(gs.reshape(-1)) > 1e-3 * np.abs(gs).max())[0]
+    pick = rng.choice(flat, size=min(12, len(flat)), replace=False)
+    for e in pick:
+        h = 1e-6
+        up = sc.sh.copy().reshape(-1); up[e] += h
+        dn = sc.sh.copy().reshape(-1); dn[e] -= h
+        fd = (_loss(dataclasses.replace(sc, sh=up.reshape(sc.sh.shape)), cam, K, g, pixels, act)
+              - _loss(dataclasses.replace(sc, sh=dn.reshape(sc.sh.shape)), cam, K, g, pixels, act)) / (2 * h)
+        assert gs.reshape(-1)[e] == pytest.approx(fd, rel=1e-5, abs=1e-8 * np.abs(gs).max())
+
+
+# --------------------------------------------------------------------------
+# projection to tiles (Sec. 3.1.2 "Projection to image space") is
+# conservative: every ray-voxel hit lies in the voxel's tile rectangle, and
+# every pixel's own sign pattern is in its tile's mask
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("which", ["cfg0", "tiny"])
+def test_tile_assignment_is_conservative(which):
+    if which == "cfg0":
+        sc, cam = S.scene_cfg0(), S.camera_cfg0()
+    else:
+        sc = S.tiny_random_scene(5, max_level=4)
+        cam = S.look_at(40, 30, 70.0, [1.2, 0.9, 0.7], target=(0.5, 0.5, 0.5))
+    tw = th = 8
+    out = oracle.render(sc, cam, K=1, t_stop=0.0, max_seq=256)
+    _, r_may = oracle.voxel_tiles(sc, cam, tw, th)
+    r_must, _ = oracle.voxel_tiles(sc, cam, tw, th)
+    _, m_may = oracle.tile_masks(cam, tw, th)
+    ntx = (cam.W + tw - 1) // tw
+    nhits = 0
+    for p in range(cam.W * cam.H):
+        u, v = p % cam.W, p // cam.W
+        tx, ty = u // tw, v // th
+        for vid in out["seq"][p]:
+            if vid < 0:
+                break
+            R = r_may[vid]
+            assert R[0] <= tx <= R[1] and R[2] <= ty <= R[3]
+            nhits += 1
+        assert m_may[ty * ntx + tx] != 0
+    assert nhits > 50
+    # the must set is inside the may set
+    ok = r_must[:, 0] <= r_must[:, 1]
+    assert np.all(r_may[ok, 0] <= r_must[ok, 0]) and np.all(r_may[ok, 1] >= r_must[ok, 1])
