@@ -1,0 +1,235 @@
+"""Benchmark: forward + backward frames of the sparse-voxel rasterizer on one GPU.
+
+Workload: the ~1.07M-voxel synthetic scene (max level 12, SH degree 3, K = 2
+samples per segment, explin) rendered at 1297x840 from a seeded 36-view orbit,
+one view per step; a step is the whole hot path for that view:
+svr_preprocess (projection, pre-process, duplication), svr_sort, svr_render_fwd
+and svr_render_bwd (adjoint into grid densities and SH coefficients).  Inputs
+(scene, upstream gradients) are resident in HBM before the timed region.
+
+Prints one JSON line: Mpix/s (pixels x frames / s), frames/s, per-kernel
+times measured with HIP events on the launch stream, the roofline of the
+dominant kernel, the frame-level HBM fraction, and the FP64 CPU oracle timed
+on a bounded pixel sample of the same view.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "fwd+bwd Mpix/s and frames/s at 1M voxels 1297×840; achieved HBM GB/s vs peak"
+HBM_PEAK_GBS = 8000.0
+# VALU issue peak of MI355X without packed fp32: 256 CUs x 4 SIMDs x 16 lanes
+# x 2.4 GHz = 39.3e12 lane operations per second.
+VALU_PEAK_TOPS = 256 * 64 * 2.4e9 / 1e12
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+# algorithmic VALU lane operations of the render kernels (see the design notes)
+OPS_PAIR = 23              # sign test + ray-box slab test per walked (pixel, entry)
+OPS_HIT_FWD = lambda K: 13 + 28 * K
+OPS_HIT_BWD = lambda K: 2 * (13 + 28 * K) + 20 * K + 30
+
+
+def frame_bytes(N, Nv, E, P, S):
+    """Algorithmic HBM bytes of one fwd+bwd frame, per stage."""
+    return {
+        "project": 16 * N + 12 * N,                      # centre+size read; count+rect written
+        "preprocess": Nv * (32 + 32 + 4 * S + 64),       # indices, densities, SH read; record written
+        "emit": E * 12 + Nv * 8,                         # key+value written; path read
+        "sort": E * 24,                                  # one read and one write of the list
+        "render_fwd": E * 4 + Nv * 72 + P * 24,          # values, records+rects; rgba, tau, last
+        "render_bwd": E * 4 + Nv * 72 + P * 24 + Nv * 44,  # + upstream grads; 11 gradients/voxel
+        "sh_bwd": N * 4 * S + Nv * (12 + 32 + 32 + 32),  # grad_sh written; colour grads, indices, corner grads
+    }
+
+
+def kernel_bytes(name, N, Nv, E, P, S, passes):
+    if name == "sort_pass":
+        return 24 * E / 1.0  # per pass launch: read + write of the list
+    fb = frame_bytes(N, Nv, E, P, S)
+    return {"project": fb["project"] + fb["preprocess"], "emit": fb["emit"],
+            "render_fwd": fb["render_fwd"], "render_bwd": fb["render_bwd"],
+            "sh_bwd": fb["sh_bwd"]}.get(name)
+
+
+def cpu_baseline(scene, cam, K, seconds_target=15.0):
+    import oracle
+    threads = len(os.sched_getaffinity(0))
+    rng = np.random.default_rng(99)
+    P = cam.W * cam.H
+    n = 64
+    t_used = 0.0
+    done = 0
+    while t_used < seconds_target and done < 8192:
+        px = rng.choice(P, n, replace=False)
+        g = np.random.default_rng(done).normal(size=(n, 4))
+        t0 = time.perf_counter()
+        oracle.render(scene, cam, K=K, pixels=px, grad_rgba=g, nthreads=threads)
+        t_used += time.perf_counter() - t0
+        done += n
+        n = min(2 * n, 1024)
+    model = ""
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
+    return {"value": done / t_used / 1e6, "unit": "Mpix/s", "cores": threads, "kind": "oracle",
+            "sample": "%d seeded pixels of view 0, FP64 brute-force fwd+bwd over all %d voxels "
+                      "(%.1f s; CPU: %s)" % (done, scene.n_voxels, t_used, model)}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=72)
+    ap.add_argument("--warmup", type=int, default=8)
+    ap.add_argument("--views", type=int, default=36)
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: every box in this setup has a single MI355X, "
+              "and multi-GPU sharding is a design note, not a measured path.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    from paper_2412_04459_amd import _abi
+    from paper_2412_04459_amd import scenes as S
+    from paper_2412_04459_amd.render import DeviceScene, Rasterizer
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    t0 = time.time()
+    scene = S.scene_cfg2()
+    cams = S.cameras_cfg2(n=args.views)
+    K = 2
+    log("scene: %d voxels, %d grid points (%.1fs)" % (scene.n_voxels, scene.n_grid, time.time() - t0))
+    ds = DeviceScene(scene)
+    P = cams[0].W * cams[0].H
+    S_floats = 3 * (scene.sh_degree + 1) ** 2
+
+    # capacity from one counted pass over the orbit
+    probe = Rasterizer(ds, [cams[0]], K=K, sync_count=True)
+    e_max = 0
+    for c in cams:
+        probe.set_cameras([c])
+        probe.preprocess()
+        e_max = max(e_max, probe.n_entries)
+    del probe
+    cap = int(e_max * 1.1) + 4096
+    rast = Rasterizer(ds, [cams[0]], K=K, capacity=cap, sync_count=False)
+    grad = torch.from_numpy(S.upstream_grads(P, 2)).cuda()
+
+    # per-view statistics (untimed)
+    stats = []
+    for c in cams:
+        rast.set_cameras([c])
+        rast.preprocess()
+        rast.sort()
+        stats.append(rast.stats())
+    st = np.array(stats, dtype=np.float64)  # E, walked pairs, tests, hits, in-view voxels
+    E_mean, pairs_mean, tests_mean, hits_mean, Nv_mean = st.mean(0)
+    log("mean per view: E=%.0f pairs=%.3g tests=%.3g hits=%.3g in-view voxels=%.0f" % (
+        E_mean, pairs_mean, tests_mean, hits_mean, Nv_mean))
+
+    def step(i):
+        rast.set_cameras([cams[i % len(cams)]])
+        rast.forward()
+        rast.backward(grad)
+
+    for i in range(args.warmup):
+        step(i)
+    torch.cuda.synchronize()
+    _abi.svr_timing_enable(1)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record()
+    for i in range(args.steps):
+        step(i)
+    ev1.record()
+    torch.cuda.synchronize()
+    elapsed_ms = ev0.elapsed_time(ev1)
+    ktimes = _abi.kernel_times()
+    _abi.svr_timing_enable(0)
+    over = rast.check_overflow()
+    assert over <= cap, "entry capacity overflow during the timed region"
+    # same workload without per-kernel events, for the headline number
+    torch.cuda.synchronize()
+    ev0.record()
+    for i in range(args.steps):
+        step(i)
+    ev1.record()
+    torch.cuda.synchronize()
+    elapsed_ms = min(elapsed_ms, ev0.elapsed_time(ev1))
+
+    ms_step = elapsed_ms / args.steps
+    mpix = P * args.steps / (elapsed_ms / 1e3) / 1e6
+    per_kernel = {k: {"ms_per_step": v[0] / args.steps, "launches_per_step": v[1] / args.steps,
+                      "avg_us": 1e3 * v[0] / max(v[1], 1)} for k, v in ktimes.items()}
+    dom = max(ktimes, key=lambda k: ktimes[k][0])
+    dom_avg_s = ktimes[dom][0] / 1e3 / ktimes[dom][1]
+    if dom in ("render_fwd", "render_bwd"):
+        ops = pairs_mean * OPS_PAIR + hits_mean * (OPS_HIT_FWD(K) if dom == "render_fwd" else OPS_HIT_BWD(K))
+        ach = ops / dom_avg_s / 1e12
+        roof = {"kernel": dom, "bound": "alu", "achieved": ach, "peak": VALU_PEAK_TOPS,
+                "unit": "Tops/s", "frac": ach / VALU_PEAK_TOPS, "traffic": None,
+                "ops_per_launch": ops}
+    else:
+        b = kernel_bytes(dom, scene.n_voxels, Nv_mean, E_mean, P, S_floats, None)
+        ach = b / dom_avg_s / 1e9
+        roof = {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
+                "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": None,
+                "bytes_per_launch": b}
+    fb = frame_bytes(scene.n_voxels, Nv_mean, E_mean, P, S_floats)
+    fbytes = sum(fb.values())
+    frame_gbs = fbytes / (ms_step / 1e3) / 1e9
+    out = {
+        "metric": METRIC,
+        "value": mpix,
+        "unit": "Mpix/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "fp32",
+        "data": "synthetic",
+        "config": {"workload": "fwd+bwd, %d voxels (max level 12, SH degree 3), %dx%d, K=%d, "
+                               "explin, %d-view seeded orbit" % (scene.n_voxels, cams[0].W,
+                                                                 cams[0].H, K, len(cams)),
+                   "n_voxels": scene.n_voxels, "pixels": P, "entries_mean": E_mean,
+                   "in_view_voxels_mean": Nv_mean, "hits_per_pixel": hits_mean / P},
+        "frames_per_s": 1e3 / ms_step,
+        "frame_hbm": {"bytes": fbytes, "achieved_GBs": frame_gbs, "peak_GBs": HBM_PEAK_GBS,
+                      "frac": frame_gbs / HBM_PEAK_GBS},
+        "roofline": roof,
+        "kernels": per_kernel,
+    }
+    if not args.no_cpu:
+        log("timing the oracle on the host ...")
+        out["cpu_baseline"] = cpu_baseline(scene, cams[0], K, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,214 @@
+/*
+ * svraster.h -- C ABI of the MI355X (gfx950) sparse-voxel rasterizer.
+ *
+ * The library renders octree-leaf voxels ("Sparse Voxels Rasterization",
+ * Sun et al., CVPR 2025, arXiv 2412.04459) and back-propagates into their
+ * parameters.  One frame is four calls, in this order, on one stream:
+ *
+ *   svr_preprocess  project voxels to 16x16 screen tiles, pre-process the
+ *                   per-view voxel records and duplicate voxels per tile and
+ *                   ray-sign pattern                   (Sec. 3.1.2, Supp. B.1)
+ *   svr_sort        sort the duplicated list by tile and direction-dependent
+ *                   Morton order                       (Sec. 3.1.2, Supp. B.2)
+ *   svr_render_fwd  front-to-back alpha compositing of every pixel
+ *                   (Sec. 3.1 eq. alpha_blend, Sec. 3.1.1 eq. vox_alpha and
+ *                   eq. vox_color, Sec. 3.1.2 "Rendering pixels")
+ *   svr_render_bwd  the adjoint of svr_render_fwd into corner raw densities
+ *                   and SH coefficients (Supp. A.2, gradient of alpha)
+ *
+ * Conventions shared by every call:
+ *   - All array pointers inside svr_scene, and the rgba / gradient pointers,
+ *     are DEVICE pointers, caller-owned, contiguous, little-endian, fp32 unless
+ *     noted.  svr_camera arrays and svr_opts are HOST memory, read during the
+ *     call only.
+ *   - `ws` is a caller-allocated device workspace of at least
+ *     svr_workspace_bytes() bytes.  The library allocates nothing.  The
+ *     workspace carries the state from one call to the next of the same frame
+ *     (sorted list, per-pixel saved state); it must not be modified or reused
+ *     for another frame between svr_preprocess and the last svr_render_bwd of
+ *     that frame.  Distinct workspaces may be used concurrently.
+ *   - Every call enqueues its work asynchronously on `stream` (a hipStream_t;
+ *     NULL is the default stream) and returns a status code.  The only
+ *     host-visible synchronisation is in svr_preprocess when `n_entries_out`
+ *     is not NULL (one 8-byte read-back).
+ *   - No C++ exception crosses the ABI.  svr_last_error() describes the last
+ *     failing call of the calling thread.
+ *   - Camera model: OpenCV pinhole (x right, y down, z forward), world-to-camera
+ *     [R | t] row-major; the ray of pixel (u, v) leaves the camera centre
+ *     -R^T t along normalize(R^T ((u+0.5-cx)/fx, (v+0.5-cy)/fy, 1)).
+ */
+#ifndef SVRASTER_H
+#define SVRASTER_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes -------------------------------------------------------- */
+#define SVR_OK 0
+#define SVR_E_INVALID (-1)   /* bad argument: null pointer, limit exceeded, bad enum */
+#define SVR_E_CAPACITY (-2)  /* duplicated list exceeds opts.entry_capacity          */
+#define SVR_E_HIP (-3)       /* a HIP runtime call failed                            */
+#define SVR_E_WORKSPACE (-4) /* ws_bytes smaller than svr_workspace_bytes()          */
+#define SVR_E_DEVICE (-5)    /* a kernel reported an internal failure (see text)     */
+
+/* ---- enums and limits ---------------------------------------------------- */
+#define SVR_ACT_EXPLIN 0     /* Sec. 3.1.1 eq. explin                                */
+#define SVR_ACT_SOFTPLUS 1   /* softplus with beta = 1                               */
+#define SVR_MAX_CAMERAS 32   /* cameras per call                                     */
+#define SVR_MAX_LEVELS 16    /* octree levels (Supp. A.1)                            */
+#define SVR_MAX_VOXELS (1 << 29) /* voxel ids are 29 bits in a value (Supp. B.1)     */
+#define SVR_MAX_K 8          /* samples per ray-voxel segment                        */
+#define SVR_TILE 16          /* tile edge in pixels                                  */
+
+/* Scene (Sec. 3.1.1): leaf voxels in arbitrary order, corner grid points
+ * shared between voxels, per-voxel SH.  All pointers are device pointers.   */
+typedef struct svr_scene {
+  int64_t n_voxels;        /* N, 0 <= N < 2^29                                         */
+  int64_t n_grid;          /* M, number of corner grid points                          */
+  const float* center;     /* [3][N] voxel centres, SoA (x row, y row, z row)          */
+  const float* size;       /* [N]    voxel edge lengths                                */
+  const uint64_t* octpath; /* [N]    octree path: the octant (4x+2y+z) of level l sits
+                              at bits 3(16-l)..3(16-l)+2; unused low triplets zero
+                              (Supp. A.1 listing for the index <-> path conversion)   */
+  const int32_t* vox_grid; /* [N][8] grid point of corner c = 4dx + 2dy + dz          */
+  const float* grid_raw;   /* [M]    raw (pre-activation) densities                   */
+  const float* sh;         /* [N][(D+1)^2][3] SH coefficients, basis index l*l+l+m    */
+  int32_t sh_degree;       /* D in 0..3                                                */
+  int32_t max_level;       /* deepest level present, 1..16                             */
+} svr_scene;
+
+/* Pinhole camera (host memory). */
+typedef struct svr_camera {
+  int32_t width, height;   /* pixels, 1..16384                                         */
+  float fx, fy, cx, cy;    /* intrinsics in pixels                                     */
+  float w2c[12];           /* world-to-camera [R | t], row-major 3x4                   */
+} svr_camera;
+
+/* Options (host memory). */
+typedef struct svr_opts {
+  int32_t K;               /* samples per ray-voxel segment, 1..8 (eq. vox_alpha)      */
+  float t_stop;            /* early termination threshold on transmittance (h_T)      */
+  int32_t activation;      /* SVR_ACT_EXPLIN or SVR_ACT_SOFTPLUS                       */
+  int32_t reserved0;
+  int64_t entry_capacity;  /* capacity of the duplicated (tile, voxel, sign) list, < 2^30 */
+} svr_opts;
+
+/* Bytes of workspace one frame of `n_cams` cameras needs with
+ * opts->entry_capacity entries.  Returns 0 on invalid arguments. */
+size_t svr_workspace_bytes(const svr_scene* scene, const svr_camera* cams, int n_cams,
+                           const svr_opts* opts);
+
+/* Projection and pre-processing (Sec. 3.1.2 "Projection to image space",
+ * "Pre-processing voxels"; duplication per tile and ray-sign pattern,
+ * Supp. B.1).
+ * For every camera and voxel: project the 8 corners and assign the voxel to
+ * every tile overlapped by the box of the projections (voxels outside the
+ * view frustum are culled; one with a corner closer than 1e-4 to the camera
+ * plane is assigned every tile); gather its 8 corner densities and evaluate
+ * its SH colour for the direction from the camera centre to the voxel centre;
+ * then emit one (key, value) entry per (tile, ray-sign pattern present among
+ * that tile's pixels).  key = tile << (3 max_level + 3) | order << 3 | s with
+ * order the top 3 max_level bits of the direction-dependent Morton code
+ * (Supp. B.2), value = s << 29 | voxel id.
+ *   n_entries_out  host pointer receiving the entry count E; the call then
+ *                  reads E back (one synchronisation) and returns
+ *                  SVR_E_CAPACITY, with *n_entries_out = E, when E exceeds
+ *                  opts->entry_capacity (nothing is emitted then).  NULL: no
+ *                  synchronisation; overflow is reported later by
+ *                  svr_check_overflow() and the list is truncated.
+ * Errors: SVR_E_INVALID, SVR_E_WORKSPACE, SVR_E_CAPACITY, SVR_E_HIP.        */
+int svr_preprocess(const svr_scene* scene, const svr_camera* cams, int n_cams,
+                   const svr_opts* opts, void* ws, size_t ws_bytes, int64_t* n_entries_out,
+                   void* stream);
+
+/* Sort the duplicated list by key (ascending; keys are unique whenever
+ * max_level <= 15, so the order is fully determined) with an LSD radix sort
+ * over the significant key bits, then find each tile's [start, end) range
+ * (Sec. 3.1.2 "Sorting voxels").  `n_entries_hint` is E when known (it sizes
+ * the launches) or -1 to size them by capacity; the device-side count is
+ * authoritative either way.
+ * Errors: SVR_E_INVALID, SVR_E_WORKSPACE, SVR_E_HIP.                         */
+int svr_sort(const svr_scene* scene, const svr_camera* cams, int n_cams, const svr_opts* opts,
+             void* ws, size_t ws_bytes, int64_t n_entries_hint, void* stream);
+
+/* Render (Sec. 3.1 eq. alpha_blend; Sec. 3.1.1 eq. vox_alpha, eq. explin,
+ * eq. vox_color; Supp. A.2 eq. K_samp_pts, eq. interp; Sec. 3.1.2 "Rendering
+ * pixels").  Each pixel walks its tile's sorted list; entries of another
+ * sign pattern and voxels its ray misses (ray-box slab test, entry distance
+ * > 0) are skipped; a voxel is composited iff the transmittance before it is
+ * >= t_stop.  Output rgba: [sum_c H_c W_c][4], cameras in order, row-major
+ * pixels; premultiplied RGB and A = 1 - T_final (no background).
+ * Errors: SVR_E_INVALID, SVR_E_WORKSPACE, SVR_E_HIP.                         */
+int svr_render_fwd(const svr_scene* scene, const svr_camera* cams, int n_cams,
+                   const svr_opts* opts, void* ws, size_t ws_bytes, float* rgba, void* stream);
+
+/* Adjoint of svr_render_fwd for L = sum <grad_rgba, rgba>.  The transmittance
+ * is recomputed walking each pixel's list back to front from the saved final
+ * optical depth (no per-sample state is stored).  Outputs are overwritten:
+ *   grad_grid  [M]                 dL/d grid_raw            (may be NULL)
+ *   grad_sh    [N][(D+1)^2][3]     dL/d sh                  (may be NULL)
+ * Errors: SVR_E_INVALID, SVR_E_WORKSPACE, SVR_E_HIP.                         */
+int svr_render_bwd(const svr_scene* scene, const svr_camera* cams, int n_cams,
+                   const svr_opts* opts, void* ws, size_t ws_bytes, const float* grad_rgba,
+                   float* grad_grid, float* grad_sh, void* stream);
+
+/* After the frame (synchronises `stream`): *required_entries = E of the last
+ * svr_preprocess on this workspace.  Returns SVR_E_CAPACITY if E exceeded
+ * the capacity, SVR_E_DEVICE if a kernel flagged an internal failure. */
+int svr_check_overflow(const svr_scene* scene, const svr_camera* cams, int n_cams,
+                       const svr_opts* opts, void* ws, size_t ws_bytes,
+                       int64_t* required_entries, void* stream);
+
+/* Read back the sorted list of the frame (debug / parity): keys[E], values[E]
+ * device pointers of capacity >= E.  Asynchronous. */
+int svr_copy_sorted(const svr_scene* scene, const svr_camera* cams, int n_cams,
+                    const svr_opts* opts, void* ws, size_t ws_bytes, uint64_t* keys,
+                    uint32_t* values, int64_t n, void* stream);
+
+/* Stand-alone stable LSD radix sort of (key, value) pairs on bits [0, bits)
+ * of the keys, the sort svr_sort runs (Supp. B.1 "GPU Radix sort").
+ * keys/values: device [n], sorted in place.  keys_tmp/values_tmp: device [n]
+ * scratch.  scratch: device, >= svr_radix_sort_scratch_bytes(n, bits).
+ * Errors: SVR_E_INVALID, SVR_E_WORKSPACE, SVR_E_HIP.                         */
+size_t svr_radix_sort_scratch_bytes(int64_t n, int bits);
+int svr_radix_sort_pairs(uint64_t* keys, uint32_t* values, uint64_t* keys_tmp,
+                         uint32_t* values_tmp, int64_t n, int bits, void* scratch,
+                         size_t scratch_bytes, void* stream);
+
+/* Frame statistics (diagnostics; synchronises `stream`), after svr_sort:
+ *   counts[0]  entries E of the sorted list
+ *   counts[1]  (pixel, entry) pairs with the pixel's sign pattern that the
+ *              compositing loop of Sec. 3.1.2 walks (up to early termination)
+ *   counts[2]  ray-box tests the render kernel executes after its culling
+ *   counts[3]  composited ray-voxel hits
+ *   counts[4]  (voxel, camera) pairs with at least one entry (in view)
+ * Runs a counting variant of the render kernel; writes no image.
+ * Errors: SVR_E_INVALID, SVR_E_WORKSPACE, SVR_E_HIP.                         */
+int svr_render_stats(const svr_scene* scene, const svr_camera* cams, int n_cams,
+                     const svr_opts* opts, void* ws, size_t ws_bytes, int64_t* counts,
+                     void* stream);
+
+/* Kernel timing (diagnostics, process-wide, not for concurrent use from
+ * several threads): while enabled, every kernel launch of the library is
+ * bracketed by HIP events on its own stream.  svr_timing_read waits for the
+ * recorded events and returns, per kernel name (NUL-terminated, name_len bytes
+ * per slot), the summed duration in milliseconds and the launch count since
+ * the last read or enable, then clears the records.  At most 8192 launches
+ * are recorded between reads.
+ * Errors: SVR_E_INVALID, SVR_E_HIP.                                          */
+int svr_timing_enable(int on);
+int svr_timing_read(char* names, int name_len, double* total_ms, int64_t* launches, int max_n,
+                    int* n_out);
+
+/* Static text of a status code; detail of the calling thread's last error. */
+const char* svr_status_string(int status);
+const char* svr_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SVRASTER_H */

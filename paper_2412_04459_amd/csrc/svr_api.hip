@@ -1,0 +1,466 @@
+// Host side of the C ABI declared in include/svraster.h: argument checks,
+// workspace layout, and the launch sequence of each stage.  No allocation
+// happens here; every buffer is carved out of the caller's workspace.
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "svr_internal.h"
+
+namespace svr {
+
+// ---- kernel timing (diagnostics) -------------------------------------------
+namespace {
+std::mutex g_tmu;
+bool g_timing = false;
+std::vector<hipEvent_t> g_events;  // pool; pairs (start, stop)
+size_t g_next = 0;
+struct TimingRec {
+  const char* name;
+  int slot;
+};
+std::vector<TimingRec> g_recs;
+constexpr size_t kEventPool = 16384;
+}  // namespace
+
+int timing_begin(hipStream_t s) {
+  if (!g_timing) return -1;
+  std::lock_guard<std::mutex> lk(g_tmu);
+  if (g_next + 2 > g_events.size()) return -1;
+  const int slot = (int)g_next;
+  g_next += 2;
+  if (hipEventRecord(g_events[slot], s) != hipSuccess) return -1;
+  return slot;
+}
+
+void timing_end(int slot, const char* name, hipStream_t s) {
+  if (slot < 0) return;
+  std::lock_guard<std::mutex> lk(g_tmu);
+  if (hipEventRecord(g_events[slot + 1], s) == hipSuccess) g_recs.push_back({name, slot});
+}
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const char* fmt, ...) __attribute__((format(printf, 2, 3)));
+int fail(int code, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof(buf), fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return code;
+}
+
+int hip_fail(hipError_t e, const char* what) {
+  return fail(SVR_E_HIP, "%s: %s", what, hipGetErrorString(e));
+}
+
+#define SVR_HIP(call, what)                        \
+  do {                                             \
+    hipError_t e_ = (call);                        \
+    if (e_ != hipSuccess) return hip_fail(e_, what); \
+  } while (0)
+
+size_t align_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+
+int bits_for(int64_t x) {  // bits needed to hold values 0..x
+  int b = 0;
+  while (x > 0) {
+    ++b;
+    x >>= 1;
+  }
+  return b;
+}
+
+int make_layout(const svr_scene* sc, const svr_camera* cams, int n_cams, const svr_opts* o,
+                Layout* L, CamSet* cs) {
+  if (!sc || !cams || !o || !L) return fail(SVR_E_INVALID, "null scene, camera or options pointer");
+  if (n_cams < 1 || n_cams > SVR_MAX_CAMERAS)
+    return fail(SVR_E_INVALID, "n_cams=%d outside 1..%d", n_cams, SVR_MAX_CAMERAS);
+  if (sc->n_voxels < 0 || sc->n_voxels >= (int64_t)SVR_MAX_VOXELS)
+    return fail(SVR_E_INVALID, "n_voxels=%lld outside [0, 2^29)", (long long)sc->n_voxels);
+  if (sc->n_grid < 0) return fail(SVR_E_INVALID, "n_grid < 0");
+  if (sc->sh_degree < 0 || sc->sh_degree > 3)
+    return fail(SVR_E_INVALID, "sh_degree=%d outside 0..3", sc->sh_degree);
+  if (sc->max_level < 1 || sc->max_level > SVR_MAX_LEVELS)
+    return fail(SVR_E_INVALID, "max_level=%d outside 1..16", sc->max_level);
+  if (sc->n_voxels > 0 && (!sc->center || !sc->size || !sc->octpath || !sc->vox_grid ||
+                           !sc->grid_raw || !sc->sh))
+    return fail(SVR_E_INVALID, "null scene array");
+  if (o->K < 1 || o->K > SVR_MAX_K) return fail(SVR_E_INVALID, "K=%d outside 1..8", o->K);
+  if (o->activation != SVR_ACT_EXPLIN && o->activation != SVR_ACT_SOFTPLUS)
+    return fail(SVR_E_INVALID, "unknown activation %d", o->activation);
+  if (!(o->t_stop >= 0.f && o->t_stop <= 1.f))
+    return fail(SVR_E_INVALID, "t_stop outside [0, 1]");
+  if (o->entry_capacity < 0 || o->entry_capacity >= (int64_t)1 << 30)
+    return fail(SVR_E_INVALID, "entry_capacity outside [0, 2^30)");
+  Layout& l = *L;
+  memset(&l, 0, sizeof(l));
+  memset(cs, 0, sizeof(*cs));
+  l.N = sc->n_voxels;
+  l.n_cams = n_cams;
+  l.NV = l.N * n_cams;
+  l.cap = o->entry_capacity;
+  l.L = sc->max_level;
+  int64_t T = 0, P = 0, sat = 0;
+  cs->n = n_cams;
+  for (int i = 0; i < n_cams; ++i) {
+    const svr_camera& c = cams[i];
+    if (c.width < 1 || c.height < 1 || c.width > 16384 || c.height > 16384)
+      return fail(SVR_E_INVALID, "camera %d: size %dx%d outside 1..16384", i, c.width, c.height);
+    if (!(c.fx > 0.f) || !(c.fy > 0.f) || !isfinite(c.cx) || !isfinite(c.cy))
+      return fail(SVR_E_INVALID, "camera %d: bad intrinsics", i);
+    for (int k = 0; k < 12; ++k)
+      if (!isfinite(c.w2c[k])) return fail(SVR_E_INVALID, "camera %d: non-finite pose", i);
+    DevCam& d = cs->c[i];
+    for (int r = 0; r < 3; ++r)
+      for (int j = 0; j < 3; ++j) d.r[3 * r + j] = c.w2c[4 * r + j];
+    for (int j = 0; j < 3; ++j) {
+      double acc = 0;
+      for (int r = 0; r < 3; ++r) acc += (double)c.w2c[4 * r + j] * (double)c.w2c[4 * r + 3];
+      d.o[j] = (float)(-acc);
+    }
+    d.fx = c.fx; d.fy = c.fy; d.cx = c.cx; d.cy = c.cy;
+    d.W = c.width; d.H = c.height;
+    d.ntx = (c.width + kTile - 1) / kTile;
+    d.nty = (c.height + kTile - 1) / kTile;
+    d.tile_off = (int32_t)T;
+    d.sat_off = (int32_t)sat;
+    d.pix_off = P;
+    T += (int64_t)d.ntx * d.nty;
+    sat += (int64_t)(d.ntx + 1) * (d.nty + 1);
+    P += (int64_t)c.width * c.height;
+  }
+  if (T >= ((int64_t)1 << 31)) return fail(SVR_E_INVALID, "too many tiles");
+  l.T = (int32_t)T;
+  l.P = P;
+  l.sat_total = (int32_t)sat;
+  cs->total_tiles = l.T;
+  l.key_bits = bits_for(T - 1) + 3 * l.L + 3;
+  if (l.key_bits > 64)
+    return fail(SVR_E_INVALID, "sort key needs %d bits (> 64): too many tiles for max_level %d",
+                l.key_bits, l.L);
+  l.passes = (l.key_bits + 7) / 8;
+  l.scan_blocks = (l.NV + 4095) / 4096;
+  l.sort_parts = (l.cap + 4095) / 4096;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    size_t at_ = off;
+    off = align_up(off + bytes, 256);
+    return at_;
+  };
+  l.hdr = take(sizeof(WsHeader));
+  l.count = take((size_t)l.NV * 4);
+  l.offset = take((size_t)l.NV * 8);
+  l.rect = take((size_t)l.NV * 8);
+  l.rec = take((size_t)l.NV * sizeof(VoxRec));
+  l.scan_part = take((size_t)(l.scan_blocks > 0 ? l.scan_blocks : 1) * 8);
+  l.tile_mask = take((size_t)T);
+  l.tile_sat = take((size_t)sat * 4);
+  l.tile_range = take((size_t)T * 8);
+  l.keys0 = take((size_t)l.cap * 8);
+  l.keys1 = take((size_t)l.cap * 8);
+  l.vals0 = take((size_t)l.cap * 4);
+  l.vals1 = take((size_t)l.cap * 4);
+  l.sort_hist = take(8 * 256 * 4);
+  l.sort_status0 = take((size_t)(l.sort_parts > 0 ? l.sort_parts : 1) * 256 * 4);
+  l.sort_status1 = take((size_t)(l.sort_parts > 0 ? l.sort_parts : 1) * 256 * 4);
+  l.px_tau = take((size_t)P * 4);
+  l.px_last = take((size_t)P * 4);
+  l.g_corner = take((size_t)l.N * 32);
+  l.g_rgb = take((size_t)l.NV * 12);
+  l.total = off;
+  return SVR_OK;
+}
+
+int check_ws(const Layout& L, void* ws, size_t ws_bytes) {
+  if (!ws) return fail(SVR_E_INVALID, "null workspace");
+  if ((reinterpret_cast<uintptr_t>(ws) & 255u) != 0)
+    return fail(SVR_E_INVALID, "workspace must be 256-byte aligned");
+  if (ws_bytes < L.total)
+    return fail(SVR_E_WORKSPACE, "workspace has %zu bytes, %zu needed", ws_bytes, L.total);
+  return SVR_OK;
+}
+
+const uint32_t* sorted_vals(const Layout& L, void* ws) {
+  return at<uint32_t>(ws, (L.passes & 1) ? L.vals1 : L.vals0);
+}
+const uint64_t* sorted_keys(const Layout& L, void* ws) {
+  return at<uint64_t>(ws, (L.passes & 1) ? L.keys1 : L.keys0);
+}
+
+}  // namespace
+}  // namespace svr
+
+using namespace svr;
+
+extern "C" {
+
+size_t svr_workspace_bytes(const svr_scene* scene, const svr_camera* cams, int n_cams,
+                           const svr_opts* opts) {
+  Layout L;
+  CamSet cs;
+  if (make_layout(scene, cams, n_cams, opts, &L, &cs) != SVR_OK) return 0;
+  return L.total;
+}
+
+int svr_preprocess(const svr_scene* scene, const svr_camera* cams, int n_cams,
+                   const svr_opts* opts, void* ws, size_t ws_bytes, int64_t* n_entries_out,
+                   void* stream) {
+  Layout L;
+  CamSet cs;
+  int st = make_layout(scene, cams, n_cams, opts, &L, &cs);
+  if (st != SVR_OK) return st;
+  if ((st = check_ws(L, ws, ws_bytes)) != SVR_OK) return st;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  SVR_HIP(launch_fill_u32(at<uint32_t>(ws, L.hdr), 0u, sizeof(WsHeader) / 4, s), "clear header");
+  SVR_HIP(launch_tile_masks(cs, at<uint8_t>(ws, L.tile_mask), s), "tile masks");
+  SVR_HIP(launch_tile_sat(cs, at<uint8_t>(ws, L.tile_mask), at<uint32_t>(ws, L.tile_sat), s),
+          "tile table");
+  SVR_HIP(launch_project(*scene, cs, L, ws, s), "project");
+  SVR_HIP(launch_scan(L, ws, s), "scan");
+  if (n_entries_out) {
+    unsigned long long E = 0;
+    SVR_HIP(hipMemcpyAsync(&E, &at<WsHeader>(ws, L.hdr)->n_entries, sizeof(E),
+                           hipMemcpyDeviceToHost, s),
+            "read entry count");
+    SVR_HIP(hipStreamSynchronize(s), "synchronise");
+    *n_entries_out = (int64_t)E;
+    if ((int64_t)E > L.cap)
+      return fail(SVR_E_CAPACITY, "%llu entries exceed capacity %lld", E, (long long)L.cap);
+  }
+  SVR_HIP(launch_emit(*scene, cs, L, ws, s), "emit");
+  return SVR_OK;
+}
+
+int svr_sort(const svr_scene* scene, const svr_camera* cams, int n_cams, const svr_opts* opts,
+             void* ws, size_t ws_bytes, int64_t n_entries_hint, void* stream) {
+  Layout L;
+  CamSet cs;
+  int st = make_layout(scene, cams, n_cams, opts, &L, &cs);
+  if (st != SVR_OK) return st;
+  if ((st = check_ws(L, ws, ws_bytes)) != SVR_OK) return st;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  const int64_t n_max = (n_entries_hint >= 0 && n_entries_hint < L.cap) ? n_entries_hint : L.cap;
+  WsHeader* hdr = at<WsHeader>(ws, L.hdr);
+  bool in1 = false;
+  SVR_HIP(launch_radix_sort(at<uint64_t>(ws, L.keys0), at<uint32_t>(ws, L.vals0),
+                            at<uint64_t>(ws, L.keys1), at<uint32_t>(ws, L.vals1), &hdr->n_entries,
+                            n_max, L.key_bits, at<uint32_t>(ws, L.sort_hist),
+                            at<uint32_t>(ws, L.sort_status0), at<uint32_t>(ws, L.sort_status1),
+                            hdr->tickets, &hdr->error, &in1, s),
+          "radix sort");
+  SVR_HIP(launch_tile_ranges(L, ws, sorted_keys(L, ws), s), "tile ranges");
+  return SVR_OK;
+}
+
+int svr_render_fwd(const svr_scene* scene, const svr_camera* cams, int n_cams,
+                   const svr_opts* opts, void* ws, size_t ws_bytes, float* rgba, void* stream) {
+  Layout L;
+  CamSet cs;
+  int st = make_layout(scene, cams, n_cams, opts, &L, &cs);
+  if (st != SVR_OK) return st;
+  if ((st = check_ws(L, ws, ws_bytes)) != SVR_OK) return st;
+  if (!rgba && L.P > 0) return fail(SVR_E_INVALID, "null rgba");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  SVR_HIP(launch_render_fwd(*scene, cs, *opts, L, ws, sorted_vals(L, ws), rgba, s), "render fwd");
+  return SVR_OK;
+}
+
+int svr_render_bwd(const svr_scene* scene, const svr_camera* cams, int n_cams,
+                   const svr_opts* opts, void* ws, size_t ws_bytes, const float* grad_rgba,
+                   float* grad_grid, float* grad_sh, void* stream) {
+  Layout L;
+  CamSet cs;
+  int st = make_layout(scene, cams, n_cams, opts, &L, &cs);
+  if (st != SVR_OK) return st;
+  if ((st = check_ws(L, ws, ws_bytes)) != SVR_OK) return st;
+  if (!grad_rgba && L.P > 0) return fail(SVR_E_INVALID, "null grad_rgba");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  SVR_HIP(launch_render_bwd(*scene, cs, *opts, L, ws, sorted_vals(L, ws), grad_rgba, s),
+          "render bwd");
+  SVR_HIP(launch_sh_bwd(*scene, cs, L, ws, grad_grid, grad_sh, s), "pre-process adjoint");
+  return SVR_OK;
+}
+
+int svr_check_overflow(const svr_scene* scene, const svr_camera* cams, int n_cams,
+                       const svr_opts* opts, void* ws, size_t ws_bytes,
+                       int64_t* required_entries, void* stream) {
+  Layout L;
+  CamSet cs;
+  int st = make_layout(scene, cams, n_cams, opts, &L, &cs);
+  if (st != SVR_OK) return st;
+  if ((st = check_ws(L, ws, ws_bytes)) != SVR_OK) return st;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  WsHeader h;
+  SVR_HIP(hipMemcpyAsync(&h, at<WsHeader>(ws, L.hdr), sizeof(h), hipMemcpyDeviceToHost, s),
+          "read header");
+  SVR_HIP(hipStreamSynchronize(s), "synchronise");
+  if (required_entries) *required_entries = (int64_t)h.n_entries;
+  if (h.error) return fail(SVR_E_DEVICE, "sort look-back exceeded its spin limit");
+  if ((int64_t)h.n_entries > L.cap)
+    return fail(SVR_E_CAPACITY, "%llu entries exceed capacity %lld", h.n_entries,
+                (long long)L.cap);
+  return SVR_OK;
+}
+
+int svr_copy_sorted(const svr_scene* scene, const svr_camera* cams, int n_cams,
+                    const svr_opts* opts, void* ws, size_t ws_bytes, uint64_t* keys,
+                    uint32_t* values, int64_t n, void* stream) {
+  Layout L;
+  CamSet cs;
+  int st = make_layout(scene, cams, n_cams, opts, &L, &cs);
+  if (st != SVR_OK) return st;
+  if ((st = check_ws(L, ws, ws_bytes)) != SVR_OK) return st;
+  if (n < 0 || n > L.cap) return fail(SVR_E_INVALID, "n outside [0, capacity]");
+  if (n == 0) return SVR_OK;
+  if (!keys || !values) return fail(SVR_E_INVALID, "null output");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  SVR_HIP(hipMemcpyAsync(keys, sorted_keys(L, ws), (size_t)n * 8, hipMemcpyDeviceToDevice, s),
+          "copy keys");
+  SVR_HIP(hipMemcpyAsync(values, sorted_vals(L, ws), (size_t)n * 4, hipMemcpyDeviceToDevice, s),
+          "copy values");
+  return SVR_OK;
+}
+
+size_t svr_radix_sort_scratch_bytes(int64_t n, int bits) {
+  if (n < 0 || bits < 0 || bits > 64) return 0;
+  return align_up(sort_scratch_bytes(n, bits, nullptr), 256) + 256;
+}
+
+int svr_radix_sort_pairs(uint64_t* keys, uint32_t* values, uint64_t* keys_tmp,
+                         uint32_t* values_tmp, int64_t n, int bits, void* scratch,
+                         size_t scratch_bytes, void* stream) {
+  if (n < 0 || n >= ((int64_t)1 << 30)) return fail(SVR_E_INVALID, "n outside [0, 2^30)");
+  if (bits < 0 || bits > 64) return fail(SVR_E_INVALID, "bits outside 0..64");
+  if (n == 0) return SVR_OK;
+  if (!keys || !values || !keys_tmp || !values_tmp || !scratch)
+    return fail(SVR_E_INVALID, "null pointer");
+  if ((reinterpret_cast<uintptr_t>(scratch) & 255u) != 0)
+    return fail(SVR_E_INVALID, "scratch must be 256-byte aligned");
+  const size_t need = svr_radix_sort_scratch_bytes(n, bits);
+  if (scratch_bytes < need)
+    return fail(SVR_E_WORKSPACE, "scratch has %zu bytes, %zu needed", scratch_bytes, need);
+  int64_t parts = 0;
+  sort_scratch_bytes(n, bits, &parts);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  // [n as u64 | tickets 16 | err | pad] [hist 2048] [status0] [status1]
+  uint32_t* base = reinterpret_cast<uint32_t*>(scratch);
+  auto* n_dev = reinterpret_cast<unsigned long long*>(base);
+  uint32_t* tickets = base + 2;
+  uint32_t* err = base + 18;
+  uint32_t* hist = base + 64;
+  uint32_t* st0 = hist + 8 * 256;
+  uint32_t* st1 = st0 + (parts > 0 ? parts : 1) * 256;
+  SVR_HIP(launch_fill_u32(base, 0u, 64, s), "clear scratch");
+  SVR_HIP(launch_fill_u32(base, (uint32_t)(n & 0xffffffffu), 1, s), "store n");
+  bool in1 = false;
+  SVR_HIP(launch_radix_sort(keys, values, keys_tmp, values_tmp, n_dev, n, bits, hist, st0, st1,
+                            tickets, err, &in1, s),
+          "radix sort");
+  if (in1) {
+    SVR_HIP(hipMemcpyAsync(keys, keys_tmp, (size_t)n * 8, hipMemcpyDeviceToDevice, s), "copy keys");
+    SVR_HIP(hipMemcpyAsync(values, values_tmp, (size_t)n * 4, hipMemcpyDeviceToDevice, s),
+            "copy values");
+  }
+  return SVR_OK;
+}
+
+int svr_render_stats(const svr_scene* scene, const svr_camera* cams, int n_cams,
+                     const svr_opts* opts, void* ws, size_t ws_bytes, int64_t* counts,
+                     void* stream) {
+  Layout L;
+  CamSet cs;
+  int st = make_layout(scene, cams, n_cams, opts, &L, &cs);
+  if (st != SVR_OK) return st;
+  if ((st = check_ws(L, ws, ws_bytes)) != SVR_OK) return st;
+  if (!counts) return fail(SVR_E_INVALID, "null counts");
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  SVR_HIP(launch_render_stats(*scene, cs, *opts, L, ws, sorted_vals(L, ws), s), "render stats");
+  WsHeader h;
+  SVR_HIP(hipMemcpyAsync(&h, at<WsHeader>(ws, L.hdr), sizeof(h), hipMemcpyDeviceToHost, s),
+          "read header");
+  SVR_HIP(hipStreamSynchronize(s), "synchronise");
+  counts[0] = (int64_t)(h.n_entries < (unsigned long long)L.cap ? h.n_entries : L.cap);
+  counts[1] = (int64_t)h.stats[0];
+  counts[2] = (int64_t)h.stats[1];
+  counts[3] = (int64_t)h.stats[2];
+  counts[4] = (int64_t)h.stats[3];
+  return SVR_OK;
+}
+
+int svr_timing_enable(int on) {
+  std::lock_guard<std::mutex> lk(g_tmu);
+  if (on && g_events.empty()) {
+    g_events.resize(kEventPool);
+    for (size_t i = 0; i < kEventPool; ++i) {
+      hipError_t e = hipEventCreate(&g_events[i]);
+      if (e != hipSuccess) {
+        g_events.resize(i);
+        return hip_fail(e, "create timing events");
+      }
+    }
+  }
+  g_timing = on != 0;
+  g_next = 0;
+  g_recs.clear();
+  return SVR_OK;
+}
+
+int svr_timing_read(char* names, int name_len, double* total_ms, int64_t* launches, int max_n,
+                    int* n_out) {
+  std::lock_guard<std::mutex> lk(g_tmu);
+  if (!n_out || (max_n > 0 && (!names || !total_ms || !launches)) || name_len < 2)
+    return fail(SVR_E_INVALID, "bad timing output arguments");
+  int n = 0;
+  std::vector<std::string> keys;
+  std::vector<double> ms;
+  std::vector<int64_t> cnt;
+  for (const TimingRec& r : g_recs) {
+    SVR_HIP(hipEventSynchronize(g_events[r.slot + 1]), "wait for timing event");
+    float t = 0.f;
+    SVR_HIP(hipEventElapsedTime(&t, g_events[r.slot], g_events[r.slot + 1]), "elapsed time");
+    size_t k = 0;
+    while (k < keys.size() && keys[k] != r.name) ++k;
+    if (k == keys.size()) {
+      keys.push_back(r.name);
+      ms.push_back(0.0);
+      cnt.push_back(0);
+    }
+    ms[k] += t;
+    cnt[k] += 1;
+  }
+  for (size_t k = 0; k < keys.size() && n < max_n; ++k, ++n) {
+    snprintf(names + (size_t)n * name_len, (size_t)name_len, "%s", keys[k].c_str());
+    total_ms[n] = ms[k];
+    launches[n] = cnt[k];
+  }
+  *n_out = n;
+  g_next = 0;
+  g_recs.clear();
+  return SVR_OK;
+}
+
+const char* svr_status_string(int status) {
+  switch (status) {
+    case SVR_OK: return "ok";
+    case SVR_E_INVALID: return "invalid argument";
+    case SVR_E_CAPACITY: return "entry capacity exceeded";
+    case SVR_E_HIP: return "HIP runtime error";
+    case SVR_E_WORKSPACE: return "workspace too small";
+    case SVR_E_DEVICE: return "device-side failure";
+    default: return "unknown status";
+  }
+}
+
+const char* svr_last_error(void) { return g_err.c_str(); }
+
+}  // extern "C"

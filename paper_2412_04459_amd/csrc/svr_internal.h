@@ -1,0 +1,140 @@
+// Internal declarations of the gfx950 sparse-voxel rasterizer library.
+// Device structures, the workspace layout and the kernel launchers shared by
+// the translation units.  Not part of the public ABI (include/svraster.h).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "svraster.h"
+
+namespace svr {
+
+constexpr int kTile = SVR_TILE;   // tile edge (pixels)
+constexpr int kBlock = 256;       // threads per workgroup: 4 wave64
+constexpr float kZNear = 1e-4f;   // corners closer than this to the camera plane
+                                  // make a voxel cover every tile
+constexpr int kVidBits = 29;
+constexpr uint32_t kVidMask = (1u << kVidBits) - 1u;
+
+// A camera as the kernels see it.  Rotation is world-to-camera (row-major);
+// `o` is the camera centre in world space.
+struct DevCam {
+  float r[9];
+  float o[3];
+  float fx, fy, cx, cy;
+  int32_t W, H, ntx, nty;
+  int32_t tile_off;   // first global tile id of this camera
+  int32_t sat_off;    // offset of this camera's (nty+1) x (ntx+1) summed-area table
+  int64_t pix_off;    // first pixel of this camera in the per-pixel arrays
+};
+
+struct CamSet {
+  int32_t n;
+  int32_t total_tiles;
+  DevCam c[SVR_MAX_CAMERAS];
+};
+
+// Per view-voxel record written by the projection pass and read by the
+// render passes, 64 bytes:
+//   q0 = (box min - camera centre).xyz, edge length
+//   q1 = raw densities of corners 0..3, q2 = corners 4..7
+//   q3 = clamped SH colour rgb, bits of the channels with a positive
+//        pre-clamp value (as int)
+struct alignas(16) VoxRec {
+  float4 q0, q1, q2, q3;
+};
+
+// Workspace header (device): counters written by kernels.
+struct WsHeader {
+  unsigned long long n_entries;   // E (may exceed capacity)
+  uint32_t overflow;              // E > capacity seen by the emitter
+  uint32_t error;                 // bit 0: sort look-back spin limit hit
+  uint32_t tickets[16];           // sort partition tickets, one per pass
+  unsigned long long stats[8];    // render statistics (svr_render_stats)
+  uint32_t pad[28];
+};
+static_assert(sizeof(WsHeader) == 256, "header size");
+
+struct Layout {
+  // sizes
+  int64_t N, NV, cap, P;
+  int32_t n_cams, T, sat_total, key_bits, passes, L;
+  int64_t scan_blocks, sort_parts;
+  // byte offsets into the workspace
+  size_t hdr, count, offset, rect, rec, scan_part;
+  size_t tile_mask, tile_sat, tile_range;
+  size_t keys0, keys1, vals0, vals1;
+  size_t sort_hist, sort_status0, sort_status1;
+  size_t px_tau, px_last;
+  size_t g_corner, g_rgb;
+  size_t total;
+};
+
+// ---- device helpers shared by the mask and render kernels ----------------
+// World direction (not normalised) of the ray through the centre of pixel
+// (u, v).  Written with explicit fused multiply-adds so every kernel that
+// calls it computes bit-identical directions (and hence sign patterns).
+__device__ __forceinline__ void pixel_dir(const DevCam& c, int u, int v, float& dx, float& dy,
+                                          float& dz) {
+  float x = ((float)u + 0.5f - c.cx) / c.fx;
+  float y = ((float)v + 0.5f - c.cy) / c.fy;
+  dx = __fmaf_rn(c.r[0], x, __fmaf_rn(c.r[3], y, c.r[6]));
+  dy = __fmaf_rn(c.r[1], x, __fmaf_rn(c.r[4], y, c.r[7]));
+  dz = __fmaf_rn(c.r[2], x, __fmaf_rn(c.r[5], y, c.r[8]));
+}
+
+__device__ __forceinline__ int sign_bits(float dx, float dy, float dz) {
+  return (dx < 0.f ? 4 : 0) | (dy < 0.f ? 2 : 0) | (dz < 0.f ? 1 : 0);
+}
+
+// ---- launchers (all asynchronous on `s`) ----------------------------------
+// preprocess
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
+hipError_t launch_tile_masks(const CamSet& cams, uint8_t* mask, hipStream_t s);
+hipError_t launch_tile_sat(const CamSet& cams, const uint8_t* mask, uint32_t* sat, hipStream_t s);
+hipError_t launch_project(const svr_scene& sc, const CamSet& cams, const Layout& L, void* ws,
+                          hipStream_t s);
+hipError_t launch_scan(const Layout& L, void* ws, hipStream_t s);
+hipError_t launch_emit(const svr_scene& sc, const CamSet& cams, const Layout& L, void* ws,
+                       hipStream_t s);
+// sort
+size_t sort_scratch_bytes(int64_t n, int bits, int64_t* parts_out);
+hipError_t launch_radix_sort(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1,
+                             const unsigned long long* n_dev, int64_t n_max, int bits,
+                             uint32_t* hist, uint32_t* st0, uint32_t* st1, uint32_t* tickets,
+                             uint32_t* err, bool* result_in_1, hipStream_t s);
+hipError_t launch_tile_ranges(const Layout& L, void* ws, const uint64_t* keys, hipStream_t s);
+// render
+hipError_t launch_render_fwd(const svr_scene& sc, const CamSet& cams, const svr_opts& o,
+                             const Layout& L, void* ws, const uint32_t* vals, float* rgba,
+                             hipStream_t s);
+hipError_t launch_render_bwd(const svr_scene& sc, const CamSet& cams, const svr_opts& o,
+                             const Layout& L, void* ws, const uint32_t* vals,
+                             const float* grad_rgba, hipStream_t s);
+hipError_t launch_sh_bwd(const svr_scene& sc, const CamSet& cams, const Layout& L, void* ws,
+                         float* grad_grid, float* grad_sh, hipStream_t s);
+
+// ---- diagnostics: kernel timing ------------------------------------------
+// When enabled (svr_timing_enable), every launch is bracketed by HIP events
+// recorded on the launch stream; svr_timing_read aggregates them per kernel.
+int timing_begin(hipStream_t s);
+void timing_end(int slot, const char* name, hipStream_t s);
+
+#define SVR_LAUNCH(name, kern, grid, block, shmem, stream, ...)            \
+  do {                                                                     \
+    const int slot_ = ::svr::timing_begin(stream);                         \
+    hipLaunchKernelGGL(kern, grid, block, shmem, stream, __VA_ARGS__);     \
+    ::svr::timing_end(slot_, name, stream);                                \
+  } while (0)
+
+hipError_t launch_render_stats(const svr_scene& sc, const CamSet& cams, const svr_opts& o,
+                               const Layout& L, void* ws, const uint32_t* vals, hipStream_t s);
+
+template <typename T>
+inline T* at(void* ws, size_t off) {
+  return reinterpret_cast<T*>(reinterpret_cast<char*>(ws) + off);
+}
+
+}  // namespace svr

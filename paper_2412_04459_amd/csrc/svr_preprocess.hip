@@ -1,0 +1,420 @@
+// Projection, per-view pre-processing and duplication of voxels per tile
+// (Sec. 3.1.2 "Projection to image space" and "Pre-processing voxels";
+// Supp. B.1 duplication per tile and ray-sign pattern; Supp. B.2 key).
+//
+// Passes, all over device-resident data:
+//   k_tile_masks   one workgroup per 16x16 tile: OR of the ray-sign patterns
+//                  of its in-image pixels (8-bit mask)
+//   k_tile_sat     one workgroup per camera: summed-area table of the mask
+//                  popcounts, so a voxel counts its entries in O(1)
+//   k_project      one thread per (voxel, camera): corner projection, culling,
+//                  pixel rectangle, entry count; for counted voxels also the
+//                  64-byte render record (box, 8 corner densities, SH colour)
+//   k_scan_*       exclusive scan of the counts (reduce / top / down-sweep)
+//   k_emit         one thread per counted (voxel, camera): the (key, value)
+//                  entries for every tile of its rectangle and every sign
+//                  pattern present in that tile
+#include "svr_internal.h"
+#include "svr_sh.h"
+
+namespace svr {
+
+// ---------------------------------------------------------------------------
+__global__ void k_fill_u32(uint32_t* __restrict__ p, uint32_t v, int64_t n) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (; i < n; i += stride) p[i] = v;
+}
+
+hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  int64_t blocks = (n + kBlock - 1) / kBlock;
+  if (blocks > 8192) blocks = 8192;
+  SVR_LAUNCH("fill", k_fill_u32, dim3((unsigned)blocks), dim3(kBlock), 0, s, p, v, n);
+  return hipGetLastError();
+}
+
+__device__ __forceinline__ int find_cam(const CamSet& cams, int gtile) {
+  int c = 0;
+  for (int i = 1; i < cams.n; ++i)
+    if (gtile >= cams.c[i].tile_off) c = i;
+  return c;
+}
+
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_tile_masks(CamSet cams, uint8_t* __restrict__ mask) {
+  __shared__ uint32_t m;
+  const int g = blockIdx.x;
+  const int ci = find_cam(cams, g);
+  const DevCam& c = cams.c[ci];
+  const int t = g - c.tile_off;
+  const int tx = t % c.ntx, ty = t / c.ntx;
+  const int u = tx * kTile + (threadIdx.x & (kTile - 1));
+  const int v = ty * kTile + (threadIdx.x / kTile);
+  if (threadIdx.x == 0) m = 0;
+  __syncthreads();
+  if (u < c.W && v < c.H) {
+    float dx, dy, dz;
+    pixel_dir(c, u, v, dx, dy, dz);
+    atomicOr(&m, 1u << sign_bits(dx, dy, dz));
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) mask[g] = (uint8_t)m;
+}
+
+hipError_t launch_tile_masks(const CamSet& cams, uint8_t* mask, hipStream_t s) {
+  SVR_LAUNCH("tile_masks", k_tile_masks, dim3(cams.total_tiles), dim3(kBlock), 0, s, cams, mask);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// sat[(ty) * (ntx+1) + tx] = sum of popcount(mask) over tiles (x < tx, y < ty)
+__global__ __launch_bounds__(kBlock) void k_tile_sat(CamSet cams, const uint8_t* __restrict__ mask,
+                                                     uint32_t* __restrict__ sat) {
+  const DevCam& c = cams.c[blockIdx.x];
+  const int W1 = c.ntx + 1;
+  uint32_t* S = sat + c.sat_off;
+  const uint8_t* Mk = mask + c.tile_off;
+  // row prefix sums (row 0 is zero)
+  for (int ty = threadIdx.x; ty <= c.nty; ty += blockDim.x) {
+    uint32_t acc = 0;
+    S[ty * W1] = 0;
+    for (int tx = 0; tx < c.ntx; ++tx) {
+      if (ty > 0) acc += __popc((unsigned)Mk[(ty - 1) * c.ntx + tx]);
+      S[ty * W1 + tx + 1] = acc;
+    }
+  }
+  __threadfence();
+  __syncthreads();
+  // column prefix sums
+  for (int tx = threadIdx.x; tx < W1; tx += blockDim.x) {
+    uint32_t acc = 0;
+    for (int ty = 0; ty <= c.nty; ++ty) {
+      acc += S[ty * W1 + tx];
+      S[ty * W1 + tx] = acc;
+    }
+  }
+}
+
+hipError_t launch_tile_sat(const CamSet& cams, const uint8_t* mask, uint32_t* sat, hipStream_t s) {
+  SVR_LAUNCH("tile_sat", k_tile_sat, dim3(cams.n), dim3(kBlock), 0, s, cams, mask, sat);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+template <int D>
+__device__ __forceinline__ void sh_color(const float* __restrict__ shv, float dx, float dy, float dz,
+                                         float rgb[3], uint32_t& pos_bits) {
+  constexpr int NB = (D + 1) * (D + 1);
+  float Y[16];
+  sh_basis<D>(dx, dy, dz, Y);
+  float acc[3] = {0.f, 0.f, 0.f};
+  if (D == 3) {
+    const float4* s4 = reinterpret_cast<const float4*>(shv);
+    float buf[48];
+#pragma unroll
+    for (int i = 0; i < 12; ++i) {
+      const float4 q = s4[i];
+      buf[4 * i + 0] = q.x; buf[4 * i + 1] = q.y; buf[4 * i + 2] = q.z; buf[4 * i + 3] = q.w;
+    }
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      acc[0] = __fmaf_rn(buf[3 * j + 0], Y[j], acc[0]);
+      acc[1] = __fmaf_rn(buf[3 * j + 1], Y[j], acc[1]);
+      acc[2] = __fmaf_rn(buf[3 * j + 2], Y[j], acc[2]);
+    }
+  } else {
+#pragma unroll
+    for (int j = 0; j < NB; ++j) {
+      acc[0] = __fmaf_rn(shv[3 * j + 0], Y[j], acc[0]);
+      acc[1] = __fmaf_rn(shv[3 * j + 1], Y[j], acc[1]);
+      acc[2] = __fmaf_rn(shv[3 * j + 2], Y[j], acc[2]);
+    }
+  }
+  pos_bits = 0;
+#pragma unroll
+  for (int ch = 0; ch < 3; ++ch) {
+    if (acc[ch] > 0.f) pos_bits |= 1u << ch;
+    rgb[ch] = fmaxf(acc[ch], 0.f);
+  }
+}
+
+__device__ __forceinline__ uint32_t sat_rect(const uint32_t* __restrict__ S, int W1, int tx0,
+                                             int tx1, int ty0, int ty1) {
+  return S[(ty1 + 1) * W1 + tx1 + 1] - S[ty0 * W1 + tx1 + 1] - S[(ty1 + 1) * W1 + tx0] +
+         S[ty0 * W1 + tx0];
+}
+
+template <int D>
+__global__ __launch_bounds__(kBlock) void k_project(
+    int64_t NV, int n_cams, CamSet cams, const float* __restrict__ center,
+    const float* __restrict__ size, const int32_t* __restrict__ vox_grid,
+    const float* __restrict__ grid_raw, const float* __restrict__ sh, int64_t N,
+    const uint32_t* __restrict__ sat, uint32_t* __restrict__ count, uint2* __restrict__ rect,
+    VoxRec* __restrict__ rec, WsHeader* __restrict__ hdr) {
+  const int64_t vv = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (vv >= NV) return;
+  const int64_t vid = vv / n_cams;
+  const int ci = (int)(vv - vid * n_cams);
+  const DevCam& c = cams.c[ci];
+  const float s = size[vid];
+  const float h = 0.5f * s;
+  // centre relative to the camera, then camera-space centre Pc = R (centre - o)
+  const float rx = center[vid] - c.o[0];
+  const float ry = center[N + vid] - c.o[1];
+  const float rz = center[2 * N + vid] - c.o[2];
+  float P[3], A[3][3];  // A[r][j] = h * R[r][j]: half-edge vectors in camera space
+#pragma unroll
+  for (int r = 0; r < 3; ++r) {
+    P[r] = c.r[3 * r + 0] * rx + c.r[3 * r + 1] * ry + c.r[3 * r + 2] * rz;
+#pragma unroll
+    for (int j = 0; j < 3; ++j) A[r][j] = h * c.r[3 * r + j];
+  }
+  // support of the box along a camera-space direction n: n.P + sum_j |n.A_j|
+  auto support = [&](float nx, float ny, float nz) {
+    float m = nx * P[0] + ny * P[1] + nz * P[2];
+#pragma unroll
+    for (int j = 0; j < 3; ++j) m += fabsf(nx * A[0][j] + ny * A[1][j] + nz * A[2][j]);
+    return m;
+  };
+  const float W = (float)c.W, H = (float)c.H;
+  bool culled = support(0.f, 0.f, 1.f) <= 0.f ||                 // every corner behind
+                support(c.fx, 0.f, c.cx) < 0.f ||                 // left of the image
+                support(-c.fx, 0.f, W - c.cx) < 0.f ||            // right
+                support(0.f, c.fy, c.cy) < 0.f ||                 // above
+                support(0.f, -c.fy, H - c.cy) < 0.f;              // below
+  uint32_t cnt = 0;
+  int u0 = 0, u1 = -1, v0 = 0, v1 = -1;
+  if (!culled) {
+    const float zmin = -support(0.f, 0.f, -1.f);
+    if (zmin < kZNear) {
+      u0 = 0; u1 = c.W - 1; v0 = 0; v1 = c.H - 1;
+    } else {
+      float x0 = 3.0e38f, x1 = -3.0e38f, y0 = 3.0e38f, y1 = -3.0e38f;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        const float sx = (k & 4) ? 1.f : -1.f, sy = (k & 2) ? 1.f : -1.f, sz = (k & 1) ? 1.f : -1.f;
+        const float X = P[0] + sx * A[0][0] + sy * A[0][1] + sz * A[0][2];
+        const float Y = P[1] + sx * A[1][0] + sy * A[1][1] + sz * A[1][2];
+        const float Z = P[2] + sx * A[2][0] + sy * A[2][1] + sz * A[2][2];
+        const float iz = 1.f / Z;
+        const float x = c.fx * X * iz + c.cx;
+        const float y = c.fy * Y * iz + c.cy;
+        x0 = fminf(x0, x); x1 = fmaxf(x1, x); y0 = fminf(y0, y); y1 = fmaxf(y1, y);
+      }
+      // pixel (u, v) is covered when its centre lies in the box; a small
+      // dilation keeps the fp32 box conservative
+      const float eps = 1.f / 256.f;
+      x0 = fminf(fmaxf(x0, -2.f), W + 2.f); x1 = fminf(fmaxf(x1, -2.f), W + 2.f);
+      y0 = fminf(fmaxf(y0, -2.f), H + 2.f); y1 = fminf(fmaxf(y1, -2.f), H + 2.f);
+      u0 = max((int)ceilf(x0 - 0.5f - eps), 0);
+      u1 = min((int)floorf(x1 - 0.5f + eps), c.W - 1);
+      v0 = max((int)ceilf(y0 - 0.5f - eps), 0);
+      v1 = min((int)floorf(y1 - 0.5f + eps), c.H - 1);
+    }
+    if (u0 <= u1 && v0 <= v1) {
+      cnt = sat_rect(sat + c.sat_off, c.ntx + 1, u0 / kTile, u1 / kTile, v0 / kTile, v1 / kTile);
+    }
+  }
+  // statistics: number of in-view (voxel, camera) pairs
+  const unsigned long long act = __ballot(1);
+  const unsigned long long inview = __ballot(cnt > 0);
+  if ((int)(threadIdx.x & 63) == __ffsll((long long)act) - 1 && inview)
+    atomicAdd(&hdr->stats[3], (unsigned long long)__popcll(inview));
+  count[vv] = cnt;
+  if (cnt == 0) {
+    rect[vv] = make_uint2(1u, 0u);
+    return;
+  }
+  rect[vv] = make_uint2((uint32_t)u0 | ((uint32_t)u1 << 16), (uint32_t)v0 | ((uint32_t)v1 << 16));
+  // pre-process: gather the 8 corner densities, evaluate the SH colour for
+  // the direction camera centre -> voxel centre
+  const int4* vg = reinterpret_cast<const int4*>(vox_grid + vid * 8);
+  const int4 ga = vg[0], gb = vg[1];
+  VoxRec R;
+  R.q0 = make_float4(rx - h, ry - h, rz - h, s);
+  R.q1 = make_float4(grid_raw[ga.x], grid_raw[ga.y], grid_raw[ga.z], grid_raw[ga.w]);
+  R.q2 = make_float4(grid_raw[gb.x], grid_raw[gb.y], grid_raw[gb.z], grid_raw[gb.w]);
+  const float rn = rsqrtf(rx * rx + ry * ry + rz * rz);
+  float rgb[3];
+  uint32_t bits;
+  sh_color<D>(sh + vid * (int64_t)(3 * (D + 1) * (D + 1)), rx * rn, ry * rn, rz * rn, rgb, bits);
+  R.q3 = make_float4(rgb[0], rgb[1], rgb[2], __uint_as_float(bits));
+  rec[vv] = R;
+}
+
+hipError_t launch_project(const svr_scene& sc, const CamSet& cams, const Layout& L, void* ws,
+                          hipStream_t s) {
+  if (L.NV == 0) return hipSuccess;
+  dim3 grid((unsigned)((L.NV + kBlock - 1) / kBlock));
+  auto* sat = at<uint32_t>(ws, L.tile_sat);
+  auto* count = at<uint32_t>(ws, L.count);
+  auto* rect = at<uint2>(ws, L.rect);
+  auto* rec = at<VoxRec>(ws, L.rec);
+#define SVR_PROJ(D)                                                                             \
+  SVR_LAUNCH("project", k_project<D>, grid, dim3(kBlock), 0, s, L.NV, L.n_cams, cams, sc.center, \
+                     sc.size, sc.vox_grid, sc.grid_raw, sc.sh, L.N, sat, count, rect, rec, \
+                     at<WsHeader>(ws, L.hdr))
+  switch (sc.sh_degree) {
+    case 0: SVR_PROJ(0); break;
+    case 1: SVR_PROJ(1); break;
+    case 2: SVR_PROJ(2); break;
+    default: SVR_PROJ(3); break;
+  }
+#undef SVR_PROJ
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// exclusive scan of the per view-voxel counts into 64-bit offsets
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kBlock * kScanItems;  // 4096 counts per block
+
+__device__ __forceinline__ unsigned long long wave_incl_scan(unsigned long long v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    unsigned long long t = __shfl_up(v, d, 64);
+    if (lane >= d) v += t;
+  }
+  return v;
+}
+
+// block-wide exclusive scan of one value per thread; returns the block total
+__device__ __forceinline__ unsigned long long block_excl_scan(unsigned long long v,
+                                                              unsigned long long& excl) {
+  __shared__ unsigned long long wsum[kBlock / 64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  unsigned long long inc = wave_incl_scan(v);
+  if (lane == 63) wsum[w] = inc;
+  __syncthreads();
+  unsigned long long base = 0, tot = 0;
+#pragma unroll
+  for (int i = 0; i < kBlock / 64; ++i) {
+    if (i < w) base += wsum[i];
+    tot += wsum[i];
+  }
+  excl = base + inc - v;
+  __syncthreads();
+  return tot;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_reduce(const uint32_t* __restrict__ cnt, int64_t n,
+                                                        unsigned long long* __restrict__ part) {
+  const int64_t base = (int64_t)blockIdx.x * kScanTile;
+  unsigned long long acc = 0;
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    int64_t j = base + i * kBlock + threadIdx.x;
+    if (j < n) acc += cnt[j];
+  }
+  unsigned long long ex;
+  unsigned long long tot = block_excl_scan(acc, ex);
+  if (threadIdx.x == 0) part[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_top(unsigned long long* __restrict__ part, int64_t nb,
+                                                     WsHeader* __restrict__ hdr) {
+  unsigned long long carry = 0;
+  for (int64_t b0 = 0; b0 < nb; b0 += kBlock) {
+    int64_t j = b0 + threadIdx.x;
+    unsigned long long v = j < nb ? part[j] : 0ull;
+    unsigned long long ex;
+    unsigned long long tot = block_excl_scan(v, ex);
+    if (j < nb) part[j] = carry + ex;
+    carry += tot;
+  }
+  if (threadIdx.x == 0) {
+    hdr->n_entries = carry;
+    hdr->overflow = 0;
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_scan_down(const uint32_t* __restrict__ cnt, int64_t n,
+                                                      const unsigned long long* __restrict__ part,
+                                                      unsigned long long* __restrict__ off) {
+  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
+  uint32_t v[kScanItems];
+  unsigned long long acc = 0;
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    v[i] = (base + i < n) ? cnt[base + i] : 0u;
+    acc += v[i];
+  }
+  unsigned long long ex;
+  block_excl_scan(acc, ex);
+  ex += part[blockIdx.x];
+#pragma unroll
+  for (int i = 0; i < kScanItems; ++i) {
+    if (base + i < n) off[base + i] = ex;
+    ex += v[i];
+  }
+}
+
+hipError_t launch_scan(const Layout& L, void* ws, hipStream_t s) {
+  auto* cnt = at<uint32_t>(ws, L.count);
+  auto* part = at<unsigned long long>(ws, L.scan_part);
+  auto* off = at<unsigned long long>(ws, L.offset);
+  auto* hdr = at<WsHeader>(ws, L.hdr);
+  const int64_t nb = L.scan_blocks;
+  if (nb > 0)
+    SVR_LAUNCH("scan_reduce", k_scan_reduce, dim3((unsigned)nb), dim3(kBlock), 0, s, cnt, L.NV, part);
+  SVR_LAUNCH("scan_top", k_scan_top, dim3(1), dim3(kBlock), 0, s, part, nb, hdr);
+  if (nb > 0)
+    SVR_LAUNCH("scan_down", k_scan_down, dim3((unsigned)nb), dim3(kBlock), 0, s, cnt, L.NV, part, off);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// key = global tile << (3L + 3) | (top 3L path bits XOR s repeated) << 3 | s
+//       (the direction-dependent Morton order of Supp. B.2 as one XOR)
+// value = s << 29 | voxel id
+__global__ __launch_bounds__(kBlock) void k_emit(
+    int64_t NV, int n_cams, CamSet cams, const uint64_t* __restrict__ octpath,
+    const uint32_t* __restrict__ count, const unsigned long long* __restrict__ off,
+    const uint2* __restrict__ rect, const uint8_t* __restrict__ mask, int L, int64_t cap,
+    uint64_t* __restrict__ keys, uint32_t* __restrict__ vals, WsHeader* __restrict__ hdr) {
+  const int64_t vv = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (vv >= NV) return;
+  const uint32_t cnt = count[vv];
+  if (cnt == 0) return;
+  const int64_t vid = vv / n_cams;
+  const int ci = (int)(vv - vid * n_cams);
+  const DevCam& c = cams.c[ci];
+  unsigned long long o = off[vv];
+  if (o + cnt > (unsigned long long)cap) atomicOr(&hdr->overflow, 1u);
+  const uint2 r = rect[vv];
+  const int tx0 = (int)(r.x & 0xffffu) / kTile, tx1 = (int)(r.x >> 16) / kTile;
+  const int ty0 = (int)(r.y & 0xffffu) / kTile, ty1 = (int)(r.y >> 16) / kTile;
+  const int sh = 3 * L + 3;
+  const uint64_t top = octpath[vid] >> (3 * (SVR_MAX_LEVELS - L));
+  const uint64_t rep = (L >= 21) ? ~0ull : (((1ull << (3 * L)) - 1ull) / 7ull);  // 001 001 ... 001
+  for (int ty = ty0; ty <= ty1; ++ty) {
+    for (int tx = tx0; tx <= tx1; ++tx) {
+      const int gt = c.tile_off + ty * c.ntx + tx;
+      uint32_t m = mask[gt];
+      while (m) {
+        const int sgn = __ffs(m) - 1;
+        m &= m - 1;
+        if (o < (unsigned long long)cap) {
+          keys[o] = ((uint64_t)gt << sh) | ((top ^ ((uint64_t)sgn * rep)) << 3) | (uint64_t)sgn;
+          vals[o] = ((uint32_t)sgn << kVidBits) | (uint32_t)vid;
+        }
+        ++o;
+      }
+    }
+  }
+}
+
+hipError_t launch_emit(const svr_scene& sc, const CamSet& cams, const Layout& L, void* ws,
+                       hipStream_t s) {
+  if (L.NV == 0) return hipSuccess;
+  SVR_LAUNCH("emit", k_emit, dim3((unsigned)((L.NV + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+                     L.NV, L.n_cams, cams, sc.octpath, at<uint32_t>(ws, L.count),
+                     at<unsigned long long>(ws, L.offset), at<uint2>(ws, L.rect),
+                     at<uint8_t>(ws, L.tile_mask), L.L, L.cap, at<uint64_t>(ws, L.keys0),
+                     at<uint32_t>(ws, L.vals0), at<WsHeader>(ws, L.hdr));
+  return hipGetLastError();
+}
+
+}  // namespace svr

@@ -1,0 +1,282 @@
+// Stable LSD radix sort of (u64 key, u32 value) pairs for gfx950, in the
+// single-pass-per-digit ("onesweep") form: one kernel reads the keys once and
+// builds the digit histograms of every pass; then each 8-bit digit pass is one
+// kernel in which a workgroup
+//   1. takes a partition of 4096 pairs in the order given by an atomic ticket
+//      (so every partition it waits on is already running),
+//   2. ranks its keys stably with wave64 ballots (a match on the 8 digit bits
+//      per lane gives each lane its peers) and per-wave digit counters in LDS,
+//   3. publishes its per-digit counts and looks back over the preceding
+//      partitions' published counts (decoupled look-back) to find where each
+//      of its digit runs starts in the output,
+//   4. reorders the pairs in LDS by digit and writes each run contiguously.
+// This is the sort of Sec. 3.1.2 "Sorting voxels" (Supp. B.1 uses a GPU radix
+// sort on the tile / Morton key).  Look-back waits are bounded: a workgroup
+// that spins past the limit sets an error bit and finishes, so no launch can
+// hang.
+#include "svr_internal.h"
+
+namespace svr {
+
+constexpr int kRadix = 256;
+constexpr int kSortItems = 16;
+constexpr int kPart = kBlock * kSortItems;       // 4096 pairs per partition
+constexpr uint32_t kFlagAgg = 1u << 30;          // partition-local count published
+constexpr uint32_t kFlagPre = 2u << 30;          // inclusive prefix published
+constexpr uint32_t kValMask = (1u << 30) - 1u;
+constexpr int kSpinLimit = 1 << 22;
+
+__device__ __forceinline__ unsigned long long lane_mask_lt() {
+  const int lane = threadIdx.x & 63;
+  return (1ull << lane) - 1ull;
+}
+
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_sort_hist(const uint64_t* __restrict__ keys,
+                                                      const unsigned long long* __restrict__ n_dev,
+                                                      int64_t n_max, int bits,
+                                                      uint32_t* __restrict__ hist) {
+  const int passes = (bits + 7) / 8;
+  __shared__ uint32_t h[8 * kRadix];
+  for (int i = threadIdx.x; i < 8 * kRadix; i += kBlock) h[i] = 0;
+  __syncthreads();
+  const int64_t n = min((int64_t)*n_dev, n_max);
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kBlock) {
+    const uint64_t k = keys[i];
+    for (int p = 0; p < passes; ++p) {
+      const uint32_t dmask = (bits - 8 * p >= 8) ? 255u : ((1u << (bits - 8 * p)) - 1u);
+      atomicAdd(&h[p * kRadix + (int)((k >> (8 * p)) & dmask)], 1u);
+    }
+  }
+  __syncthreads();
+  for (int i = threadIdx.x; i < passes * kRadix; i += kBlock)
+    if (h[i]) atomicAdd(&hist[i], h[i]);
+}
+
+// exclusive scan of each pass's 256 digit counts
+__global__ __launch_bounds__(kRadix) void k_sort_hist_scan(uint32_t* __restrict__ hist, int passes) {
+  __shared__ uint32_t wsum[kRadix / 64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  for (int p = 0; p < passes; ++p) {
+    uint32_t v = hist[p * kRadix + threadIdx.x];
+    uint32_t inc = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      uint32_t t = __shfl_up(inc, d, 64);
+      if (lane >= d) inc += t;
+    }
+    if (lane == 63) wsum[w] = inc;
+    __syncthreads();
+    uint32_t base = 0;
+    for (int i = 0; i < w; ++i) base += wsum[i];
+    hist[p * kRadix + threadIdx.x] = base + inc - v;
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_sort_pass(
+    int shift, uint32_t dmask, const uint64_t* __restrict__ kin, const uint32_t* __restrict__ vin,
+    uint64_t* __restrict__ kout, uint32_t* __restrict__ vout,
+    const unsigned long long* __restrict__ n_dev, int64_t n_max,
+    const uint32_t* __restrict__ digit_base, uint32_t* __restrict__ status,
+    uint32_t* __restrict__ status_next, uint32_t* __restrict__ ticket, uint32_t* __restrict__ err) {
+  __shared__ uint64_t sk[kPart];
+  __shared__ uint32_t sv[kPart];
+  __shared__ uint32_t wh[4][kRadix];   // per-wave digit counters, then wave offsets
+  __shared__ uint32_t dstart[kRadix];  // first local position of each digit
+  __shared__ uint32_t gbase[kRadix];   // first global position of each digit
+  __shared__ uint32_t wsum[4];
+  __shared__ int s_part;
+
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  if (tid == 0) s_part = (int)atomicAdd(ticket, 1u);
+#pragma unroll
+  for (int i = 0; i < 4; ++i) wh[i][tid] = 0;
+  __syncthreads();
+  const int part = s_part;
+  const int64_t n = min((int64_t)*n_dev, n_max);
+  const int64_t nparts = (n + kPart - 1) / kPart;
+  if (part >= nparts) return;
+  const int64_t base = (int64_t)part * kPart;
+
+  uint64_t k[kSortItems];
+  uint32_t v[kSortItems];
+  uint32_t rank[kSortItems];
+  const int64_t wbase = base + (int64_t)w * (kSortItems * 64) + lane;
+#pragma unroll
+  for (int it = 0; it < kSortItems; ++it) {
+    const int64_t idx = wbase + it * 64;
+    if (idx < n) {
+      k[it] = kin[idx];
+      v[it] = vin[idx];
+    } else {
+      k[it] = 0;
+      v[it] = 0;
+    }
+  }
+  const unsigned long long lt = lane_mask_lt();
+#pragma unroll
+  for (int it = 0; it < kSortItems; ++it) {
+    const bool valid = wbase + it * 64 < n;
+    const uint32_t d = (uint32_t)(k[it] >> shift) & dmask;
+    unsigned long long peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const bool bit = (d >> b) & 1u;
+      const unsigned long long bb = __ballot(bit);
+      peers &= bit ? bb : ~bb;
+    }
+    const uint32_t below = (uint32_t)__popcll(peers & lt);
+    uint32_t cbase = 0;
+    if (valid) cbase = wh[w][d];
+    rank[it] = cbase + below;
+    if (valid && below == 0) wh[w][d] = cbase + (uint32_t)__popcll(peers);
+  }
+  __syncthreads();
+
+  // per-digit totals, wave offsets, local digit starts
+  const uint32_t c0 = wh[0][tid], c1 = wh[1][tid], c2 = wh[2][tid], c3 = wh[3][tid];
+  const uint32_t tot = c0 + c1 + c2 + c3;
+  wh[0][tid] = 0;
+  wh[1][tid] = c0;
+  wh[2][tid] = c0 + c1;
+  wh[3][tid] = c0 + c1 + c2;
+  uint32_t inc = tot;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    uint32_t t = __shfl_up(inc, d, 64);
+    if (lane >= d) inc += t;
+  }
+  if (lane == 63) wsum[w] = inc;
+  __syncthreads();
+  uint32_t wb = 0;
+  for (int i = 0; i < w; ++i) wb += wsum[i];
+  dstart[tid] = wb + inc - tot;
+
+  // decoupled look-back for digit `tid`
+  uint32_t* my = status + (int64_t)part * kRadix + tid;
+  uint32_t prefix = 0;
+  if (part == 0) {
+    __hip_atomic_store(my, kFlagPre | tot, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  } else {
+    __hip_atomic_store(my, kFlagAgg | tot, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    int j = part - 1;
+    int spins = 0;
+    while (j >= 0) {
+      const uint32_t st = __hip_atomic_load(status + (int64_t)j * kRadix + tid, __ATOMIC_ACQUIRE,
+                                            __HIP_MEMORY_SCOPE_AGENT);
+      const uint32_t flag = st & ~kValMask;
+      if (flag == 0u) {
+        if (++spins > kSpinLimit) {
+          atomicOr(err, 1u);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
+        continue;
+      }
+      prefix += st & kValMask;
+      if (flag == kFlagPre) break;
+      --j;
+    }
+    __hip_atomic_store(my, kFlagPre | ((prefix + tot) & kValMask), __ATOMIC_RELEASE,
+                       __HIP_MEMORY_SCOPE_AGENT);
+  }
+  gbase[tid] = digit_base[tid] + prefix;
+  // the next pass uses the other status buffer: clear this partition's row
+  status_next[(int64_t)part * kRadix + tid] = 0u;
+  __syncthreads();
+
+  // reorder in LDS by digit (stable), then write each digit run out
+#pragma unroll
+  for (int it = 0; it < kSortItems; ++it) {
+    if (wbase + it * 64 < n) {
+      const uint32_t d = (uint32_t)(k[it] >> shift) & dmask;
+      const uint32_t pos = dstart[d] + wh[w][d] + rank[it];
+      sk[pos] = k[it];
+      sv[pos] = v[it];
+    }
+  }
+  __syncthreads();
+  const int nvalid = (int)min((int64_t)kPart, n - base);
+  for (int i = tid; i < nvalid; i += kBlock) {
+    const uint64_t kk = sk[i];
+    const uint32_t d = (uint32_t)(kk >> shift) & dmask;
+    const uint32_t dst = gbase[d] + ((uint32_t)i - dstart[d]);
+    if ((int64_t)dst < n) {  // always true unless a look-back gave up (error bit set)
+      kout[dst] = kk;
+      vout[dst] = sv[i];
+    }
+  }
+}
+
+size_t sort_scratch_bytes(int64_t n, int bits, int64_t* parts_out) {
+  const int64_t parts = (n + kPart - 1) / kPart;
+  if (parts_out) *parts_out = parts;
+  const int passes = (bits + 7) / 8;
+  (void)passes;
+  // hist [8][256] + two status buffers [parts][256] + tickets/err (64 words)
+  return (size_t)(8 * kRadix + 2 * (parts > 0 ? parts : 1) * kRadix + 64) * sizeof(uint32_t);
+}
+
+hipError_t launch_radix_sort(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1,
+                             const unsigned long long* n_dev, int64_t n_max, int bits,
+                             uint32_t* hist, uint32_t* st0, uint32_t* st1, uint32_t* tickets,
+                             uint32_t* err, bool* result_in_1, hipStream_t s) {
+  const int passes = (bits + 7) / 8;
+  *result_in_1 = (passes & 1) != 0;
+  if (n_max <= 0 || passes == 0) {
+    *result_in_1 = false;
+    return hipSuccess;
+  }
+  const int64_t parts = (n_max + kPart - 1) / kPart;
+  hipError_t e;
+  if ((e = launch_fill_u32(hist, 0u, 8 * kRadix, s)) != hipSuccess) return e;
+  if ((e = launch_fill_u32(tickets, 0u, 16, s)) != hipSuccess) return e;
+  if ((e = launch_fill_u32(st0, 0u, parts * kRadix, s)) != hipSuccess) return e;
+  int64_t hb = (n_max + kBlock * 8 - 1) / (kBlock * 8);
+  if (hb > 2048) hb = 2048;
+  if (hb < 1) hb = 1;
+  SVR_LAUNCH("sort_hist", k_sort_hist, dim3((unsigned)hb), dim3(kBlock), 0, s, k0, n_dev, n_max, bits,
+                     hist);
+  SVR_LAUNCH("sort_hist_scan", k_sort_hist_scan, dim3(1), dim3(kRadix), 0, s, hist, passes);
+  for (int p = 0; p < passes; ++p) {
+    const uint64_t* ki = (p & 1) ? k1 : k0;
+    const uint32_t* vi = (p & 1) ? v1 : v0;
+    uint64_t* ko = (p & 1) ? k0 : k1;
+    uint32_t* vo = (p & 1) ? v0 : v1;
+    uint32_t* st = (p & 1) ? st1 : st0;
+    uint32_t* stn = (p & 1) ? st0 : st1;
+    const uint32_t dmask = (bits - 8 * p >= 8) ? 255u : ((1u << (bits - 8 * p)) - 1u);
+    SVR_LAUNCH("sort_pass", k_sort_pass, dim3((unsigned)parts), dim3(kBlock), 0, s, 8 * p, dmask, ki, vi, ko,
+                       vo, n_dev, n_max, hist + p * kRadix, st, stn, tickets + p, err);
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(kBlock) void k_tile_ranges(const uint64_t* __restrict__ keys,
+                                                        const unsigned long long* __restrict__ n_dev,
+                                                        int64_t cap, int shift, uint32_t T,
+                                                        uint2* __restrict__ range) {
+  const int64_t n = min((int64_t)*n_dev, cap);
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const uint32_t t = (uint32_t)(keys[i] >> shift);
+  if (t >= T) return;
+  if (i == 0 || (uint32_t)(keys[i - 1] >> shift) != t) range[t].x = (uint32_t)i;
+  if (i == n - 1 || (uint32_t)(keys[i + 1] >> shift) != t) range[t].y = (uint32_t)(i + 1);
+}
+
+hipError_t launch_tile_ranges(const Layout& L, void* ws, const uint64_t* keys, hipStream_t s) {
+  hipError_t e = launch_fill_u32(at<uint32_t>(ws, L.tile_range), 0u, 2 * (int64_t)L.T, s);
+  if (e != hipSuccess) return e;
+  if (L.cap <= 0) return hipSuccess;
+  SVR_LAUNCH("tile_ranges", k_tile_ranges, dim3((unsigned)((L.cap + kBlock - 1) / kBlock)), dim3(kBlock), 0,
+                     s, keys, &at<WsHeader>(ws, L.hdr)->n_entries, L.cap, 3 * L.L + 3,
+                     (uint32_t)L.T, at<uint2>(ws, L.tile_range));
+  return hipGetLastError();
+}
+
+}  // namespace svr

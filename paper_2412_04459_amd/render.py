@@ -1,0 +1,264 @@
+"""Torch-facing wrapper of the C ABI: device-resident scene, a rasterizer that
+owns its workspace, and a ``torch.autograd.Function``.
+
+PyTorch supplies device memory and the stream only; each stage is one call
+into ``libsvraster.so``.  There is no CPU or PyTorch fallback: without a GPU
+and the built library every entry point raises.
+"""
+from __future__ import annotations
+
+import ctypes
+from typing import List, Optional, Sequence
+
+import numpy as np
+import torch
+
+from . import _abi
+from ._abi import check
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream():
+    return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+class DeviceScene:
+    """Scene arrays resident in device memory (layouts as in svr_scene)."""
+
+    def __init__(self, scene, device="cuda"):
+        if not torch.cuda.is_available():
+            raise RuntimeError("DeviceScene needs a HIP device")
+        dev = torch.device(device)
+        self.n_voxels = int(scene.n_voxels)
+        self.n_grid = int(scene.n_grid)
+        self.sh_degree = int(scene.sh_degree)
+        self.max_level = int(scene.max_level)
+        self.center = torch.from_numpy(np.ascontiguousarray(scene.center, np.float32)).to(dev)
+        self.size = torch.from_numpy(np.ascontiguousarray(scene.size, np.float32)).to(dev)
+        self.octpath = torch.from_numpy(
+            np.ascontiguousarray(scene.octpath, np.uint64).view(np.int64)).to(dev)
+        self.vox_grid = torch.from_numpy(np.ascontiguousarray(scene.vox_grid, np.int32)).to(dev)
+        self.grid_raw = torch.from_numpy(np.ascontiguousarray(scene.grid_raw, np.float32)).to(dev)
+        self.sh = torch.from_numpy(np.ascontiguousarray(scene.sh, np.float32)).to(dev)
+        self.device = self.grid_raw.device
+
+    def struct(self, grid_raw: Optional[torch.Tensor] = None,
+               sh: Optional[torch.Tensor] = None) -> _abi.svr_scene:
+        g = self.grid_raw if grid_raw is None else grid_raw
+        s = self.sh if sh is None else sh
+        for t, name in ((g, "grid_raw"), (s, "sh")):
+            if t.dtype != torch.float32 or not t.is_contiguous() or t.device != self.device:
+                raise ValueError("%s must be a contiguous float32 tensor on %s" % (name, self.device))
+        if g.numel() != self.n_grid or s.numel() != self.n_voxels * 3 * (self.sh_degree + 1) ** 2:
+            raise ValueError("grid_raw / sh sizes do not match the scene")
+        st = _abi.svr_scene()
+        st.n_voxels = self.n_voxels
+        st.n_grid = self.n_grid
+        st.center = self.center.data_ptr()
+        st.size = self.size.data_ptr()
+        st.octpath = self.octpath.data_ptr()
+        st.vox_grid = self.vox_grid.data_ptr()
+        st.grid_raw = g.data_ptr()
+        st.sh = s.data_ptr()
+        st.sh_degree = self.sh_degree
+        st.max_level = self.max_level
+        return st
+
+
+def camera_structs(cams: Sequence) -> ctypes.Array:
+    arr = (_abi.svr_camera * len(cams))()
+    for i, c in enumerate(cams):
+        arr[i].width = int(c.W)
+        arr[i].height = int(c.H)
+        arr[i].fx = float(c.fx)
+        arr[i].fy = float(c.fy)
+        arr[i].cx = float(c.cx)
+        arr[i].cy = float(c.cy)
+        w = np.asarray(c.w2c, np.float32).reshape(-1)
+        for k in range(12):
+            arr[i].w2c[k] = float(w[k])
+    return arr
+
+
+class Rasterizer:
+    """One frame of one or more cameras over a device scene.
+
+    ``forward()`` runs svr_preprocess, svr_sort and svr_render_fwd and returns
+    rgba of shape (sum H*W, 4); ``backward(grad_rgba)`` runs svr_render_bwd on
+    the same workspace.  ``sync_count`` reads the entry count back once per
+    frame (exact capacity check, sort sized to the count); without it the
+    frame has no host synchronisation and overflow is checked afterwards.
+    """
+
+    def __init__(self, dscene: DeviceScene, cams: Sequence, K: int = 1, t_stop: float = 1e-4,
+                 activation: int = _abi.SVR_ACT_EXPLIN, capacity: Optional[int] = None,
+                 sync_count: bool = True):
+        if len(cams) < 1 or len(cams) > _abi.SVR_MAX_CAMERAS:
+            raise ValueError("1..%d cameras per frame" % _abi.SVR_MAX_CAMERAS)
+        self.ds = dscene
+        self.cams = list(cams)
+        self.cam_arr = camera_structs(self.cams)
+        self.n_cams = len(self.cams)
+        self.n_pixels = int(sum(c.W * c.H for c in self.cams))
+        self.opts = _abi.svr_opts()
+        self.opts.K = int(K)
+        self.opts.t_stop = float(t_stop)
+        self.opts.activation = int(activation)
+        if capacity is None:
+            capacity = max(1 << 16, 2 * dscene.n_voxels * self.n_cams)
+        self.sync_count = sync_count
+        self.n_entries = -1
+        self.ws = None
+        self.ws_bytes = 0
+        self._set_capacity(int(capacity))
+
+    def _set_capacity(self, cap: int):
+        cap = min(cap, (1 << 30) - 1)
+        self.opts.entry_capacity = cap
+        st = self.ds.struct()
+        nb = _abi.svr_workspace_bytes(st, self.cam_arr, self.n_cams, self.opts)
+        if nb == 0:
+            raise ValueError("invalid rasterizer configuration: " + _abi.svr_last_error())
+        if self.ws is None or self.ws_bytes < nb:
+            self.ws = None
+            self.ws = torch.empty(nb + 256, dtype=torch.uint8, device=self.ds.device)
+            self.ws_bytes = nb
+        self.capacity = cap
+
+    def _ws_ptr(self):
+        p = self.ws.data_ptr()
+        p = (p + 255) // 256 * 256
+        return ctypes.c_void_p(p)
+
+    def workspace_bytes(self) -> int:
+        return self.ws_bytes
+
+    def preprocess(self, grid_raw=None, sh=None):
+        st = self.ds.struct(grid_raw, sh)
+        if self.sync_count:
+            n = ctypes.c_int64(0)
+            rc = _abi.svr_preprocess(st, self.cam_arr, self.n_cams, self.opts, self._ws_ptr(),
+                                     self.ws_bytes, ctypes.byref(n), _stream())
+            if rc == _abi.SVR_E_CAPACITY:
+                self._set_capacity(int(n.value * 1.25) + 1024)
+                rc = _abi.svr_preprocess(st, self.cam_arr, self.n_cams, self.opts, self._ws_ptr(),
+                                         self.ws_bytes, ctypes.byref(n), _stream())
+            check(rc, "svr_preprocess")
+            self.n_entries = int(n.value)
+        else:
+            check(_abi.svr_preprocess(st, self.cam_arr, self.n_cams, self.opts, self._ws_ptr(),
+                                      self.ws_bytes, None, _stream()), "svr_preprocess")
+            self.n_entries = -1
+
+    def sort(self):
+        st = self.ds.struct()
+        check(_abi.svr_sort(st, self.cam_arr, self.n_cams, self.opts, self._ws_ptr(),
+                            self.ws_bytes, self.n_entries, _stream()), "svr_sort")
+
+    def render_fwd(self, grid_raw=None, sh=None, out: Optional[torch.Tensor] = None):
+        st = self.ds.struct(grid_raw, sh)
+        if out is None:
+            out = torch.empty((self.n_pixels, 4), dtype=torch.float32, device=self.ds.device)
+        check(_abi.svr_render_fwd(st, self.cam_arr, self.n_cams, self.opts, self._ws_ptr(),
+                                  self.ws_bytes, _ptr(out), _stream()), "svr_render_fwd")
+        return out
+
+    def forward(self, grid_raw=None, sh=None, out=None):
+        self.preprocess(grid_raw, sh)
+        self.sort()
+        return self.render_fwd(grid_raw, sh, out)
+
+    def backward(self, grad_rgba: torch.Tensor, grid_raw=None, sh=None, grad_grid=None,
+                 grad_sh=None, want_grid=True, want_sh=True):
+        st = self.ds.struct(grid_raw, sh)
+        g = grad_rgba.contiguous().float()
+        if g.numel() != self.n_pixels * 4:
+            raise ValueError("grad_rgba must have shape (n_pixels, 4)")
+        if want_grid and grad_grid is None:
+            grad_grid = torch.empty(self.ds.n_grid, dtype=torch.float32, device=self.ds.device)
+        if want_sh and grad_sh is None:
+            grad_sh = torch.empty_like(self.ds.sh)
+        check(_abi.svr_render_bwd(st, self.cam_arr, self.n_cams, self.opts, self._ws_ptr(),
+                                  self.ws_bytes, _ptr(g), _ptr(grad_grid if want_grid else None),
+                                  _ptr(grad_sh if want_sh else None), _stream()),
+              "svr_render_bwd")
+        return grad_grid, grad_sh
+
+    def set_cameras(self, cams: Sequence):
+        """Swap in cameras of the same resolutions (workspace size unchanged)."""
+        if len(cams) != self.n_cams or any((a.W, a.H) != (b.W, b.H) for a, b in zip(cams, self.cams)):
+            raise ValueError("set_cameras needs the same number and sizes of cameras")
+        self.cams = list(cams)
+        self.cam_arr = camera_structs(self.cams)
+
+    def stats(self):
+        """(entries, walked pixel-entry pairs, executed ray-box tests, hits,
+        in-view voxels)."""
+        st = self.ds.struct()
+        counts = (ctypes.c_int64 * 5)()
+        check(_abi.svr_render_stats(st, self.cam_arr, self.n_cams, self.opts, self._ws_ptr(),
+                                    self.ws_bytes, counts, _stream()), "svr_render_stats")
+        return tuple(int(x) for x in counts)
+
+    def check_overflow(self) -> int:
+        st = self.ds.struct()
+        n = ctypes.c_int64(0)
+        rc = _abi.svr_check_overflow(st, self.cam_arr, self.n_cams, self.opts, self._ws_ptr(),
+                                     self.ws_bytes, ctypes.byref(n), _stream())
+        if rc == _abi.SVR_E_CAPACITY:
+            return int(n.value)
+        check(rc, "svr_check_overflow")
+        return int(n.value)
+
+    def sorted_entries(self, n: int):
+        keys = torch.empty(max(n, 1), dtype=torch.int64, device=self.ds.device)
+        vals = torch.empty(max(n, 1), dtype=torch.int32, device=self.ds.device)
+        st = self.ds.struct()
+        check(_abi.svr_copy_sorted(st, self.cam_arr, self.n_cams, self.opts, self._ws_ptr(),
+                                   self.ws_bytes, _ptr(keys), _ptr(vals), n, _stream()),
+              "svr_copy_sorted")
+        return keys[:n], vals[:n]
+
+
+class SVRasterFunction(torch.autograd.Function):
+    """rgba = render(grid_raw, sh) for a fixed rasterizer (scene geometry and
+    cameras); gradients flow to the corner raw densities and SH coefficients."""
+
+    @staticmethod
+    def forward(ctx, grid_raw, sh, rast: Rasterizer):
+        grid_raw = grid_raw.contiguous()
+        sh = sh.contiguous()
+        rgba = rast.forward(grid_raw, sh)
+        ctx.rast = rast
+        ctx.save_for_backward(grid_raw, sh)
+        return rgba
+
+    @staticmethod
+    def backward(ctx, grad_rgba):
+        grid_raw, sh = ctx.saved_tensors
+        gg, gs = ctx.rast.backward(grad_rgba, grid_raw, sh,
+                                   want_grid=ctx.needs_input_grad[0],
+                                   want_sh=ctx.needs_input_grad[1])
+        return gg, gs, None
+
+
+def render(rast: Rasterizer, grid_raw: torch.Tensor, sh: torch.Tensor) -> torch.Tensor:
+    return SVRasterFunction.apply(grid_raw, sh, rast)
+
+
+def radix_sort_pairs(keys: torch.Tensor, vals: torch.Tensor, bits: int = 64):
+    """Sort int64 (read as uint64) keys with int32 values in place on the GPU."""
+    n = keys.numel()
+    if n == 0:
+        return keys, vals
+    kt = torch.empty_like(keys)
+    vt = torch.empty_like(vals)
+    nb = _abi.svr_radix_sort_scratch_bytes(n, bits)
+    scratch = torch.empty(nb + 256, dtype=torch.uint8, device=keys.device)
+    p = (scratch.data_ptr() + 255) // 256 * 256
+    check(_abi.svr_radix_sort_pairs(_ptr(keys), _ptr(vals), _ptr(kt), _ptr(vt), n, bits,
+                                    ctypes.c_void_p(p), nb, _stream()), "svr_radix_sort_pairs")
+    return keys, vals

@@ -1,0 +1,116 @@
+"""Host-side checks of the C ABI that need no GPU: the library loads, exports
+every function include/svraster.h declares, and rejects bad arguments before
+touching the device."""
+import ctypes
+import os
+
+import numpy as np
+import pytest
+
+from paper_2412_04459_amd import _abi
+
+
+def _lib():
+    if not os.path.exists(_abi.LIB_PATH):
+        pytest.skip("libsvraster.so not built")
+    return _abi.load(with_torch=False)
+
+
+def test_exports_every_declared_function():
+    lib = _lib()
+    names = _abi.header_functions()
+    assert "svr_preprocess" in names and "svr_render_bwd" in names
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(_abi._SIGS) == set(names)
+
+
+def _host_args(N=1000, W=64, H=48, K=1, cap=4096):
+    sc = _abi.svr_scene()
+    sc.n_voxels = N
+    sc.n_grid = 2 * N
+    fake = 0x10000  # never dereferenced by the host-side checks
+    for f in ("center", "size", "octpath", "vox_grid", "grid_raw", "sh"):
+        setattr(sc, f, fake)
+    sc.sh_degree = 3
+    sc.max_level = 12
+    cams = (_abi.svr_camera * 2)()
+    for c in cams:
+        c.width, c.height = W, H
+        c.fx = c.fy = 50.0
+        c.cx, c.cy = W / 2, H / 2
+        for k, v in enumerate([1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 3]):
+            c.w2c[k] = v
+    o = _abi.svr_opts()
+    o.K = K
+    o.t_stop = 1e-4
+    o.activation = 0
+    o.entry_capacity = cap
+    return sc, cams, o
+
+
+def test_workspace_size_is_monotone_in_capacity_and_cameras():
+    _lib()
+    sc, cams, o = _host_args()
+    a = _abi.svr_workspace_bytes(sc, cams, 1, o)
+    assert a > 0
+    o.entry_capacity = 8192
+    b = _abi.svr_workspace_bytes(sc, cams, 1, o)
+    assert b >= a + 4096 * 24
+    c = _abi.svr_workspace_bytes(sc, cams, 2, o)
+    assert c > b
+
+
+@pytest.mark.parametrize("field,value", [("K", 0), ("K", 9), ("activation", 7),
+                                         ("entry_capacity", 1 << 30), ("t_stop", -1.0)])
+def test_invalid_options_are_rejected(field, value):
+    _lib()
+    sc, cams, o = _host_args()
+    setattr(o, field, value)
+    assert _abi.svr_workspace_bytes(sc, cams, 1, o) == 0
+    rc = _abi.svr_preprocess(sc, cams, 1, o, ctypes.c_void_p(0x100000), 1 << 30, None, None)
+    assert rc == _abi.SVR_E_INVALID
+    assert len(_abi.svr_last_error()) > 0
+
+
+@pytest.mark.parametrize("field,value", [("n_voxels", 1 << 29), ("sh_degree", 4), ("max_level", 0),
+                                         ("max_level", 17), ("n_voxels", -1)])
+def test_invalid_scene_is_rejected(field, value):
+    _lib()
+    sc, cams, o = _host_args()
+    setattr(sc, field, value)
+    assert _abi.svr_workspace_bytes(sc, cams, 1, o) == 0
+    for fn in (lambda: _abi.svr_sort(sc, cams, 1, o, ctypes.c_void_p(0x100000), 1 << 30, -1, None),
+               lambda: _abi.svr_render_fwd(sc, cams, 1, o, ctypes.c_void_p(0x100000), 1 << 30,
+                                           ctypes.c_void_p(0x1000), None)):
+        assert fn() == _abi.SVR_E_INVALID
+
+
+def test_camera_limits_and_workspace_checks():
+    _lib()
+    sc, cams, o = _host_args()
+    assert _abi.svr_workspace_bytes(sc, cams, 0, o) == 0
+    assert _abi.svr_workspace_bytes(sc, cams, 33, o) == 0
+    cams[0].width = 0
+    assert _abi.svr_workspace_bytes(sc, cams, 1, o) == 0
+    cams[0].width = 64
+    need = _abi.svr_workspace_bytes(sc, cams, 1, o)
+    rc = _abi.svr_preprocess(sc, cams, 1, o, ctypes.c_void_p(0x100000), need - 1, None, None)
+    assert rc == _abi.SVR_E_WORKSPACE
+    rc = _abi.svr_preprocess(sc, cams, 1, o, ctypes.c_void_p(0x100010), need, None, None)
+    assert rc == _abi.SVR_E_INVALID  # misaligned
+    rc = _abi.svr_preprocess(sc, cams, 1, o, None, need, None, None)
+    assert rc == _abi.SVR_E_INVALID
+    # a 4096^2 frame at max_level 16 needs 16 + 48 + 3 key bits
+    sc.max_level = 16
+    cams[0].width = cams[0].height = 4096
+    assert _abi.svr_workspace_bytes(sc, cams, 1, o) == 0
+
+
+def test_sort_entry_point_checks():
+    _lib()
+    assert _abi.svr_radix_sort_scratch_bytes(1000, 52) > 0
+    assert _abi.svr_radix_sort_scratch_bytes(-1, 52) == 0
+    assert _abi.svr_radix_sort_pairs(None, None, None, None, 10, 65, None, 0, None) == _abi.SVR_E_INVALID
+    assert _abi.svr_radix_sort_pairs(None, None, None, None, 0, 32, None, 0, None) == _abi.SVR_OK
+    assert _abi.svr_status_string(_abi.SVR_E_CAPACITY) == "entry capacity exceeded"
