@@ -208,22 +208,27 @@ def keys(tile, vid, s, octpath, max_level):
 
 def _triples(rect, mask, ntx):
     """All (tile, vid, s) of voxel tile rectangles x tile sign masks."""
+    ok = np.nonzero((rect[:, 0] <= rect[:, 1]) & (rect[:, 2] <= rect[:, 3]))[0]
+    r = rect[ok].astype(np.int64)
+    w = r[:, 1] - r[:, 0] + 1
+    h = r[:, 3] - r[:, 2] + 1
+    n = w * h
+    total = int(n.sum())
+    vid = np.repeat(ok.astype(np.int64), n)
+    first = np.repeat(np.cumsum(n) - n, n)
+    local = np.arange(total, dtype=np.int64) - first
+    wr = np.repeat(w, n)
+    tx = np.repeat(r[:, 0], n) + local % wr
+    ty = np.repeat(r[:, 2], n) + local // wr
+    tile = ty * ntx + tx
+    m = mask[tile].astype(np.int64)
     tiles, vids, ss = [], [], []
-    ok = np.nonzero(rect[:, 0] <= rect[:, 1])[0]
-    for i in ok:
-        tx0, tx1, ty0, ty1 = (int(x) for x in rect[i])
-        if ty0 > ty1:
-            continue
-        for ty in range(ty0, ty1 + 1):
-            for tx in range(tx0, tx1 + 1):
-                t = ty * ntx + tx
-                m = int(mask[t])
-                for s in range(8):
-                    if m >> s & 1:
-                        tiles.append(t)
-                        vids.append(i)
-                        ss.append(s)
-    return (np.asarray(tiles, np.int64), np.asarray(vids, np.int64), np.asarray(ss, np.uint8))
+    for s in range(8):
+        sel = ((m >> s) & 1).astype(bool)
+        tiles.append(tile[sel])
+        vids.append(vid[sel])
+        ss.append(np.full(int(sel.sum()), s, np.uint8))
+    return np.concatenate(tiles), np.concatenate(vids), np.concatenate(ss)
 
 
 def expected_entries(scene, cam, tile_w=16, tile_h=16, z_near=Z_NEAR, band=0.02,

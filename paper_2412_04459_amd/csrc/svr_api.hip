@@ -126,6 +126,7 @@ int make_layout(const svr_scene* sc, const svr_camera* cams, int n_cams, const s
     for (int j = 0; j < 3; ++j) {
       double acc = 0;
       for (int r = 0; r < 3; ++r) acc += (double)c.w2c[4 * r + j] * (double)c.w2c[4 * r + 3];
+      d.od[j] = -acc;
       d.o[j] = (float)(-acc);
     }
     d.fx = c.fx; d.fy = c.fy; d.cx = c.cx; d.cy = c.cy;

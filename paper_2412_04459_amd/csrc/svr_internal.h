@@ -21,6 +21,7 @@ constexpr uint32_t kVidMask = (1u << kVidBits) - 1u;
 // A camera as the kernels see it.  Rotation is world-to-camera (row-major);
 // `o` is the camera centre in world space.
 struct DevCam {
+  double od[3];       // camera centre in fp64 (ray origin of the render passes)
   float r[9];
   float o[3];
   float fx, fy, cx, cy;
@@ -38,7 +39,7 @@ struct CamSet {
 
 // Per view-voxel record written by the projection pass and read by the
 // render passes, 64 bytes:
-//   q0 = (box min - camera centre).xyz, edge length
+//   q0 = voxel centre xyz, edge length
 //   q1 = raw densities of corners 0..3, q2 = corners 4..7
 //   q3 = clamped SH colour rgb, bits of the channels with a positive
 //        pre-clamp value (as int)
@@ -83,6 +84,20 @@ __device__ __forceinline__ void pixel_dir(const DevCam& c, int u, int v, float& 
   dx = __fmaf_rn(c.r[0], x, __fmaf_rn(c.r[3], y, c.r[6]));
   dy = __fmaf_rn(c.r[1], x, __fmaf_rn(c.r[4], y, c.r[7]));
   dz = __fmaf_rn(c.r[2], x, __fmaf_rn(c.r[5], y, c.r[8]));
+}
+
+// The same ray in fp64, normalised: the geometry of the render passes (ray-box
+// test and sample positions) runs in double precision, so the segment length
+// of a grazing hit keeps its relative precision.
+__device__ __forceinline__ void pixel_dir_f64(const DevCam& c, int u, int v, double& dx, double& dy,
+                                              double& dz) {
+  const double x = ((double)u + 0.5 - (double)c.cx) / (double)c.fx;
+  const double y = ((double)v + 0.5 - (double)c.cy) / (double)c.fy;
+  dx = (double)c.r[0] * x + (double)c.r[3] * y + (double)c.r[6];
+  dy = (double)c.r[1] * x + (double)c.r[4] * y + (double)c.r[7];
+  dz = (double)c.r[2] * x + (double)c.r[5] * y + (double)c.r[8];
+  const double n = 1.0 / sqrt(dx * dx + dy * dy + dz * dz);
+  dx *= n; dy *= n; dz *= n;
 }
 
 __device__ __forceinline__ int sign_bits(float dx, float dy, float dz) {

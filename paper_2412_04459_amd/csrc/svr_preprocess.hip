@@ -232,7 +232,7 @@ __global__ __launch_bounds__(kBlock) void k_project(
   const int4* vg = reinterpret_cast<const int4*>(vox_grid + vid * 8);
   const int4 ga = vg[0], gb = vg[1];
   VoxRec R;
-  R.q0 = make_float4(rx - h, ry - h, rz - h, s);
+  R.q0 = make_float4(center[vid], center[N + vid], center[2 * N + vid], s);
   R.q1 = make_float4(grid_raw[ga.x], grid_raw[ga.y], grid_raw[ga.z], grid_raw[ga.w]);
   R.q2 = make_float4(grid_raw[gb.x], grid_raw[gb.y], grid_raw[gb.z], grid_raw[gb.w]);
   const float rn = rsqrtf(rx * rx + ry * ry + rz * rz);
@@ -369,39 +369,90 @@ hipError_t launch_scan(const Layout& L, void* ws, hipStream_t s) {
 // key = global tile << (3L + 3) | (top 3L path bits XOR s repeated) << 3 | s
 //       (the direction-dependent Morton order of Supp. B.2 as one XOR)
 // value = s << 29 | voxel id
+// A thread emits the entries of a voxel with few entries; voxels with more
+// than kBigEmit entries are queued in LDS and emitted by the whole workgroup,
+// one tile of the voxel's rectangle per thread, each tile's output offset
+// read from the summed-area table (row-major tiles, ascending s per tile).
+constexpr uint32_t kBigEmit = 64;
+
+struct EmitCtx {
+  uint64_t top, rep;
+  int sh;
+  uint32_t vid;
+};
+
+__device__ __forceinline__ void emit_tile(const EmitCtx& e, int gt, uint32_t m,
+                                          unsigned long long o, int64_t cap,
+                                          uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+  while (m) {
+    const int sgn = __ffs(m) - 1;
+    m &= m - 1;
+    if (o < (unsigned long long)cap) {
+      keys[o] = ((uint64_t)gt << e.sh) | ((e.top ^ ((uint64_t)sgn * e.rep)) << 3) | (uint64_t)sgn;
+      vals[o] = ((uint32_t)sgn << kVidBits) | e.vid;
+    }
+    ++o;
+  }
+}
+
 __global__ __launch_bounds__(kBlock) void k_emit(
     int64_t NV, int n_cams, CamSet cams, const uint64_t* __restrict__ octpath,
     const uint32_t* __restrict__ count, const unsigned long long* __restrict__ off,
-    const uint2* __restrict__ rect, const uint8_t* __restrict__ mask, int L, int64_t cap,
-    uint64_t* __restrict__ keys, uint32_t* __restrict__ vals, WsHeader* __restrict__ hdr) {
+    const uint2* __restrict__ rect, const uint8_t* __restrict__ mask,
+    const uint32_t* __restrict__ sat, int L, int64_t cap, uint64_t* __restrict__ keys,
+    uint32_t* __restrict__ vals, WsHeader* __restrict__ hdr) {
+  __shared__ int s_nbig;
+  __shared__ int64_t s_big[kBlock];
+  if (threadIdx.x == 0) s_nbig = 0;
+  __syncthreads();
   const int64_t vv = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (vv >= NV) return;
-  const uint32_t cnt = count[vv];
-  if (cnt == 0) return;
-  const int64_t vid = vv / n_cams;
-  const int ci = (int)(vv - vid * n_cams);
-  const DevCam& c = cams.c[ci];
-  unsigned long long o = off[vv];
-  if (o + cnt > (unsigned long long)cap) atomicOr(&hdr->overflow, 1u);
-  const uint2 r = rect[vv];
-  const int tx0 = (int)(r.x & 0xffffu) / kTile, tx1 = (int)(r.x >> 16) / kTile;
-  const int ty0 = (int)(r.y & 0xffffu) / kTile, ty1 = (int)(r.y >> 16) / kTile;
+  const uint32_t cnt = vv < NV ? count[vv] : 0u;
   const int sh = 3 * L + 3;
-  const uint64_t top = octpath[vid] >> (3 * (SVR_MAX_LEVELS - L));
-  const uint64_t rep = (L >= 21) ? ~0ull : (((1ull << (3 * L)) - 1ull) / 7ull);  // 001 001 ... 001
-  for (int ty = ty0; ty <= ty1; ++ty) {
-    for (int tx = tx0; tx <= tx1; ++tx) {
-      const int gt = c.tile_off + ty * c.ntx + tx;
-      uint32_t m = mask[gt];
-      while (m) {
-        const int sgn = __ffs(m) - 1;
-        m &= m - 1;
-        if (o < (unsigned long long)cap) {
-          keys[o] = ((uint64_t)gt << sh) | ((top ^ ((uint64_t)sgn * rep)) << 3) | (uint64_t)sgn;
-          vals[o] = ((uint32_t)sgn << kVidBits) | (uint32_t)vid;
+  const uint64_t rep = ((1ull << (3 * L)) - 1ull) / 7ull;  // 001 001 ... 001 (L triplets)
+  if (cnt > 0) {
+    if (off[vv] + cnt > (unsigned long long)cap) atomicOr(&hdr->overflow, 1u);
+    if (cnt > kBigEmit) {
+      s_big[atomicAdd(&s_nbig, 1)] = vv;
+    } else {
+      const int64_t vid = vv / n_cams;
+      const DevCam& c = cams.c[(int)(vv - vid * n_cams)];
+      const EmitCtx e{octpath[vid] >> (3 * (SVR_MAX_LEVELS - L)), rep, sh, (uint32_t)vid};
+      unsigned long long o = off[vv];
+      const uint2 r = rect[vv];
+      const int tx0 = (int)(r.x & 0xffffu) / kTile, tx1 = (int)(r.x >> 16) / kTile;
+      const int ty0 = (int)(r.y & 0xffffu) / kTile, ty1 = (int)(r.y >> 16) / kTile;
+      for (int ty = ty0; ty <= ty1; ++ty) {
+        for (int tx = tx0; tx <= tx1; ++tx) {
+          const int gt = c.tile_off + ty * c.ntx + tx;
+          const uint32_t m = mask[gt];
+          emit_tile(e, gt, m, o, cap, keys, vals);
+          o += __popc(m);
         }
-        ++o;
       }
+    }
+  }
+  __syncthreads();
+  const int nbig = s_nbig;
+  for (int b = 0; b < nbig; ++b) {
+    const int64_t bv = s_big[b];
+    const int64_t vid = bv / n_cams;
+    const DevCam& c = cams.c[(int)(bv - vid * n_cams)];
+    const EmitCtx e{octpath[vid] >> (3 * (SVR_MAX_LEVELS - L)), rep, sh, (uint32_t)vid};
+    const uint2 r = rect[bv];
+    const int tx0 = (int)(r.x & 0xffffu) / kTile, tx1 = (int)(r.x >> 16) / kTile;
+    const int ty0 = (int)(r.y & 0xffffu) / kTile, ty1 = (int)(r.y >> 16) / kTile;
+    const int wdt = tx1 - tx0 + 1;
+    const int ntiles = wdt * (ty1 - ty0 + 1);
+    const uint32_t* S = sat + c.sat_off;
+    const int W1 = c.ntx + 1;
+    const unsigned long long o0 = off[bv];
+    for (int jt = threadIdx.x; jt < ntiles; jt += kBlock) {
+      const int tx = tx0 + jt % wdt, ty = ty0 + jt / wdt;
+      unsigned long long o = o0;
+      if (ty > ty0) o += sat_rect(S, W1, tx0, tx1, ty0, ty - 1);
+      if (tx > tx0) o += sat_rect(S, W1, tx0, tx - 1, ty, ty);
+      const int gt = c.tile_off + ty * c.ntx + tx;
+      emit_tile(e, gt, mask[gt], o, cap, keys, vals);
     }
   }
 }
@@ -410,10 +461,10 @@ hipError_t launch_emit(const svr_scene& sc, const CamSet& cams, const Layout& L,
                        hipStream_t s) {
   if (L.NV == 0) return hipSuccess;
   SVR_LAUNCH("emit", k_emit, dim3((unsigned)((L.NV + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
-                     L.NV, L.n_cams, cams, sc.octpath, at<uint32_t>(ws, L.count),
-                     at<unsigned long long>(ws, L.offset), at<uint2>(ws, L.rect),
-                     at<uint8_t>(ws, L.tile_mask), L.L, L.cap, at<uint64_t>(ws, L.keys0),
-                     at<uint32_t>(ws, L.vals0), at<WsHeader>(ws, L.hdr));
+             L.NV, L.n_cams, cams, sc.octpath, at<uint32_t>(ws, L.count),
+             at<unsigned long long>(ws, L.offset), at<uint2>(ws, L.rect),
+             at<uint8_t>(ws, L.tile_mask), at<uint32_t>(ws, L.tile_sat), L.L, L.cap,
+             at<uint64_t>(ws, L.keys0), at<uint32_t>(ws, L.vals0), at<WsHeader>(ws, L.hdr));
   return hipGetLastError();
 }
 

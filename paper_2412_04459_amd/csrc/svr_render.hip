@@ -52,9 +52,19 @@ __device__ __forceinline__ float act_df(float v) {
   return 1.f / (1.f + __expf(-v));
 }
 
+// alpha = 1 - exp(-x) (eq. vox_alpha).  For small optical depth the
+// difference cancels in fp32 (exp(-x) rounds to 1 for x < 6e-8), so below
+// x = 2^-7 the Taylor series x (1 - x/2 + x^2/6) is used instead; its
+// truncation error x^3/24 relative is below 1e-7 there.
+__device__ __forceinline__ float alpha_of(float x) {
+  const float taylor = x * __fmaf_rn(x, __fmaf_rn(x, 1.f / 6.f, -0.5f), 1.f);
+  return x < 0.0078125f ? taylor : 1.f - __expf(-x);
+}
+
 struct LdsBatch {
-  float lx[kBatch], ly[kBatch], lz[kBatch];  // box min - camera centre
-  float sz[kBatch], isz[kBatch];             // edge, 1 / edge
+  double lo[3][kBatch];                      // box min - camera centre (fp64)
+  double hi[3][kBatch];                      // box max - camera centre (fp64)
+  float isz[kBatch];                         // 1 / edge
   float V[8][kBatch];                        // corner raw densities
   float cr[kBatch], cg[kBatch], cb[kBatch];  // colour
   uint32_t meta[kBatch];                     // sign bits | quadrant mask << 3
@@ -78,7 +88,7 @@ __device__ __forceinline__ int find_cam_r(const CamSet& cams, int gtile) {
 
 // stage one entry of the sorted list in LDS
 __device__ __forceinline__ void stage_entry(LdsBatch& B, int slot, uint32_t val, int ci, int n_cams,
-                                            const VoxRec* __restrict__ rec,
+                                            const DevCam& c, const VoxRec* __restrict__ rec,
                                             const uint2* __restrict__ rect, int qu0, int qv0) {
   const uint32_t vid = val & kVidMask;
   const int64_t vv = (int64_t)vid * n_cams + ci;
@@ -92,8 +102,14 @@ __device__ __forceinline__ void stage_entry(LdsBatch& B, int slot, uint32_t val,
     const int a0 = qu0 + (q & 1) * 8, b0 = qv0 + (q >> 1) * 8;
     if (u0 <= a0 + 7 && u1 >= a0 && v0 <= b0 + 7 && v1 >= b0) qm |= 1u << q;
   }
-  B.lx[slot] = R.q0.x; B.ly[slot] = R.q0.y; B.lz[slot] = R.q0.z;
-  B.sz[slot] = R.q0.w; B.isz[slot] = 1.f / R.q0.w;
+  const double h = 0.5 * (double)R.q0.w;
+  B.lo[0][slot] = ((double)R.q0.x - h) - c.od[0];
+  B.lo[1][slot] = ((double)R.q0.y - h) - c.od[1];
+  B.lo[2][slot] = ((double)R.q0.z - h) - c.od[2];
+  B.hi[0][slot] = ((double)R.q0.x + h) - c.od[0];
+  B.hi[1][slot] = ((double)R.q0.y + h) - c.od[1];
+  B.hi[2][slot] = ((double)R.q0.z + h) - c.od[2];
+  B.isz[slot] = 1.f / R.q0.w;
   B.V[0][slot] = R.q1.x; B.V[1][slot] = R.q1.y; B.V[2][slot] = R.q1.z; B.V[3][slot] = R.q1.w;
   B.V[4][slot] = R.q2.x; B.V[5][slot] = R.q2.y; B.V[6][slot] = R.q2.z; B.V[7][slot] = R.q2.w;
   B.cr[slot] = R.q3.x; B.cg[slot] = R.q3.y; B.cb[slot] = R.q3.z;
@@ -101,17 +117,27 @@ __device__ __forceinline__ void stage_entry(LdsBatch& B, int slot, uint32_t val,
   B.vid[slot] = vid;
 }
 
-// ray-box slab test against the staged entry j; returns (a, b) and hit flag
-__device__ __forceinline__ bool slab(const LdsBatch& B, int j, float idx, float idy, float idz,
-                                     float& a, float& b) {
-  const float s = B.sz[j];
-  const float lx = B.lx[j], ly = B.ly[j], lz = B.lz[j];
-  const float t0x = lx * idx, t1x = (lx + s) * idx;
-  const float t0y = ly * idy, t1y = (ly + s) * idy;
-  const float t0z = lz * idz, t1z = (lz + s) * idz;
-  a = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fminf(t0z, t1z));
-  b = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fmaxf(t0z, t1z));
-  return (a <= b) && (a > 0.f);
+// Ray-box slab test (Supp. A.2 listing "ray_aabb") against staged entry j, in
+// fp64: entry/exit distances a <= b, hit iff a <= b and a > 0.
+__device__ __forceinline__ bool slab(const LdsBatch& B, int j, double idx, double idy, double idz,
+                                     double& a, double& b) {
+  const double t0x = B.lo[0][j] * idx, t1x = B.hi[0][j] * idx;
+  const double t0y = B.lo[1][j] * idy, t1y = B.hi[1][j] * idy;
+  const double t0z = B.lo[2][j] * idz, t1z = B.hi[2][j] * idz;
+  a = fmax(fmax(fmin(t0x, t1x), fmin(t0y, t1y)), fmin(t0z, t1z));
+  b = fmin(fmin(fmax(t0x, t1x), fmax(t0y, t1y)), fmax(t0z, t1z));
+  return (a <= b) && (a > 0.0);
+}
+
+// local voxel coordinate of the point at distance t on the ray (Supp. A.2
+// eq. K_samp_pts): q = (o + t d - box min) / edge, in fp64 then rounded
+__device__ __forceinline__ void local_coord(const LdsBatch& B, int j, double t, double dx,
+                                            double dy, double dz, float& qx, float& qy,
+                                            float& qz) {
+  const float is = B.isz[j];
+  qx = (float)fma(t, dx, -B.lo[0][j]) * is;
+  qy = (float)fma(t, dy, -B.lo[1][j]) * is;
+  qz = (float)fma(t, dz, -B.lo[2][j]) * is;
 }
 
 // trilinear interpolation of the staged corners at local coordinate q
@@ -124,6 +150,29 @@ __device__ __forceinline__ float trilerp(const LdsBatch& B, int j, float qx, flo
   const float v0 = __fmaf_rn(qy, v01 - v00, v00);
   const float v1 = __fmaf_rn(qy, v11 - v10, v10);
   return __fmaf_rn(qx, v1 - v0, v0);
+}
+
+struct PixelRay {
+  int u, v;
+  bool inside;
+  uint32_t spat;         // ray sign bits (from the fp32 direction, as the tile masks)
+  double dx, dy, dz;     // unit direction, fp64
+  double idx, idy, idz;  // its reciprocal
+};
+
+__device__ __forceinline__ PixelRay make_ray(const DevCam& c, int qu0, int qv0, int w, int lane) {
+  PixelRay r;
+  r.u = qu0 + (w & 1) * 8 + (lane & 7);
+  r.v = qv0 + (w >> 1) * 8 + (lane >> 3);
+  r.inside = r.u < c.W && r.v < c.H;
+  float fx, fy, fz;
+  pixel_dir(c, r.u, r.v, fx, fy, fz);
+  r.spat = (uint32_t)sign_bits(fx, fy, fz);
+  pixel_dir_f64(c, r.u, r.v, r.dx, r.dy, r.dz);
+  r.idx = 1.0 / r.dx;
+  r.idy = 1.0 / r.dy;
+  r.idz = 1.0 / r.dz;
+  return r;
 }
 
 // ---------------------------------------------------------------------------
@@ -145,47 +194,39 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(
   const int tx = tl % c.ntx, ty = tl / c.ntx;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int qu0 = tx * kTile, qv0 = ty * kTile;
-  const int u = qu0 + (w & 1) * 8 + (lane & 7);
-  const int v = qv0 + (w >> 1) * 8 + (lane >> 3);
-  const bool inside = u < c.W && v < c.H;
-  float dx, dy, dz;
-  pixel_dir(c, u, v, dx, dy, dz);
-  const uint32_t spat = (uint32_t)sign_bits(dx, dy, dz);
-  const float rn = rsqrtf(dx * dx + dy * dy + dz * dz);
-  dx *= rn; dy *= rn; dz *= rn;
-  const float idx = 1.f / dx, idy = 1.f / dy, idz = 1.f / dz;
+  const PixelRay r = make_ray(c, qu0, qv0, w, lane);
 
   const uint2 rg = range[g];
   const uint32_t start = rg.x, end = rg.y;
   float tau = 0.f, Tr = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
   uint32_t last = start;
-  bool done = !inside;
+  bool done = !r.inside;
   uint32_t n_pairs = 0, n_tests = 0, n_hits = 0;
   for (uint32_t b0 = start; b0 < end; b0 += kBatch) {
     const uint32_t i = b0 + tid;
-    if (i < end) stage_entry(B, tid, vals[i], ci, n_cams, rec, rect, qu0, qv0);
+    if (i < end) stage_entry(B, tid, vals[i], ci, n_cams, c, rec, rect, qu0, qv0);
     __syncthreads();
     const int n = (int)min((uint32_t)kBatch, end - b0);
     for (int j = 0; j < n; ++j) {
       const uint32_t meta = __builtin_amdgcn_readfirstlane(B.meta[j]);
-      if (STATS && !done && (meta & 7u) == spat) ++n_pairs;
+      if (STATS && !done && (meta & 7u) == r.spat) ++n_pairs;
       if (!((meta >> (3 + w)) & 1u)) continue;
-      if (done || (meta & 7u) != spat) continue;
-      float a, bb;
+      if (done || (meta & 7u) != r.spat) continue;
+      double a, bb;
       if (STATS) ++n_tests;
-      if (!slab(B, j, idx, idy, idz, a, bb)) continue;
+      if (!slab(B, j, r.idx, r.idy, r.idz, a, bb)) continue;
       if (STATS) ++n_hits;
-      const float l = bb - a;
-      const float lx = B.lx[j], ly = B.ly[j], lz = B.lz[j], is = B.isz[j];
+      const double lseg = bb - a;
       float x = 0.f;
 #pragma unroll
       for (int k = 0; k < K; ++k) {
-        const float t = __fmaf_rn(((float)k + 0.5f) * (1.f / K), l, a);
-        const float qx = (t * dx - lx) * is, qy = (t * dy - ly) * is, qz = (t * dz - lz) * is;
+        const double t = fma(((double)k + 0.5) * (1.0 / K), lseg, a);
+        float qx, qy, qz;
+        local_coord(B, j, t, r.dx, r.dy, r.dz, qx, qy, qz);
         x += act_f<ACT>(trilerp(B, j, qx, qy, qz));
       }
-      x *= l * (1.f / K);
-      const float wgt = Tr * (1.f - __expf(-x));
+      x *= (float)lseg * (1.f / K);
+      const float wgt = Tr * alpha_of(x);
       C0 = __fmaf_rn(wgt, B.cr[j], C0);
       C1 = __fmaf_rn(wgt, B.cg[j], C1);
       C2 = __fmaf_rn(wgt, B.cb[j], C2);
@@ -211,8 +252,8 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(
     }
     return;
   }
-  if (inside) {
-    const int64_t p = c.pix_off + (int64_t)v * c.W + u;
+  if (r.inside) {
+    const int64_t p = c.pix_off + (int64_t)r.v * c.W + r.u;
     rgba[p] = make_float4(C0, C1, C2, 1.f - Tr);
     px_tau[p] = tau;
     px_last[p] = last;
@@ -220,9 +261,28 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(
 }
 
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ float wave_sum(float x) {
+// Sum 16 per-lane values over the wave by recursive halving: at each step a
+// lane keeps half of its values and adds its partner's copy of that half, so
+// after 4 steps (xor 32, 16, 8, 4) lane L holds one value, slot (L >> 2) & 15,
+// summed over 16 lanes; two more xor steps complete the sum.  Lane 4 i ends
+// with the wave total of value i (17 shuffles instead of 16 x 6).
+__device__ __forceinline__ float wave_reduce16(float v[16]) {
+  const int lane = threadIdx.x & 63;
 #pragma unroll
-  for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+  for (int step = 0; step < 4; ++step) {
+    const int h = 8 >> step;
+    const int m = 32 >> step;
+    const bool upper = (lane & m) != 0;
+#pragma unroll
+    for (int i = 0; i < h; ++i) {
+      const float keep = upper ? v[i + h] : v[i];
+      const float send = upper ? v[i] : v[i + h];
+      v[i] = keep + __shfl_xor(send, m, 64);
+    }
+  }
+  float x = v[0];
+  x += __shfl_xor(x, 2, 64);
+  x += __shfl_xor(x, 1, 64);
   return x;
 }
 
@@ -242,22 +302,16 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(
   const int tx = tl % c.ntx, ty = tl / c.ntx;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int qu0 = tx * kTile, qv0 = ty * kTile;
-  const int u = qu0 + (w & 1) * 8 + (lane & 7);
-  const int v = qv0 + (w >> 1) * 8 + (lane >> 3);
-  const bool inside = u < c.W && v < c.H;
-  float dx, dy, dz;
-  pixel_dir(c, u, v, dx, dy, dz);
-  const uint32_t spat = (uint32_t)sign_bits(dx, dy, dz);
-  const float rn = rsqrtf(dx * dx + dy * dy + dz * dz);
-  dx *= rn; dy *= rn; dz *= rn;
-  const float idx = 1.f / dx, idy = 1.f / dy, idz = 1.f / dz;
+  const PixelRay r = make_ray(c, qu0, qv0, w, lane);
+  const int slot = (lane >> 2) & 15;  // reduced value this lane ends up holding
+  const bool writer = (lane & 3) == 0 && slot < 11;
 
   const uint2 rg = range[g];
   const uint32_t start = rg.x;
   float tau = 0.f, gr = 0.f, gg = 0.f, gb = 0.f, ga = 0.f;
   uint32_t last = start;
-  if (inside) {
-    const int64_t p = c.pix_off + (int64_t)v * c.W + u;
+  if (r.inside) {
+    const int64_t p = c.pix_off + (int64_t)r.v * c.W + r.u;
     tau = px_tau[p];
     last = px_last[p];
     const float4 gq = grad_rgba[p];
@@ -276,26 +330,27 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(
     const uint32_t b0 = bend - min((uint32_t)kBatch, bend - start);
     const int n = (int)(bend - b0);
     bend = b0;
-    if (tid < n) stage_entry(B, tid, vals[b0 + tid], ci, n_cams, rec, rect, qu0, qv0);
+    if (tid < n) stage_entry(B, tid, vals[b0 + tid], ci, n_cams, c, rec, rect, qu0, qv0);
     __syncthreads();
     for (int j = n - 1; j >= 0; --j) {
       const uint32_t meta = __builtin_amdgcn_readfirstlane(B.meta[j]);
       if (!((meta >> (3 + w)) & 1u)) continue;
-      float a = 0.f, bb = 0.f;
-      bool hit = (b0 + (uint32_t)j < last) && ((meta & 7u) == spat);
-      if (hit) hit = slab(B, j, idx, idy, idz, a, bb);
+      double a = 0.0, bb = 0.0;
+      bool hit = (b0 + (uint32_t)j < last) && ((meta & 7u) == r.spat);
+      if (hit) hit = slab(B, j, r.idx, r.idy, r.idz, a, bb);
       if (__ballot(hit) == 0ull) continue;
-      float gV[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-      float gc0 = 0.f, gc1 = 0.f, gc2 = 0.f;
+      float gv[16];
+#pragma unroll
+      for (int m = 0; m < 16; ++m) gv[m] = 0.f;
       if (hit) {
-        const float l = bb - a;
-        const float lx = B.lx[j], ly = B.ly[j], lz = B.lz[j], is = B.isz[j];
+        const double lseg = bb - a;
         float x = 0.f;
         float dw[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};  // sum_k act'(v_k) w_m(q_k)
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-          const float t = __fmaf_rn(((float)k + 0.5f) * (1.f / K), l, a);
-          const float qx = (t * dx - lx) * is, qy = (t * dy - ly) * is, qz = (t * dz - lz) * is;
+          const double t = fma(((double)k + 0.5) * (1.0 / K), lseg, a);
+          float qx, qy, qz;
+          local_coord(B, j, t, r.dx, r.dy, r.dz, qx, qy, qz);
           const float vk = trilerp(B, j, qx, qy, qz);
           x += act_f<ACT>(vk);
           const float dk = act_df<ACT>(vk);
@@ -306,36 +361,29 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(
           dw[4] = __fmaf_rn(a10, pz, dw[4]); dw[5] = __fmaf_rn(a10, qz, dw[5]);
           dw[6] = __fmaf_rn(a11, pz, dw[6]); dw[7] = __fmaf_rn(a11, qz, dw[7]);
         }
-        const float lK = l * (1.f / K);
+        const float lK = (float)lseg * (1.f / K);
         x *= lK;
-        const float e = __expf(-x);
-        const float alpha = 1.f - e;
+        const float alpha = alpha_of(x);
         const float Tnext = __expf(-tau);
         tau -= x;
         const float Ti = __expf(-tau);
         const float cr = B.cr[j], cg = B.cg[j], cb = B.cb[j];
         const float wgt = Ti * alpha;
-        gc0 = gr * wgt; gc1 = gg * wgt; gc2 = gb * wgt;
+        gv[8] = gr * wgt; gv[9] = gg * wgt; gv[10] = gb * wgt;
         const float dLdx = Tnext * (gr * (cr - S0) + gg * (cg - S1) + gb * (cb - S2)) + ga * Tfin;
         S0 = __fmaf_rn(alpha, cr - S0, S0);
         S1 = __fmaf_rn(alpha, cg - S1, S1);
         S2 = __fmaf_rn(alpha, cb - S2, S2);
         const float f = dLdx * lK;
 #pragma unroll
-        for (int m = 0; m < 8; ++m) gV[m] = f * dw[m];
+        for (int m = 0; m < 8; ++m) gv[m] = f * dw[m];
       }
-#pragma unroll
-      for (int m = 0; m < 8; ++m) gV[m] = wave_sum(gV[m]);
-      gc0 = wave_sum(gc0); gc1 = wave_sum(gc1); gc2 = wave_sum(gc2);
-      if (lane == 0) {
+      const float tot = wave_reduce16(gv);
+      if (writer) {
         const uint32_t vid = B.vid[j];
-        float* gcp = g_corner + (int64_t)vid * 8;
-#pragma unroll
-        for (int m = 0; m < 8; ++m) unsafeAtomicAdd(gcp + m, gV[m]);
-        float* grp = g_rgb + ((int64_t)vid * n_cams + ci) * 3;
-        unsafeAtomicAdd(grp + 0, gc0);
-        unsafeAtomicAdd(grp + 1, gc1);
-        unsafeAtomicAdd(grp + 2, gc2);
+        float* dst = slot < 8 ? g_corner + (int64_t)vid * 8 + slot
+                              : g_rgb + ((int64_t)vid * n_cams + ci) * 3 + (slot - 8);
+        unsafeAtomicAdd(dst, tot);
       }
     }
     __syncthreads();
@@ -343,6 +391,9 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(
 }
 
 // ---------------------------------------------------------------------------
+// SH and grid adjoint, one thread per voxel.  The (D+1)^2 x 3 SH gradients of
+// the workgroup's 256 voxels are staged in LDS (odd row stride: no bank
+// conflicts) and written out as one contiguous, coalesced block.
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_sh_bwd(
     int64_t N, int n_cams, CamSet cams, const float* __restrict__ center,
@@ -350,41 +401,49 @@ __global__ __launch_bounds__(kBlock) void k_sh_bwd(
     const VoxRec* __restrict__ rec, const float* __restrict__ g_rgb,
     const float* __restrict__ g_corner, float* __restrict__ grad_grid, float* __restrict__ grad_sh) {
   constexpr int NB = (D + 1) * (D + 1);
-  const int64_t vid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (vid >= N) return;
+  constexpr int F = 3 * NB;
+  constexpr int FP = F | 1;
+  __shared__ float stage[kBlock * FP];
+  const int64_t base = (int64_t)blockIdx.x * kBlock;
+  const int64_t vid = base + threadIdx.x;
   if (grad_sh) {
     float acc[NB][3];
 #pragma unroll
     for (int j = 0; j < NB; ++j) acc[j][0] = acc[j][1] = acc[j][2] = 0.f;
-    for (int ci = 0; ci < n_cams; ++ci) {
-      const int64_t vv = vid * n_cams + ci;
-      if (count[vv] == 0) continue;
-      const DevCam& c = cams.c[ci];
-      const uint32_t bits = __float_as_uint(rec[vv].q3.w);
-      float g3[3];
+    if (vid < N) {
+      for (int ci = 0; ci < n_cams; ++ci) {
+        const int64_t vv = vid * n_cams + ci;
+        if (count[vv] == 0) continue;
+        const DevCam& c = cams.c[ci];
+        const uint32_t bits = __float_as_uint(rec[vv].q3.w);
+        float g3[3];
 #pragma unroll
-      for (int ch = 0; ch < 3; ++ch) g3[ch] = ((bits >> ch) & 1u) ? g_rgb[vv * 3 + ch] : 0.f;
-      const float rx = center[vid] - c.o[0], ry = center[N + vid] - c.o[1],
-                  rz = center[2 * N + vid] - c.o[2];
-      const float rn = rsqrtf(rx * rx + ry * ry + rz * rz);
-      float Y[16];
-      sh_basis<D>(rx * rn, ry * rn, rz * rn, Y);
+        for (int ch = 0; ch < 3; ++ch) g3[ch] = ((bits >> ch) & 1u) ? g_rgb[vv * 3 + ch] : 0.f;
+        const float rx = center[vid] - c.o[0], ry = center[N + vid] - c.o[1],
+                    rz = center[2 * N + vid] - c.o[2];
+        const float rn = rsqrtf(rx * rx + ry * ry + rz * rz);
+        float Y[16];
+        sh_basis<D>(rx * rn, ry * rn, rz * rn, Y);
 #pragma unroll
-      for (int j = 0; j < NB; ++j) {
-        acc[j][0] = __fmaf_rn(g3[0], Y[j], acc[j][0]);
-        acc[j][1] = __fmaf_rn(g3[1], Y[j], acc[j][1]);
-        acc[j][2] = __fmaf_rn(g3[2], Y[j], acc[j][2]);
+        for (int j = 0; j < NB; ++j) {
+          acc[j][0] = __fmaf_rn(g3[0], Y[j], acc[j][0]);
+          acc[j][1] = __fmaf_rn(g3[1], Y[j], acc[j][1]);
+          acc[j][2] = __fmaf_rn(g3[2], Y[j], acc[j][2]);
+        }
       }
     }
-    float* o = grad_sh + vid * (3 * NB);
 #pragma unroll
     for (int j = 0; j < NB; ++j) {
-      o[3 * j + 0] = acc[j][0];
-      o[3 * j + 1] = acc[j][1];
-      o[3 * j + 2] = acc[j][2];
+      stage[threadIdx.x * FP + 3 * j + 0] = acc[j][0];
+      stage[threadIdx.x * FP + 3 * j + 1] = acc[j][1];
+      stage[threadIdx.x * FP + 3 * j + 2] = acc[j][2];
     }
+    __syncthreads();
+    const int nv = (int)min((int64_t)kBlock, N - base);
+    float* o = grad_sh + base * F;
+    for (int i = threadIdx.x; i < nv * F; i += kBlock) o[i] = stage[(i / F) * FP + (i % F)];
   }
-  if (grad_grid) {
+  if (grad_grid && vid < N) {
     const float4* gc = reinterpret_cast<const float4*>(g_corner + vid * 8);
     const float4 ga = gc[0], gb = gc[1];
     const float gv[8] = {ga.x, ga.y, ga.z, ga.w, gb.x, gb.y, gb.z, gb.w};

@@ -25,6 +25,7 @@ constexpr uint32_t kFlagAgg = 1u << 30;          // partition-local count publis
 constexpr uint32_t kFlagPre = 2u << 30;          // inclusive prefix published
 constexpr uint32_t kValMask = (1u << 30) - 1u;
 constexpr int kSpinLimit = 1 << 22;
+constexpr int kLookWin = 16;                     // partitions read per look-back round
 
 __device__ __forceinline__ unsigned long long lane_mask_lt() {
   const int lane = threadIdx.x & 63;
@@ -155,32 +156,53 @@ __global__ __launch_bounds__(kBlock) void k_sort_pass(
   for (int i = 0; i < w; ++i) wb += wsum[i];
   dstart[tid] = wb + inc - tot;
 
-  // decoupled look-back for digit `tid`
+  // decoupled look-back for digit `tid`: each round reads the status words of
+  // the next kLookWin preceding partitions at once (independent loads, one
+  // round trip) and consumes them nearest first, up to the first one not yet
+  // published or the first inclusive prefix.  Only counts travel through the
+  // status words, so relaxed device-scope atomics suffice.
   uint32_t* my = status + (int64_t)part * kRadix + tid;
   uint32_t prefix = 0;
   if (part == 0) {
-    __hip_atomic_store(my, kFlagPre | tot, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(my, kFlagPre | tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
   } else {
-    __hip_atomic_store(my, kFlagAgg | tot, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    __hip_atomic_store(my, kFlagAgg | tot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
     int j = part - 1;
     int spins = 0;
-    while (j >= 0) {
-      const uint32_t st = __hip_atomic_load(status + (int64_t)j * kRadix + tid, __ATOMIC_ACQUIRE,
-                                            __HIP_MEMORY_SCOPE_AGENT);
-      const uint32_t flag = st & ~kValMask;
-      if (flag == 0u) {
+    while (true) {
+      uint32_t st[kLookWin];
+#pragma unroll
+      for (int k = 0; k < kLookWin; ++k) {
+        const int jj = j - k;
+        st[k] = jj >= 0 ? __hip_atomic_load(status + (int64_t)jj * kRadix + tid, __ATOMIC_RELAXED,
+                                            __HIP_MEMORY_SCOPE_AGENT)
+                        : kFlagPre;
+      }
+      int used = 0;
+      bool stop = false, fin = false;
+#pragma unroll
+      for (int k = 0; k < kLookWin; ++k) {
+        if (stop) continue;
+        const uint32_t flag = st[k] & ~kValMask;
+        if (flag == 0u) {
+          stop = true;
+        } else {
+          prefix += st[k] & kValMask;
+          ++used;
+          if (flag == kFlagPre) stop = fin = true;
+        }
+      }
+      if (fin) break;
+      j -= used;
+      if (used == 0) {
         if (++spins > kSpinLimit) {
           atomicOr(err, 1u);
           break;
         }
         __builtin_amdgcn_s_sleep(1);
-        continue;
       }
-      prefix += st & kValMask;
-      if (flag == kFlagPre) break;
-      --j;
     }
-    __hip_atomic_store(my, kFlagPre | ((prefix + tot) & kValMask), __ATOMIC_RELEASE,
+    __hip_atomic_store(my, kFlagPre | ((prefix + tot) & kValMask), __ATOMIC_RELAXED,
                        __HIP_MEMORY_SCOPE_AGENT);
   }
   gbase[tid] = digit_base[tid] + prefix;

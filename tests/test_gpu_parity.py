@@ -282,3 +282,24 @@ def test_forward_invariant_to_sync_mode(torch_dev, cfg2):
     a = _gpu_frame(torch, scene, cams, K=2, sync=True)["rgba"]
     b = _gpu_frame(torch, scene, cams, K=2, sync=False)["rgba"]
     assert np.array_equal(a, b)
+
+
+def test_cfg2_sorted_entries_bit_exact(torch_dev, cfg2):
+    """Sorted list at the benchmark's full size (about 1.1M entries)."""
+    torch = torch_dev
+    scene, cams = cfg2
+    _say("sorted entries cfg2")
+    out = _gpu_frame(torch, scene, cams, K=2)
+    rast = out["rast"]
+    keys, vals = rast.sorted_entries(rast.n_entries)
+    gk = keys.cpu().numpy().view(np.uint64)
+    gv = vals.cpu().numpy().view(np.uint32)
+    assert np.all(gk[1:] > gk[:-1])
+    sh = np.uint64(3 * scene.max_level + 3)
+    _, kc, val = oracle.keys((gk >> sh).astype(np.int64),
+                             (gv & np.uint32((1 << 29) - 1)).astype(np.int64),
+                             (gv >> np.uint32(29)).astype(np.uint8), scene.octpath, scene.max_level)
+    assert np.array_equal(kc, gk) and np.array_equal(val, gv)
+    exp = oracle.expected_entries(scene, cams[0])
+    assert np.all(np.isin(exp["must"][0], gk))
+    assert np.all(np.isin(gk, exp["may"][0]))
