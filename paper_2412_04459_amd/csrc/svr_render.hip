@@ -261,28 +261,62 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(
 }
 
 // ---------------------------------------------------------------------------
-// Sum 16 per-lane values over the wave by recursive halving: at each step a
-// lane keeps half of its values and adds its partner's copy of that half, so
-// after 4 steps (xor 32, 16, 8, 4) lane L holds one value, slot (L >> 2) & 15,
-// summed over 16 lanes; two more xor steps complete the sum.  Lane 4 i ends
-// with the wave total of value i (17 shuffles instead of 16 x 6).
-__device__ __forceinline__ float wave_reduce16(float v[16]) {
+// Wave sum of 11 per-lane values by recursive halving with gfx950 cross-lane
+// VALU operations (no LDS): at each step a lane keeps one half of its values
+// and adds its partner lane's copy of that half.
+//   step 1: v_permlane32_swap pairs lane L with L ^ 32  (8 pairs -> 8 values)
+//   step 2: v_permlane16_swap pairs 16-lane rows 0<->1, 2<->3 (-> 4 values)
+//   step 3: DPP row_mirror pairs i <-> 15 - i in a row     (-> 2 values)
+//   step 4: DPP row_half_mirror pairs i <-> 7 - i          (-> 1 value)
+//   step 5: two quad DPP adds (xor 1, xor 2) finish the sum.
+// Lane L then holds the wave total of value (L >> 2) & 15; lanes 4 i hold
+// value i.  About 35 VALU instructions in all.
+__device__ __forceinline__ float swap32_sum(float lo, float hi) {
+  // upper 32 lanes of the first operand <-> lower 32 lanes of the second
+  const auto r = __builtin_amdgcn_permlane32_swap(__float_as_uint(lo), __float_as_uint(hi), false,
+                                                  false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+__device__ __forceinline__ float swap16_sum(float lo, float hi) {
+  // odd rows of the first operand <-> even rows of the second
+  const auto r = __builtin_amdgcn_permlane16_swap(__float_as_uint(lo), __float_as_uint(hi), false,
+                                                  false);
+  return __uint_as_float(r[0]) + __uint_as_float(r[1]);
+}
+
+template <int CTRL>
+__device__ __forceinline__ float dpp(float x) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), CTRL, 0xf, 0xf, false));
+}
+
+template <int CTRL>
+__device__ __forceinline__ float dpp_pair_sum(float lo, float hi, bool upper) {
+  const float keep = upper ? hi : lo;
+  const float send = upper ? lo : hi;
+  return keep + dpp<CTRL>(send);
+}
+
+constexpr int kDppRowMirror = 0x140;
+constexpr int kDppRowHalfMirror = 0x141;
+constexpr int kDppQuadXor1 = 0xB1;  // quad_perm [1,0,3,2]
+constexpr int kDppQuadXor2 = 0x4E;  // quad_perm [2,3,0,1]
+
+__device__ __forceinline__ float wave_reduce11(float g0, float g1, float g2, float g3, float g4,
+                                               float g5, float g6, float g7, float g8, float g9,
+                                               float g10) {
   const int lane = threadIdx.x & 63;
-#pragma unroll
-  for (int step = 0; step < 4; ++step) {
-    const int h = 8 >> step;
-    const int m = 32 >> step;
-    const bool upper = (lane & m) != 0;
-#pragma unroll
-    for (int i = 0; i < h; ++i) {
-      const float keep = upper ? v[i + h] : v[i];
-      const float send = upper ? v[i] : v[i + h];
-      v[i] = keep + __shfl_xor(send, m, 64);
-    }
-  }
-  float x = v[0];
-  x += __shfl_xor(x, 2, 64);
-  x += __shfl_xor(x, 1, 64);
+  const float s0 = swap32_sum(g0, g8), s1 = swap32_sum(g1, g9), s2 = swap32_sum(g2, g10);
+  const float s3 = swap32_sum(g3, 0.f), s4 = swap32_sum(g4, 0.f), s5 = swap32_sum(g5, 0.f);
+  const float s6 = swap32_sum(g6, 0.f), s7 = swap32_sum(g7, 0.f);
+  const float t0 = swap16_sum(s0, s4), t1 = swap16_sum(s1, s5);
+  const float t2 = swap16_sum(s2, s6), t3 = swap16_sum(s3, s7);
+  const bool u8 = (lane & 8) != 0, u4 = (lane & 4) != 0;
+  const float w0 = dpp_pair_sum<kDppRowMirror>(t0, t2, u8);
+  const float w1 = dpp_pair_sum<kDppRowMirror>(t1, t3, u8);
+  float x = dpp_pair_sum<kDppRowHalfMirror>(w0, w1, u4);
+  x += dpp<kDppQuadXor1>(x);
+  x += dpp<kDppQuadXor2>(x);
   return x;
 }
 
@@ -339,9 +373,9 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(
       bool hit = (b0 + (uint32_t)j < last) && ((meta & 7u) == r.spat);
       if (hit) hit = slab(B, j, r.idx, r.idy, r.idz, a, bb);
       if (__ballot(hit) == 0ull) continue;
-      float gv[16];
+      float gv[11];
 #pragma unroll
-      for (int m = 0; m < 16; ++m) gv[m] = 0.f;
+      for (int m = 0; m < 11; ++m) gv[m] = 0.f;
       if (hit) {
         const double lseg = bb - a;
         float x = 0.f;
@@ -378,7 +412,8 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(
 #pragma unroll
         for (int m = 0; m < 8; ++m) gv[m] = f * dw[m];
       }
-      const float tot = wave_reduce16(gv);
+      const float tot = wave_reduce11(gv[0], gv[1], gv[2], gv[3], gv[4], gv[5], gv[6], gv[7],
+                                      gv[8], gv[9], gv[10]);
       if (writer) {
         const uint32_t vid = B.vid[j];
         float* dst = slot < 8 ? g_corner + (int64_t)vid * 8 + slot
