@@ -117,8 +117,8 @@ def main():
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
     t0 = time.time()
-    scene = S.scene_cfg2()
-    cams = S.cameras_cfg2(n=args.views)
+    scene = S.spheres_background_scene()
+    cams = S.orbit_cameras_1297x840(n=args.views)
     K = 2
     log("scene: %d voxels, %d grid points (%.1fs)" % (scene.n_voxels, scene.n_grid, time.time() - t0))
     ds = DeviceScene(scene)

@@ -329,20 +329,20 @@ def _sphere_shell_cfg(seed, n_spheres, lo, hi, rlo, rhi, level):
     return [Sphere(tuple(c), float(r), level) for c, r in zip(cs, rs)]
 
 
-def scene_cfg0(opaque=False, seed=0) -> Scene:
+def sphere_shell_scene(opaque=False, seed=0) -> Scene:
     """~3.3k leaves: a level-6 shell of the sphere |p| = 0.5 inside [0,1]^3,
     kept where |SDF(centre)| < voxel size; SH degree 0, colour U(0,1)."""
     return make_scene((0.5, 0.5, 0.5), 1.0, 6, [Sphere((0, 0, 0), 0.5, 6)], kappa=1.0,
                       sh_degree=0, sh_mode="rgb_uniform", opaque=opaque, seed=seed)
 
 
-def camera_cfg0(seed=0) -> Camera:
+def sphere_shell_camera(seed=0) -> Camera:
     rng = np.random.default_rng(np.random.SeedSequence(seed).spawn(6)[3])
     d = random_direction(rng)
     return look_at(64, 64, 50.0, 2.0 * d)
 
 
-def scene_cfg1(opaque=False, seed=1, kappa=0.68) -> Scene:
+def spheres_plane_scene(opaque=False, seed=1, kappa=0.68) -> Scene:
     """~185k leaves, max level 9: three level-9 sphere shells plus a level-8
     ground plane (off the dyadic grid), SH degree 3 ~ N(0, 0.2)."""
     rng = np.random.default_rng(np.random.SeedSequence(seed).spawn(6)[0])
@@ -354,7 +354,7 @@ def scene_cfg1(opaque=False, seed=1, kappa=0.68) -> Scene:
                       sh_mode="normal", sh_std=0.2, opaque=opaque, seed=seed)
 
 
-def camera_cfg1(seed=1) -> Camera:
+def spheres_plane_camera(seed=1) -> Camera:
     rng = np.random.default_rng(np.random.SeedSequence(seed).spawn(6)[3])
     d = random_direction(rng)
     d[2] = abs(d[2]) * 0.5 + 0.2
@@ -362,7 +362,7 @@ def camera_cfg1(seed=1) -> Camera:
     return look_at(800, 800, 50.0, 2.5 * d)
 
 
-def scene_cfg2(seed=2, max_level=12, n_spheres=4, kappa=1.0, opaque=False) -> Scene:
+def spheres_background_scene(seed=2, max_level=12, n_spheres=4, kappa=1.0, opaque=False) -> Scene:
     """~1.1M leaves in [-8,8]^3, max level 12: four level-12 sphere shells near
     the origin plus a sparse background shell (levels 4..7) for radius 2.5..8."""
     rng = np.random.default_rng(np.random.SeedSequence(seed).spawn(6)[0])
@@ -374,13 +374,13 @@ def scene_cfg2(seed=2, max_level=12, n_spheres=4, kappa=1.0, opaque=False) -> Sc
                       sh_degree=3, sh_mode="normal", sh_std=0.2, opaque=opaque, seed=seed)
 
 
-def cameras_cfg2(n=36, seed=2, W=1297, H=840) -> List[Camera]:
+def orbit_cameras_1297x840(n=36, seed=2, W=1297, H=840) -> List[Camera]:
     rng = np.random.default_rng(np.random.SeedSequence(seed).spawn(6)[3])
     phase = float(rng.uniform(0, 2 * math.pi))
     return orbit_cameras(n, W, H, 60.0, 2.0, 8.5, phase)
 
 
-def cameras_cfg3(n=24, seed=3) -> List[Camera]:
+def mixed_resolution_cameras(n=24, seed=3) -> List[Camera]:
     rng = np.random.default_rng(np.random.SeedSequence(seed).spawn(6)[3])
     phase = float(rng.uniform(0, 2 * math.pi))
     res = [RESOLUTION_MIX[int(i)] for i in rng.integers(0, len(RESOLUTION_MIX), size=n)]
@@ -483,14 +483,20 @@ def camera_from_pose(W, H, fx, fy, cx, cy, R, t) -> Camera:
 
 
 def workload(name: str, **kw) -> Workload:
-    if name == "cfg0":
-        return Workload("cfg0", scene_cfg0(**kw), [camera_cfg0()], K=1, grad_seed=0)
-    if name == "cfg0_opaque":
-        return Workload("cfg0_opaque", scene_cfg0(opaque=True), [camera_cfg0()], K=1, grad_seed=0)
-    if name == "cfg1":
-        return Workload("cfg1", scene_cfg1(**kw), [camera_cfg1()], K=1, grad_seed=1)
-    if name == "cfg2":
-        return Workload("cfg2", scene_cfg2(**kw), cameras_cfg2(), K=2, grad_seed=2)
-    if name == "cfg3":
-        return Workload("cfg3", scene_cfg2(**kw), cameras_cfg3(), K=2, grad_seed=3)
+    """Named workloads: "sphere_shell_3k", "sphere_shell_3k_opaque",
+    "spheres_plane_184k", "orbit_1m_1297x840", "mixed_24cams_1m"."""
+    if name == "sphere_shell_3k":
+        return Workload(name, sphere_shell_scene(**kw), [sphere_shell_camera()], K=1, grad_seed=0)
+    if name == "sphere_shell_3k_opaque":
+        return Workload(name, sphere_shell_scene(opaque=True), [sphere_shell_camera()], K=1,
+                        grad_seed=0)
+    if name == "spheres_plane_184k":
+        return Workload(name, spheres_plane_scene(**kw), [spheres_plane_camera()], K=1,
+                        grad_seed=1)
+    if name == "orbit_1m_1297x840":
+        return Workload(name, spheres_background_scene(**kw), orbit_cameras_1297x840(), K=2,
+                        grad_seed=2)
+    if name == "mixed_24cams_1m":
+        return Workload(name, spheres_background_scene(**kw), mixed_resolution_cameras(), K=2,
+                        grad_seed=3)
     raise KeyError(name)

@@ -99,10 +99,10 @@ def test_radix_sort_matches_stable_sort(torch_dev, n, bits):
 # duplicated, sorted (key, value) list
 # ---------------------------------------------------------------------------
 def _key_cases():
-    return [("cfg0", lambda: (S.scene_cfg0(), [S.camera_cfg0()])),
-            ("cfg0_ragged", lambda: (S.scene_cfg0(), [S.look_at(77, 51, 60.0, [1.5, -1.2, 1.0],
+    return [("shell", lambda: (S.sphere_shell_scene(), [S.sphere_shell_camera()])),
+            ("shell_ragged", lambda: (S.sphere_shell_scene(), [S.look_at(77, 51, 60.0, [1.5, -1.2, 1.0],
                                                                   target=(0.3, 0.3, 0.3))])),
-            ("cfg1", lambda: (S.scene_cfg1(), [S.camera_cfg1()])),
+            ("spheres_plane", lambda: (S.spheres_plane_scene(), [S.spheres_plane_camera()])),
             ("tiny_multisign", lambda: (S.tiny_random_scene(4, max_level=4),
                                         [S.look_at(90, 70, 100.0, [0.5, 0.45, 0.55],
                                                    target=(0.9, 0.8, 0.7))]))]
@@ -144,16 +144,16 @@ def test_sorted_entries_bit_exact(torch_dev, name):
 # ---------------------------------------------------------------------------
 # forward RGBA
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("case,K,act", [("cfg0", 1, 0), ("cfg0_opaque", 1, 0), ("cfg0_opaque", 3, 1),
+@pytest.mark.parametrize("case,K,act", [("shell", 1, 0), ("shell_opaque", 1, 0), ("shell_opaque", 3, 1),
                                         ("ragged_opaque", 2, 0), ("tiny", 4, 0)])
 def test_render_fwd_matches_oracle(torch_dev, case, K, act):
     torch = torch_dev
-    if case == "cfg0":
-        scene, cams = S.scene_cfg0(), [S.camera_cfg0()]
-    elif case == "cfg0_opaque":
-        scene, cams = S.scene_cfg0(opaque=True), [S.camera_cfg0()]
+    if case == "shell":
+        scene, cams = S.sphere_shell_scene(), [S.sphere_shell_camera()]
+    elif case == "shell_opaque":
+        scene, cams = S.sphere_shell_scene(opaque=True), [S.sphere_shell_camera()]
     elif case == "ragged_opaque":
-        scene = S.scene_cfg0(opaque=True)
+        scene = S.sphere_shell_scene(opaque=True)
         cams = [S.look_at(77, 51, 60.0, [1.5, -1.2, 1.0], target=(0.3, 0.3, 0.3))]
     else:
         scene = S.tiny_random_scene(9, max_level=4, sh_degree=3)
@@ -166,10 +166,10 @@ def test_render_fwd_matches_oracle(torch_dev, case, K, act):
     _say("  max err %.3g" % err)
 
 
-def test_render_fwd_cfg1_sampled(torch_dev):
+def test_render_fwd_spheres_plane_sampled(torch_dev):
     torch = torch_dev
-    scene, cams = S.scene_cfg1(), [S.camera_cfg1()]
-    _say("render fwd cfg1 sampled")
+    scene, cams = S.spheres_plane_scene(), [S.spheres_plane_camera()]
+    _say("render fwd spheres+plane sampled")
     out = _gpu_frame(torch, scene, cams, K=1)
     rng = np.random.default_rng(11)
     # sample among pixels with hits and some empty ones
@@ -183,13 +183,13 @@ def test_render_fwd_cfg1_sampled(torch_dev):
 # ---------------------------------------------------------------------------
 # gradients
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("case,K,act", [("cfg0", 1, 0), ("cfg0_opaque", 2, 0), ("tiny", 3, 1),
+@pytest.mark.parametrize("case,K,act", [("shell", 1, 0), ("shell_opaque", 2, 0), ("tiny", 3, 1),
                                         ("tiny_opaque", 2, 0)])
 def test_render_bwd_matches_oracle(torch_dev, case, K, act):
     torch = torch_dev
     import dataclasses
-    if case.startswith("cfg0"):
-        scene, cams = S.scene_cfg0(opaque=case.endswith("opaque")), [S.camera_cfg0()]
+    if case.startswith("shell"):
+        scene, cams = S.sphere_shell_scene(opaque=case.endswith("opaque")), [S.sphere_shell_camera()]
     else:
         scene = S.tiny_random_scene(9, max_level=4, sh_degree=3)
         if case.endswith("opaque"):
@@ -207,10 +207,10 @@ def test_render_bwd_matches_oracle(torch_dev, case, K, act):
     _check_grad(out["grad_sh"], ref["grad_sh"], "grad_sh")
 
 
-def test_render_bwd_cfg1_sampled(torch_dev):
+def test_render_bwd_spheres_plane_sampled(torch_dev):
     torch = torch_dev
-    scene, cams = S.scene_cfg1(), [S.camera_cfg1()]
-    _say("render bwd cfg1 sampled")
+    scene, cams = S.spheres_plane_scene(), [S.spheres_plane_camera()]
+    _say("render bwd spheres+plane sampled")
     P = cams[0].W * cams[0].H
     rng = np.random.default_rng(12)
     px = rng.choice(P, 3000, replace=False)
@@ -227,7 +227,7 @@ def test_render_bwd_cfg1_sampled(torch_dev):
 def test_autograd_function_matches_direct_backward(torch_dev):
     torch = torch_dev
     from paper_2412_04459_amd.render import DeviceScene, Rasterizer, render
-    scene, cams = S.scene_cfg0(opaque=True), [S.camera_cfg0()]
+    scene, cams = S.sphere_shell_scene(opaque=True), [S.sphere_shell_camera()]
     ds = DeviceScene(scene)
     rast = Rasterizer(ds, cams, K=2)
     grid = ds.grid_raw.clone().requires_grad_(True)
@@ -246,18 +246,18 @@ def test_autograd_function_matches_direct_backward(torch_dev):
 # against the oracle in the same launch configuration the benchmark times
 # ---------------------------------------------------------------------------
 @pytest.fixture(scope="module")
-def cfg2(torch_dev):
-    scene = S.scene_cfg2()
-    cams = S.cameras_cfg2()[:1]
+def bench_scene(torch_dev):
+    scene = S.spheres_background_scene()
+    cams = S.orbit_cameras_1297x840()[:1]
     return scene, cams
 
 
-def test_cfg2_sampled_parity(torch_dev, cfg2):
+def test_bench_scene_sampled_parity(torch_dev, bench_scene):
     torch = torch_dev
-    scene, cams = cfg2
+    scene, cams = bench_scene
     cam = cams[0]
     P = cam.W * cam.H
-    _say("cfg2 sampled parity N=%d" % scene.n_voxels)
+    _say("1.07M-voxel scene sampled parity N=%d" % scene.n_voxels)
     rng = np.random.default_rng(13)
     g_full = S.upstream_grads(P, 2)
     out_f = _gpu_frame(torch, scene, cams, K=2)
@@ -274,21 +274,21 @@ def test_cfg2_sampled_parity(torch_dev, cfg2):
     _check_grad(out["grad_sh"], ref["grad_sh"], "grad_sh")
 
 
-def test_forward_invariant_to_sync_mode(torch_dev, cfg2):
+def test_forward_invariant_to_sync_mode(torch_dev, bench_scene):
     """The forward has no atomics: the image is bit-identical whether the entry
     count is read back (sort sized to E) or not (sort sized to capacity)."""
     torch = torch_dev
-    scene, cams = cfg2
+    scene, cams = bench_scene
     a = _gpu_frame(torch, scene, cams, K=2, sync=True)["rgba"]
     b = _gpu_frame(torch, scene, cams, K=2, sync=False)["rgba"]
     assert np.array_equal(a, b)
 
 
-def test_cfg2_sorted_entries_bit_exact(torch_dev, cfg2):
+def test_bench_scene_sorted_entries_bit_exact(torch_dev, bench_scene):
     """Sorted list at the benchmark's full size (about 1.1M entries)."""
     torch = torch_dev
-    scene, cams = cfg2
-    _say("sorted entries cfg2")
+    scene, cams = bench_scene
+    _say("sorted entries, 1.07M-voxel scene")
     out = _gpu_frame(torch, scene, cams, K=2)
     rast = out["rast"]
     keys, vals = rast.sorted_entries(rast.n_entries)

@@ -119,7 +119,7 @@ def test_octpath_round_trip():
 def test_octpath_matches_octree_recursion():
     # the scene builder appends child octants level by level; the listing's
     # bit interleaving of (i, j, k) must give the same code
-    for sc in (S.scene_cfg0(), S.tiny_random_scene(3, max_level=5)):
+    for sc in (S.sphere_shell_scene(), S.tiny_random_scene(3, max_level=5)):
         for n in range(0, sc.n_voxels, max(1, sc.n_voxels // 300)):
             i, j, k = (int(x) for x in sc.ijk[n])
             assert oracle.to_octpath(i, j, k, int(sc.level[n])) == int(sc.octpath[n])
@@ -353,9 +353,9 @@ def test_camera_inside_voxel_skips_it():
 # compositing invariants on the workload scenes
 # --------------------------------------------------------------------------
 @pytest.mark.parametrize("opaque", [False, True])
-def test_compositing_invariants_cfg0(opaque):
-    sc = S.scene_cfg0(opaque=opaque)
-    cam = S.camera_cfg0()
+def test_compositing_invariants_sphere_shell(opaque):
+    sc = S.sphere_shell_scene(opaque=opaque)
+    cam = S.sphere_shell_camera()
     out = oracle.render(sc, cam, K=1)
     rgba = out["rgba"]
     assert np.all(rgba[:, :3] >= 0)
@@ -419,10 +419,10 @@ def test_adjoint_matches_central_differences(K, act, opaque):
 # conservative: every ray-voxel hit lies in the voxel's tile rectangle, and
 # every pixel's own sign pattern is in its tile's mask
 # --------------------------------------------------------------------------
-@pytest.mark.parametrize("which", ["cfg0", "tiny"])
+@pytest.mark.parametrize("which", ["shell", "tiny"])
 def test_tile_assignment_is_conservative(which):
-    if which == "cfg0":
-        sc, cam = S.scene_cfg0(), S.camera_cfg0()
+    if which == "shell":
+        sc, cam = S.sphere_shell_scene(), S.sphere_shell_camera()
     else:
         sc = S.tiny_random_scene(5, max_level=4)
         cam = S.look_at(40, 30, 70.0, [1.2, 0.9, 0.7], target=(0.5, 0.5, 0.5))
