@@ -5,7 +5,7 @@
  * Sun et al., CVPR 2025, arXiv 2412.04459) and back-propagates into their
  * parameters.  One frame is four calls, in this order, on one stream:
  *
- *   svr_preprocess  project voxels to 16x16 screen tiles, pre-process the
+ *   svr_preprocess  project voxels to screen tiles (16x16 by default), pre-process the
  *                   per-view voxel records and duplicate voxels per tile and
  *                   ray-sign pattern                   (Sec. 3.1.2, Supp. B.1)
  *   svr_sort        sort the duplicated list by tile and direction-dependent
@@ -62,7 +62,7 @@ extern "C" {
 #define SVR_MAX_LEVELS 16    /* octree levels (Supp. A.1)                            */
 #define SVR_MAX_VOXELS (1 << 29) /* voxel ids are 29 bits in a value (Supp. B.1)     */
 #define SVR_MAX_K 8          /* samples per ray-voxel segment                        */
-#define SVR_TILE 16          /* tile edge in pixels                                  */
+#define SVR_TILE 16          /* default tile edge in pixels                          */
 
 /* Scene (Sec. 3.1.1): leaf voxels in arbitrary order, corner grid points
  * shared between voxels, per-voxel SH.  All pointers are device pointers.   */
@@ -93,8 +93,12 @@ typedef struct svr_opts {
   int32_t K;               /* samples per ray-voxel segment, 1..8 (eq. vox_alpha)      */
   float t_stop;            /* early termination threshold on transmittance (h_T)      */
   int32_t activation;      /* SVR_ACT_EXPLIN or SVR_ACT_SOFTPLUS                       */
-  int32_t reserved0;
+  int32_t tile;            /* tile edge in pixels: 8, 16 or 32 (0 means 16)            */
   int64_t entry_capacity;  /* capacity of the duplicated (tile, voxel, sign) list, < 2^30 */
+  int32_t persistent;      /* 0: one render workgroup per tile; n > 0: n workgroups take
+                              tiles from per-XCD counters until all are done           */
+  int32_t accumulate;      /* svr_render_bwd: 0 overwrites grad_grid / grad_sh, 1 adds
+                              into them (several camera groups, one gradient)          */
 } svr_opts;
 
 /* Bytes of workspace one frame of `n_cams` cameras needs with
@@ -148,7 +152,8 @@ int svr_render_fwd(const svr_scene* scene, const svr_camera* cams, int n_cams,
 
 /* Adjoint of svr_render_fwd for L = sum <grad_rgba, rgba>.  The transmittance
  * is recomputed walking each pixel's list back to front from the saved final
- * optical depth (no per-sample state is stored).  Outputs are overwritten:
+ * optical depth (no per-sample state is stored).  Outputs are overwritten
+ * (added into when opts->accumulate is 1):
  *   grad_grid  [M]                 dL/d grid_raw            (may be NULL)
  *   grad_sh    [N][(D+1)^2][3]     dL/d sh                  (may be NULL)
  * Errors: SVR_E_INVALID, SVR_E_WORKSPACE, SVR_E_HIP.                         */
@@ -203,6 +208,25 @@ int svr_render_stats(const svr_scene* scene, const svr_camera* cams, int n_cams,
 int svr_timing_enable(int on);
 int svr_timing_read(char* names, int name_len, double* total_ms, int64_t* launches, int max_n,
                     int* n_out);
+
+/* Whole-frame hipGraph (the batched form: all cameras of the call in one
+ * launch per stage, no host synchronisation).  svr_graph_capture records, on
+ * `stream` (must not be the NULL stream), svr_preprocess (without read-back),
+ * svr_sort (sized by capacity), svr_render_fwd into `rgba` and, when
+ * grad_rgba is not NULL, svr_render_bwd into grad_grid / grad_sh; it returns
+ * an executable graph in *graph_out.  Cameras and options are baked into the
+ * graph; scene arrays, workspace and outputs are read and written through the
+ * pointers given here at every replay.  svr_graph_launch replays it on a
+ * stream; check capacity overflow with svr_check_overflow afterwards.
+ * Kernel timing is suspended while capturing.  No device memory is allocated
+ * (the graph objects are host-side).
+ * Errors: SVR_E_INVALID, SVR_E_WORKSPACE, SVR_E_HIP.                         */
+int svr_graph_capture(const svr_scene* scene, const svr_camera* cams, int n_cams,
+                      const svr_opts* opts, void* ws, size_t ws_bytes, float* rgba,
+                      const float* grad_rgba, float* grad_grid, float* grad_sh, void* stream,
+                      void** graph_out);
+int svr_graph_launch(void* graph, void* stream);
+int svr_graph_destroy(void* graph);
 
 /* Static text of a status code; detail of the calling thread's last error. */
 const char* svr_status_string(int status);

@@ -44,8 +44,8 @@ class svr_camera(ctypes.Structure):
 
 
 class svr_opts(ctypes.Structure):
-    _fields_ = [("K", I32), ("t_stop", ctypes.c_float), ("activation", I32), ("reserved0", I32),
-                ("entry_capacity", I64)]
+    _fields_ = [("K", I32), ("t_stop", ctypes.c_float), ("activation", I32), ("tile", I32),
+                ("entry_capacity", I64), ("persistent", I32), ("accumulate", I32)]
 
 
 _SIGS = {
@@ -61,6 +61,10 @@ _SIGS = {
     "svr_render_stats": (ctypes.c_int, [P, P, ctypes.c_int, P, P, ctypes.c_size_t, P, P]),
     "svr_timing_enable": (ctypes.c_int, [ctypes.c_int]),
     "svr_timing_read": (ctypes.c_int, [P, ctypes.c_int, P, P, ctypes.c_int, P]),
+    "svr_graph_capture": (ctypes.c_int, [P, P, ctypes.c_int, P, P, ctypes.c_size_t, P, P, P, P, P,
+                                         P]),
+    "svr_graph_launch": (ctypes.c_int, [P, P]),
+    "svr_graph_destroy": (ctypes.c_int, [P]),
     "svr_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "svr_last_error": (ctypes.c_char_p, []),
 }
@@ -188,6 +192,20 @@ def kernel_times():
         nm = names.raw[i * L:(i + 1) * L].split(b"\0", 1)[0].decode()
         out[nm] = (float(ms[i]), int(cnt[i]))
     return out
+
+
+def svr_graph_capture(scene, cams, n_cams, opts, ws, ws_bytes, rgba, grad_rgba, grad_grid, grad_sh,
+                      stream, graph_out):
+    return load().svr_graph_capture(_ref(scene), cams, n_cams, _ref(opts), ws, ws_bytes, rgba,
+                                    grad_rgba, grad_grid, grad_sh, stream, graph_out)
+
+
+def svr_graph_launch(graph, stream):
+    return load().svr_graph_launch(graph, stream)
+
+
+def svr_graph_destroy(graph):
+    return load().svr_graph_destroy(graph)
 
 
 def svr_status_string(status):

@@ -102,6 +102,10 @@ int make_layout(const svr_scene* sc, const svr_camera* cams, int n_cams, const s
     return fail(SVR_E_INVALID, "t_stop outside [0, 1]");
   if (o->entry_capacity < 0 || o->entry_capacity >= (int64_t)1 << 30)
     return fail(SVR_E_INVALID, "entry_capacity outside [0, 2^30)");
+  if (o->tile != 0 && o->tile != 8 && o->tile != 16 && o->tile != 32)
+    return fail(SVR_E_INVALID, "tile=%d is not 8, 16 or 32", o->tile);
+  if (o->persistent < 0) return fail(SVR_E_INVALID, "persistent < 0");
+  if (o->accumulate != 0 && o->accumulate != 1) return fail(SVR_E_INVALID, "accumulate not 0/1");
   Layout& l = *L;
   memset(&l, 0, sizeof(l));
   memset(cs, 0, sizeof(*cs));
@@ -110,8 +114,13 @@ int make_layout(const svr_scene* sc, const svr_camera* cams, int n_cams, const s
   l.NV = l.N * n_cams;
   l.cap = o->entry_capacity;
   l.L = sc->max_level;
+  l.tile = o->tile == 0 ? SVR_TILE : o->tile;
+  l.tshift = l.tile == 8 ? 3 : (l.tile == 16 ? 4 : 5);
+  l.persistent = o->persistent;
   int64_t T = 0, P = 0, sat = 0;
   cs->n = n_cams;
+  cs->tile = l.tile;
+  cs->tshift = l.tshift;
   for (int i = 0; i < n_cams; ++i) {
     const svr_camera& c = cams[i];
     if (c.width < 1 || c.height < 1 || c.width > 16384 || c.height > 16384)
@@ -131,8 +140,8 @@ int make_layout(const svr_scene* sc, const svr_camera* cams, int n_cams, const s
     }
     d.fx = c.fx; d.fy = c.fy; d.cx = c.cx; d.cy = c.cy;
     d.W = c.width; d.H = c.height;
-    d.ntx = (c.width + kTile - 1) / kTile;
-    d.nty = (c.height + kTile - 1) / kTile;
+    d.ntx = (c.width + l.tile - 1) / l.tile;
+    d.nty = (c.height + l.tile - 1) / l.tile;
     d.tile_off = (int32_t)T;
     d.sat_off = (int32_t)sat;
     d.pix_off = P;
@@ -288,7 +297,8 @@ int svr_render_bwd(const svr_scene* scene, const svr_camera* cams, int n_cams,
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   SVR_HIP(launch_render_bwd(*scene, cs, *opts, L, ws, sorted_vals(L, ws), grad_rgba, s),
           "render bwd");
-  SVR_HIP(launch_sh_bwd(*scene, cs, L, ws, grad_grid, grad_sh, s), "pre-process adjoint");
+  SVR_HIP(launch_sh_bwd(*scene, cs, L, ws, grad_grid, grad_sh, opts->accumulate != 0, s),
+          "pre-process adjoint");
   return SVR_OK;
 }
 
@@ -447,6 +457,78 @@ int svr_timing_read(char* names, int name_len, double* total_ms, int64_t* launch
   *n_out = n;
   g_next = 0;
   g_recs.clear();
+  return SVR_OK;
+}
+
+namespace {
+struct SvrGraph {
+  hipGraph_t graph;
+  hipGraphExec_t exec;
+};
+}  // namespace
+
+int svr_graph_capture(const svr_scene* scene, const svr_camera* cams, int n_cams,
+                      const svr_opts* opts, void* ws, size_t ws_bytes, float* rgba,
+                      const float* grad_rgba, float* grad_grid, float* grad_sh, void* stream,
+                      void** graph_out) {
+  if (!graph_out) return fail(SVR_E_INVALID, "null graph_out");
+  *graph_out = nullptr;
+  if (!stream) return fail(SVR_E_INVALID, "capture needs a non-default stream");
+  Layout L;
+  CamSet cs;
+  int st = make_layout(scene, cams, n_cams, opts, &L, &cs);
+  if (st != SVR_OK) return st;
+  if ((st = check_ws(L, ws, ws_bytes)) != SVR_OK) return st;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  bool timing;
+  {
+    std::lock_guard<std::mutex> lk(g_tmu);
+    timing = g_timing;
+    g_timing = false;
+  }
+  SVR_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "begin capture");
+  st = svr_preprocess(scene, cams, n_cams, opts, ws, ws_bytes, nullptr, stream);
+  if (st == SVR_OK) st = svr_sort(scene, cams, n_cams, opts, ws, ws_bytes, -1, stream);
+  if (st == SVR_OK) st = svr_render_fwd(scene, cams, n_cams, opts, ws, ws_bytes, rgba, stream);
+  if (st == SVR_OK && grad_rgba)
+    st = svr_render_bwd(scene, cams, n_cams, opts, ws, ws_bytes, grad_rgba, grad_grid, grad_sh,
+                        stream);
+  hipGraph_t g = nullptr;
+  hipError_t e = hipStreamEndCapture(s, &g);
+  {
+    std::lock_guard<std::mutex> lk(g_tmu);
+    g_timing = timing;
+  }
+  if (st != SVR_OK) {
+    if (g) (void)hipGraphDestroy(g);
+    return st;
+  }
+  if (e != hipSuccess) return hip_fail(e, "end capture");
+  hipGraphExec_t x = nullptr;
+  e = hipGraphInstantiate(&x, g, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(g);
+    return hip_fail(e, "instantiate graph");
+  }
+  *graph_out = new SvrGraph{g, x};
+  return SVR_OK;
+}
+
+int svr_graph_launch(void* graph, void* stream) {
+  if (!graph) return fail(SVR_E_INVALID, "null graph");
+  SvrGraph* G = static_cast<SvrGraph*>(graph);
+  SVR_HIP(hipGraphLaunch(G->exec, reinterpret_cast<hipStream_t>(stream)), "graph launch");
+  return SVR_OK;
+}
+
+int svr_graph_destroy(void* graph) {
+  if (!graph) return SVR_OK;
+  SvrGraph* G = static_cast<SvrGraph*>(graph);
+  hipError_t e1 = hipGraphExecDestroy(G->exec);
+  hipError_t e2 = hipGraphDestroy(G->graph);
+  delete G;
+  if (e1 != hipSuccess) return hip_fail(e1, "destroy graph exec");
+  if (e2 != hipSuccess) return hip_fail(e2, "destroy graph");
   return SVR_OK;
 }
 

@@ -11,7 +11,6 @@
 
 namespace svr {
 
-constexpr int kTile = SVR_TILE;   // tile edge (pixels)
 constexpr int kBlock = 256;       // threads per workgroup: 4 wave64
 constexpr float kZNear = 1e-4f;   // corners closer than this to the camera plane
                                   // make a voxel cover every tile
@@ -34,6 +33,8 @@ struct DevCam {
 struct CamSet {
   int32_t n;
   int32_t total_tiles;
+  int32_t tile;       // tile edge in pixels (8, 16 or 32)
+  int32_t tshift;     // log2(tile)
   DevCam c[SVR_MAX_CAMERAS];
 };
 
@@ -54,7 +55,8 @@ struct WsHeader {
   uint32_t error;                 // bit 0: sort look-back spin limit hit
   uint32_t tickets[16];           // sort partition tickets, one per pass
   unsigned long long stats[8];    // render statistics (svr_render_stats)
-  uint32_t pad[28];
+  uint32_t work[8];               // persistent render: per-XCD tile counters
+  uint32_t pad[20];
 };
 static_assert(sizeof(WsHeader) == 256, "header size");
 
@@ -62,6 +64,7 @@ struct Layout {
   // sizes
   int64_t N, NV, cap, P;
   int32_t n_cams, T, sat_total, key_bits, passes, L;
+  int32_t tile, tshift, persistent;
   int64_t scan_blocks, sort_parts;
   // byte offsets into the workspace
   size_t hdr, count, offset, rect, rec, scan_part;
@@ -129,7 +132,7 @@ hipError_t launch_render_bwd(const svr_scene& sc, const CamSet& cams, const svr_
                              const Layout& L, void* ws, const uint32_t* vals,
                              const float* grad_rgba, hipStream_t s);
 hipError_t launch_sh_bwd(const svr_scene& sc, const CamSet& cams, const Layout& L, void* ws,
-                         float* grad_grid, float* grad_sh, hipStream_t s);
+                         float* grad_grid, float* grad_sh, bool accumulate, hipStream_t s);
 
 // ---- diagnostics: kernel timing ------------------------------------------
 // When enabled (svr_timing_enable), every launch is bracketed by HIP events

@@ -49,15 +49,20 @@ __global__ __launch_bounds__(kBlock) void k_tile_masks(CamSet cams, uint8_t* __r
   const DevCam& c = cams.c[ci];
   const int t = g - c.tile_off;
   const int tx = t % c.ntx, ty = t / c.ntx;
-  const int u = tx * kTile + (threadIdx.x & (kTile - 1));
-  const int v = ty * kTile + (threadIdx.x / kTile);
+  const int ts = cams.tile;
   if (threadIdx.x == 0) m = 0;
   __syncthreads();
-  if (u < c.W && v < c.H) {
-    float dx, dy, dz;
-    pixel_dir(c, u, v, dx, dy, dz);
-    atomicOr(&m, 1u << sign_bits(dx, dy, dz));
+  uint32_t mine = 0;
+  for (int k = threadIdx.x; k < ts * ts; k += kBlock) {
+    const int u = tx * ts + (k & (ts - 1));
+    const int v = ty * ts + (k >> cams.tshift);
+    if (u < c.W && v < c.H) {
+      float dx, dy, dz;
+      pixel_dir(c, u, v, dx, dy, dz);
+      mine |= 1u << sign_bits(dx, dy, dz);
+    }
   }
+  if (mine) atomicOr(&m, mine);
   __syncthreads();
   if (threadIdx.x == 0) mask[g] = (uint8_t)m;
 }
@@ -213,7 +218,8 @@ __global__ __launch_bounds__(kBlock) void k_project(
       v1 = min((int)floorf(y1 - 0.5f + eps), c.H - 1);
     }
     if (u0 <= u1 && v0 <= v1) {
-      cnt = sat_rect(sat + c.sat_off, c.ntx + 1, u0 / kTile, u1 / kTile, v0 / kTile, v1 / kTile);
+      cnt = sat_rect(sat + c.sat_off, c.ntx + 1, u0 >> cams.tshift, u1 >> cams.tshift,
+                     v0 >> cams.tshift, v1 >> cams.tshift);
     }
   }
   // statistics: number of in-view (voxel, camera) pairs
@@ -419,8 +425,8 @@ __global__ __launch_bounds__(kBlock) void k_emit(
       const EmitCtx e{octpath[vid] >> (3 * (SVR_MAX_LEVELS - L)), rep, sh, (uint32_t)vid};
       unsigned long long o = off[vv];
       const uint2 r = rect[vv];
-      const int tx0 = (int)(r.x & 0xffffu) / kTile, tx1 = (int)(r.x >> 16) / kTile;
-      const int ty0 = (int)(r.y & 0xffffu) / kTile, ty1 = (int)(r.y >> 16) / kTile;
+      const int tx0 = (int)(r.x & 0xffffu) >> cams.tshift, tx1 = (int)(r.x >> 16) >> cams.tshift;
+      const int ty0 = (int)(r.y & 0xffffu) >> cams.tshift, ty1 = (int)(r.y >> 16) >> cams.tshift;
       for (int ty = ty0; ty <= ty1; ++ty) {
         for (int tx = tx0; tx <= tx1; ++tx) {
           const int gt = c.tile_off + ty * c.ntx + tx;
@@ -439,8 +445,8 @@ __global__ __launch_bounds__(kBlock) void k_emit(
     const DevCam& c = cams.c[(int)(bv - vid * n_cams)];
     const EmitCtx e{octpath[vid] >> (3 * (SVR_MAX_LEVELS - L)), rep, sh, (uint32_t)vid};
     const uint2 r = rect[bv];
-    const int tx0 = (int)(r.x & 0xffffu) / kTile, tx1 = (int)(r.x >> 16) / kTile;
-    const int ty0 = (int)(r.y & 0xffffu) / kTile, ty1 = (int)(r.y >> 16) / kTile;
+    const int tx0 = (int)(r.x & 0xffffu) >> cams.tshift, tx1 = (int)(r.x >> 16) >> cams.tshift;
+    const int ty0 = (int)(r.y & 0xffffu) >> cams.tshift, ty1 = (int)(r.y >> 16) >> cams.tshift;
     const int wdt = tx1 - tx0 + 1;
     const int ntiles = wdt * (ty1 - ty0 + 1);
     const uint32_t* S = sat + c.sat_off;

@@ -1,21 +1,22 @@
 // Pixel rendering and its adjoint.
 //
 // Forward (Sec. 3.1 eq. alpha_blend; Sec. 3.1.2 "Rendering pixels"): one
-// workgroup (4 wave64) per 16x16 tile, each wave an 8x8 quadrant, one pixel
-// per lane.  The workgroup stages batches of 256 entries of the tile's sorted
-// list in LDS (the 64-byte voxel records gathered by voxel id), together with
-// a 4-bit mask of the quadrants the voxel's projected rectangle touches; a
-// wave skips entries outside its quadrant with a scalar branch.  Per lane: the
-// entry's sign pattern must equal the pixel's; the ray-box slab test (Supp.
-// A.2 listing "ray_aabb", entry distance > 0) decides a hit; a hit takes K
-// midpoint samples (Supp. A.2 eq. K_samp_pts), trilinear corner densities
-// (eq. interp), the activation (eq. explin or softplus), optical depth
-// x = (l/K) sum act(v_k) and alpha = 1 - exp(-x) (eq. vox_alpha), and is
-// composited with the voxel's SH colour.  Transmittance is carried in the
-// log domain (tau = sum x), and a lane stops once exp(-tau) < t_stop, i.e.
-// a voxel is composited iff the transmittance before it is >= t_stop.  The
-// workgroup leaves as soon as all its lanes have stopped.  Saved per pixel:
-// tau_final and the list position after the last composited entry.
+// workgroup per TSxTS tile (TS = 8, 16 or 32: 1, 4 or 16 wave64), each wave an
+// 8x8 pixel block, one pixel per lane.  The workgroup stages batches of up to
+// 256 entries of the tile's sorted list in LDS (the 64-byte voxel records
+// gathered by voxel id), together with a mask of the 8x8 blocks the voxel's
+// projected rectangle touches; a wave skips entries outside its block with a
+// scalar branch.  Per lane: the entry's sign pattern must equal the pixel's;
+// the ray-box slab test (Supp. A.2 listing "ray_aabb", entry distance > 0)
+// decides a hit; a hit takes K midpoint samples (Supp. A.2 eq. K_samp_pts),
+// trilinear corner densities (eq. interp), the activation (eq. explin or
+// softplus), optical depth x = (l/K) sum act(v_k) and alpha = 1 - exp(-x)
+// (eq. vox_alpha), and is composited with the voxel's SH colour.
+// Transmittance is carried in the log domain (tau = sum x), and a lane stops
+// once exp(-tau) < t_stop, i.e. a voxel is composited iff the transmittance
+// before it is >= t_stop.  A tile ends as soon as all its lanes have stopped.
+// Saved per pixel: tau_final and the list position after the last composited
+// entry.
 //
 // Backward: the same tiling, walking each pixel's list back to front from its
 // saved position and recomputing x and alpha per hit; the transmittance before
@@ -25,15 +26,19 @@
 //   dL/dx_i = T_{i+1} <g_rgb, c_i - S_i> + g_A T_final
 //   dL/dV_m = dL/dx_i (l/K) sum_k act'(v_k) w_m(q_k)    (Supp. A.2 gradient)
 // The 11 per-hit gradients are summed over the wave and added with one
-// float atomic each.  The pre-process adjoint then maps colour gradients to SH
-// coefficients (through the clamp at 0) and scatters corner gradients onto the
-// shared grid points.
+// 11-lane float atomic.  The pre-process adjoint then maps colour gradients to
+// SH coefficients (through the clamp at 0) and scatters corner gradients onto
+// the shared grid points.
+//
+// Tile scheduling: either one workgroup per tile, mapped so that each XCD
+// (workgroups are dealt round-robin to the 8 XCDs) renders a contiguous block
+// of tiles whose voxel records overlap in that XCD's L2; or a persistent grid
+// whose workgroups take tiles from 8 per-XCD counters over the same blocks and
+// steal from the other blocks when their own is exhausted.
 #include "svr_internal.h"
 #include "svr_sh.h"
 
 namespace svr {
-
-constexpr int kBatch = kBlock;
 
 // Sec. 3.1.1 eq. explin:  x for x > 1.1, else exp(x / 1.1 - 1 + ln 1.1)
 constexpr float kInv11 = 1.f / 1.1f;
@@ -61,22 +66,65 @@ __device__ __forceinline__ float alpha_of(float x) {
   return x < 0.0078125f ? taylor : 1.f - __expf(-x);
 }
 
-struct LdsBatch {
-  double lo[3][kBatch];                      // box min - camera centre (fp64)
-  double hi[3][kBatch];                      // box max - camera centre (fp64)
-  float isz[kBatch];                         // 1 / edge
-  float V[8][kBatch];                        // corner raw densities
-  float cr[kBatch], cg[kBatch], cb[kBatch];  // colour
-  uint32_t meta[kBatch];                     // sign bits | quadrant mask << 3
-  uint32_t vid[kBatch];
+
+template <int TS>
+struct TileGeom {
+  static constexpr int kThreads = TS * TS;
+  static constexpr int kWaves = kThreads / 64;
+  static constexpr int kBpr = TS / 8;  // 8x8 blocks per tile row
+  static constexpr int kBatch = kThreads < 256 ? kThreads : 256;
 };
 
-// Map workgroup -> tile so that each XCD (workgroups are dealt round-robin to
-// the 8 XCDs) renders a contiguous block of tiles, which share voxel records
-// in that XCD's L2.
+template <int NB>
+struct LdsBatch {
+  double lo[3][NB];                    // box min - camera centre (fp64)
+  double hi[3][NB];                    // box max - camera centre (fp64)
+  float isz[NB];                       // 1 / edge
+  float V[8][NB];                      // corner raw densities
+  float cr[NB], cg[NB], cb[NB];        // colour
+  uint32_t meta[NB];                   // sign bits | block mask << 3
+  uint32_t vid[NB];
+};
+
+// arguments shared by the render kernels
+struct RenderArgs {
+  CamSet cams;
+  int T, n_cams, K, persistent;
+  float t_stop;
+  const uint2* range;
+  const uint32_t* vals;
+  const VoxRec* rec;
+  const uint2* rect;
+  float4* rgba;
+  float* px_tau;
+  uint32_t* px_last;
+  unsigned long long* stats;
+  const float4* grad_rgba;
+  float* g_corner;
+  float* g_rgb;
+  uint32_t* work;  // 8 per-XCD tile counters (persistent mode)
+};
+
 __device__ __forceinline__ int xcd_tile(int b, int T) {
   const int per = (T + 7) >> 3;
   return (b & 7) * per + (b >> 3);
+}
+
+// next tile of a persistent workgroup: own XCD block first, then steal
+__device__ __forceinline__ int next_tile(uint32_t* work, int T) {
+  const int per = (T + 7) >> 3;
+  const int x0 = (int)(blockIdx.x & 7);
+  for (int k = 0; k < 8; ++k) {
+    const int x = (x0 + k) & 7;
+    const int lo = x * per;
+    const int hi = min(T, lo + per);
+    if (lo >= hi) continue;
+    if ((int)__hip_atomic_load(work + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= hi - lo)
+      continue;
+    const int t = (int)atomicAdd(work + x, 1u);
+    if (lo + t < hi) return lo + t;
+  }
+  return -1;
 }
 
 __device__ __forceinline__ int find_cam_r(const CamSet& cams, int gtile) {
@@ -87,9 +135,12 @@ __device__ __forceinline__ int find_cam_r(const CamSet& cams, int gtile) {
 }
 
 // stage one entry of the sorted list in LDS
-__device__ __forceinline__ void stage_entry(LdsBatch& B, int slot, uint32_t val, int ci, int n_cams,
-                                            const DevCam& c, const VoxRec* __restrict__ rec,
+template <int TS, int NB>
+__device__ __forceinline__ void stage_entry(LdsBatch<NB>& B, int slot, uint32_t val, int ci,
+                                            int n_cams, const DevCam& c,
+                                            const VoxRec* __restrict__ rec,
                                             const uint2* __restrict__ rect, int qu0, int qv0) {
+  using G = TileGeom<TS>;
   const uint32_t vid = val & kVidMask;
   const int64_t vv = (int64_t)vid * n_cams + ci;
   const VoxRec R = rec[vv];
@@ -98,8 +149,8 @@ __device__ __forceinline__ void stage_entry(LdsBatch& B, int slot, uint32_t val,
   const int v0 = (int)(rc.y & 0xffffu), v1 = (int)(rc.y >> 16);
   uint32_t qm = 0;
 #pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const int a0 = qu0 + (q & 1) * 8, b0 = qv0 + (q >> 1) * 8;
+  for (int q = 0; q < G::kWaves; ++q) {
+    const int a0 = qu0 + (q % G::kBpr) * 8, b0 = qv0 + (q / G::kBpr) * 8;
     if (u0 <= a0 + 7 && u1 >= a0 && v0 <= b0 + 7 && v1 >= b0) qm |= 1u << q;
   }
   const double h = 0.5 * (double)R.q0.w;
@@ -119,8 +170,9 @@ __device__ __forceinline__ void stage_entry(LdsBatch& B, int slot, uint32_t val,
 
 // Ray-box slab test (Supp. A.2 listing "ray_aabb") against staged entry j, in
 // fp64: entry/exit distances a <= b, hit iff a <= b and a > 0.
-__device__ __forceinline__ bool slab(const LdsBatch& B, int j, double idx, double idy, double idz,
-                                     double& a, double& b) {
+template <int NB>
+__device__ __forceinline__ bool slab(const LdsBatch<NB>& B, int j, double idx, double idy,
+                                     double idz, double& a, double& b) {
   const double t0x = B.lo[0][j] * idx, t1x = B.hi[0][j] * idx;
   const double t0y = B.lo[1][j] * idy, t1y = B.hi[1][j] * idy;
   const double t0z = B.lo[2][j] * idz, t1z = B.hi[2][j] * idz;
@@ -131,7 +183,8 @@ __device__ __forceinline__ bool slab(const LdsBatch& B, int j, double idx, doubl
 
 // local voxel coordinate of the point at distance t on the ray (Supp. A.2
 // eq. K_samp_pts): q = (o + t d - box min) / edge, in fp64 then rounded
-__device__ __forceinline__ void local_coord(const LdsBatch& B, int j, double t, double dx,
+template <int NB>
+__device__ __forceinline__ void local_coord(const LdsBatch<NB>& B, int j, double t, double dx,
                                             double dy, double dz, float& qx, float& qy,
                                             float& qz) {
   const float is = B.isz[j];
@@ -142,7 +195,9 @@ __device__ __forceinline__ void local_coord(const LdsBatch& B, int j, double t, 
 
 // trilinear interpolation of the staged corners at local coordinate q
 // (corner c = 4x + 2y + z, Supp. A.2 eq. interp)
-__device__ __forceinline__ float trilerp(const LdsBatch& B, int j, float qx, float qy, float qz) {
+template <int NB>
+__device__ __forceinline__ float trilerp(const LdsBatch<NB>& B, int j, float qx, float qy,
+                                         float qz) {
   const float v00 = __fmaf_rn(qz, B.V[1][j] - B.V[0][j], B.V[0][j]);
   const float v01 = __fmaf_rn(qz, B.V[3][j] - B.V[2][j], B.V[2][j]);
   const float v10 = __fmaf_rn(qz, B.V[5][j] - B.V[4][j], B.V[4][j]);
@@ -160,10 +215,12 @@ struct PixelRay {
   double idx, idy, idz;  // its reciprocal
 };
 
+template <int TS>
 __device__ __forceinline__ PixelRay make_ray(const DevCam& c, int qu0, int qv0, int w, int lane) {
+  using G = TileGeom<TS>;
   PixelRay r;
-  r.u = qu0 + (w & 1) * 8 + (lane & 7);
-  r.v = qv0 + (w >> 1) * 8 + (lane >> 3);
+  r.u = qu0 + (w % G::kBpr) * 8 + (lane & 7);
+  r.v = qv0 + (w / G::kBpr) * 8 + (lane >> 3);
   r.inside = r.u < c.W && r.v < c.H;
   float fx, fy, fz;
   pixel_dir(c, r.u, r.v, fx, fy, fz);
@@ -175,38 +232,63 @@ __device__ __forceinline__ PixelRay make_ray(const DevCam& c, int qu0, int qv0, 
   return r;
 }
 
+// optical depth of staged entry j on the ray over [a, b]; with DW also the
+// sums sum_k act'(v_k) w_m(q_k) of the 8 corner weights
+template <int KT, int ACT, bool DW, int NB>
+__device__ __forceinline__ float segment_x(const LdsBatch<NB>& B, int j, const PixelRay& r,
+                                           double a, double lseg, int Krt, float* dw) {
+  const int K = KT > 0 ? KT : Krt;
+  const double step = 1.0 / (double)K;
+  float x = 0.f;
+#pragma unroll
+  for (int k = 0; k < (KT > 0 ? KT : SVR_MAX_K); ++k) {
+    if (KT == 0 && k >= K) break;
+    const double t = fma(((double)k + 0.5) * step, lseg, a);
+    float qx, qy, qz;
+    local_coord(B, j, t, r.dx, r.dy, r.dz, qx, qy, qz);
+    const float vk = trilerp(B, j, qx, qy, qz);
+    x += act_f<ACT>(vk);
+    if (DW) {
+      const float dk = act_df<ACT>(vk);
+      const float px = 1.f - qx, py = 1.f - qy, pz = 1.f - qz;
+      const float a00 = dk * px * py, a01 = dk * px * qy, a10 = dk * qx * py, a11 = dk * qx * qy;
+      dw[0] = __fmaf_rn(a00, pz, dw[0]); dw[1] = __fmaf_rn(a00, qz, dw[1]);
+      dw[2] = __fmaf_rn(a01, pz, dw[2]); dw[3] = __fmaf_rn(a01, qz, dw[3]);
+      dw[4] = __fmaf_rn(a10, pz, dw[4]); dw[5] = __fmaf_rn(a10, qz, dw[5]);
+      dw[6] = __fmaf_rn(a11, pz, dw[6]); dw[7] = __fmaf_rn(a11, qz, dw[7]);
+    }
+  }
+  return x * ((float)lseg / (float)K);
+}
+
 // ---------------------------------------------------------------------------
 // STATS: count, per frame, the (pixel, entry) pairs of matching sign pattern
-// the method walks, the ray-box tests this kernel executes after its
-// quadrant culling, and the composited hits (into stats[0..2]); no outputs.
-template <int K, int ACT, bool STATS>
-__global__ __launch_bounds__(kBlock) void k_render_fwd(
-    CamSet cams, int T, int n_cams, const uint2* __restrict__ range, const uint32_t* __restrict__ vals,
-    const VoxRec* __restrict__ rec, const uint2* __restrict__ rect, float t_stop,
-    float4* __restrict__ rgba, float* __restrict__ px_tau, uint32_t* __restrict__ px_last,
-    unsigned long long* __restrict__ stats) {
-  __shared__ LdsBatch B;
-  const int g = xcd_tile(blockIdx.x, T);
-  if (g >= T) return;
-  const int ci = find_cam_r(cams, g);
-  const DevCam& c = cams.c[ci];
+// the method walks, the ray-box tests this kernel executes after its block
+// culling, and the composited hits (into stats[0..2]); no outputs.
+template <int TS, int KT, int ACT, bool STATS>
+__device__ __forceinline__ void render_tile_fwd(const RenderArgs& A, int g,
+                                                LdsBatch<TileGeom<TS>::kBatch>& B) {
+  using G = TileGeom<TS>;
+  constexpr int NB = G::kBatch;
+  const int ci = find_cam_r(A.cams, g);
+  const DevCam& c = A.cams.c[ci];
   const int tl = g - c.tile_off;
   const int tx = tl % c.ntx, ty = tl / c.ntx;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int qu0 = tx * kTile, qv0 = ty * kTile;
-  const PixelRay r = make_ray(c, qu0, qv0, w, lane);
+  const int qu0 = tx * TS, qv0 = ty * TS;
+  const PixelRay r = make_ray<TS>(c, qu0, qv0, w, lane);
 
-  const uint2 rg = range[g];
+  const uint2 rg = A.range[g];
   const uint32_t start = rg.x, end = rg.y;
   float tau = 0.f, Tr = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
   uint32_t last = start;
   bool done = !r.inside;
   uint32_t n_pairs = 0, n_tests = 0, n_hits = 0;
-  for (uint32_t b0 = start; b0 < end; b0 += kBatch) {
+  for (uint32_t b0 = start; b0 < end; b0 += NB) {
     const uint32_t i = b0 + tid;
-    if (i < end) stage_entry(B, tid, vals[i], ci, n_cams, c, rec, rect, qu0, qv0);
+    if (tid < NB && i < end) stage_entry<TS>(B, tid, A.vals[i], ci, A.n_cams, c, A.rec, A.rect, qu0, qv0);
     __syncthreads();
-    const int n = (int)min((uint32_t)kBatch, end - b0);
+    const int n = (int)min((uint32_t)NB, end - b0);
     for (int j = 0; j < n; ++j) {
       const uint32_t meta = __builtin_amdgcn_readfirstlane(B.meta[j]);
       if (STATS && !done && (meta & 7u) == r.spat) ++n_pairs;
@@ -216,16 +298,7 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(
       if (STATS) ++n_tests;
       if (!slab(B, j, r.idx, r.idy, r.idz, a, bb)) continue;
       if (STATS) ++n_hits;
-      const double lseg = bb - a;
-      float x = 0.f;
-#pragma unroll
-      for (int k = 0; k < K; ++k) {
-        const double t = fma(((double)k + 0.5) * (1.0 / K), lseg, a);
-        float qx, qy, qz;
-        local_coord(B, j, t, r.dx, r.dy, r.dz, qx, qy, qz);
-        x += act_f<ACT>(trilerp(B, j, qx, qy, qz));
-      }
-      x *= (float)lseg * (1.f / K);
+      const float x = segment_x<KT, ACT, false>(B, j, r, a, bb - a, A.K, nullptr);
       const float wgt = Tr * alpha_of(x);
       C0 = __fmaf_rn(wgt, B.cr[j], C0);
       C1 = __fmaf_rn(wgt, B.cg[j], C1);
@@ -233,7 +306,7 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(
       tau += x;
       Tr = __expf(-tau);
       last = b0 + (uint32_t)j + 1u;
-      if (Tr < t_stop) done = true;
+      if (Tr < A.t_stop) done = true;
     }
     if (__syncthreads_and(done)) break;
   }
@@ -246,17 +319,36 @@ __global__ __launch_bounds__(kBlock) void k_render_fwd(
       a2 += __shfl_xor(a2, o, 64);
     }
     if (lane == 0) {
-      atomicAdd(stats + 0, a0);
-      atomicAdd(stats + 1, a1);
-      atomicAdd(stats + 2, a2);
+      atomicAdd(A.stats + 0, a0);
+      atomicAdd(A.stats + 1, a1);
+      atomicAdd(A.stats + 2, a2);
     }
     return;
   }
   if (r.inside) {
     const int64_t p = c.pix_off + (int64_t)r.v * c.W + r.u;
-    rgba[p] = make_float4(C0, C1, C2, 1.f - Tr);
-    px_tau[p] = tau;
-    px_last[p] = last;
+    A.rgba[p] = make_float4(C0, C1, C2, 1.f - Tr);
+    A.px_tau[p] = tau;
+    A.px_last[p] = last;
+  }
+}
+
+template <int TS, int KT, int ACT, bool STATS>
+__global__ __launch_bounds__(TS * TS) void k_render_fwd(RenderArgs A) {
+  __shared__ LdsBatch<TileGeom<TS>::kBatch> B;
+  __shared__ int s_tile;
+  if (!A.persistent) {
+    const int g = xcd_tile(blockIdx.x, A.T);
+    if (g < A.T) render_tile_fwd<TS, KT, ACT, STATS>(A, g, B);
+    return;
+  }
+  while (true) {
+    if (threadIdx.x == 0) s_tile = next_tile(A.work, A.T);
+    __syncthreads();
+    const int g = s_tile;
+    if (g < 0) break;
+    render_tile_fwd<TS, KT, ACT, STATS>(A, g, B);
+    __syncthreads();
   }
 }
 
@@ -320,35 +412,31 @@ __device__ __forceinline__ float wave_reduce11(float g0, float g1, float g2, flo
   return x;
 }
 
-template <int K, int ACT>
-__global__ __launch_bounds__(kBlock) void k_render_bwd(
-    CamSet cams, int T, int n_cams, const uint2* __restrict__ range, const uint32_t* __restrict__ vals,
-    const VoxRec* __restrict__ rec, const uint2* __restrict__ rect,
-    const float* __restrict__ px_tau, const uint32_t* __restrict__ px_last,
-    const float4* __restrict__ grad_rgba, float* __restrict__ g_corner, float* __restrict__ g_rgb) {
-  __shared__ LdsBatch B;
-  __shared__ uint32_t s_lmax;
-  const int g = xcd_tile(blockIdx.x, T);
-  if (g >= T) return;
-  const int ci = find_cam_r(cams, g);
-  const DevCam& c = cams.c[ci];
+template <int TS, int KT, int ACT>
+__device__ __forceinline__ void render_tile_bwd(const RenderArgs& A, int g,
+                                                LdsBatch<TileGeom<TS>::kBatch>& B,
+                                                uint32_t& s_lmax) {
+  using G = TileGeom<TS>;
+  constexpr int NB = G::kBatch;
+  const int ci = find_cam_r(A.cams, g);
+  const DevCam& c = A.cams.c[ci];
   const int tl = g - c.tile_off;
   const int tx = tl % c.ntx, ty = tl / c.ntx;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-  const int qu0 = tx * kTile, qv0 = ty * kTile;
-  const PixelRay r = make_ray(c, qu0, qv0, w, lane);
+  const int qu0 = tx * TS, qv0 = ty * TS;
+  const PixelRay r = make_ray<TS>(c, qu0, qv0, w, lane);
   const int slot = (lane >> 2) & 15;  // reduced value this lane ends up holding
   const bool writer = (lane & 3) == 0 && slot < 11;
 
-  const uint2 rg = range[g];
+  const uint2 rg = A.range[g];
   const uint32_t start = rg.x;
   float tau = 0.f, gr = 0.f, gg = 0.f, gb = 0.f, ga = 0.f;
   uint32_t last = start;
   if (r.inside) {
     const int64_t p = c.pix_off + (int64_t)r.v * c.W + r.u;
-    tau = px_tau[p];
-    last = px_last[p];
-    const float4 gq = grad_rgba[p];
+    tau = A.px_tau[p];
+    last = A.px_last[p];
+    const float4 gq = A.grad_rgba[p];
     gr = gq.x; gg = gq.y; gb = gq.z; ga = gq.w;
   }
   const float Tfin = __expf(-tau);
@@ -361,10 +449,10 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(
 
   uint32_t bend = lmax;
   while (bend > start) {
-    const uint32_t b0 = bend - min((uint32_t)kBatch, bend - start);
+    const uint32_t b0 = bend - min((uint32_t)NB, bend - start);
     const int n = (int)(bend - b0);
     bend = b0;
-    if (tid < n) stage_entry(B, tid, vals[b0 + tid], ci, n_cams, c, rec, rect, qu0, qv0);
+    if (tid < n) stage_entry<TS>(B, tid, A.vals[b0 + tid], ci, A.n_cams, c, A.rec, A.rect, qu0, qv0);
     __syncthreads();
     for (int j = n - 1; j >= 0; --j) {
       const uint32_t meta = __builtin_amdgcn_readfirstlane(B.meta[j]);
@@ -377,26 +465,10 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(
 #pragma unroll
       for (int m = 0; m < 11; ++m) gv[m] = 0.f;
       if (hit) {
+        float dw[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
         const double lseg = bb - a;
-        float x = 0.f;
-        float dw[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};  // sum_k act'(v_k) w_m(q_k)
-#pragma unroll
-        for (int k = 0; k < K; ++k) {
-          const double t = fma(((double)k + 0.5) * (1.0 / K), lseg, a);
-          float qx, qy, qz;
-          local_coord(B, j, t, r.dx, r.dy, r.dz, qx, qy, qz);
-          const float vk = trilerp(B, j, qx, qy, qz);
-          x += act_f<ACT>(vk);
-          const float dk = act_df<ACT>(vk);
-          const float px = 1.f - qx, py = 1.f - qy, pz = 1.f - qz;
-          const float a00 = dk * px * py, a01 = dk * px * qy, a10 = dk * qx * py, a11 = dk * qx * qy;
-          dw[0] = __fmaf_rn(a00, pz, dw[0]); dw[1] = __fmaf_rn(a00, qz, dw[1]);
-          dw[2] = __fmaf_rn(a01, pz, dw[2]); dw[3] = __fmaf_rn(a01, qz, dw[3]);
-          dw[4] = __fmaf_rn(a10, pz, dw[4]); dw[5] = __fmaf_rn(a10, qz, dw[5]);
-          dw[6] = __fmaf_rn(a11, pz, dw[6]); dw[7] = __fmaf_rn(a11, qz, dw[7]);
-        }
-        const float lK = (float)lseg * (1.f / K);
-        x *= lK;
+        const float x = segment_x<KT, ACT, true>(B, j, r, a, lseg, A.K, dw);
+        const float lK = (float)lseg / (float)(KT > 0 ? KT : A.K);
         const float alpha = alpha_of(x);
         const float Tnext = __expf(-tau);
         tau -= x;
@@ -416,8 +488,8 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(
                                       gv[8], gv[9], gv[10]);
       if (writer) {
         const uint32_t vid = B.vid[j];
-        float* dst = slot < 8 ? g_corner + (int64_t)vid * 8 + slot
-                              : g_rgb + ((int64_t)vid * n_cams + ci) * 3 + (slot - 8);
+        float* dst = slot < 8 ? A.g_corner + (int64_t)vid * 8 + slot
+                              : A.g_rgb + ((int64_t)vid * A.n_cams + ci) * 3 + (slot - 8);
         unsafeAtomicAdd(dst, tot);
       }
     }
@@ -425,7 +497,26 @@ __global__ __launch_bounds__(kBlock) void k_render_bwd(
   }
 }
 
-// ---------------------------------------------------------------------------
+template <int TS, int KT, int ACT>
+__global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderArgs A) {
+  __shared__ LdsBatch<TileGeom<TS>::kBatch> B;
+  __shared__ uint32_t s_lmax;
+  __shared__ int s_tile;
+  if (!A.persistent) {
+    const int g = xcd_tile(blockIdx.x, A.T);
+    if (g < A.T) render_tile_bwd<TS, KT, ACT>(A, g, B, s_lmax);
+    return;
+  }
+  while (true) {
+    if (threadIdx.x == 0) s_tile = next_tile(A.work, A.T);
+    __syncthreads();
+    const int g = s_tile;
+    if (g < 0) break;
+    render_tile_bwd<TS, KT, ACT>(A, g, B, s_lmax);
+    __syncthreads();
+  }
+}
+
 // SH and grid adjoint, one thread per voxel.  The (D+1)^2 x 3 SH gradients of
 // the workgroup's 256 voxels are staged in LDS (odd row stride: no bank
 // conflicts) and written out as one contiguous, coalesced block.
@@ -434,7 +525,8 @@ __global__ __launch_bounds__(kBlock) void k_sh_bwd(
     int64_t N, int n_cams, CamSet cams, const float* __restrict__ center,
     const int32_t* __restrict__ vox_grid, const uint32_t* __restrict__ count,
     const VoxRec* __restrict__ rec, const float* __restrict__ g_rgb,
-    const float* __restrict__ g_corner, float* __restrict__ grad_grid, float* __restrict__ grad_sh) {
+    const float* __restrict__ g_corner, float* __restrict__ grad_grid, float* __restrict__ grad_sh,
+    int accumulate) {
   constexpr int NB = (D + 1) * (D + 1);
   constexpr int F = 3 * NB;
   constexpr int FP = F | 1;
@@ -476,7 +568,11 @@ __global__ __launch_bounds__(kBlock) void k_sh_bwd(
     __syncthreads();
     const int nv = (int)min((int64_t)kBlock, N - base);
     float* o = grad_sh + base * F;
-    for (int i = threadIdx.x; i < nv * F; i += kBlock) o[i] = stage[(i / F) * FP + (i % F)];
+    if (accumulate) {
+      for (int i = threadIdx.x; i < nv * F; i += kBlock) o[i] += stage[(i / F) * FP + (i % F)];
+    } else {
+      for (int i = threadIdx.x; i < nv * F; i += kBlock) o[i] = stage[(i / F) * FP + (i % F)];
+    }
   }
   if (grad_grid && vid < N) {
     const float4* gc = reinterpret_cast<const float4*>(g_corner + vid * 8);
@@ -492,60 +588,90 @@ __global__ __launch_bounds__(kBlock) void k_sh_bwd(
 }
 
 // ---------------------------------------------------------------------------
-template <int K, int ACT>
-static void launch_fwd_t(dim3 grid, hipStream_t s, const CamSet& cams, const Layout& L, void* ws,
-                         const uint32_t* vals, float t_stop, float* rgba) {
-  SVR_LAUNCH("render_fwd", (k_render_fwd<K, ACT, false>), grid, dim3(kBlock), 0, s, cams, L.T,
-             L.n_cams, at<uint2>(ws, L.tile_range), vals, at<VoxRec>(ws, L.rec),
-             at<uint2>(ws, L.rect), t_stop, reinterpret_cast<float4*>(rgba),
-             at<float>(ws, L.px_tau), at<uint32_t>(ws, L.px_last), nullptr);
+enum class RKind { kFwd, kStats, kBwd };
+
+static RenderArgs render_args(const CamSet& cams, const svr_opts& o, const Layout& L, void* ws,
+                              const uint32_t* vals) {
+  RenderArgs A;
+  A.cams = cams;
+  A.T = L.T;
+  A.n_cams = L.n_cams;
+  A.K = o.K;
+  A.persistent = L.persistent > 0 ? 1 : 0;
+  A.t_stop = o.t_stop;
+  A.range = at<uint2>(ws, L.tile_range);
+  A.vals = vals;
+  A.rec = at<VoxRec>(ws, L.rec);
+  A.rect = at<uint2>(ws, L.rect);
+  A.rgba = nullptr;
+  A.px_tau = at<float>(ws, L.px_tau);
+  A.px_last = at<uint32_t>(ws, L.px_last);
+  A.stats = at<WsHeader>(ws, L.hdr)->stats;
+  A.grad_rgba = nullptr;
+  A.g_corner = at<float>(ws, L.g_corner);
+  A.g_rgb = at<float>(ws, L.g_rgb);
+  A.work = at<WsHeader>(ws, L.hdr)->work;
+  return A;
 }
 
-template <int K, int ACT>
-static void launch_stats_t(dim3 grid, hipStream_t s, const CamSet& cams, const Layout& L, void* ws,
-                           const uint32_t* vals, float t_stop) {
-  SVR_LAUNCH("render_stats", (k_render_fwd<K, ACT, true>), grid, dim3(kBlock), 0, s, cams, L.T,
-             L.n_cams, at<uint2>(ws, L.tile_range), vals, at<VoxRec>(ws, L.rec),
-             at<uint2>(ws, L.rect), t_stop, nullptr, nullptr, nullptr,
-             at<WsHeader>(ws, L.hdr)->stats);
-}
-
-template <int K, int ACT>
-static void launch_bwd_t(dim3 grid, hipStream_t s, const CamSet& cams, const Layout& L, void* ws,
-                         const uint32_t* vals, const float* grad_rgba) {
-  SVR_LAUNCH("render_bwd", (k_render_bwd<K, ACT>), grid, dim3(kBlock), 0, s, cams, L.T, L.n_cams,
-                     at<uint2>(ws, L.tile_range), vals, at<VoxRec>(ws, L.rec), at<uint2>(ws, L.rect),
-                     at<float>(ws, L.px_tau), at<uint32_t>(ws, L.px_last),
-                     reinterpret_cast<const float4*>(grad_rgba), at<float>(ws, L.g_corner),
-                     at<float>(ws, L.g_rgb));
-}
-
-#define SVR_DISPATCH_K(FN, ACT, ...)             \
-  switch (o.K) {                                 \
-    case 1: FN<1, ACT>(__VA_ARGS__); break;      \
-    case 2: FN<2, ACT>(__VA_ARGS__); break;      \
-    case 3: FN<3, ACT>(__VA_ARGS__); break;      \
-    case 4: FN<4, ACT>(__VA_ARGS__); break;      \
-    case 5: FN<5, ACT>(__VA_ARGS__); break;      \
-    case 6: FN<6, ACT>(__VA_ARGS__); break;      \
-    case 7: FN<7, ACT>(__VA_ARGS__); break;      \
-    default: FN<8, ACT>(__VA_ARGS__); break;     \
+template <int TS, int KT, int ACT>
+static void launch_kind(RKind kind, const RenderArgs& A, unsigned grid, hipStream_t s) {
+  const dim3 blk(TS * TS);
+  switch (kind) {
+    case RKind::kFwd:
+      SVR_LAUNCH("render_fwd", (k_render_fwd<TS, KT, ACT, false>), dim3(grid), blk, 0, s, A);
+      break;
+    case RKind::kStats:
+      SVR_LAUNCH("render_stats", (k_render_fwd<TS, KT, ACT, true>), dim3(grid), blk, 0, s, A);
+      break;
+    case RKind::kBwd:
+      SVR_LAUNCH("render_bwd", (k_render_bwd<TS, KT, ACT>), dim3(grid), blk, 0, s, A);
+      break;
   }
+}
 
-static dim3 render_grid(int T) { return dim3((unsigned)(((T + 7) >> 3) << 3)); }
+template <int TS, int ACT>
+static void launch_k(RKind kind, const RenderArgs& A, unsigned grid, hipStream_t s) {
+  switch (A.K) {
+    case 1: launch_kind<TS, 1, ACT>(kind, A, grid, s); break;
+    case 2: launch_kind<TS, 2, ACT>(kind, A, grid, s); break;
+    case 3: launch_kind<TS, 3, ACT>(kind, A, grid, s); break;
+    default: launch_kind<TS, 0, ACT>(kind, A, grid, s); break;
+  }
+}
+
+template <int TS>
+static void launch_act(RKind kind, const RenderArgs& A, int act, unsigned grid, hipStream_t s) {
+  if (act == SVR_ACT_SOFTPLUS) launch_k<TS, SVR_ACT_SOFTPLUS>(kind, A, grid, s);
+  else launch_k<TS, SVR_ACT_EXPLIN>(kind, A, grid, s);
+}
+
+static hipError_t launch_render(RKind kind, const RenderArgs& A, const svr_opts& o, const Layout& L,
+                                void* ws, hipStream_t s) {
+  if (L.T == 0) return hipSuccess;
+  unsigned grid;
+  if (L.persistent > 0) {
+    hipError_t e = launch_fill_u32(at<WsHeader>(ws, L.hdr)->work, 0u, 8, s);
+    if (e != hipSuccess) return e;
+    grid = (unsigned)min((int64_t)L.persistent, (int64_t)L.T);
+  } else {
+    grid = (unsigned)(((L.T + 7) >> 3) << 3);
+  }
+  switch (L.tile) {
+    case 8: launch_act<8>(kind, A, o.activation, grid, s); break;
+    case 32: launch_act<32>(kind, A, o.activation, grid, s); break;
+    default: launch_act<16>(kind, A, o.activation, grid, s); break;
+  }
+  return hipGetLastError();
+}
 
 hipError_t launch_render_fwd(const svr_scene& sc, const CamSet& cams, const svr_opts& o,
                              const Layout& L, void* ws, const uint32_t* vals, float* rgba,
                              hipStream_t s) {
   (void)sc;
-  if (L.T == 0) return hipSuccess;
-  const dim3 grid = render_grid(L.T);
-  if (o.activation == SVR_ACT_SOFTPLUS) {
-    SVR_DISPATCH_K(launch_fwd_t, SVR_ACT_SOFTPLUS, grid, s, cams, L, ws, vals, o.t_stop, rgba)
-  } else {
-    SVR_DISPATCH_K(launch_fwd_t, SVR_ACT_EXPLIN, grid, s, cams, L, ws, vals, o.t_stop, rgba)
-  }
-  return hipGetLastError();
+  RenderArgs A = render_args(cams, o, L, ws, vals);
+  A.rgba = reinterpret_cast<float4*>(rgba);
+  return launch_render(RKind::kFwd, A, o, L, ws, s);
 }
 
 hipError_t launch_render_stats(const svr_scene& sc, const CamSet& cams, const svr_opts& o,
@@ -554,14 +680,8 @@ hipError_t launch_render_stats(const svr_scene& sc, const CamSet& cams, const sv
   hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(at<WsHeader>(ws, L.hdr)->stats), 0u,
                                  6, s);
   if (e != hipSuccess) return e;
-  if (L.T == 0) return hipSuccess;
-  const dim3 grid = render_grid(L.T);
-  if (o.activation == SVR_ACT_SOFTPLUS) {
-    SVR_DISPATCH_K(launch_stats_t, SVR_ACT_SOFTPLUS, grid, s, cams, L, ws, vals, o.t_stop)
-  } else {
-    SVR_DISPATCH_K(launch_stats_t, SVR_ACT_EXPLIN, grid, s, cams, L, ws, vals, o.t_stop)
-  }
-  return hipGetLastError();
+  RenderArgs A = render_args(cams, o, L, ws, vals);
+  return launch_render(RKind::kStats, A, o, L, ws, s);
 }
 
 hipError_t launch_render_bwd(const svr_scene& sc, const CamSet& cams, const svr_opts& o,
@@ -572,19 +692,14 @@ hipError_t launch_render_bwd(const svr_scene& sc, const CamSet& cams, const svr_
   if (e != hipSuccess) return e;
   e = launch_fill_u32(at<uint32_t>(ws, L.g_rgb), 0u, L.NV * 3, s);
   if (e != hipSuccess) return e;
-  if (L.T == 0) return hipSuccess;
-  const dim3 grid = render_grid(L.T);
-  if (o.activation == SVR_ACT_SOFTPLUS) {
-    SVR_DISPATCH_K(launch_bwd_t, SVR_ACT_SOFTPLUS, grid, s, cams, L, ws, vals, grad_rgba)
-  } else {
-    SVR_DISPATCH_K(launch_bwd_t, SVR_ACT_EXPLIN, grid, s, cams, L, ws, vals, grad_rgba)
-  }
-  return hipGetLastError();
+  RenderArgs A = render_args(cams, o, L, ws, vals);
+  A.grad_rgba = reinterpret_cast<const float4*>(grad_rgba);
+  return launch_render(RKind::kBwd, A, o, L, ws, s);
 }
 
 hipError_t launch_sh_bwd(const svr_scene& sc, const CamSet& cams, const Layout& L, void* ws,
-                         float* grad_grid, float* grad_sh, hipStream_t s) {
-  if (grad_grid) {
+                         float* grad_grid, float* grad_sh, bool accumulate, hipStream_t s) {
+  if (grad_grid && !accumulate) {
     hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(grad_grid), 0u, sc.n_grid, s);
     if (e != hipSuccess) return e;
   }
@@ -592,8 +707,9 @@ hipError_t launch_sh_bwd(const svr_scene& sc, const CamSet& cams, const Layout& 
   const dim3 grid((unsigned)((L.N + kBlock - 1) / kBlock));
 #define SVR_SHB(D)                                                                             \
   SVR_LAUNCH("sh_bwd", k_sh_bwd<D>, grid, dim3(kBlock), 0, s, L.N, L.n_cams, cams, sc.center,   \
-                     sc.vox_grid, at<uint32_t>(ws, L.count), at<VoxRec>(ws, L.rec),            \
-                     at<float>(ws, L.g_rgb), at<float>(ws, L.g_corner), grad_grid, grad_sh)
+             sc.vox_grid, at<uint32_t>(ws, L.count), at<VoxRec>(ws, L.rec),                     \
+             at<float>(ws, L.g_rgb), at<float>(ws, L.g_corner), grad_grid, grad_sh,            \
+             accumulate ? 1 : 0)
   switch (sc.sh_degree) {
     case 0: SVR_SHB(0); break;
     case 1: SVR_SHB(1); break;

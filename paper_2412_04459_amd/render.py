@@ -95,7 +95,8 @@ class Rasterizer:
 
     def __init__(self, dscene: DeviceScene, cams: Sequence, K: int = 1, t_stop: float = 1e-4,
                  activation: int = _abi.SVR_ACT_EXPLIN, capacity: Optional[int] = None,
-                 sync_count: bool = True):
+                 sync_count: bool = True, tile: int = 16, persistent: int = 0,
+                 accumulate: bool = False):
         if len(cams) < 1 or len(cams) > _abi.SVR_MAX_CAMERAS:
             raise ValueError("1..%d cameras per frame" % _abi.SVR_MAX_CAMERAS)
         self.ds = dscene
@@ -107,6 +108,10 @@ class Rasterizer:
         self.opts.K = int(K)
         self.opts.t_stop = float(t_stop)
         self.opts.activation = int(activation)
+        self.opts.tile = int(tile)
+        self.opts.persistent = int(persistent)
+        self.opts.accumulate = 1 if accumulate else 0
+        self._graph = None
         if capacity is None:
             capacity = max(1 << 16, 2 * dscene.n_voxels * self.n_cams)
         self.sync_count = sync_count
@@ -187,6 +192,40 @@ class Rasterizer:
               "svr_render_bwd")
         return grad_grid, grad_sh
 
+    # -- whole-frame hipGraph ----------------------------------------------------
+    def capture(self, rgba: torch.Tensor, grad_rgba: Optional[torch.Tensor] = None,
+                grad_grid: Optional[torch.Tensor] = None, grad_sh: Optional[torch.Tensor] = None,
+                stream: Optional[torch.cuda.Stream] = None):
+        """Capture preprocess + sort + fwd (+ bwd) of this frame into a hipGraph
+        that writes the given tensors at every replay."""
+        self.release_graph()
+        stream = stream or torch.cuda.Stream()
+        st = self.ds.struct()
+        h = ctypes.c_void_p(0)
+        torch.cuda.synchronize()
+        check(_abi.svr_graph_capture(st, self.cam_arr, self.n_cams, self.opts, self._ws_ptr(),
+                                     self.ws_bytes, _ptr(rgba), _ptr(grad_rgba), _ptr(grad_grid),
+                                     _ptr(grad_sh), ctypes.c_void_p(stream.cuda_stream),
+                                     ctypes.byref(h)), "svr_graph_capture")
+        self._graph = h
+        self._graph_keep = (rgba, grad_rgba, grad_grid, grad_sh)
+        return h
+
+    def replay(self, stream: Optional[torch.cuda.Stream] = None):
+        s = (stream or torch.cuda.current_stream()).cuda_stream
+        check(_abi.svr_graph_launch(self._graph, ctypes.c_void_p(s)), "svr_graph_launch")
+
+    def release_graph(self):
+        if self._graph is not None:
+            _abi.svr_graph_destroy(self._graph)
+            self._graph = None
+
+    def __del__(self):
+        try:
+            self.release_graph()
+        except Exception:
+            pass
+
     def set_cameras(self, cams: Sequence):
         """Swap in cameras of the same resolutions (workspace size unchanged)."""
         if len(cams) != self.n_cams or any((a.W, a.H) != (b.W, b.H) for a, b in zip(cams, self.cams)):
@@ -221,6 +260,62 @@ class Rasterizer:
                                    self.ws_bytes, _ptr(keys), _ptr(vals), n, _stream()),
               "svr_copy_sorted")
         return keys[:n], vals[:n]
+
+
+class BatchRenderer:
+    """Forward + backward of many cameras (any mix of resolutions) as groups of
+    `group` cameras, each group one hipGraph (one launch per stage for all its
+    cameras); the gradients of all groups accumulate into one pair of buffers.
+    """
+
+    def __init__(self, dscene: DeviceScene, cams: Sequence, K: int, group: int, tile: int = 16,
+                 persistent: int = 0, activation: int = _abi.SVR_ACT_EXPLIN,
+                 t_stop: float = 1e-4, slack: float = 1.1):
+        self.ds = dscene
+        self.cams = list(cams)
+        self.group = max(1, min(int(group), len(self.cams), _abi.SVR_MAX_CAMERAS))
+        self.groups = [self.cams[i:i + self.group] for i in range(0, len(self.cams), self.group)]
+        self.n_pixels = int(sum(c.W * c.H for c in self.cams))
+        dev = dscene.device
+        self.rgba = torch.empty((self.n_pixels, 4), dtype=torch.float32, device=dev)
+        self.grad_grid = torch.empty(dscene.n_grid, dtype=torch.float32, device=dev)
+        self.grad_sh = torch.empty_like(dscene.sh)
+        self.rasts = []
+        off = 0
+        for gi, gc in enumerate(self.groups):
+            probe = Rasterizer(dscene, gc, K=K, t_stop=t_stop, activation=activation,
+                               sync_count=True, tile=tile)
+            probe.preprocess()
+            cap = int(probe.n_entries * slack) + 4096
+            del probe
+            r = Rasterizer(dscene, gc, K=K, t_stop=t_stop, activation=activation, capacity=cap,
+                           sync_count=False, tile=tile, persistent=persistent,
+                           accumulate=gi > 0)
+            npx = r.n_pixels
+            r._rows = (off, off + npx)
+            off += npx
+            self.rasts.append(r)
+        self.stream = torch.cuda.Stream()
+
+    def workspace_bytes(self) -> int:
+        return int(sum(r.ws_bytes for r in self.rasts))
+
+    def capture(self, grad_rgba: torch.Tensor):
+        self.grad_rgba = grad_rgba.contiguous()
+        for r in self.rasts:
+            a, b = r._rows
+            r.capture(self.rgba[a:b], self.grad_rgba[a:b], self.grad_grid, self.grad_sh,
+                      self.stream)
+
+    def replay(self):
+        for r in self.rasts:
+            r.replay(self.stream)
+
+    def check_overflow(self) -> bool:
+        ok = True
+        for r in self.rasts:
+            ok &= r.check_overflow() <= r.capacity
+        return ok
 
 
 class SVRasterFunction(torch.autograd.Function):

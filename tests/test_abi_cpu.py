@@ -62,7 +62,9 @@ def test_workspace_size_is_monotone_in_capacity_and_cameras():
 
 
 @pytest.mark.parametrize("field,value", [("K", 0), ("K", 9), ("activation", 7),
-                                         ("entry_capacity", 1 << 30), ("t_stop", -1.0)])
+                                         ("entry_capacity", 1 << 30), ("t_stop", -1.0),
+                                         ("tile", 12), ("tile", 64), ("persistent", -1),
+                                         ("accumulate", 2)])
 def test_invalid_options_are_rejected(field, value):
     _lib()
     sc, cams, o = _host_args()
@@ -114,3 +116,23 @@ def test_sort_entry_point_checks():
     assert _abi.svr_radix_sort_pairs(None, None, None, None, 10, 65, None, 0, None) == _abi.SVR_E_INVALID
     assert _abi.svr_radix_sort_pairs(None, None, None, None, 0, 32, None, 0, None) == _abi.SVR_OK
     assert _abi.svr_status_string(_abi.SVR_E_CAPACITY) == "entry capacity exceeded"
+
+
+def test_graph_entry_points_check_arguments():
+    _lib()
+    sc, cams, o = _host_args()
+    h = ctypes.c_void_p(0)
+    # the NULL stream cannot be captured
+    rc = _abi.svr_graph_capture(sc, cams, 1, o, ctypes.c_void_p(0x100000), 1 << 30, None, None,
+                                None, None, None, ctypes.byref(h))
+    assert rc == _abi.SVR_E_INVALID and h.value is None
+    assert _abi.svr_graph_launch(None, None) == _abi.SVR_E_INVALID
+    assert _abi.svr_graph_destroy(None) == _abi.SVR_OK
+
+
+@pytest.mark.parametrize("tile", [8, 16, 32])
+def test_workspace_shrinks_with_larger_tiles(tile):
+    _lib()
+    sc, cams, o = _host_args(W=640, H=480)
+    o.tile = tile
+    assert _abi.svr_workspace_bytes(sc, cams, 1, o) > 0
