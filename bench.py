@@ -95,6 +95,89 @@ def cpu_baseline(scene, cam, K, seconds_target=15.0):
                       "(%.1f s; CPU: %s)" % (done, scene.n_voxels, t_used, model)}
 
 
+def measured_traffic(kernel_prefix):
+    """HBM bytes per dispatch of a kernel from a committed rocprofv3 summary
+    under profiles/, if that summary was taken on the current HIP sources."""
+    import glob
+    import re as _re
+    from paper_2412_04459_amd.profsum import source_hash
+    h = source_hash()
+    for f in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        m = _re.search(r"```json\n(.*?)\n```", open(f).read(), _re.S)
+        if not m:
+            continue
+        blk = json.loads(m.group(1))
+        if blk.get("source_hash") != h:
+            continue
+        for k, v in blk.get("traffic", {}).items():
+            if k.startswith(kernel_prefix) and blk.get("fetch_factor"):
+                return v["bytes_scaled"], os.path.relpath(f, ROOT)
+    return None, None
+
+
+def batched_comparison(ds, K, log):
+    """24 cameras of uneven resolution over the same scene: 24 single-view
+    frames (one fwd+bwd each, eager launches) against the autotuned batched
+    path (camera groups in one launch per stage, each group one hipGraph)."""
+    import torch
+    from paper_2412_04459_amd import scenes as S
+    from paper_2412_04459_amd.autotune import time_batch, tune
+    from paper_2412_04459_amd.render import BatchRenderer, Rasterizer
+
+    cams = S.mixed_resolution_cameras()
+    P = sum(c.W * c.H for c in cams)
+    grad = torch.from_numpy(S.upstream_grads(P, 3)).cuda()
+    # single-view launches
+    singles = []
+    off = 0
+    for c in cams:
+        probe = Rasterizer(ds, [c], K=K, sync_count=True)
+        probe.preprocess()
+        cap = int(probe.n_entries * 1.1) + 4096
+        del probe
+        r = Rasterizer(ds, [c], K=K, capacity=cap, sync_count=False)
+        singles.append((r, grad[off:off + c.W * c.H]))
+        off += c.W * c.H
+
+    def run_singles():
+        for r, g in singles:
+            r.forward()
+            r.backward(g)
+
+    run_singles()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    reps = 3
+    e0.record()
+    for _ in range(reps):
+        run_singles()
+    e1.record()
+    torch.cuda.synchronize()
+    single_ms = e0.elapsed_time(e1) / reps
+    del singles
+    torch.cuda.empty_cache()
+    log("24 single-view frames: %.2f ms" % single_ms)
+    res = tune(ds, cams, K, grad, reps=3, log=log)
+    br = BatchRenderer(ds, cams, K, group=res["group"], tile=res["tile"],
+                       persistent=res["persistent"])
+    br.capture(grad)
+    batched_ms = time_batch(br, reps=5)
+    ok = br.check_overflow()
+    ws = br.workspace_bytes()
+    del br
+    torch.cuda.empty_cache()
+    res_rows = [{k: r[k] for k in ("group", "tile", "persistent", "ms")} for r in res["table"]]
+    return {"cameras": len(cams), "pixels": P,
+            "resolutions": sorted({"%dx%d" % (c.W, c.H) for c in cams}),
+            "single_view_ms": single_ms, "single_view_mpix_s": P / (single_ms / 1e3) / 1e6,
+            "batched_ms": batched_ms, "batched_mpix_s": P / (batched_ms / 1e3) / 1e6,
+            "speedup": single_ms / batched_ms, "overflow": not ok,
+            "autotuned": {"tile": res["tile"], "persistent": res["persistent"],
+                          "cameras_per_launch": res["group"]},
+            "workspace_bytes": ws, "autotune_table": res_rows}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -103,6 +186,10 @@ def main():
     ap.add_argument("--views", type=int, default=36)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the 24-camera batched comparison")
+    ap.add_argument("--calibrate", action="store_true",
+                    help="run a plain 1 GiB device copy first (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: every box in this setup has a single MI355X, "
@@ -116,6 +203,13 @@ def main():
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
+    if args.calibrate:
+        # a plain copy of known size, for scaling FETCH_SIZE / WRITE_SIZE
+        src = torch.ones(1 << 28, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     t0 = time.time()
     scene = S.spheres_background_scene()
     cams = S.orbit_cameras_1297x840(n=args.views)
@@ -134,8 +228,49 @@ def main():
         e_max = max(e_max, probe.n_entries)
     del probe
     cap = int(e_max * 1.1) + 4096
-    rast = Rasterizer(ds, [cams[0]], K=K, capacity=cap, sync_count=False)
     grad = torch.from_numpy(S.upstream_grads(P, 2)).cuda()
+    # tile edge: a short measurement over the orbit picks it (as the autotuner
+    # does for batches); the capacity above covers 16x16 tiles, so the other
+    # edges get their own counted pass
+    tile_ms = {}
+    for tile in (8, 16, 32):
+        probe = Rasterizer(ds, [cams[0]], K=K, sync_count=True, tile=tile)
+        e_t = 0
+        for c in cams[:: max(1, len(cams) // 6)]:
+            probe.set_cameras([c])
+            probe.preprocess()
+            e_t = max(e_t, probe.n_entries)
+        del probe
+        r = Rasterizer(ds, [cams[0]], K=K, capacity=int(e_t * 1.25) + 4096, sync_count=False,
+                       tile=tile)
+        for i in range(2):
+            r.set_cameras([cams[i]])
+            r.forward()
+            r.backward(grad)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for i in range(6):
+            r.set_cameras([cams[(5 * i) % len(cams)]])
+            r.forward()
+            r.backward(grad)
+        e1.record()
+        torch.cuda.synchronize()
+        tile_ms[tile] = e0.elapsed_time(e1) / 6
+        del r
+    tile = min(tile_ms, key=tile_ms.get)
+    log("tile edge: %s -> %d" % (", ".join("%d: %.3f ms" % kv for kv in sorted(tile_ms.items())),
+                                  tile))
+    probe = Rasterizer(ds, [cams[0]], K=K, sync_count=True, tile=tile)
+    e_max = 0
+    for c in cams:
+        probe.set_cameras([c])
+        probe.preprocess()
+        e_max = max(e_max, probe.n_entries)
+    del probe
+    cap = int(e_max * 1.1) + 4096
+    rast = Rasterizer(ds, [cams[0]], K=K, capacity=cap, sync_count=False, tile=tile)
 
     # per-view statistics (untimed)
     stats = []
@@ -198,6 +333,10 @@ def main():
         roof = {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": None,
                 "bytes_per_launch": b}
+    tb, tsrc = measured_traffic("k_" + dom)
+    if tb is not None:
+        roof["traffic"] = tb
+        roof["traffic_source"] = tsrc
     fb = frame_bytes(scene.n_voxels, Nv_mean, E_mean, P, S_floats)
     fbytes = sum(fb.values())
     frame_gbs = fbytes / (ms_step / 1e3) / 1e9
@@ -217,7 +356,8 @@ def main():
         "config": {"workload": "fwd+bwd, %d voxels (max level 12, SH degree 3), %dx%d, K=%d, "
                                "explin, %d-view seeded orbit" % (scene.n_voxels, cams[0].W,
                                                                  cams[0].H, K, len(cams)),
-                   "n_voxels": scene.n_voxels, "pixels": P, "entries_mean": E_mean,
+                   "n_voxels": scene.n_voxels, "pixels": P, "entries_mean": E_mean, "tile": tile,
+                   "tile_ms": tile_ms,
                    "in_view_voxels_mean": Nv_mean, "hits_per_pixel": hits_mean / P},
         "frames_per_s": 1e3 / ms_step,
         "frame_hbm": {"bytes": fbytes, "achieved_GBs": frame_gbs, "peak_GBs": HBM_PEAK_GBS,
@@ -225,6 +365,8 @@ def main():
         "roofline": roof,
         "kernels": per_kernel,
     }
+    if not args.no_batched:
+        out["batched"] = batched_comparison(ds, K, log)
     if not args.no_cpu:
         log("timing the oracle on the host ...")
         out["cpu_baseline"] = cpu_baseline(scene, cams[0], K, args.cpu_seconds)

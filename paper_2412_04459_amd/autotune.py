@@ -50,8 +50,6 @@ def tune(ds: DeviceScene, cams: Sequence, K: int, grad_rgba: torch.Tensor,
          log: Optional[Callable[[str], None]] = None) -> Dict:
     n = len(cams)
     cus = torch.cuda.get_device_properties(0).multi_processor_count
-    if persistent is None:
-        persistent = (0, 2 * cus, 4 * cus)
     if groups is None:
         cand = {n, math.ceil(n / 2), math.ceil(n / 3), math.ceil(n / 4), math.ceil(n / 8)}
         groups = sorted(g for g in cand if 1 <= g <= 32)
@@ -69,6 +67,10 @@ def tune(ds: DeviceScene, cams: Sequence, K: int, grad_rgba: torch.Tensor,
 
     g0 = max(groups)
     best_tile = min(tiles, key=lambda t: run(g0, t, 0))
+    if persistent is None:
+        # persistent grids sized in resident waves per SIMD (4 SIMDs per CU)
+        waves_per_wg = max(1, best_tile * best_tile // 64)
+        persistent = [0] + [cus * 4 * w // waves_per_wg for w in (4, 8)]
     best_pers = min(persistent, key=lambda p: (run(g0, best_tile, p) if p else
                                                next(r["ms"] for r in table
                                                     if r["tile"] == best_tile and
