@@ -115,6 +115,43 @@ def measured_traffic(kernel_prefix):
     return None, None
 
 
+def large_scene_run(log):
+    """~8M voxels (max level 14), 16 views at 1920x1080, K = 1, fwd+bwd of all
+    16 views in one batched graph (16x16 tiles, one launch per stage), plus
+    the memory footprint of the duplicated list and of the sort."""
+    import torch
+    from paper_2412_04459_amd import scenes as S
+    from paper_2412_04459_amd.autotune import time_batch
+    from paper_2412_04459_amd.render import BatchRenderer, DeviceScene, Rasterizer
+
+    t0 = time.time()
+    scene = S.large_shells_scene()
+    cams = S.orbit_cameras_1080p()
+    log("large scene: %d voxels, %d grid points (%.0fs)" % (scene.n_voxels, scene.n_grid,
+                                                          time.time() - t0))
+    ds = DeviceScene(scene)
+    del scene
+    P = sum(c.W * c.H for c in cams)
+    grad = torch.from_numpy(S.upstream_grads(P, 4)).cuda()
+    out = {"n_voxels": ds.n_voxels, "views": len(cams), "resolution": "1920x1080", "K": 1}
+    for tile in (8, 16):
+        br = BatchRenderer(ds, cams, 1, group=len(cams), tile=tile, persistent=0)
+        br.capture(grad)
+        ms = time_batch(br, reps=3)
+        r = br.rasts[0]
+        E = r.check_overflow()
+        out["tile%d" % tile] = {
+            "ms": ms, "mpix_s": P / (ms / 1e3) / 1e6, "entries": E,
+            "entries_per_view": E / len(cams),
+            "list_bytes": 2 * E * 12,                 # keys + values, double buffered
+            "workspace_bytes": br.workspace_bytes(), "overflow": E > r.capacity}
+        log("large scene, tile %d: %.1f ms for 16 views (%.0f Mpix/s), E = %d, workspace %.2f GB"
+            % (tile, ms, P / (ms / 1e3) / 1e6, E, br.workspace_bytes() / 1e9))
+        del br
+        torch.cuda.empty_cache()
+    return out
+
+
 def batched_comparison(ds, K, log):
     """24 cameras of uneven resolution over the same scene: 24 single-view
     frames (one fwd+bwd each, eager launches) against the autotuned batched
@@ -188,6 +225,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the 24-camera batched comparison")
+    ap.add_argument("--large", action="store_true",
+                    help="also run the ~8M-voxel scene, 16 views at 1920x1080, batched")
     ap.add_argument("--calibrate", action="store_true",
                     help="run a plain 1 GiB device copy first (counter calibration)")
     args = ap.parse_args()
@@ -367,6 +406,10 @@ def main():
     }
     if not args.no_batched:
         out["batched"] = batched_comparison(ds, K, log)
+    if args.large:
+        del rast
+        torch.cuda.empty_cache()
+        out["large"] = large_scene_run(log)
     if not args.no_cpu:
         log("timing the oracle on the host ...")
         out["cpu_baseline"] = cpu_baseline(scene, cams[0], K, args.cpu_seconds)

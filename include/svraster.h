@@ -79,6 +79,8 @@ typedef struct svr_scene {
   const float* sh;         /* [N][(D+1)^2][3] SH coefficients, basis index l*l+l+m    */
   int32_t sh_degree;       /* D in 0..3                                                */
   int32_t max_level;       /* deepest level present, 1..16                             */
+  const int32_t* grid_adj_off; /* [M+1] optional (NULL: atomics): corner adjacency of   */
+  const int32_t* grid_adj;     /* [8N]  the grid points, see svr_build_grid_adjacency   */
 } svr_scene;
 
 /* Pinhole camera (host memory). */
@@ -227,6 +229,19 @@ int svr_graph_capture(const svr_scene* scene, const svr_camera* cams, int n_cams
                       void** graph_out);
 int svr_graph_launch(void* graph, void* stream);
 int svr_graph_destroy(void* graph);
+
+/* Corner adjacency of the grid points, a property of the scene topology
+ * (build once per vox_grid): for grid point m, adj[adj_off[m] .. adj_off[m+1])
+ * lists, in increasing order, the corner slots 8 v + c whose vox_grid entry is
+ * m.  With it in svr_scene, svr_render_bwd forms grad_grid by a gather in a
+ * fixed order (deterministic, no atomics) instead of scattering with atomics.
+ *   vox_grid  device [N][8] (as in svr_scene); adj_off device [M+1]; adj device
+ *   [8N]; scratch device >= svr_grid_adjacency_scratch_bytes(N, M).
+ * Errors: SVR_E_INVALID, SVR_E_WORKSPACE, SVR_E_HIP.                         */
+size_t svr_grid_adjacency_scratch_bytes(int64_t n_voxels, int64_t n_grid);
+int svr_build_grid_adjacency(const int32_t* vox_grid, int64_t n_voxels, int64_t n_grid,
+                             int32_t* adj_off, int32_t* adj, void* scratch, size_t scratch_bytes,
+                             void* stream);
 
 /* Static text of a status code; detail of the calling thread's last error. */
 const char* svr_status_string(int status);

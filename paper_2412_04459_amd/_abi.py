@@ -35,7 +35,7 @@ I32 = ctypes.c_int32
 class svr_scene(ctypes.Structure):
     _fields_ = [("n_voxels", I64), ("n_grid", I64), ("center", P), ("size", P), ("octpath", P),
                 ("vox_grid", P), ("grid_raw", P), ("sh", P), ("sh_degree", I32),
-                ("max_level", I32)]
+                ("max_level", I32), ("grid_adj_off", P), ("grid_adj", P)]
 
 
 class svr_camera(ctypes.Structure):
@@ -65,6 +65,8 @@ _SIGS = {
                                          P]),
     "svr_graph_launch": (ctypes.c_int, [P, P]),
     "svr_graph_destroy": (ctypes.c_int, [P]),
+    "svr_grid_adjacency_scratch_bytes": (ctypes.c_size_t, [I64, I64]),
+    "svr_build_grid_adjacency": (ctypes.c_int, [P, I64, I64, P, P, P, ctypes.c_size_t, P]),
     "svr_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "svr_last_error": (ctypes.c_char_p, []),
 }
@@ -206,6 +208,16 @@ def svr_graph_launch(graph, stream):
 
 def svr_graph_destroy(graph):
     return load().svr_graph_destroy(graph)
+
+
+def svr_grid_adjacency_scratch_bytes(n_voxels, n_grid):
+    return load().svr_grid_adjacency_scratch_bytes(n_voxels, n_grid)
+
+
+def svr_build_grid_adjacency(vox_grid, n_voxels, n_grid, adj_off, adj, scratch, scratch_bytes,
+                             stream):
+    return load().svr_build_grid_adjacency(vox_grid, n_voxels, n_grid, adj_off, adj, scratch,
+                                           scratch_bytes, stream)
 
 
 def svr_status_string(status):

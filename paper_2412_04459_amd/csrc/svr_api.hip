@@ -532,6 +532,35 @@ int svr_graph_destroy(void* graph) {
   return SVR_OK;
 }
 
+size_t svr_grid_adjacency_scratch_bytes(int64_t n_voxels, int64_t n_grid) {
+  if (n_voxels < 0 || n_voxels >= (int64_t)SVR_MAX_VOXELS || n_grid < 0 || n_grid >= ((int64_t)1 << 31))
+    return 0;
+  return grid_adjacency_scratch_bytes(n_voxels, n_grid) + 256;
+}
+
+int svr_build_grid_adjacency(const int32_t* vox_grid, int64_t n_voxels, int64_t n_grid,
+                             int32_t* adj_off, int32_t* adj, void* scratch, size_t scratch_bytes,
+                             void* stream) {
+  if (n_voxels < 0 || n_voxels >= (int64_t)SVR_MAX_VOXELS)
+    return fail(SVR_E_INVALID, "n_voxels outside [0, 2^29)");
+  if (n_grid < 0 || n_grid >= ((int64_t)1 << 31)) return fail(SVR_E_INVALID, "n_grid out of range");
+  if (!adj_off || (n_voxels > 0 && (!vox_grid || !adj || !scratch)))
+    return fail(SVR_E_INVALID, "null pointer");
+  if ((reinterpret_cast<uintptr_t>(scratch) & 255u) != 0)
+    return fail(SVR_E_INVALID, "scratch must be 256-byte aligned");
+  const size_t need = svr_grid_adjacency_scratch_bytes(n_voxels, n_grid);
+  if (scratch_bytes < need)
+    return fail(SVR_E_WORKSPACE, "scratch has %zu bytes, %zu needed", scratch_bytes, need);
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  if (n_voxels == 0) {
+    SVR_HIP(launch_fill_u32(reinterpret_cast<uint32_t*>(adj_off), 0u, n_grid + 1, s), "clear offsets");
+    return SVR_OK;
+  }
+  SVR_HIP(launch_grid_adjacency(vox_grid, n_voxels, n_grid, adj_off, adj, scratch, s),
+          "grid adjacency");
+  return SVR_OK;
+}
+
 const char* svr_status_string(int status) {
   switch (status) {
     case SVR_OK: return "ok";

@@ -124,6 +124,9 @@ hipError_t launch_radix_sort(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t*
                              uint32_t* hist, uint32_t* st0, uint32_t* st1, uint32_t* tickets,
                              uint32_t* err, bool* result_in_1, hipStream_t s);
 hipError_t launch_tile_ranges(const Layout& L, void* ws, const uint64_t* keys, hipStream_t s);
+hipError_t launch_grid_adjacency(const int32_t* vox_grid, int64_t N, int64_t M, int32_t* adj_off,
+                                 int32_t* adj, void* scratch, hipStream_t s);
+size_t grid_adjacency_scratch_bytes(int64_t N, int64_t M);
 // render
 hipError_t launch_render_fwd(const svr_scene& sc, const CamSet& cams, const svr_opts& o,
                              const Layout& L, void* ws, const uint32_t* vals, float* rgba,

@@ -84,6 +84,7 @@ struct LdsBatch {
   float cr[NB], cg[NB], cb[NB];        // colour
   uint32_t meta[NB];                   // sign bits | block mask << 3
   uint32_t vid[NB];
+  uint32_t rx[NB], ry[NB];             // pixel rectangle: u0 | u1 << 16, v0 | v1 << 16
 };
 
 // arguments shared by the render kernels
@@ -166,6 +167,8 @@ __device__ __forceinline__ void stage_entry(LdsBatch<NB>& B, int slot, uint32_t 
   B.cr[slot] = R.q3.x; B.cg[slot] = R.q3.y; B.cb[slot] = R.q3.z;
   B.meta[slot] = (val >> kVidBits) | (qm << 3);
   B.vid[slot] = vid;
+  B.rx[slot] = rc.x;
+  B.ry[slot] = rc.y;
 }
 
 // Ray-box slab test (Supp. A.2 listing "ray_aabb") against staged entry j, in
@@ -235,8 +238,8 @@ __device__ __forceinline__ PixelRay make_ray(const DevCam& c, int qu0, int qv0, 
 // optical depth of staged entry j on the ray over [a, b]; with DW also the
 // sums sum_k act'(v_k) w_m(q_k) of the 8 corner weights
 template <int KT, int ACT, bool DW, int NB>
-__device__ __forceinline__ float segment_x(const LdsBatch<NB>& B, int j, const PixelRay& r,
-                                           double a, double lseg, int Krt, float* dw) {
+__device__ __forceinline__ float segment_x(const LdsBatch<NB>& B, int j, double dx, double dy,
+                                           double dz, double a, double lseg, int Krt, float* dw) {
   const int K = KT > 0 ? KT : Krt;
   const double step = 1.0 / (double)K;
   float x = 0.f;
@@ -245,7 +248,7 @@ __device__ __forceinline__ float segment_x(const LdsBatch<NB>& B, int j, const P
     if (KT == 0 && k >= K) break;
     const double t = fma(((double)k + 0.5) * step, lseg, a);
     float qx, qy, qz;
-    local_coord(B, j, t, r.dx, r.dy, r.dz, qx, qy, qz);
+    local_coord(B, j, t, dx, dy, dz, qx, qy, qz);
     const float vk = trilerp(B, j, qx, qy, qz);
     x += act_f<ACT>(vk);
     if (DW) {
@@ -262,14 +265,56 @@ __device__ __forceinline__ float segment_x(const LdsBatch<NB>& B, int j, const P
 }
 
 // ---------------------------------------------------------------------------
+// Forward, dense form.  Hits are sparse in a wave (a voxel a few pixels wide
+// covers a handful of the 64 pixels of a block), so the per-hit work is not
+// run entry by entry with most lanes idle.  Per staged batch, each wave
+//   A. walks the entries touching its block once: lanes whose pixel lies in
+//      the voxel's projected rectangle (and whose sign pattern matches, and
+//      which have not terminated) append the entry to their own list, and a
+//      wave-wide task queue records (lane, list slot) in entry order;
+//   B. takes the queued candidates 64 at a time, one per lane: the fp64
+//      ray-box test with the owning pixel's ray and, for a hit, the optical
+//      depth x over K samples (written back to the owner's list, -1 on a
+//      miss);
+//   C. lets every lane composite its own list in entry order (the only
+//      sequential part: a few operations per hit).
+// A lane list holding kListCap candidates triggers B and C early, so order
+// and early termination are those of the plain per-pixel walk.
+template <int TS>
+struct DenseCfg {
+  static constexpr int kListCap = TS == 32 ? 8 : 16;
+};
+
+template <int CAP>
+struct WaveLists {
+  uint16_t queue[64 * CAP];  // task -> owner lane << 8 | list slot
+  uint8_t jl[CAP][64];       // staged entry index of a lane's candidate
+  float xl[CAP][64];         // its optical depth (< 0: the ray misses the box)
+  double d[3][64];           // lane ray direction (fp64)
+  double id[3][64];          // and its reciprocal
+};
+
+__device__ __forceinline__ uint32_t lane_rank(unsigned long long mask) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                   __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // STATS: count, per frame, the (pixel, entry) pairs of matching sign pattern
-// the method walks, the ray-box tests this kernel executes after its block
-// culling, and the composited hits (into stats[0..2]); no outputs.
+// the method walks, the ray-box tests this kernel executes (candidates after
+// the rectangle test), and the composited hits (into stats[0..2]); no outputs.
 template <int TS, int KT, int ACT, bool STATS>
 __device__ __forceinline__ void render_tile_fwd(const RenderArgs& A, int g,
-                                                LdsBatch<TileGeom<TS>::kBatch>& B) {
+                                                LdsBatch<TileGeom<TS>::kBatch>& B,
+                                                WaveLists<DenseCfg<TS>::kListCap>* WLs) {
   using G = TileGeom<TS>;
   constexpr int NB = G::kBatch;
+  constexpr int CAP = DenseCfg<TS>::kListCap;
   const int ci = find_cam_r(A.cams, g);
   const DevCam& c = A.cams.c[ci];
   const int tl = g - c.tile_off;
@@ -277,6 +322,9 @@ __device__ __forceinline__ void render_tile_fwd(const RenderArgs& A, int g,
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int qu0 = tx * TS, qv0 = ty * TS;
   const PixelRay r = make_ray<TS>(c, qu0, qv0, w, lane);
+  WaveLists<CAP>& WL = WLs[w];
+  WL.d[0][lane] = r.dx; WL.d[1][lane] = r.dy; WL.d[2][lane] = r.dz;
+  WL.id[0][lane] = r.idx; WL.id[1][lane] = r.idy; WL.id[2][lane] = r.idz;
 
   const uint2 rg = A.range[g];
   const uint32_t start = rg.x, end = rg.y;
@@ -284,30 +332,74 @@ __device__ __forceinline__ void render_tile_fwd(const RenderArgs& A, int g,
   uint32_t last = start;
   bool done = !r.inside;
   uint32_t n_pairs = 0, n_tests = 0, n_hits = 0;
+  const uint32_t u = (uint32_t)r.u, v = (uint32_t)r.v;
+
   for (uint32_t b0 = start; b0 < end; b0 += NB) {
     const uint32_t i = b0 + tid;
     if (tid < NB && i < end) stage_entry<TS>(B, tid, A.vals[i], ci, A.n_cams, c, A.rec, A.rect, qu0, qv0);
     __syncthreads();
     const int n = (int)min((uint32_t)NB, end - b0);
+    int cnt = 0;    // this lane's list length
+    uint32_t nq = 0;  // queue length (wave-uniform)
+    auto flush = [&]() {
+      wave_sync_lds();
+      // B: candidates, one per lane
+      for (uint32_t t = lane; t < nq; t += 64) {
+        const uint32_t q = WL.queue[t];
+        const int ow = (int)(q >> 8), k = (int)(q & 0xffu);
+        const int j = WL.jl[k][ow];
+        double a, bb;
+        float x = -1.f;
+        if (slab(B, j, WL.id[0][ow], WL.id[1][ow], WL.id[2][ow], a, bb))
+          x = segment_x<KT, ACT, false>(B, j, WL.d[0][ow], WL.d[1][ow], WL.d[2][ow], a, bb - a,
+                                        A.K, nullptr);
+        WL.xl[k][ow] = x;
+        if (STATS) ++n_tests;
+      }
+      wave_sync_lds();
+      // C: each lane composites its own list in entry order
+      for (int k = 0; k < CAP; ++k) {
+        if (__ballot(k < cnt) == 0ull) break;
+        if (k < cnt && !done) {
+          const float x = WL.xl[k][lane];
+          if (x >= 0.f) {
+            const int j = WL.jl[k][lane];
+            const float wgt = Tr * alpha_of(x);
+            C0 = __fmaf_rn(wgt, B.cr[j], C0);
+            C1 = __fmaf_rn(wgt, B.cg[j], C1);
+            C2 = __fmaf_rn(wgt, B.cb[j], C2);
+            tau += x;
+            Tr = __expf(-tau);
+            last = b0 + (uint32_t)j + 1u;
+            if (STATS) ++n_hits;
+            if (Tr < A.t_stop) done = true;
+          }
+        }
+      }
+      wave_sync_lds();
+      cnt = 0;
+      nq = 0;
+    };
+    // A: candidate lists
     for (int j = 0; j < n; ++j) {
       const uint32_t meta = __builtin_amdgcn_readfirstlane(B.meta[j]);
       if (STATS && !done && (meta & 7u) == r.spat) ++n_pairs;
       if (!((meta >> (3 + w)) & 1u)) continue;
-      if (done || (meta & 7u) != r.spat) continue;
-      double a, bb;
-      if (STATS) ++n_tests;
-      if (!slab(B, j, r.idx, r.idy, r.idz, a, bb)) continue;
-      if (STATS) ++n_hits;
-      const float x = segment_x<KT, ACT, false>(B, j, r, a, bb - a, A.K, nullptr);
-      const float wgt = Tr * alpha_of(x);
-      C0 = __fmaf_rn(wgt, B.cr[j], C0);
-      C1 = __fmaf_rn(wgt, B.cg[j], C1);
-      C2 = __fmaf_rn(wgt, B.cb[j], C2);
-      tau += x;
-      Tr = __expf(-tau);
-      last = b0 + (uint32_t)j + 1u;
-      if (Tr < A.t_stop) done = true;
+      const uint32_t rx = __builtin_amdgcn_readfirstlane(B.rx[j]);
+      const uint32_t ry = __builtin_amdgcn_readfirstlane(B.ry[j]);
+      const bool cand = !done && (meta & 7u) == r.spat && u >= (rx & 0xffffu) && u <= (rx >> 16) &&
+                        v >= (ry & 0xffffu) && v <= (ry >> 16);
+      const unsigned long long m = __ballot(cand);
+      if (m == 0ull) continue;
+      if (cand) {
+        WL.queue[nq + lane_rank(m)] = (uint16_t)((lane << 8) | cnt);
+        WL.jl[cnt][lane] = (uint8_t)j;
+        ++cnt;
+      }
+      nq += (uint32_t)__popcll(m);
+      if (__ballot(cnt == CAP) != 0ull) flush();
     }
+    if (nq > 0) flush();
     if (__syncthreads_and(done)) break;
   }
   if (STATS) {
@@ -336,10 +428,11 @@ __device__ __forceinline__ void render_tile_fwd(const RenderArgs& A, int g,
 template <int TS, int KT, int ACT, bool STATS>
 __global__ __launch_bounds__(TS * TS) void k_render_fwd(RenderArgs A) {
   __shared__ LdsBatch<TileGeom<TS>::kBatch> B;
+  __shared__ WaveLists<DenseCfg<TS>::kListCap> WL[TileGeom<TS>::kWaves];
   __shared__ int s_tile;
   if (!A.persistent) {
     const int g = xcd_tile(blockIdx.x, A.T);
-    if (g < A.T) render_tile_fwd<TS, KT, ACT, STATS>(A, g, B);
+    if (g < A.T) render_tile_fwd<TS, KT, ACT, STATS>(A, g, B, WL);
     return;
   }
   while (true) {
@@ -347,7 +440,7 @@ __global__ __launch_bounds__(TS * TS) void k_render_fwd(RenderArgs A) {
     __syncthreads();
     const int g = s_tile;
     if (g < 0) break;
-    render_tile_fwd<TS, KT, ACT, STATS>(A, g, B);
+    render_tile_fwd<TS, KT, ACT, STATS>(A, g, B, WL);
     __syncthreads();
   }
 }
@@ -467,7 +560,7 @@ __device__ __forceinline__ void render_tile_bwd(const RenderArgs& A, int g,
       if (hit) {
         float dw[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
         const double lseg = bb - a;
-        const float x = segment_x<KT, ACT, true>(B, j, r, a, lseg, A.K, dw);
+        const float x = segment_x<KT, ACT, true>(B, j, r.dx, r.dy, r.dz, a, lseg, A.K, dw);
         const float lK = (float)lseg / (float)(KT > 0 ? KT : A.K);
         const float alpha = alpha_of(x);
         const float Tnext = __expf(-tau);
@@ -526,7 +619,7 @@ __global__ __launch_bounds__(kBlock) void k_sh_bwd(
     const int32_t* __restrict__ vox_grid, const uint32_t* __restrict__ count,
     const VoxRec* __restrict__ rec, const float* __restrict__ g_rgb,
     const float* __restrict__ g_corner, float* __restrict__ grad_grid, float* __restrict__ grad_sh,
-    int accumulate) {
+    int accumulate, int scatter) {
   constexpr int NB = (D + 1) * (D + 1);
   constexpr int F = 3 * NB;
   constexpr int FP = F | 1;
@@ -574,7 +667,7 @@ __global__ __launch_bounds__(kBlock) void k_sh_bwd(
       for (int i = threadIdx.x; i < nv * F; i += kBlock) o[i] = stage[(i / F) * FP + (i % F)];
     }
   }
-  if (grad_grid && vid < N) {
+  if (grad_grid && scatter && vid < N) {
     const float4* gc = reinterpret_cast<const float4*>(g_corner + vid * 8);
     const float4 ga = gc[0], gb = gc[1];
     const float gv[8] = {ga.x, ga.y, ga.z, ga.w, gb.x, gb.y, gb.z, gb.w};
@@ -697,26 +790,48 @@ hipError_t launch_render_bwd(const svr_scene& sc, const CamSet& cams, const svr_
   return launch_render(RKind::kBwd, A, o, L, ws, s);
 }
 
+// grad_grid[m] = sum of the corner gradients of the corner slots sharing grid
+// point m, in the adjacency's fixed order (no atomics)
+__global__ __launch_bounds__(kBlock) void k_grid_gather(int64_t M, const int32_t* __restrict__ off,
+                                                        const int32_t* __restrict__ adj,
+                                                        const float* __restrict__ g_corner,
+                                                        float* __restrict__ grad_grid,
+                                                        int accumulate) {
+  const int64_t m = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (m >= M) return;
+  float acc = 0.f;
+  const int32_t e1 = off[m + 1];
+  for (int32_t e = off[m]; e < e1; ++e) acc += g_corner[adj[e]];
+  grad_grid[m] = accumulate ? grad_grid[m] + acc : acc;
+}
+
 hipError_t launch_sh_bwd(const svr_scene& sc, const CamSet& cams, const Layout& L, void* ws,
                          float* grad_grid, float* grad_sh, bool accumulate, hipStream_t s) {
-  if (grad_grid && !accumulate) {
+  const bool gather = sc.grid_adj_off != nullptr && sc.grid_adj != nullptr;
+  if (grad_grid && !accumulate && !gather) {
     hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(grad_grid), 0u, sc.n_grid, s);
     if (e != hipSuccess) return e;
   }
-  if (L.N == 0) return hipSuccess;
-  const dim3 grid((unsigned)((L.N + kBlock - 1) / kBlock));
+  if (L.N > 0) {
+    const dim3 grid((unsigned)((L.N + kBlock - 1) / kBlock));
 #define SVR_SHB(D)                                                                             \
   SVR_LAUNCH("sh_bwd", k_sh_bwd<D>, grid, dim3(kBlock), 0, s, L.N, L.n_cams, cams, sc.center,   \
              sc.vox_grid, at<uint32_t>(ws, L.count), at<VoxRec>(ws, L.rec),                     \
              at<float>(ws, L.g_rgb), at<float>(ws, L.g_corner), grad_grid, grad_sh,            \
-             accumulate ? 1 : 0)
-  switch (sc.sh_degree) {
-    case 0: SVR_SHB(0); break;
-    case 1: SVR_SHB(1); break;
-    case 2: SVR_SHB(2); break;
-    default: SVR_SHB(3); break;
-  }
+             accumulate ? 1 : 0, gather ? 0 : 1)
+    switch (sc.sh_degree) {
+      case 0: SVR_SHB(0); break;
+      case 1: SVR_SHB(1); break;
+      case 2: SVR_SHB(2); break;
+      default: SVR_SHB(3); break;
+    }
 #undef SVR_SHB
+  }
+  if (grad_grid && gather && sc.n_grid > 0) {
+    SVR_LAUNCH("grid_gather", k_grid_gather, dim3((unsigned)((sc.n_grid + kBlock - 1) / kBlock)),
+               dim3(kBlock), 0, s, sc.n_grid, sc.grid_adj_off, sc.grid_adj,
+               at<float>(ws, L.g_corner), grad_grid, accumulate ? 1 : 0);
+  }
   return hipGetLastError();
 }
 

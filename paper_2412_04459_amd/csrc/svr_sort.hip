@@ -301,4 +301,75 @@ hipError_t launch_tile_ranges(const Layout& L, void* ws, const uint64_t* keys, h
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// corner adjacency of the grid points: sort (grid index, corner slot) pairs by
+// grid index (stable, so slots stay increasing), then mark where each grid
+// point's run starts
+__global__ __launch_bounds__(kBlock) void k_adj_pairs(const int32_t* __restrict__ vox_grid,
+                                                      int64_t n8, uint64_t* __restrict__ keys,
+                                                      uint32_t* __restrict__ vals) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n8) return;
+  keys[i] = (uint64_t)(uint32_t)vox_grid[i];
+  vals[i] = (uint32_t)i;
+}
+
+__global__ __launch_bounds__(kBlock) void k_adj_offsets(const uint64_t* __restrict__ keys,
+                                                        int64_t n8, int64_t M,
+                                                        int32_t* __restrict__ off) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i > n8) return;
+  // grid points strictly between the previous key and this one start here
+  const int64_t lo = i == 0 ? -1 : (int64_t)keys[i - 1];
+  const int64_t hi = i == n8 ? M : min((int64_t)keys[i], M);
+  for (int64_t m = lo + 1; m <= hi && m <= M; ++m) off[m] = (int32_t)i;
+}
+
+hipError_t launch_grid_adjacency(const int32_t* vox_grid, int64_t N, int64_t M, int32_t* adj_off,
+                                 int32_t* adj, void* scratch, hipStream_t s) {
+  const int64_t n8 = 8 * N;
+  int bits = 1;
+  while (bits < 32 && ((int64_t)1 << bits) <= M) ++bits;
+  int64_t parts = 0;
+  const size_t sb = sort_scratch_bytes(n8, bits, &parts);
+  char* p = reinterpret_cast<char*>(scratch);
+  auto take = [&](size_t b) { char* q = p; p += (b + 255) / 256 * 256; return q; };
+  uint64_t* k0 = reinterpret_cast<uint64_t*>(take((size_t)n8 * 8));
+  uint64_t* k1 = reinterpret_cast<uint64_t*>(take((size_t)n8 * 8));
+  uint32_t* v1 = reinterpret_cast<uint32_t*>(take((size_t)n8 * 4));
+  uint32_t* base = reinterpret_cast<uint32_t*>(take(sb + 256));
+  auto* n_dev = reinterpret_cast<unsigned long long*>(base);
+  uint32_t* hist = base + 64;
+  uint32_t* st0 = hist + 8 * kRadix;
+  uint32_t* st1 = st0 + (parts > 0 ? parts : 1) * kRadix;
+  uint32_t* v0 = reinterpret_cast<uint32_t*>(adj);
+  hipError_t e;
+  if ((e = launch_fill_u32(base, 0u, 64, s)) != hipSuccess) return e;
+  if ((e = launch_fill_u32(base, (uint32_t)(n8 & 0xffffffffu), 1, s)) != hipSuccess) return e;
+  if ((e = launch_fill_u32(base + 1, (uint32_t)(n8 >> 32), 1, s)) != hipSuccess) return e;
+  const unsigned grid = (unsigned)((n8 + kBlock - 1) / kBlock);
+  SVR_LAUNCH("adj_pairs", k_adj_pairs, dim3(grid), dim3(kBlock), 0, s, vox_grid, n8, k0, v0);
+  bool in1 = false;
+  if ((e = launch_radix_sort(k0, v0, k1, v1, n_dev, n8, bits, hist, st0, st1, base + 2, base + 18,
+                             &in1, s)) != hipSuccess)
+    return e;
+  const uint64_t* ks = in1 ? k1 : k0;
+  if (in1) {
+    if ((e = hipMemcpyAsync(adj, v1, (size_t)n8 * 4, hipMemcpyDeviceToDevice, s)) != hipSuccess)
+      return e;
+  }
+  SVR_LAUNCH("adj_offsets", k_adj_offsets, dim3((unsigned)((n8 + kBlock) / kBlock)), dim3(kBlock),
+             0, s, ks, n8, M, adj_off);
+  return hipGetLastError();
+}
+
+size_t grid_adjacency_scratch_bytes(int64_t N, int64_t M) {
+  const int64_t n8 = 8 * N;
+  int bits = 1;
+  while (bits < 32 && ((int64_t)1 << bits) <= M) ++bits;
+  const size_t r = 256;
+  auto up = [&](size_t b) { return (b + r - 1) / r * r; };
+  return up((size_t)n8 * 8) * 2 + up((size_t)n8 * 4) + up(sort_scratch_bytes(n8, bits, nullptr) + 256);
+}
+
 }  // namespace svr

@@ -28,7 +28,7 @@ def _stream():
 class DeviceScene:
     """Scene arrays resident in device memory (layouts as in svr_scene)."""
 
-    def __init__(self, scene, device="cuda"):
+    def __init__(self, scene, device="cuda", grid_adjacency: bool = True):
         if not torch.cuda.is_available():
             raise RuntimeError("DeviceScene needs a HIP device")
         dev = torch.device(device)
@@ -44,6 +44,24 @@ class DeviceScene:
         self.grid_raw = torch.from_numpy(np.ascontiguousarray(scene.grid_raw, np.float32)).to(dev)
         self.sh = torch.from_numpy(np.ascontiguousarray(scene.sh, np.float32)).to(dev)
         self.device = self.grid_raw.device
+        self.adj_off = self.adj = None
+        if grid_adjacency:
+            self.build_adjacency()
+
+    def build_adjacency(self):
+        """Corner adjacency of the grid points (svr_build_grid_adjacency): makes the
+        grid gradient a deterministic gather instead of atomics."""
+        off = torch.empty(self.n_grid + 1, dtype=torch.int32, device=self.device)
+        adj = torch.empty(max(1, 8 * self.n_voxels), dtype=torch.int32, device=self.device)
+        nb = _abi.svr_grid_adjacency_scratch_bytes(self.n_voxels, self.n_grid)
+        scratch = torch.empty(nb + 256, dtype=torch.uint8, device=self.device)
+        p = (scratch.data_ptr() + 255) // 256 * 256
+        check(_abi.svr_build_grid_adjacency(_ptr(self.vox_grid), self.n_voxels, self.n_grid,
+                                            _ptr(off), _ptr(adj), ctypes.c_void_p(p), nb,
+                                            _stream()), "svr_build_grid_adjacency")
+        torch.cuda.current_stream().synchronize()
+        del scratch
+        self.adj_off, self.adj = off, adj
 
     def struct(self, grid_raw: Optional[torch.Tensor] = None,
                sh: Optional[torch.Tensor] = None) -> _abi.svr_scene:
@@ -65,6 +83,9 @@ class DeviceScene:
         st.sh = s.data_ptr()
         st.sh_degree = self.sh_degree
         st.max_level = self.max_level
+        if self.adj_off is not None:
+            st.grid_adj_off = self.adj_off.data_ptr()
+            st.grid_adj = self.adj.data_ptr()
         return st
 
 

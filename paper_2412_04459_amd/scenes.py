@@ -380,6 +380,25 @@ def orbit_cameras_1297x840(n=36, seed=2, W=1297, H=840) -> List[Camera]:
     return orbit_cameras(n, W, H, 60.0, 2.0, 8.5, phase)
 
 
+def large_shells_scene(seed=4, kappa=0.875, n_spheres=3) -> Scene:
+    """~8M leaves in [-8,8]^3, max level 14: three level-14 sphere shells
+    (radii U(0.25, 0.4)) plus the sparse background shell of levels 4..7 for
+    radius 2.5..8; SH degree 3 ~ N(0, 0.2)."""
+    rng = np.random.default_rng(np.random.SeedSequence(seed).spawn(6)[0])
+    cs = rng.uniform(-0.7, 0.7, size=(n_spheres, 3))
+    rs = rng.uniform(0.25, 0.4, size=n_spheres)
+    surf = [Sphere(tuple(c), float(r), 14) for c, r in zip(cs, rs)]
+    bg = Background(2.5, 8.0, 4, 7, 0.5)
+    return make_scene((0.0, 0.0, 0.0), 16.0, 14, surf, kappa=kappa, background=bg, sh_degree=3,
+                      sh_mode="normal", sh_std=0.2, seed=seed)
+
+
+def orbit_cameras_1080p(n=16, seed=4) -> List[Camera]:
+    rng = np.random.default_rng(np.random.SeedSequence(seed).spawn(6)[3])
+    phase = float(rng.uniform(0, 2 * math.pi))
+    return orbit_cameras(n, 1920, 1080, 60.0, 2.0, 8.5, phase)
+
+
 def mixed_resolution_cameras(n=24, seed=3) -> List[Camera]:
     rng = np.random.default_rng(np.random.SeedSequence(seed).spawn(6)[3])
     phase = float(rng.uniform(0, 2 * math.pi))
@@ -484,7 +503,8 @@ def camera_from_pose(W, H, fx, fy, cx, cy, R, t) -> Camera:
 
 def workload(name: str, **kw) -> Workload:
     """Named workloads: "sphere_shell_3k", "sphere_shell_3k_opaque",
-    "spheres_plane_184k", "orbit_1m_1297x840", "mixed_24cams_1m"."""
+    "spheres_plane_184k", "orbit_1m_1297x840", "mixed_24cams_1m",
+    "large_8m_16x1080p"."""
     if name == "sphere_shell_3k":
         return Workload(name, sphere_shell_scene(**kw), [sphere_shell_camera()], K=1, grad_seed=0)
     if name == "sphere_shell_3k_opaque":
@@ -496,6 +516,8 @@ def workload(name: str, **kw) -> Workload:
     if name == "orbit_1m_1297x840":
         return Workload(name, spheres_background_scene(**kw), orbit_cameras_1297x840(), K=2,
                         grad_seed=2)
+    if name == "large_8m_16x1080p":
+        return Workload(name, large_shells_scene(**kw), orbit_cameras_1080p(), K=1, grad_seed=4)
     if name == "mixed_24cams_1m":
         return Workload(name, spheres_background_scene(**kw), mixed_resolution_cameras(), K=2,
                         grad_seed=3)

@@ -154,3 +154,35 @@ def test_autotuner_runs_and_picks_a_measured_candidate(torch_dev):
     assert res["tile"] in (8, 16) and res["group"] in (1, 2, 3)
     assert any(r["tile"] == res["tile"] and r["group"] == res["group"] and
                r["persistent"] == res["persistent"] for r in res["table"])
+
+
+def test_grid_adjacency_and_gather_path(torch_dev):
+    """The corner adjacency lists, for every grid point, exactly the corner
+    slots that reference it (increasing); the gather path of the grid gradient
+    equals the atomic path to rounding (the per-voxel corner gradients still
+    come from float atomics, so neither is bit-reproducible run to run)."""
+    torch = torch_dev
+    from paper_2412_04459_amd.render import DeviceScene, Rasterizer
+    scene = S.spheres_plane_scene()
+    cam = S.spheres_plane_camera()
+    ds = DeviceScene(scene, grid_adjacency=True)
+    off = ds.adj_off.cpu().numpy().astype(np.int64)
+    adj = ds.adj.cpu().numpy().astype(np.int64)
+    vg = scene.vox_grid.reshape(-1).astype(np.int64)
+    order = np.argsort(vg, kind="stable")
+    assert off[0] == 0 and off[-1] == vg.size
+    assert np.array_equal(adj, order)
+    assert np.array_equal(np.diff(off), np.bincount(vg, minlength=scene.n_grid))
+    g = torch.from_numpy(S.upstream_grads(cam.W * cam.H, 11)).cuda()
+    r1 = Rasterizer(ds, [cam], K=1)
+    r1.forward()
+    ga, sa = r1.backward(g)
+    gb, sb = r1.backward(g)
+    torch.cuda.synchronize()
+    assert _grad_close(ga, gb)
+    ds_atomic = DeviceScene(scene, grid_adjacency=False)
+    r2 = Rasterizer(ds_atomic, [cam], K=1)
+    r2.forward()
+    gc, sc = r2.backward(g)
+    torch.cuda.synchronize()
+    assert _grad_close(ga, gc) and _grad_close(sa, sc)
