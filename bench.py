@@ -141,10 +141,11 @@ def large_scene_run(log):
         r = br.rasts[0]
         E = r.check_overflow()
         out["tile%d" % tile] = {
-            "ms": ms, "mpix_s": P / (ms / 1e3) / 1e6, "entries": E,
-            "entries_per_view": E / len(cams),
-            "list_bytes": 2 * E * 12,                 # keys + values, double buffered
-            "workspace_bytes": br.workspace_bytes(), "overflow": E > r.capacity}
+            "ms": ms, "mpix_s": P / (ms / 1e3) / 1e6, "frames_per_s": len(cams) / (ms / 1e3),
+            "entries": E, "entries_per_view": E / len(cams),
+            "list_bytes_at_E": 2 * E * 12,            # keys + values, double buffered
+            "workspace_bytes": br.workspace_bytes(), "workspace_parts": br.workspace_parts(),
+            "scene_bytes": ds.nbytes(), "overflow": E > r.capacity}
         log("large scene, tile %d: %.1f ms for 16 views (%.0f Mpix/s), E = %d, workspace %.2f GB"
             % (tile, ms, P / (ms / 1e3) / 1e6, E, br.workspace_bytes() / 1e9))
         del br

@@ -50,6 +50,7 @@ class svr_opts(ctypes.Structure):
 
 _SIGS = {
     "svr_workspace_bytes": (ctypes.c_size_t, [P, P, ctypes.c_int, P]),
+    "svr_workspace_parts": (ctypes.c_int, [P, P, ctypes.c_int, P, P, ctypes.c_int]),
     "svr_preprocess": (ctypes.c_int, [P, P, ctypes.c_int, P, P, ctypes.c_size_t, P, P]),
     "svr_sort": (ctypes.c_int, [P, P, ctypes.c_int, P, P, ctypes.c_size_t, I64, P]),
     "svr_render_fwd": (ctypes.c_int, [P, P, ctypes.c_int, P, P, ctypes.c_size_t, P, P]),
@@ -127,6 +128,20 @@ def check(status, where):
 # -- thin pass-throughs with the C names --------------------------------------
 def svr_workspace_bytes(scene, cams, n_cams, opts):
     return load().svr_workspace_bytes(_ref(scene), cams, n_cams, _ref(opts))
+
+
+SVR_WS_PARTS = 7
+WS_PART_NAMES = ("header_and_tile_tables", "per_voxel_camera_records", "scan_partials",
+                 "keys_values_x2", "sort_histograms_and_status", "per_pixel_state",
+                 "gradient_scratch")
+
+
+def svr_workspace_parts(scene, cams, n_cams, opts):
+    """Workspace bytes by purpose, as a dict keyed by WS_PART_NAMES."""
+    arr = (ctypes.c_size_t * SVR_WS_PARTS)()
+    check(load().svr_workspace_parts(_ref(scene), cams, n_cams, _ref(opts), arr, SVR_WS_PARTS),
+          "svr_workspace_parts")
+    return dict(zip(WS_PART_NAMES, (int(x) for x in arr)))
 
 
 def svr_preprocess(scene, cams, n_cams, opts, ws, ws_bytes, n_entries_out, stream):

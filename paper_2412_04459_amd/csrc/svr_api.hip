@@ -222,6 +222,28 @@ size_t svr_workspace_bytes(const svr_scene* scene, const svr_camera* cams, int n
   return L.total;
 }
 
+int svr_workspace_parts(const svr_scene* scene, const svr_camera* cams, int n_cams,
+                        const svr_opts* opts, size_t* parts, int n_parts) {
+  Layout L;
+  CamSet cs;
+  int st = make_layout(scene, cams, n_cams, opts, &L, &cs);
+  if (st != SVR_OK) return st;
+  if (!parts || n_parts < 0) return fail(SVR_E_INVALID, "null parts array");
+  // region boundaries in layout order; each part is the span between them
+  const size_t b[] = {L.hdr,       L.count,        L.scan_part,    L.tile_mask, L.keys0,
+                      L.sort_hist, L.px_tau,       L.g_corner,     L.total};
+  size_t v[SVR_WS_PARTS] = {0};
+  v[0] = (b[1] - b[0]) + (b[4] - b[3]);  // header + tile tables
+  v[1] = b[2] - b[1];                    // per (voxel, camera)
+  v[2] = b[3] - b[2];                    // scan partials
+  v[3] = b[5] - b[4];                    // keys + values, two buffers
+  v[4] = b[6] - b[5];                    // sort histograms + status
+  v[5] = b[7] - b[6];                    // per-pixel state
+  v[6] = b[8] - b[7];                    // gradient scratch
+  for (int i = 0; i < n_parts && i < SVR_WS_PARTS; ++i) parts[i] = v[i];
+  return SVR_OK;
+}
+
 int svr_preprocess(const svr_scene* scene, const svr_camera* cams, int n_cams,
                    const svr_opts* opts, void* ws, size_t ws_bytes, int64_t* n_entries_out,
                    void* stream) {

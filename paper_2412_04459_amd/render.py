@@ -63,6 +63,12 @@ class DeviceScene:
         del scratch
         self.adj_off, self.adj = off, adj
 
+    def nbytes(self) -> int:
+        """Device bytes of the scene arrays (adjacency included)."""
+        ts = [self.center, self.size, self.octpath, self.vox_grid, self.grid_raw, self.sh,
+              self.adj_off, self.adj]
+        return int(sum(t.numel() * t.element_size() for t in ts if t is not None))
+
     def struct(self, grid_raw: Optional[torch.Tensor] = None,
                sh: Optional[torch.Tensor] = None) -> _abi.svr_scene:
         g = self.grid_raw if grid_raw is None else grid_raw
@@ -153,6 +159,10 @@ class Rasterizer:
             self.ws = torch.empty(nb + 256, dtype=torch.uint8, device=self.ds.device)
             self.ws_bytes = nb
         self.capacity = cap
+
+    def workspace_parts(self) -> dict:
+        """Bytes of this frame's workspace by purpose (svr_workspace_parts)."""
+        return _abi.svr_workspace_parts(self.ds.struct(), self.cam_arr, self.n_cams, self.opts)
 
     def _ws_ptr(self):
         p = self.ws.data_ptr()
@@ -320,6 +330,13 @@ class BatchRenderer:
 
     def workspace_bytes(self) -> int:
         return int(sum(r.ws_bytes for r in self.rasts))
+
+    def workspace_parts(self) -> dict:
+        tot: dict = {}
+        for r in self.rasts:
+            for k, v in r.workspace_parts().items():
+                tot[k] = tot.get(k, 0) + v
+        return tot
 
     def capture(self, grad_rgba: torch.Tensor):
         self.grad_rgba = grad_rgba.contiguous()

@@ -136,3 +136,21 @@ def test_workspace_shrinks_with_larger_tiles(tile):
     sc, cams, o = _host_args(W=640, H=480)
     o.tile = tile
     assert _abi.svr_workspace_bytes(sc, cams, 1, o) > 0
+
+
+def test_workspace_parts_sum_to_total():
+    _lib()
+    sc, cams, o = _host_args(N=5000, W=100, H=60, cap=70000)
+    for n_cams in (1, 2):
+        parts = _abi.svr_workspace_parts(sc, cams, n_cams, o)
+        assert list(parts) == list(_abi.WS_PART_NAMES)
+        assert sum(parts.values()) == _abi.svr_workspace_bytes(sc, cams, n_cams, o)
+        # keys (8 B) + values (4 B), two buffers, 256-byte aligned each
+        assert 24 * 70000 <= parts["keys_values_x2"] <= 24 * 70000 + 4 * 256
+        # count, offset, rect (4 + 8 + 8 B) and a 64-byte record per (voxel, camera)
+        nv = 5000 * n_cams
+        assert 84 * nv <= parts["per_voxel_camera_records"] <= 84 * nv + 4 * 256
+        assert 8 * 100 * 60 * n_cams <= parts["per_pixel_state"] <= 8 * 6000 * n_cams + 512
+    with pytest.raises(ValueError):
+        o.K = 0
+        _abi.svr_workspace_parts(sc, cams, 1, o)
