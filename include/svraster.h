@@ -98,7 +98,7 @@ typedef struct svr_opts {
   int32_t tile;            /* tile edge in pixels: 8, 16 or 32 (0 means 16)            */
   int64_t entry_capacity;  /* capacity of the duplicated (tile, voxel, sign) list, < 2^30 */
   int32_t persistent;      /* 0: one render workgroup per tile; n > 0: n workgroups take
-                              tiles from per-XCD counters until all are done           */
+                              tiles (heaviest first) from a counter until all are done */
   int32_t accumulate;      /* svr_render_bwd: 0 overwrites grad_grid / grad_sh, 1 adds
                               into them (several camera groups, one gradient)          */
 } svr_opts;

@@ -175,7 +175,9 @@ int make_layout(const svr_scene* sc, const svr_camera* cams, int n_cams, const s
   l.scan_part = take((size_t)(l.scan_blocks > 0 ? l.scan_blocks : 1) * 8);
   l.tile_mask = take((size_t)T);
   l.tile_sat = take((size_t)sat * 4);
-  l.tile_range = take((size_t)T * 8);
+  l.tile_range = take((size_t)T * 8 + kOrderBuckets * 4);  // ranges, then bucket counters
+  l.tile_order = take((size_t)T * 4);
+  l.tile_rank = take((size_t)T * 4);
   l.keys0 = take((size_t)l.cap * 8);
   l.keys1 = take((size_t)l.cap * 8);
   l.vals0 = take((size_t)l.cap * 4);

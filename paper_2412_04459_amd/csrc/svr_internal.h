@@ -49,13 +49,16 @@ struct alignas(16) VoxRec {
 };
 
 // Workspace header (device): counters written by kernels.
+// tiles are rendered heaviest first, in buckets of floor(log2(entries))
+constexpr int kOrderBuckets = 16;
+
 struct WsHeader {
   unsigned long long n_entries;   // E (may exceed capacity)
   uint32_t overflow;              // E > capacity seen by the emitter
   uint32_t error;                 // bit 0: sort look-back spin limit hit
   uint32_t tickets[16];           // sort partition tickets, one per pass
   unsigned long long stats[8];    // render statistics (svr_render_stats)
-  uint32_t work[8];               // persistent render: per-XCD tile counters
+  uint32_t work[8];               // persistent render: work[0] counts taken positions
   uint32_t pad[20];
 };
 static_assert(sizeof(WsHeader) == 256, "header size");
@@ -68,7 +71,7 @@ struct Layout {
   int64_t scan_blocks, sort_parts;
   // byte offsets into the workspace
   size_t hdr, count, offset, rect, rec, scan_part;
-  size_t tile_mask, tile_sat, tile_range;
+  size_t tile_mask, tile_sat, tile_range, tile_order, tile_rank;
   size_t keys0, keys1, vals0, vals1;
   size_t sort_hist, sort_status0, sort_status1;
   size_t px_tau, px_last;
@@ -110,6 +113,17 @@ __device__ __forceinline__ int sign_bits(float dx, float dy, float dz) {
 // ---- launchers (all asynchronous on `s`) ----------------------------------
 // preprocess
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
+
+// several arrays zeroed by one kernel launch (at most kFillRegions, in order)
+constexpr int kFillRegions = 4;
+struct FillSet {
+  uint32_t* p[kFillRegions] = {nullptr, nullptr, nullptr, nullptr};
+  int64_t n[kFillRegions] = {0, 0, 0, 0};
+  int64_t total = 0;
+  int k = 0;
+  void add(uint32_t* ptr, int64_t count);
+};
+hipError_t launch_zero_u32(const FillSet& f, hipStream_t s);
 hipError_t launch_tile_masks(const CamSet& cams, uint8_t* mask, hipStream_t s);
 hipError_t launch_tile_sat(const CamSet& cams, const uint8_t* mask, uint32_t* sat, hipStream_t s);
 hipError_t launch_project(const svr_scene& sc, const CamSet& cams, const Layout& L, void* ws,

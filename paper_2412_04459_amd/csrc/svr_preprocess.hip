@@ -34,6 +34,35 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
+// zero up to kFillRegions arrays in one launch: the grid-stride index runs
+// over their concatenation
+__global__ void k_zero_u32(FillSet f) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  int r = 0;
+  int64_t base = 0;
+  for (; i < f.total; i += stride) {
+    while (i >= base + f.n[r]) base += f.n[r++];
+    f.p[r][i - base] = 0u;
+  }
+}
+
+hipError_t launch_zero_u32(const FillSet& f, hipStream_t s) {
+  if (f.total <= 0) return hipSuccess;
+  int64_t blocks = (f.total + kBlock - 1) / kBlock;
+  if (blocks > 8192) blocks = 8192;
+  SVR_LAUNCH("fill", k_zero_u32, dim3((unsigned)blocks), dim3(kBlock), 0, s, f);
+  return hipGetLastError();
+}
+
+void FillSet::add(uint32_t* ptr, int64_t count) {
+  if (count <= 0) return;
+  p[k] = ptr;
+  n[k] = count;
+  ++k;
+  total += count;
+}
+
 __device__ __forceinline__ int find_cam(const CamSet& cams, int gtile) {
   int c = 0;
   for (int i = 1; i < cams.n; ++i)
@@ -42,67 +71,128 @@ __device__ __forceinline__ int find_cam(const CamSet& cams, int gtile) {
 }
 
 // ---------------------------------------------------------------------------
+// Per tile, the OR of 1 << sign_bits over its in-image pixel centres.  A
+// workgroup covers kBlock pixels: 4 tiles of 8x8, one of 16x16, or one of
+// 32x32 with 4 pixels per thread.
 __global__ __launch_bounds__(kBlock) void k_tile_masks(CamSet cams, uint8_t* __restrict__ mask) {
-  __shared__ uint32_t m;
-  const int g = blockIdx.x;
-  const int ci = find_cam(cams, g);
-  const DevCam& c = cams.c[ci];
-  const int t = g - c.tile_off;
-  const int tx = t % c.ntx, ty = t / c.ntx;
+  __shared__ uint32_t m[4];
   const int ts = cams.tile;
-  if (threadIdx.x == 0) m = 0;
+  const int tiles_per_wg = ts == 8 ? 4 : 1;
+  const int sub = ts == 8 ? (int)threadIdx.x >> 6 : 0;  // tile of this thread in the workgroup
+  const int g = (int)blockIdx.x * tiles_per_wg + sub;
+  if (threadIdx.x < 4) m[threadIdx.x] = 0;
   __syncthreads();
-  uint32_t mine = 0;
-  for (int k = threadIdx.x; k < ts * ts; k += kBlock) {
-    const int u = tx * ts + (k & (ts - 1));
-    const int v = ty * ts + (k >> cams.tshift);
-    if (u < c.W && v < c.H) {
-      float dx, dy, dz;
-      pixel_dir(c, u, v, dx, dy, dz);
-      mine |= 1u << sign_bits(dx, dy, dz);
+  if (g < cams.total_tiles) {
+    const int ci = find_cam(cams, g);
+    const DevCam& c = cams.c[ci];
+    const int t = g - c.tile_off;
+    const int tx = t % c.ntx, ty = t / c.ntx;
+    const int k0 = ts == 8 ? (int)threadIdx.x & 63 : (int)threadIdx.x;
+    const int step = ts == 8 ? 64 : kBlock;
+    uint32_t mine = 0;
+    for (int k = k0; k < ts * ts; k += step) {
+      const int u = tx * ts + (k & (ts - 1));
+      const int v = ty * ts + (k >> cams.tshift);
+      if (u < c.W && v < c.H) {
+        float dx, dy, dz;
+        pixel_dir(c, u, v, dx, dy, dz);
+        mine |= 1u << sign_bits(dx, dy, dz);
+      }
     }
+    if (mine) atomicOr(&m[sub], mine);
   }
-  if (mine) atomicOr(&m, mine);
   __syncthreads();
-  if (threadIdx.x == 0) mask[g] = (uint8_t)m;
+  if (threadIdx.x < (unsigned)tiles_per_wg) {
+    const int gt = (int)blockIdx.x * tiles_per_wg + (int)threadIdx.x;
+    if (gt < cams.total_tiles) mask[gt] = (uint8_t)m[threadIdx.x];
+  }
 }
 
 hipError_t launch_tile_masks(const CamSet& cams, uint8_t* mask, hipStream_t s) {
-  SVR_LAUNCH("tile_masks", k_tile_masks, dim3(cams.total_tiles), dim3(kBlock), 0, s, cams, mask);
+  const int per = cams.tile == 8 ? 4 : 1;
+  SVR_LAUNCH("tile_masks", k_tile_masks, dim3((cams.total_tiles + per - 1) / per), dim3(kBlock), 0,
+             s, cams, mask);
   return hipGetLastError();
 }
 
 // ---------------------------------------------------------------------------
-// sat[(ty) * (ntx+1) + tx] = sum of popcount(mask) over tiles (x < tx, y < ty)
-__global__ __launch_bounds__(kBlock) void k_tile_sat(CamSet cams, const uint8_t* __restrict__ mask,
-                                                     uint32_t* __restrict__ sat) {
-  const DevCam& c = cams.c[blockIdx.x];
-  const int W1 = c.ntx + 1;
-  uint32_t* S = sat + c.sat_off;
-  const uint8_t* Mk = mask + c.tile_off;
-  // row prefix sums (row 0 is zero)
-  for (int ty = threadIdx.x; ty <= c.nty; ty += blockDim.x) {
-    uint32_t acc = 0;
-    S[ty * W1] = 0;
-    for (int tx = 0; tx < c.ntx; ++tx) {
-      if (ty > 0) acc += __popc((unsigned)Mk[(ty - 1) * c.ntx + tx]);
-      S[ty * W1 + tx + 1] = acc;
+// Summed-area table of popcount(mask) per camera:
+//   sat[ty * (ntx+1) + tx] = sum over tiles (x < tx, y < ty)
+// in two passes: a wave per table row scans popcounts along the row, then a
+// wave per 64 columns accumulates down the rows.
+
+// camera and local index of global item `i` of a per-camera sequence whose
+// camera c holds n(c) items
+template <typename F>
+__device__ __forceinline__ int split_by_cam(const CamSet& cams, int64_t i, F n, int64_t& local) {
+  int64_t base = 0;
+  for (int c = 0; c < cams.n; ++c) {
+    const int64_t nc = n(cams.c[c]);
+    if (i < base + nc) {
+      local = i - base;
+      return c;
     }
+    base += nc;
   }
-  __threadfence();
-  __syncthreads();
-  // column prefix sums
-  for (int tx = threadIdx.x; tx < W1; tx += blockDim.x) {
-    uint32_t acc = 0;
-    for (int ty = 0; ty <= c.nty; ++ty) {
-      acc += S[ty * W1 + tx];
-      S[ty * W1 + tx] = acc;
+  return -1;
+}
+
+__global__ __launch_bounds__(kBlock) void k_sat_rows(CamSet cams, const uint8_t* __restrict__ mask,
+                                                     uint32_t* __restrict__ sat) {
+  const int64_t wv = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
+  const int lane = (int)threadIdx.x & 63;
+  int64_t ty;
+  const int ci = split_by_cam(cams, wv, [](const DevCam& c) { return (int64_t)c.nty + 1; }, ty);
+  if (ci < 0) return;
+  const DevCam& c = cams.c[ci];
+  const int W1 = c.ntx + 1;
+  uint32_t* S = sat + c.sat_off + ty * W1;
+  if (lane == 0) S[0] = 0;
+  const uint8_t* Mk = mask + c.tile_off + (ty - 1) * c.ntx;
+  uint32_t carry = 0;
+  for (int x0 = 0; x0 < c.ntx; x0 += 64) {
+    const int tx = x0 + lane;
+    uint32_t v = (ty > 0 && tx < c.ntx) ? (uint32_t)__popc((unsigned)Mk[tx]) : 0u;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+      const uint32_t t = __shfl_up(v, o, 64);
+      if (lane >= o) v += t;
     }
+    if (tx < c.ntx) S[tx + 1] = carry + v;
+    carry += __shfl(v, 63, 64);
+  }
+}
+
+__global__ __launch_bounds__(kBlock) void k_sat_cols(CamSet cams, uint32_t* __restrict__ sat) {
+  const int64_t wv = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6;
+  const int lane = (int)threadIdx.x & 63;
+  int64_t blk;
+  const int ci = split_by_cam(cams, wv, [](const DevCam& c) { return (int64_t)(c.ntx + 1 + 63) / 64; },
+                              blk);
+  if (ci < 0) return;
+  const DevCam& c = cams.c[ci];
+  const int W1 = c.ntx + 1;
+  const int tx = (int)blk * 64 + lane;
+  if (tx >= W1) return;
+  uint32_t* S = sat + c.sat_off + tx;
+  uint32_t acc = 0;
+  for (int ty = 0; ty <= c.nty; ++ty) {
+    acc += S[(int64_t)ty * W1];
+    S[(int64_t)ty * W1] = acc;
   }
 }
 
 hipError_t launch_tile_sat(const CamSet& cams, const uint8_t* mask, uint32_t* sat, hipStream_t s) {
-  SVR_LAUNCH("tile_sat", k_tile_sat, dim3(cams.n), dim3(kBlock), 0, s, cams, mask, sat);
+  int64_t rows = 0, colblocks = 0;
+  for (int i = 0; i < cams.n; ++i) {
+    rows += cams.c[i].nty + 1;
+    colblocks += (cams.c[i].ntx + 1 + 63) / 64;
+  }
+  const int wpb = kBlock / 64;
+  SVR_LAUNCH("tile_sat", k_sat_rows, dim3((unsigned)((rows + wpb - 1) / wpb)), dim3(kBlock), 0, s,
+             cams, mask, sat);
+  SVR_LAUNCH("tile_sat", k_sat_cols, dim3((unsigned)((colblocks + wpb - 1) / wpb)), dim3(kBlock), 0,
+             s, cams, sat);
   return hipGetLastError();
 }
 

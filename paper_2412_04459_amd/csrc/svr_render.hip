@@ -30,11 +30,12 @@
 // SH coefficients (through the clamp at 0) and scatters corner gradients onto
 // the shared grid points.
 //
-// Tile scheduling: either one workgroup per tile, mapped so that each XCD
-// (workgroups are dealt round-robin to the 8 XCDs) renders a contiguous block
-// of tiles whose voxel records overlap in that XCD's L2; or a persistent grid
-// whose workgroups take tiles from 8 per-XCD counters over the same blocks and
-// steal from the other blocks when their own is exhausted.
+// Tile scheduling: tiles are rendered in the order the sort stage leaves in
+// the workspace, heaviest (most entries) first, because the per-tile work is
+// skewed (a few silhouette tiles hold 10-20x the mean) and a heavy tile
+// started last would set the kernel's length.  Either one workgroup per
+// position of that order, or a persistent grid whose workgroups take the next
+// position from one counter.
 #include "svr_internal.h"
 #include "svr_sh.h"
 
@@ -103,29 +104,14 @@ struct RenderArgs {
   const float4* grad_rgba;
   float* g_corner;
   float* g_rgb;
-  uint32_t* work;  // 8 per-XCD tile counters (persistent mode)
+  uint32_t* work;  // persistent mode: counter of the next render position
+  const uint32_t* order;  // render order of the tiles (heaviest first)
 };
 
-__device__ __forceinline__ int xcd_tile(int b, int T) {
-  const int per = (T + 7) >> 3;
-  return (b & 7) * per + (b >> 3);
-}
-
-// next tile of a persistent workgroup: own XCD block first, then steal
+// next position in the render order for a persistent workgroup (-1: none left)
 __device__ __forceinline__ int next_tile(uint32_t* work, int T) {
-  const int per = (T + 7) >> 3;
-  const int x0 = (int)(blockIdx.x & 7);
-  for (int k = 0; k < 8; ++k) {
-    const int x = (x0 + k) & 7;
-    const int lo = x * per;
-    const int hi = min(T, lo + per);
-    if (lo >= hi) continue;
-    if ((int)__hip_atomic_load(work + x, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) >= hi - lo)
-      continue;
-    const int t = (int)atomicAdd(work + x, 1u);
-    if (lo + t < hi) return lo + t;
-  }
-  return -1;
+  const uint32_t p = atomicAdd(work, 1u);
+  return p < (uint32_t)T ? (int)p : -1;
 }
 
 __device__ __forceinline__ int find_cam_r(const CamSet& cams, int gtile) {
@@ -431,15 +417,15 @@ __global__ __launch_bounds__(TS * TS) void k_render_fwd(RenderArgs A) {
   __shared__ WaveLists<DenseCfg<TS>::kListCap> WL[TileGeom<TS>::kWaves];
   __shared__ int s_tile;
   if (!A.persistent) {
-    const int g = xcd_tile(blockIdx.x, A.T);
-    if (g < A.T) render_tile_fwd<TS, KT, ACT, STATS>(A, g, B, WL);
+    if ((int)blockIdx.x < A.T) render_tile_fwd<TS, KT, ACT, STATS>(A, A.order[blockIdx.x], B, WL);
     return;
   }
   while (true) {
     if (threadIdx.x == 0) s_tile = next_tile(A.work, A.T);
     __syncthreads();
-    const int g = s_tile;
-    if (g < 0) break;
+    const int p = s_tile;
+    if (p < 0) break;
+    const int g = A.order[p];
     render_tile_fwd<TS, KT, ACT, STATS>(A, g, B, WL);
     __syncthreads();
   }
@@ -596,15 +582,15 @@ __global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderArgs A) {
   __shared__ uint32_t s_lmax;
   __shared__ int s_tile;
   if (!A.persistent) {
-    const int g = xcd_tile(blockIdx.x, A.T);
-    if (g < A.T) render_tile_bwd<TS, KT, ACT>(A, g, B, s_lmax);
+    if ((int)blockIdx.x < A.T) render_tile_bwd<TS, KT, ACT>(A, A.order[blockIdx.x], B, s_lmax);
     return;
   }
   while (true) {
     if (threadIdx.x == 0) s_tile = next_tile(A.work, A.T);
     __syncthreads();
-    const int g = s_tile;
-    if (g < 0) break;
+    const int p = s_tile;
+    if (p < 0) break;
+    const int g = A.order[p];
     render_tile_bwd<TS, KT, ACT>(A, g, B, s_lmax);
     __syncthreads();
   }
@@ -704,6 +690,7 @@ static RenderArgs render_args(const CamSet& cams, const svr_opts& o, const Layou
   A.g_corner = at<float>(ws, L.g_corner);
   A.g_rgb = at<float>(ws, L.g_rgb);
   A.work = at<WsHeader>(ws, L.hdr)->work;
+  A.order = at<uint32_t>(ws, L.tile_order);
   return A;
 }
 
@@ -781,9 +768,10 @@ hipError_t launch_render_bwd(const svr_scene& sc, const CamSet& cams, const svr_
                              const Layout& L, void* ws, const uint32_t* vals,
                              const float* grad_rgba, hipStream_t s) {
   (void)sc;
-  hipError_t e = launch_fill_u32(at<uint32_t>(ws, L.g_corner), 0u, L.N * 8, s);
-  if (e != hipSuccess) return e;
-  e = launch_fill_u32(at<uint32_t>(ws, L.g_rgb), 0u, L.NV * 3, s);
+  FillSet z;
+  z.add(at<uint32_t>(ws, L.g_corner), L.N * 8);
+  z.add(at<uint32_t>(ws, L.g_rgb), L.NV * 3);
+  hipError_t e = launch_zero_u32(z, s);
   if (e != hipSuccess) return e;
   RenderArgs A = render_args(cams, o, L, ws, vals);
   A.grad_rgba = reinterpret_cast<const float4*>(grad_rgba);

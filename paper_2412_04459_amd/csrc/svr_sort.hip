@@ -254,9 +254,11 @@ hipError_t launch_radix_sort(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t*
   }
   const int64_t parts = (n_max + kPart - 1) / kPart;
   hipError_t e;
-  if ((e = launch_fill_u32(hist, 0u, 8 * kRadix, s)) != hipSuccess) return e;
-  if ((e = launch_fill_u32(tickets, 0u, 16, s)) != hipSuccess) return e;
-  if ((e = launch_fill_u32(st0, 0u, parts * kRadix, s)) != hipSuccess) return e;
+  FillSet z;
+  z.add(hist, 8 * kRadix);
+  z.add(tickets, 16);
+  z.add(st0, parts * kRadix);
+  if ((e = launch_zero_u32(z, s)) != hipSuccess) return e;
   int64_t hb = (n_max + kBlock * 8 - 1) / (kBlock * 8);
   if (hb > 2048) hb = 2048;
   if (hb < 1) hb = 1;
@@ -291,13 +293,65 @@ __global__ __launch_bounds__(kBlock) void k_tile_ranges(const uint64_t* __restri
   if (i == n - 1 || (uint32_t)(keys[i + 1] >> shift) != t) range[t].y = (uint32_t)(i + 1);
 }
 
+// Render order of the tiles: heaviest first, so that the long tiles start
+// early and the short ones fill in behind them.  Bucket b holds the tiles
+// whose entry count n has floor(log2(max(n, 1))) = kOrderBuckets - 1 - b
+// (capped); within a bucket the order is arbitrary.
+__device__ __forceinline__ uint32_t order_bucket(uint2 r) {
+  const uint32_t n = r.y - r.x;
+  const int lg = 31 - __clz((int)(n | 1u));
+  return (uint32_t)(kOrderBuckets - 1 - min(lg, kOrderBuckets - 1));
+}
+
+// rank of each tile within its bucket: a workgroup counts its tiles per
+// bucket in LDS, then reserves each bucket's run with one global atomic
+__global__ __launch_bounds__(kBlock) void k_tile_bucket(const uint2* __restrict__ range, uint32_t T,
+                                                        uint32_t* __restrict__ bucket_count,
+                                                        uint32_t* __restrict__ rank) {
+  __shared__ uint32_t cnt[kOrderBuckets], base[kOrderBuckets];
+  const uint32_t t = blockIdx.x * kBlock + threadIdx.x;
+  if (threadIdx.x < kOrderBuckets) cnt[threadIdx.x] = 0;
+  __syncthreads();
+  uint32_t b = 0, local = 0;
+  if (t < T) {
+    b = order_bucket(range[t]);
+    local = atomicAdd(cnt + b, 1u);
+  }
+  __syncthreads();
+  if (threadIdx.x < kOrderBuckets && cnt[threadIdx.x] > 0)
+    base[threadIdx.x] = atomicAdd(bucket_count + threadIdx.x, cnt[threadIdx.x]);
+  __syncthreads();
+  if (t < T) rank[t] = base[b] + local;
+}
+
+__global__ __launch_bounds__(kBlock) void k_tile_scatter(const uint2* __restrict__ range, uint32_t T,
+                                                         const uint32_t* __restrict__ bucket_count,
+                                                         const uint32_t* __restrict__ rank,
+                                                         uint32_t* __restrict__ order) {
+  const uint32_t t = blockIdx.x * kBlock + threadIdx.x;
+  if (t >= T) return;
+  const uint32_t b = order_bucket(range[t]);
+  uint32_t base = 0;
+  for (uint32_t i = 0; i < b; ++i) base += bucket_count[i];
+  order[base + rank[t]] = t;
+}
+
 hipError_t launch_tile_ranges(const Layout& L, void* ws, const uint64_t* keys, hipStream_t s) {
-  hipError_t e = launch_fill_u32(at<uint32_t>(ws, L.tile_range), 0u, 2 * (int64_t)L.T, s);
+  // ranges and the bucket counters behind them are cleared together
+  hipError_t e = launch_fill_u32(at<uint32_t>(ws, L.tile_range), 0u,
+                                 2 * (int64_t)L.T + kOrderBuckets, s);
   if (e != hipSuccess) return e;
-  if (L.cap <= 0) return hipSuccess;
-  SVR_LAUNCH("tile_ranges", k_tile_ranges, dim3((unsigned)((L.cap + kBlock - 1) / kBlock)), dim3(kBlock), 0,
-                     s, keys, &at<WsHeader>(ws, L.hdr)->n_entries, L.cap, 3 * L.L + 3,
-                     (uint32_t)L.T, at<uint2>(ws, L.tile_range));
+  uint2* range = at<uint2>(ws, L.tile_range);
+  uint32_t* counts = at<uint32_t>(ws, L.tile_range) + 2 * (int64_t)L.T;
+  if (L.cap > 0)
+    SVR_LAUNCH("tile_ranges", k_tile_ranges, dim3((unsigned)((L.cap + kBlock - 1) / kBlock)),
+               dim3(kBlock), 0, s, keys, &at<WsHeader>(ws, L.hdr)->n_entries, L.cap, 3 * L.L + 3,
+               (uint32_t)L.T, range);
+  const dim3 tg((unsigned)((L.T + kBlock - 1) / kBlock));
+  SVR_LAUNCH("tile_order", k_tile_bucket, tg, dim3(kBlock), 0, s, range, (uint32_t)L.T, counts,
+             at<uint32_t>(ws, L.tile_rank));
+  SVR_LAUNCH("tile_order", k_tile_scatter, tg, dim3(kBlock), 0, s, range, (uint32_t)L.T, counts,
+             at<uint32_t>(ws, L.tile_rank), at<uint32_t>(ws, L.tile_order));
   return hipGetLastError();
 }
 
