@@ -159,8 +159,8 @@ int make_layout(const svr_scene* sc, const svr_camera* cams, int n_cams, const s
     return fail(SVR_E_INVALID, "sort key needs %d bits (> 64): too many tiles for max_level %d",
                 l.key_bits, l.L);
   l.passes = (l.key_bits + 7) / 8;
-  l.scan_blocks = (l.NV + 4095) / 4096;
-  l.sort_parts = (l.cap + 4095) / 4096;
+  l.scan_blocks = (l.NV + kScanTile - 1) / kScanTile;
+  l.sort_parts = (l.cap + kSortPart - 1) / kSortPart;
   size_t off = 0;
   auto take = [&](size_t bytes) {
     size_t at_ = off;
@@ -420,6 +420,7 @@ int svr_render_stats(const svr_scene* scene, const svr_camera* cams, int n_cams,
   if (!counts) return fail(SVR_E_INVALID, "null counts");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   SVR_HIP(launch_render_stats(*scene, cs, *opts, L, ws, sorted_vals(L, ws), s), "render stats");
+  SVR_HIP(launch_count_inview(L, ws, s), "in-view count");
   WsHeader h;
   SVR_HIP(hipMemcpyAsync(&h, at<WsHeader>(ws, L.hdr), sizeof(h), hipMemcpyDeviceToHost, s),
           "read header");

@@ -12,6 +12,10 @@
 namespace svr {
 
 constexpr int kBlock = 256;       // threads per workgroup: 4 wave64
+constexpr int kScanItems = 16;
+constexpr int kScanTile = kBlock * kScanItems;  // counts per scan block
+constexpr int kSortItems = 16;
+constexpr int kSortPart = kBlock * kSortItems;  // (key, value) pairs per sort partition
 constexpr float kZNear = 1e-4f;   // corners closer than this to the camera plane
                                   // make a voxel cover every tile
 constexpr int kVidBits = 29;
@@ -112,6 +116,13 @@ __device__ __forceinline__ int sign_bits(float dx, float dy, float dz) {
 
 // ---- launchers (all asynchronous on `s`) ----------------------------------
 // preprocess
+// order LDS accesses between the lanes of one wave (no workgroup barrier)
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s);
 
 // several arrays zeroed by one kernel launch (at most kFillRegions, in order)
@@ -164,6 +175,7 @@ void timing_end(int slot, const char* name, hipStream_t s);
     ::svr::timing_end(slot_, name, stream);                                \
   } while (0)
 
+hipError_t launch_count_inview(const Layout& L, void* ws, hipStream_t s);
 hipError_t launch_render_stats(const svr_scene& sc, const CamSet& cams, const svr_opts& o,
                                const Layout& L, void* ws, const uint32_t* vals, hipStream_t s);
 

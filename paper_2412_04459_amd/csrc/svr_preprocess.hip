@@ -234,6 +234,40 @@ __device__ __forceinline__ void sh_color(const float* __restrict__ shv, float dx
   }
 }
 
+// SH colour (degree 3) from the voxel's 48 coefficients staged in LDS as 12
+// float4 (Sec. 3.1.1 eq. vox_color, clamped at 0)
+__device__ __forceinline__ void sh_color3_lds(const float4* __restrict__ s4, float dx, float dy,
+                                              float dz, float rgb[3], uint32_t& pos_bits) {
+  float Y[16];
+  sh_basis<3>(dx, dy, dz, Y);
+  float buf[48];
+#pragma unroll
+  for (int i = 0; i < 12; ++i) {
+    const float4 q = s4[i];
+    buf[4 * i + 0] = q.x; buf[4 * i + 1] = q.y; buf[4 * i + 2] = q.z; buf[4 * i + 3] = q.w;
+  }
+  float acc[3] = {0.f, 0.f, 0.f};
+#pragma unroll
+  for (int j = 0; j < 16; ++j) {
+    acc[0] = __fmaf_rn(buf[3 * j + 0], Y[j], acc[0]);
+    acc[1] = __fmaf_rn(buf[3 * j + 1], Y[j], acc[1]);
+    acc[2] = __fmaf_rn(buf[3 * j + 2], Y[j], acc[2]);
+  }
+  pos_bits = 0;
+#pragma unroll
+  for (int ch = 0; ch < 3; ++ch) {
+    if (acc[ch] > 0.f) pos_bits |= 1u << ch;
+    rgb[ch] = fmaxf(acc[ch], 0.f);
+  }
+}
+
+// degree-3 SH staging: a wave copies the coefficients of kShStageVox
+// consecutive voxels (contiguous in memory) into LDS with coalesced float4
+// loads, rows padded to 13 float4 so that the lanes' 16-byte reads of
+// different voxels fall in different banks
+constexpr int kShStageVox = 32;
+constexpr int kShRow = 13;
+
 __device__ __forceinline__ uint32_t sat_rect(const uint32_t* __restrict__ S, int W1, int tx0,
                                              int tx1, int ty0, int ty1) {
   return S[(ty1 + 1) * W1 + tx1 + 1] - S[ty0 * W1 + tx1 + 1] - S[(ty1 + 1) * W1 + tx0] +
@@ -246,9 +280,11 @@ __global__ __launch_bounds__(kBlock) void k_project(
     const float* __restrict__ size, const int32_t* __restrict__ vox_grid,
     const float* __restrict__ grid_raw, const float* __restrict__ sh, int64_t N,
     const uint32_t* __restrict__ sat, uint32_t* __restrict__ count, uint2* __restrict__ rect,
-    VoxRec* __restrict__ rec, WsHeader* __restrict__ hdr) {
-  const int64_t vv = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (vv >= NV) return;
+    VoxRec* __restrict__ rec) {
+  __shared__ float4 shs[D == 3 ? kBlock / 64 : 1][D == 3 ? kShStageVox * kShRow : 1];
+  const int64_t vv0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const bool active = vv0 < NV;
+  const int64_t vv = active ? vv0 : NV - 1;  // inactive lanes stay for the wave-wide staging
   const int64_t vid = vv / n_cams;
   const int ci = (int)(vv - vid * n_cams);
   const DevCam& c = cams.c[ci];
@@ -312,31 +348,80 @@ __global__ __launch_bounds__(kBlock) void k_project(
                      v0 >> cams.tshift, v1 >> cams.tshift);
     }
   }
-  // statistics: number of in-view (voxel, camera) pairs
-  const unsigned long long act = __ballot(1);
-  const unsigned long long inview = __ballot(cnt > 0);
-  if ((int)(threadIdx.x & 63) == __ffsll((long long)act) - 1 && inview)
-    atomicAdd(&hdr->stats[3], (unsigned long long)__popcll(inview));
-  count[vv] = cnt;
-  if (cnt == 0) {
-    rect[vv] = make_uint2(1u, 0u);
-    return;
+  if (!active) cnt = 0;
+  if (active) {
+    count[vv] = cnt;
+    rect[vv] = cnt == 0 ? make_uint2(1u, 0u)
+                        : make_uint2((uint32_t)u0 | ((uint32_t)u1 << 16),
+                                     (uint32_t)v0 | ((uint32_t)v1 << 16));
   }
-  rect[vv] = make_uint2((uint32_t)u0 | ((uint32_t)u1 << 16), (uint32_t)v0 | ((uint32_t)v1 << 16));
-  // pre-process: gather the 8 corner densities, evaluate the SH colour for
-  // the direction camera centre -> voxel centre
+  const bool need = cnt > 0;
+  // pre-process: SH colour for the direction camera centre -> voxel centre,
+  // then gather the 8 corner densities
+  const float rn = rsqrtf(rx * rx + ry * ry + rz * rz);
+  float rgb[3] = {0.f, 0.f, 0.f};
+  uint32_t bits = 0;
+  if (D == 3) {
+    const unsigned long long needm = __ballot(need);
+    if (needm == 0ull) return;
+    const int lane = (int)threadIdx.x & 63, w = (int)threadIdx.x >> 6;
+    // the wave's voxels: [vlo, vhi] (ids grow with the lane)
+    const int64_t vlo = __shfl(vid, 0, 64);
+    const int64_t vhi = __shfl(vid, 63, 64);
+    const float4* sh4 = reinterpret_cast<const float4*>(sh);
+    float4* S = shs[w];
+    for (int64_t vb = vlo; vb <= vhi; vb += kShStageVox) {
+      const int nv = (int)min((int64_t)kShStageVox, vhi - vb + 1);
+      for (int q = lane; q < nv * 12; q += 64) S[(q / 12) * kShRow + q % 12] = sh4[vb * 12 + q];
+      wave_sync_lds();
+      if (need && vid >= vb && vid < vb + nv)
+        sh_color3_lds(S + (vid - vb) * kShRow, rx * rn, ry * rn, rz * rn, rgb, bits);
+      wave_sync_lds();
+    }
+  } else if (need) {
+    sh_color<D>(sh + vid * (int64_t)(3 * (D + 1) * (D + 1)), rx * rn, ry * rn, rz * rn, rgb,
+                bits);
+  }
+  if (!need) return;
   const int4* vg = reinterpret_cast<const int4*>(vox_grid + vid * 8);
   const int4 ga = vg[0], gb = vg[1];
   VoxRec R;
   R.q0 = make_float4(center[vid], center[N + vid], center[2 * N + vid], s);
   R.q1 = make_float4(grid_raw[ga.x], grid_raw[ga.y], grid_raw[ga.z], grid_raw[ga.w]);
   R.q2 = make_float4(grid_raw[gb.x], grid_raw[gb.y], grid_raw[gb.z], grid_raw[gb.w]);
-  const float rn = rsqrtf(rx * rx + ry * ry + rz * rz);
-  float rgb[3];
-  uint32_t bits;
-  sh_color<D>(sh + vid * (int64_t)(3 * (D + 1) * (D + 1)), rx * rn, ry * rn, rz * rn, rgb, bits);
   R.q3 = make_float4(rgb[0], rgb[1], rgb[2], __uint_as_float(bits));
   rec[vv] = R;
+}
+
+// statistics: number of in-view (voxel, camera) pairs (count > 0), summed per
+// workgroup, one atomic per workgroup
+__global__ __launch_bounds__(kBlock) void k_count_inview(const uint32_t* __restrict__ count,
+                                                         int64_t n, unsigned long long* out) {
+  __shared__ unsigned long long part[kBlock / 64];
+  unsigned long long c = 0;
+  for (int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * kBlock)
+    c += count[i] > 0u ? 1ull : 0ull;
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) c += __shfl_xor(c, o, 64);
+  if ((threadIdx.x & 63) == 0) part[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    unsigned long long t = 0;
+    for (int w = 0; w < kBlock / 64; ++w) t += part[w];
+    if (t) atomicAdd(out, t);
+  }
+}
+
+hipError_t launch_count_inview(const Layout& L, void* ws, hipStream_t s) {
+  unsigned long long* out = &at<WsHeader>(ws, L.hdr)->stats[3];
+  hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(out), 0u, 2, s);
+  if (e != hipSuccess || L.NV == 0) return e;
+  int64_t blocks = (L.NV + kBlock * 16 - 1) / (kBlock * 16);
+  if (blocks > 1024) blocks = 1024;
+  SVR_LAUNCH("count_inview", k_count_inview, dim3((unsigned)blocks), dim3(kBlock), 0, s,
+             at<uint32_t>(ws, L.count), L.NV, out);
+  return hipGetLastError();
 }
 
 hipError_t launch_project(const svr_scene& sc, const CamSet& cams, const Layout& L, void* ws,
@@ -349,8 +434,7 @@ hipError_t launch_project(const svr_scene& sc, const CamSet& cams, const Layout&
   auto* rec = at<VoxRec>(ws, L.rec);
 #define SVR_PROJ(D)                                                                             \
   SVR_LAUNCH("project", k_project<D>, grid, dim3(kBlock), 0, s, L.NV, L.n_cams, cams, sc.center, \
-                     sc.size, sc.vox_grid, sc.grid_raw, sc.sh, L.N, sat, count, rect, rec, \
-                     at<WsHeader>(ws, L.hdr))
+                     sc.size, sc.vox_grid, sc.grid_raw, sc.sh, L.N, sat, count, rect, rec)
   switch (sc.sh_degree) {
     case 0: SVR_PROJ(0); break;
     case 1: SVR_PROJ(1); break;
@@ -363,8 +447,6 @@ hipError_t launch_project(const svr_scene& sc, const CamSet& cams, const Layout&
 
 // ---------------------------------------------------------------------------
 // exclusive scan of the per view-voxel counts into 64-bit offsets
-constexpr int kScanItems = 16;
-constexpr int kScanTile = kBlock * kScanItems;  // 4096 counts per block
 
 __device__ __forceinline__ unsigned long long wave_incl_scan(unsigned long long v) {
   const int lane = threadIdx.x & 63;

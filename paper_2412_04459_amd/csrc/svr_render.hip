@@ -285,11 +285,6 @@ __device__ __forceinline__ uint32_t lane_rank(unsigned long long mask) {
                                    __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
-__device__ __forceinline__ void wave_sync_lds() {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-  __builtin_amdgcn_wave_barrier();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
 
 // STATS: count, per frame, the (pixel, entry) pairs of matching sign pattern
 // the method walks, the ray-box tests this kernel executes (candidates after

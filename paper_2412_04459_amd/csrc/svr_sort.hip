@@ -2,7 +2,7 @@
 // single-pass-per-digit ("onesweep") form: one kernel reads the keys once and
 // builds the digit histograms of every pass; then each 8-bit digit pass is one
 // kernel in which a workgroup
-//   1. takes a partition of 4096 pairs in the order given by an atomic ticket
+//   1. takes a partition of kSortPart pairs in the order given by an atomic ticket
 //      (so every partition it waits on is already running),
 //   2. ranks its keys stably with wave64 ballots (a match on the 8 digit bits
 //      per lane gives each lane its peers) and per-wave digit counters in LDS,
@@ -19,8 +19,7 @@
 namespace svr {
 
 constexpr int kRadix = 256;
-constexpr int kSortItems = 16;
-constexpr int kPart = kBlock * kSortItems;       // 4096 pairs per partition
+constexpr int kPart = kSortPart;
 constexpr uint32_t kFlagAgg = 1u << 30;          // partition-local count published
 constexpr uint32_t kFlagPre = 2u << 30;          // inclusive prefix published
 constexpr uint32_t kValMask = (1u << 30) - 1u;
@@ -259,8 +258,10 @@ hipError_t launch_radix_sort(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t*
   z.add(tickets, 16);
   z.add(st0, parts * kRadix);
   if ((e = launch_zero_u32(z, s)) != hipSuccess) return e;
+  // few workgroups: each flushes up to 8 x 256 device-scope atomics into the
+  // same histogram, which costs more than streaming more keys per workgroup
   int64_t hb = (n_max + kBlock * 8 - 1) / (kBlock * 8);
-  if (hb > 2048) hb = 2048;
+  if (hb > 256) hb = 256;
   if (hb < 1) hb = 1;
   SVR_LAUNCH("sort_hist", k_sort_hist, dim3((unsigned)hb), dim3(kBlock), 0, s, k0, n_dev, n_max, bits,
                      hist);

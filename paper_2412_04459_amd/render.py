@@ -139,6 +139,7 @@ class Rasterizer:
         self.opts.persistent = int(persistent)
         self.opts.accumulate = 1 if accumulate else 0
         self._graph = None
+        self._view_graphs = []
         if capacity is None:
             capacity = max(1 << 16, 2 * dscene.n_voxels * self.n_cams)
         self.sync_count = sync_count
@@ -246,10 +247,39 @@ class Rasterizer:
         s = (stream or torch.cuda.current_stream()).cuda_stream
         check(_abi.svr_graph_launch(self._graph, ctypes.c_void_p(s)), "svr_graph_launch")
 
+    def capture_views(self, cams: Sequence, rgba: torch.Tensor, grad_rgba: torch.Tensor,
+                      grad_grid: torch.Tensor, grad_sh: torch.Tensor,
+                      stream: torch.cuda.Stream) -> int:
+        """One hipGraph per camera (each of this rasterizer's resolution), all
+        sharing this workspace and the given outputs: replay_view(i) runs the
+        whole frame of camera i.  Replays must run one after another on one
+        stream.  Returns the number of graphs."""
+        self.release_graph()
+        st = self.ds.struct()
+        for c in cams:
+            self.set_cameras([c])
+            h = ctypes.c_void_p(0)
+            torch.cuda.synchronize()
+            check(_abi.svr_graph_capture(st, self.cam_arr, self.n_cams, self.opts,
+                                         self._ws_ptr(), self.ws_bytes, _ptr(rgba),
+                                         _ptr(grad_rgba), _ptr(grad_grid), _ptr(grad_sh),
+                                         ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h)),
+                  "svr_graph_capture")
+            self._view_graphs.append(h)
+        self._graph_keep = (rgba, grad_rgba, grad_grid, grad_sh)
+        return len(self._view_graphs)
+
+    def replay_view(self, i: int, stream: torch.cuda.Stream):
+        check(_abi.svr_graph_launch(self._view_graphs[i], ctypes.c_void_p(stream.cuda_stream)),
+              "svr_graph_launch")
+
     def release_graph(self):
         if self._graph is not None:
             _abi.svr_graph_destroy(self._graph)
             self._graph = None
+        for h in self._view_graphs:
+            _abi.svr_graph_destroy(h)
+        self._view_graphs = []
 
     def __del__(self):
         try:

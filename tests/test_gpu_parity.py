@@ -72,7 +72,8 @@ def _check_grad(g, r, name):
 # ---------------------------------------------------------------------------
 # radix sort (bit-exact against a stable sort of the same list)
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("n,bits", [(1, 8), (100, 8), (4095, 20), (4096, 52), (4097, 52),
+@pytest.mark.parametrize("n,bits", [(1, 8), (100, 8), (2047, 12), (2048, 30), (2049, 30),
+                                    (4095, 20), (4096, 52), (4097, 52),
                                     (100_003, 36), (1_500_000, 52), (300_000, 64)])
 def test_radix_sort_matches_stable_sort(torch_dev, n, bits):
     torch = torch_dev
