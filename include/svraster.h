@@ -110,12 +110,14 @@ size_t svr_workspace_bytes(const svr_scene* scene, const svr_camera* cams, int n
 
 /* The same workspace split by purpose, in bytes (alignment padding included),
  * written to parts[0 .. min(n_parts, SVR_WS_PARTS) - 1]:
- *   [0] header, tile masks, tile summed-area table and tile ranges
+ *   [0] header, tile masks, tile summed-area table, tile ranges, render order
+ *       and the backward chunk list of heavy tiles
  *   [1] per (voxel, camera): count, offset, tile rectangle and render record
  *   [2] scan partial sums
  *   [3] sort keys and values, both buffers of the double-buffered sort
  *   [4] radix-sort digit histograms and look-back status
- *   [5] per-pixel saved state of the forward (final optical depth, last entry)
+ *   [5] per-pixel saved state of the forward (final optical depth, last entry,
+ *       and the checkpoints at chunk boundaries of heavy tiles)
  *   [6] gradient scratch (per-voxel corner gradients, per (voxel, camera) colour)
  * The parts sum to svr_workspace_bytes().  Returns SVR_OK or SVR_E_INVALID. */
 #define SVR_WS_PARTS 7

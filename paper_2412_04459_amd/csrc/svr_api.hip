@@ -175,9 +175,14 @@ int make_layout(const svr_scene* sc, const svr_camera* cams, int n_cams, const s
   l.scan_part = take((size_t)(l.scan_blocks > 0 ? l.scan_blocks : 1) * 8);
   l.tile_mask = take((size_t)T);
   l.tile_sat = take((size_t)sat * 4);
-  l.tile_range = take((size_t)T * 8 + kOrderBuckets * 4);  // ranges, then bucket counters
+  // ranges, then the bucket counters and the chunk counter (cleared together)
+  l.tile_range = take((size_t)T * 8 + (kOrderBuckets + 1) * 4);
   l.tile_order = take((size_t)T * 4);
   l.tile_rank = take((size_t)T * 4);
+  // a tile of n entries adds ceil(n / kBwdChunk) - 1 <= n / kBwdChunk chunks
+  l.max_split = l.cap / kBwdChunk + 1;
+  l.split_base = take((size_t)T * 4);
+  l.split_items = take((size_t)l.max_split * 8);
   l.keys0 = take((size_t)l.cap * 8);
   l.keys1 = take((size_t)l.cap * 8);
   l.vals0 = take((size_t)l.cap * 4);
@@ -187,6 +192,7 @@ int make_layout(const svr_scene* sc, const svr_camera* cams, int n_cams, const s
   l.sort_status1 = take((size_t)(l.sort_parts > 0 ? l.sort_parts : 1) * 256 * 4);
   l.px_tau = take((size_t)P * 4);
   l.px_last = take((size_t)P * 4);
+  l.ckpt = take((size_t)l.max_split * l.tile * l.tile * 16);
   l.g_corner = take((size_t)l.N * 32);
   l.g_rgb = take((size_t)l.NV * 12);
   l.total = off;
@@ -340,7 +346,8 @@ int svr_check_overflow(const svr_scene* scene, const svr_camera* cams, int n_cam
           "read header");
   SVR_HIP(hipStreamSynchronize(s), "synchronise");
   if (required_entries) *required_entries = (int64_t)h.n_entries;
-  if (h.error) return fail(SVR_E_DEVICE, "sort look-back exceeded its spin limit");
+  if (h.error & 1u) return fail(SVR_E_DEVICE, "sort look-back exceeded its spin limit");
+  if (h.error & 2u) return fail(SVR_E_DEVICE, "backward chunk list overflow");
   if ((int64_t)h.n_entries > L.cap)
     return fail(SVR_E_CAPACITY, "%llu entries exceed capacity %lld", h.n_entries,
                 (long long)L.cap);

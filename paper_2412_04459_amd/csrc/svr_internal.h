@@ -55,11 +55,17 @@ struct alignas(16) VoxRec {
 // Workspace header (device): counters written by kernels.
 // tiles are rendered heaviest first, in buckets of floor(log2(entries))
 constexpr int kOrderBuckets = 16;
+// the backward of a tile with more entries than this runs as several chunks
+// of this many entries, one workgroup each (a multiple of every batch size)
+constexpr int kBwdChunk = 256;
+constexpr uint32_t kNoSplit = 0xffffffffu;
+// workgroups that take the split chunks (each loops over several)
+constexpr int kSplitWgs = 2048;
 
 struct WsHeader {
   unsigned long long n_entries;   // E (may exceed capacity)
   uint32_t overflow;              // E > capacity seen by the emitter
-  uint32_t error;                 // bit 0: sort look-back spin limit hit
+  uint32_t error;                 // bit 0: sort look-back spin limit hit; bit 1: chunk list full
   uint32_t tickets[16];           // sort partition tickets, one per pass
   unsigned long long stats[8];    // render statistics (svr_render_stats)
   uint32_t work[8];               // persistent render: work[0] counts taken positions
@@ -76,6 +82,8 @@ struct Layout {
   // byte offsets into the workspace
   size_t hdr, count, offset, rect, rec, scan_part;
   size_t tile_mask, tile_sat, tile_range, tile_order, tile_rank;
+  size_t split_base, split_items, ckpt;  // backward chunks of heavy tiles
+  int64_t max_split;                     // capacity of the chunk list (>= sum of splits)
   size_t keys0, keys1, vals0, vals1;
   size_t sort_hist, sort_status0, sort_status1;
   size_t px_tau, px_last;

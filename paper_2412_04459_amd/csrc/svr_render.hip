@@ -21,14 +21,18 @@
 // Backward: the same tiling, walking each pixel's list back to front from its
 // saved position and recomputing x and alpha per hit; the transmittance before
 // hit i is exp(-(tau_{i+1} - x_i)), so no per-sample state is stored.  With
-// S the colour of everything behind hit i seen from just behind it:
+// U_{i+1} = sum_{j>i} T_j alpha_j c_j the colour composited after hit i:
 //   dL/dc_i = g_rgb T_i alpha_i
-//   dL/dx_i = T_{i+1} <g_rgb, c_i - S_i> + g_A T_final
+//   dL/dx_i = <g_rgb, T_{i+1} c_i - U_{i+1}> + g_A T_final
 //   dL/dV_m = dL/dx_i (l/K) sum_k act'(v_k) w_m(q_k)    (Supp. A.2 gradient)
-// The 11 per-hit gradients are summed over the wave and added with one
-// 11-lane float atomic.  The pre-process adjoint then maps colour gradients to
-// SH coefficients (through the clamp at 0) and scatters corner gradients onto
-// the shared grid points.
+// and U_i = U_{i+1} + T_i alpha_i c_i.  The 11 per-hit gradients are summed
+// over the wave and added with one 11-lane float atomic.  A tile with more
+// than kBwdChunk entries is split into chunks of that many entries, one
+// workgroup each: the forward saves, per pixel, tau and the colour still to
+// come at every chunk boundary it passes, which is all a chunk's reverse walk
+// needs to start.  The pre-process adjoint then maps colour gradients to SH
+// coefficients (through the clamp at 0) and gathers corner gradients onto the
+// shared grid points.
 //
 // Tile scheduling: tiles are rendered in the order the sort stage leaves in
 // the workspace, heaviest (most entries) first, because the per-tile work is
@@ -104,8 +108,14 @@ struct RenderArgs {
   const float4* grad_rgba;
   float* g_corner;
   float* g_rgb;
-  uint32_t* work;  // persistent mode: counter of the next render position
+  uint32_t* work;  // persistent mode: work[0] next chunk item, work[1] next render position
   const uint32_t* order;  // render order of the tiles (heaviest first)
+  // backward chunks of heavy tiles
+  const uint32_t* split_base;   // per tile: first item / checkpoint slot, or kNoSplit
+  const uint2* split_items;     // (tile, chunk) for every chunk but a tile's last
+  const uint32_t* split_count;  // number of items
+  float4* ckpt;                 // per slot and pixel: (tau, suffix colour) at the chunk's end
+  int max_split, split_wgs;
 };
 
 // next position in the render order for a persistent workgroup (-1: none left)
@@ -314,6 +324,10 @@ __device__ __forceinline__ void render_tile_fwd(const RenderArgs& A, int g,
   bool done = !r.inside;
   uint32_t n_pairs = 0, n_tests = 0, n_hits = 0;
   const uint32_t u = (uint32_t)r.u, v = (uint32_t)r.v;
+  // heavy tile: record (tau, colour so far) at every chunk boundary passed
+  const uint32_t sb = STATS ? kNoSplit : A.split_base[g];
+  float4* const ck = A.ckpt + (int64_t)(sb == kNoSplit ? 0u : sb) * (TS * TS) + tid;
+  uint32_t n_ck = 0;
 
   for (uint32_t b0 = start; b0 < end; b0 += NB) {
     const uint32_t i = b0 + tid;
@@ -381,7 +395,19 @@ __device__ __forceinline__ void render_tile_fwd(const RenderArgs& A, int g,
       if (__ballot(cnt == CAP) != 0ull) flush();
     }
     if (nq > 0) flush();
+    if (sb != kNoSplit) {
+      const uint32_t bend = b0 + NB;
+      if (bend < end && ((bend - start) & (kBwdChunk - 1)) == 0) {
+        ck[(int64_t)n_ck * (TS * TS)] = make_float4(tau, C0, C1, C2);
+        ++n_ck;
+      }
+    }
     if (__syncthreads_and(done)) break;
+  }
+  // the backward wants the colour still to come: final minus so far
+  for (uint32_t k = 0; k < n_ck; ++k) {
+    const float4 q = ck[(int64_t)k * (TS * TS)];
+    ck[(int64_t)k * (TS * TS)] = make_float4(q.x, C0 - q.y, C1 - q.z, C2 - q.w);
   }
   if (STATS) {
     unsigned long long a0 = n_pairs, a1 = n_tests, a2 = n_hits;
@@ -486,8 +512,14 @@ __device__ __forceinline__ float wave_reduce11(float g0, float g1, float g2, flo
   return x;
 }
 
+// Backward of chunks [m_lo, m_hi) of tile g (entries [start + m_lo C,
+// min(start + m_hi C, end)), C = kBwdChunk).  A pixel whose last composited
+// entry lies beyond the range starts from the forward's checkpoint at the
+// range's end (optical depth so far, colour still to come); the others start
+// from their final state.
 template <int TS, int KT, int ACT>
-__device__ __forceinline__ void render_tile_bwd(const RenderArgs& A, int g,
+__device__ __forceinline__ void render_tile_bwd(const RenderArgs& A, int g, uint32_t m_lo,
+                                                uint32_t m_hi,
                                                 LdsBatch<TileGeom<TS>::kBatch>& B,
                                                 uint32_t& s_lmax) {
   using G = TileGeom<TS>;
@@ -503,27 +535,36 @@ __device__ __forceinline__ void render_tile_bwd(const RenderArgs& A, int g,
   const bool writer = (lane & 3) == 0 && slot < 11;
 
   const uint2 rg = A.range[g];
-  const uint32_t start = rg.x;
-  float tau = 0.f, gr = 0.f, gg = 0.f, gb = 0.f, ga = 0.f;
-  uint32_t last = start;
+  const uint32_t e_lo = rg.x + m_lo * (uint32_t)kBwdChunk;
+  const uint32_t e_hi = min(rg.x + m_hi * (uint32_t)kBwdChunk, rg.y);
+  float tau = 0.f, gr = 0.f, gg = 0.f, gb = 0.f, ga = 0.f, Tfin = 1.f;
+  float U0 = 0.f, U1 = 0.f, U2 = 0.f;  // colour composited after the current entry
+  uint32_t last = e_lo;
   if (r.inside) {
     const int64_t p = c.pix_off + (int64_t)r.v * c.W + r.u;
-    tau = A.px_tau[p];
-    last = A.px_last[p];
+    const float tau_fin = A.px_tau[p];
+    const uint32_t lp = A.px_last[p];
     const float4 gq = A.grad_rgba[p];
     gr = gq.x; gg = gq.y; gb = gq.z; ga = gq.w;
+    Tfin = __expf(-tau_fin);
+    if (lp > e_hi) {  // only in a split chunk (e_hi < end), whose tile has checkpoints
+      const float4 q = A.ckpt[((int64_t)A.split_base[g] + m_hi - 1) * (TS * TS) + tid];
+      tau = q.x; U0 = q.y; U1 = q.z; U2 = q.w;
+      last = e_hi;
+    } else {
+      tau = tau_fin;
+      last = lp;
+    }
   }
-  const float Tfin = __expf(-tau);
-  float S0 = 0.f, S1 = 0.f, S2 = 0.f;
-  if (tid == 0) s_lmax = start;
+  if (tid == 0) s_lmax = e_lo;
   __syncthreads();
-  if (last > start) atomicMax(&s_lmax, last);
+  if (last > e_lo) atomicMax(&s_lmax, last);
   __syncthreads();
   const uint32_t lmax = s_lmax;
 
   uint32_t bend = lmax;
-  while (bend > start) {
-    const uint32_t b0 = bend - min((uint32_t)NB, bend - start);
+  while (bend > e_lo) {
+    const uint32_t b0 = bend - min((uint32_t)NB, bend - e_lo);
     const int n = (int)(bend - b0);
     bend = b0;
     if (tid < n) stage_entry<TS>(B, tid, A.vals[b0 + tid], ci, A.n_cams, c, A.rec, A.rect, qu0, qv0);
@@ -550,10 +591,11 @@ __device__ __forceinline__ void render_tile_bwd(const RenderArgs& A, int g,
         const float cr = B.cr[j], cg = B.cg[j], cb = B.cb[j];
         const float wgt = Ti * alpha;
         gv[8] = gr * wgt; gv[9] = gg * wgt; gv[10] = gb * wgt;
-        const float dLdx = Tnext * (gr * (cr - S0) + gg * (cg - S1) + gb * (cb - S2)) + ga * Tfin;
-        S0 = __fmaf_rn(alpha, cr - S0, S0);
-        S1 = __fmaf_rn(alpha, cg - S1, S1);
-        S2 = __fmaf_rn(alpha, cb - S2, S2);
+        const float dLdx = gr * (Tnext * cr - U0) + gg * (Tnext * cg - U1) +
+                           gb * (Tnext * cb - U2) + ga * Tfin;
+        U0 = __fmaf_rn(wgt, cr, U0);
+        U1 = __fmaf_rn(wgt, cg, U1);
+        U2 = __fmaf_rn(wgt, cb, U2);
         const float f = dLdx * lK;
 #pragma unroll
         for (int m = 0; m < 8; ++m) gv[m] = f * dw[m];
@@ -571,22 +613,65 @@ __device__ __forceinline__ void render_tile_bwd(const RenderArgs& A, int g,
   }
 }
 
+// chunk item k: (tile, chunk), checked against the tile before use
+template <int TS, int KT, int ACT>
+__device__ __forceinline__ void bwd_split_item(const RenderArgs& A, uint32_t k,
+                                               LdsBatch<TileGeom<TS>::kBatch>& B,
+                                               uint32_t& s_lmax) {
+  const uint2 it = A.split_items[k];
+  if (it.x >= (uint32_t)A.T || A.split_base[it.x] == kNoSplit) return;
+  const uint2 rg = A.range[it.x];
+  const uint32_t nch = (rg.y - rg.x + kBwdChunk - 1) / kBwdChunk;
+  if (it.y + 1 >= nch) return;
+  render_tile_bwd<TS, KT, ACT>(A, (int)it.x, it.y, it.y + 1, B, s_lmax);
+}
+
+// a tile's whole range, or its last chunk when the others are chunk items
+template <int TS, int KT, int ACT>
+__device__ __forceinline__ void bwd_tile_rest(const RenderArgs& A, int g,
+                                              LdsBatch<TileGeom<TS>::kBatch>& B,
+                                              uint32_t& s_lmax) {
+  const uint2 rg = A.range[g];
+  const uint32_t nch = (rg.y - rg.x + kBwdChunk - 1) / kBwdChunk;
+  const uint32_t m_lo = (A.split_base[g] == kNoSplit || nch == 0) ? 0u : nch - 1;
+  render_tile_bwd<TS, KT, ACT>(A, g, m_lo, nch, B, s_lmax);
+}
+
 template <int TS, int KT, int ACT>
 __global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderArgs A) {
   __shared__ LdsBatch<TileGeom<TS>::kBatch> B;
   __shared__ uint32_t s_lmax;
   __shared__ int s_tile;
+  const uint32_t ns = min(*A.split_count, (uint32_t)A.max_split);
   if (!A.persistent) {
-    if ((int)blockIdx.x < A.T) render_tile_bwd<TS, KT, ACT>(A, A.order[blockIdx.x], B, s_lmax);
+    // the first split_wgs workgroups take the chunk items, the others one
+    // tile each (its last chunk if it is split) in render order
+    const int b = (int)blockIdx.x;
+    if (b < A.split_wgs) {
+      for (uint32_t k = (uint32_t)b; k < ns; k += (uint32_t)A.split_wgs) {
+        bwd_split_item<TS, KT, ACT>(A, k, B, s_lmax);
+        __syncthreads();
+      }
+    } else if (b - A.split_wgs < A.T) {
+      bwd_tile_rest<TS, KT, ACT>(A, (int)A.order[b - A.split_wgs], B, s_lmax);
+    }
     return;
   }
+  while (true) {  // chunk items first, then the tiles
+    if (threadIdx.x == 0) s_tile = next_tile(A.work, (int)ns);
+    __syncthreads();
+    const int k = s_tile;
+    if (k < 0) break;
+    bwd_split_item<TS, KT, ACT>(A, (uint32_t)k, B, s_lmax);
+    __syncthreads();
+  }
+  __syncthreads();  // every thread has read the last s_tile before it is reused
   while (true) {
-    if (threadIdx.x == 0) s_tile = next_tile(A.work, A.T);
+    if (threadIdx.x == 0) s_tile = next_tile(A.work + 1, A.T);
     __syncthreads();
     const int p = s_tile;
     if (p < 0) break;
-    const int g = A.order[p];
-    render_tile_bwd<TS, KT, ACT>(A, g, B, s_lmax);
+    bwd_tile_rest<TS, KT, ACT>(A, (int)A.order[p], B, s_lmax);
     __syncthreads();
   }
 }
@@ -686,6 +771,12 @@ static RenderArgs render_args(const CamSet& cams, const svr_opts& o, const Layou
   A.g_rgb = at<float>(ws, L.g_rgb);
   A.work = at<WsHeader>(ws, L.hdr)->work;
   A.order = at<uint32_t>(ws, L.tile_order);
+  A.split_base = at<uint32_t>(ws, L.split_base);
+  A.split_items = at<uint2>(ws, L.split_items);
+  A.split_count = at<uint32_t>(ws, L.tile_range) + 2 * (int64_t)L.T + kOrderBuckets;
+  A.ckpt = at<float4>(ws, L.ckpt);
+  A.max_split = (int)L.max_split;
+  A.split_wgs = (int)min((int64_t)kSplitWgs, L.max_split);
   return A;
 }
 
@@ -728,9 +819,9 @@ static hipError_t launch_render(RKind kind, const RenderArgs& A, const svr_opts&
   if (L.persistent > 0) {
     hipError_t e = launch_fill_u32(at<WsHeader>(ws, L.hdr)->work, 0u, 8, s);
     if (e != hipSuccess) return e;
-    grid = (unsigned)min((int64_t)L.persistent, (int64_t)L.T);
+    grid = (unsigned)min((int64_t)L.persistent, (int64_t)L.T + A.max_split);
   } else {
-    grid = (unsigned)(((L.T + 7) >> 3) << 3);
+    grid = (unsigned)L.T + (kind == RKind::kBwd ? (unsigned)A.split_wgs : 0u);
   }
   switch (L.tile) {
     case 8: launch_act<8>(kind, A, o.activation, grid, s); break;

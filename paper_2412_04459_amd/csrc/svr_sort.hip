@@ -306,17 +306,39 @@ __device__ __forceinline__ uint32_t order_bucket(uint2 r) {
 
 // rank of each tile within its bucket: a workgroup counts its tiles per
 // bucket in LDS, then reserves each bucket's run with one global atomic
+//
+// The same pass lists the backward chunks of heavy tiles: a tile of n >
+// kBwdChunk entries reserves ceil(n / kBwdChunk) - 1 items (tile, chunk) for
+// all its chunks but the last, and records where they start (split_base).
 __global__ __launch_bounds__(kBlock) void k_tile_bucket(const uint2* __restrict__ range, uint32_t T,
                                                         uint32_t* __restrict__ bucket_count,
-                                                        uint32_t* __restrict__ rank) {
+                                                        uint32_t* __restrict__ rank,
+                                                        uint32_t* __restrict__ split_count,
+                                                        uint32_t* __restrict__ split_base,
+                                                        uint2* __restrict__ split_items,
+                                                        uint32_t max_split,
+                                                        uint32_t* __restrict__ err) {
   __shared__ uint32_t cnt[kOrderBuckets], base[kOrderBuckets];
   const uint32_t t = blockIdx.x * kBlock + threadIdx.x;
   if (threadIdx.x < kOrderBuckets) cnt[threadIdx.x] = 0;
   __syncthreads();
   uint32_t b = 0, local = 0;
   if (t < T) {
-    b = order_bucket(range[t]);
+    const uint2 r = range[t];
+    b = order_bucket(r);
     local = atomicAdd(cnt + b, 1u);
+    const uint32_t nch = (r.y - r.x + kBwdChunk - 1) / kBwdChunk;
+    uint32_t sb = kNoSplit;
+    if (nch > 1) {
+      const uint32_t at_ = atomicAdd(split_count, nch - 1);
+      if (at_ + (nch - 1) <= max_split) {
+        sb = at_;
+        for (uint32_t m = 0; m + 1 < nch; ++m) split_items[at_ + m] = make_uint2(t, m);
+      } else {
+        atomicOr(err, 2u);  // cannot happen while the ranges hold <= capacity entries
+      }
+    }
+    split_base[t] = sb;
   }
   __syncthreads();
   if (threadIdx.x < kOrderBuckets && cnt[threadIdx.x] > 0)
@@ -338,19 +360,21 @@ __global__ __launch_bounds__(kBlock) void k_tile_scatter(const uint2* __restrict
 }
 
 hipError_t launch_tile_ranges(const Layout& L, void* ws, const uint64_t* keys, hipStream_t s) {
-  // ranges and the bucket counters behind them are cleared together
+  // ranges and the bucket and chunk counters behind them are cleared together
   hipError_t e = launch_fill_u32(at<uint32_t>(ws, L.tile_range), 0u,
-                                 2 * (int64_t)L.T + kOrderBuckets, s);
+                                 2 * (int64_t)L.T + kOrderBuckets + 1, s);
   if (e != hipSuccess) return e;
   uint2* range = at<uint2>(ws, L.tile_range);
   uint32_t* counts = at<uint32_t>(ws, L.tile_range) + 2 * (int64_t)L.T;
+  uint32_t* split_count = counts + kOrderBuckets;
   if (L.cap > 0)
     SVR_LAUNCH("tile_ranges", k_tile_ranges, dim3((unsigned)((L.cap + kBlock - 1) / kBlock)),
                dim3(kBlock), 0, s, keys, &at<WsHeader>(ws, L.hdr)->n_entries, L.cap, 3 * L.L + 3,
                (uint32_t)L.T, range);
   const dim3 tg((unsigned)((L.T + kBlock - 1) / kBlock));
   SVR_LAUNCH("tile_order", k_tile_bucket, tg, dim3(kBlock), 0, s, range, (uint32_t)L.T, counts,
-             at<uint32_t>(ws, L.tile_rank));
+             at<uint32_t>(ws, L.tile_rank), split_count, at<uint32_t>(ws, L.split_base),
+             at<uint2>(ws, L.split_items), (uint32_t)L.max_split, &at<WsHeader>(ws, L.hdr)->error);
   SVR_LAUNCH("tile_order", k_tile_scatter, tg, dim3(kBlock), 0, s, range, (uint32_t)L.T, counts,
              at<uint32_t>(ws, L.tile_rank), at<uint32_t>(ws, L.tile_order));
   return hipGetLastError();

@@ -150,7 +150,10 @@ def test_workspace_parts_sum_to_total():
         # count, offset, rect (4 + 8 + 8 B) and a 64-byte record per (voxel, camera)
         nv = 5000 * n_cams
         assert 84 * nv <= parts["per_voxel_camera_records"] <= 84 * nv + 4 * 256
-        assert 8 * 100 * 60 * n_cams <= parts["per_pixel_state"] <= 8 * 6000 * n_cams + 512
+        # 8 B per pixel, plus a 16 B checkpoint per pixel of a 16x16 tile for
+        # each possible backward chunk (capacity / 256 + 1)
+        ck = (70000 // 256 + 1) * 256 * 16
+        assert 8 * 6000 * n_cams + ck <= parts["per_pixel_state"] <= 8 * 6000 * n_cams + ck + 768
     with pytest.raises(ValueError):
         o.K = 0
         _abi.svr_workspace_parts(sc, cams, 1, o)

@@ -34,10 +34,10 @@ def _say(msg):
     print(msg, flush=True)
 
 
-def _gpu_frame(torch, scene, cams, K, t_stop=1e-4, act=0, grad=None, sync=True):
+def _gpu_frame(torch, scene, cams, K, t_stop=1e-4, act=0, grad=None, sync=True, tile=16):
     from paper_2412_04459_amd.render import DeviceScene, Rasterizer
     ds = DeviceScene(scene)
-    rast = Rasterizer(ds, cams, K=K, t_stop=t_stop, activation=act, sync_count=sync)
+    rast = Rasterizer(ds, cams, K=K, t_stop=t_stop, activation=act, sync_count=sync, tile=tile)
     rgba = rast.forward()
     out = {"rast": rast, "rgba": rgba.cpu().numpy().astype(np.float64)}
     if grad is not None:
@@ -203,6 +203,31 @@ def test_render_bwd_matches_oracle(torch_dev, case, K, act):
     g[ref0["flags"] != 0] = 0.0
     ref = oracle.render(scene, cams[0], K=K, activation=act, grad_rgba=g.astype(np.float64))
     out = _gpu_frame(torch, scene, cams, K=K, act=act, grad=g)
+    _check_rgba(out["rgba"], ref0)
+    _check_grad(out["grad_grid"], ref["grad_grid"], "grad_grid")
+    _check_grad(out["grad_sh"], ref["grad_sh"], "grad_sh")
+
+
+@pytest.mark.parametrize("tile,K,act", [(8, 2, 0), (32, 1, 1), (16, 3, 0)])
+def test_render_bwd_split_heavy_tiles(torch_dev, tile, K, act):
+    """Tiles with more than 256 entries run their backward as 256-entry chunks,
+    one workgroup each, started from the forward's checkpoints.  The opaque
+    shell has tiles of several chunks with early termination inside them; the
+    gradients must match the oracle as for unsplit tiles."""
+    torch = torch_dev
+    scene, cams = S.sphere_shell_scene(opaque=True), [S.sphere_shell_camera()]
+    _say("render bwd, split tiles, tile %d K=%d act=%d" % (tile, K, act))
+    P = cams[0].W * cams[0].H
+    g = S.upstream_grads(P, 6)
+    ref0 = oracle.render(scene, cams[0], K=K, activation=act)
+    g[ref0["flags"] != 0] = 0.0
+    ref = oracle.render(scene, cams[0], K=K, activation=act, grad_rgba=g.astype(np.float64))
+    out = _gpu_frame(torch, scene, cams, K=K, act=act, grad=g, tile=tile)
+    rast = out["rast"]
+    keys, _ = rast.sorted_entries(rast.n_entries)
+    tiles = keys.cpu().numpy().view(np.uint64) >> np.uint64(3 * scene.max_level + 3)
+    per_tile = np.bincount(tiles.astype(np.int64))
+    assert per_tile.max() > 2 * 256, "no tile of three or more chunks"
     _check_rgba(out["rgba"], ref0)
     _check_grad(out["grad_grid"], ref["grad_grid"], "grad_grid")
     _check_grad(out["grad_sh"], ref["grad_sh"], "grad_sh")
