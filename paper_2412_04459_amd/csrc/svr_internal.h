@@ -124,6 +124,15 @@ __device__ __forceinline__ int sign_bits(float dx, float dy, float dz) {
 
 // ---- launchers (all asynchronous on `s`) ----------------------------------
 // preprocess
+// Logical block of workgroup b when the grid has 8 * ceil(nblocks / 8)
+// workgroups: workgroups are dealt to the 8 XCDs round-robin, so this gives
+// each XCD a contiguous range of logical blocks (neighbouring blocks then share
+// that XCD's L2).  Returns >= nblocks for the padding workgroups.
+__device__ __forceinline__ int64_t xcd_block(int64_t b, int64_t nblocks) {
+  const int64_t per = (nblocks + 7) >> 3;
+  return (b & 7) * per + (b >> 3);
+}
+
 // order LDS accesses between the lanes of one wave (no workgroup barrier)
 __device__ __forceinline__ void wave_sync_lds() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");

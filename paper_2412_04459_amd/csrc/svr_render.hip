@@ -278,7 +278,7 @@ __device__ __forceinline__ float segment_x(const LdsBatch<NB>& B, int j, double 
 // and early termination are those of the plain per-pixel walk.
 template <int TS>
 struct DenseCfg {
-  static constexpr int kListCap = TS == 32 ? 8 : 16;
+  static constexpr int kListCap = 8;
 };
 
 template <int CAP>
@@ -556,6 +556,9 @@ __device__ __forceinline__ void render_tile_bwd(const RenderArgs& A, int g, uint
       last = lp;
     }
   }
+  // transmittance just behind the current hit: exp(-tau) before tau drops by
+  // the hit's x, carried from one hit to the one before it
+  float Tnext = __expf(-tau);
   if (tid == 0) s_lmax = e_lo;
   __syncthreads();
   if (last > e_lo) atomicMax(&s_lmax, last);
@@ -585,7 +588,6 @@ __device__ __forceinline__ void render_tile_bwd(const RenderArgs& A, int g, uint
         const float x = segment_x<KT, ACT, true>(B, j, r.dx, r.dy, r.dz, a, lseg, A.K, dw);
         const float lK = (float)lseg / (float)(KT > 0 ? KT : A.K);
         const float alpha = alpha_of(x);
-        const float Tnext = __expf(-tau);
         tau -= x;
         const float Ti = __expf(-tau);
         const float cr = B.cr[j], cg = B.cg[j], cb = B.cb[j];
@@ -596,6 +598,7 @@ __device__ __forceinline__ void render_tile_bwd(const RenderArgs& A, int g, uint
         U0 = __fmaf_rn(wgt, cr, U0);
         U1 = __fmaf_rn(wgt, cg, U1);
         U2 = __fmaf_rn(wgt, cb, U2);
+        Tnext = Ti;
         const float f = dLdx * lK;
 #pragma unroll
         for (int m = 0; m < 8; ++m) gv[m] = f * dw[m];
@@ -871,7 +874,10 @@ __global__ __launch_bounds__(kBlock) void k_grid_gather(int64_t M, const int32_t
                                                         const float* __restrict__ g_corner,
                                                         float* __restrict__ grad_grid,
                                                         int accumulate) {
-  const int64_t m = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  // grid points of one XCD are contiguous: they share voxels, whose 8 corner
+  // gradients sit in one 32-byte block, so that block is read once per L2
+  const int64_t nb = (M + kBlock - 1) / kBlock;
+  const int64_t m = xcd_block(blockIdx.x, nb) * kBlock + threadIdx.x;
   if (m >= M) return;
   float acc = 0.f;
   const int32_t e1 = off[m + 1];
@@ -902,7 +908,8 @@ hipError_t launch_sh_bwd(const svr_scene& sc, const CamSet& cams, const Layout& 
 #undef SVR_SHB
   }
   if (grad_grid && gather && sc.n_grid > 0) {
-    SVR_LAUNCH("grid_gather", k_grid_gather, dim3((unsigned)((sc.n_grid + kBlock - 1) / kBlock)),
+    const int64_t nb = (sc.n_grid + kBlock - 1) / kBlock;
+    SVR_LAUNCH("grid_gather", k_grid_gather, dim3((unsigned)(((nb + 7) >> 3) << 3)),
                dim3(kBlock), 0, s, sc.n_grid, sc.grid_adj_off, sc.grid_adj,
                at<float>(ws, L.g_corner), grad_grid, accumulate ? 1 : 0);
   }
