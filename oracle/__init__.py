@@ -45,7 +45,7 @@ def _load():
         P = ctypes.c_void_p
         I64, I32, D = ctypes.c_int64, ctypes.c_int, ctypes.c_double
         _lib.oracle_render.argtypes = [I64, P, P, P, P, I64, P, I32, P, I32, D, I32, D, I64, P,
-                                       P, P, P, P, P, P, I32, P, P, P, I32]
+                                       P, P, P, P, P, P, I32, P, P, P, P, P, I32]
         _lib.oracle_render.restype = I32
         _lib.oracle_voxel_tiles.argtypes = [I64, P, P, P, I32, I32, D, D, P, P]
         _lib.oracle_voxel_tiles.restype = None
@@ -120,11 +120,14 @@ def morton_order(path: int, s: int) -> int:
 # rendering and gradients
 # --------------------------------------------------------------------------
 def render(scene, cam, K: int, t_stop: float = 1e-4, activation: int = 0, pixels=None,
-           band: float = 1e-3, grad_rgba=None, max_seq: int = 0, nthreads: int = 0) -> dict:
+           band: float = 1e-3, grad_rgba=None, max_seq: int = 0, nthreads: int = 0,
+           train_stats: bool = False) -> dict:
     """Brute-force FP64 render of the listed pixels (all when None).
 
-    Returns dict(rgba, rgba_alt, flags, ncomp, nhit[, seq][, grad_grid, grad_sh]).
-    ``grad_rgba`` (npix,4) gives dL/d rgba for L = sum <grad_rgba, rgba>."""
+    Returns dict(rgba, rgba_alt, flags, ncomp, nhit[, seq][, grad_grid, grad_sh]
+    [, max_weight][, priority]).  ``grad_rgba`` (npix,4) gives dL/d rgba for
+    L = sum <grad_rgba, rgba>.  ``train_stats`` adds the per-voxel maximum
+    blending weight and (with grad_rgba) the subdivision priority."""
     lib = _load()
     W, H = cam.W, cam.H
     if pixels is None:
@@ -151,11 +154,17 @@ def render(scene, cam, K: int, t_stop: float = 1e-4, activation: int = 0, pixels
         g = np.ascontiguousarray(grad_rgba, np.float64).reshape(npix, 4)
         gg = np.zeros(M, np.float64)
         gs = np.zeros(sh.shape, np.float64)
+    mw = np.zeros(N, np.float64) if train_stats else None
+    pr = np.zeros(N, np.float64) if (train_stats and g is not None) else None
     lib.oracle_render(N, _p(center), _p(size), _p(vg), _p(raw), M, _p(sh), int(scene.sh_degree),
                       _p(ca), int(K), float(t_stop), int(activation), float(band), npix,
                       _p(pixels), _p(rgba), _p(alt), _p(flags), _p(ncomp), _p(nhit), _p(seq),
-                      int(max_seq), _p(g), _p(gg), _p(gs), int(nthreads))
+                      int(max_seq), _p(g), _p(gg), _p(gs), _p(mw), _p(pr), int(nthreads))
     out = dict(rgba=rgba, rgba_alt=alt, flags=flags, ncomp=ncomp, nhit=nhit, pixels=pixels)
+    if mw is not None:
+        out["max_weight"] = mw
+    if pr is not None:
+        out["priority"] = pr
     if seq is not None:
         out["seq"] = seq
     if g is not None:

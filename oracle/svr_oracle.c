@@ -325,9 +325,11 @@ static int64_t collect_hits(const scene_t* S, const double o[3], const double d[
   return n;
 }
 
-/* gradient record of one composited hit */
+/* record of one composited hit */
 typedef struct {
   int64_t id;
+  double w;     /* blending weight T_i alpha_i */
+  double prio;  /* |alpha_i dL/dalpha_i| */
   double g[11]; /* dL/dV[8], dL/dc[3] */
   double pre[3];
   double Y[16];
@@ -346,13 +348,18 @@ typedef struct {
  *   seq[p*max_seq+...]  composited voxel ids in order (if seq != NULL)
  * With g_rgba != NULL also accumulates, in pixel order, dL/d grid_raw and
  * dL/d sh for L = sum_p <g_rgba[p], rgba[p]>.
+ * Training statistics of Sec. 3.2.2 (NULL: not computed), per voxel over the
+ * listed pixels' composited hits:
+ *   max_weight[N]  max of the blending weight T_i alpha_i ("Pruning")
+ *   priority[N]    sum of |alpha_i dL/dalpha_i| (eq. priority; needs g_rgba)
  */
 int oracle_render(int64_t N, const double* center, const double* size, const int32_t* vox_grid,
                   const double* grid_raw, int64_t M, const double* sh, int sh_degree,
                   const double* cam, int K, double t_stop, int act, double band, int64_t npix,
                   const int64_t* pix, double* rgba, double* rgba_alt, uint8_t* flags,
                   int32_t* ncomp, int32_t* nhit, int32_t* seq, int max_seq, const double* g_rgba,
-                  double* grad_grid, double* grad_sh, int nthreads) {
+                  double* grad_grid, double* grad_sh, double* max_weight, double* priority,
+                  int nthreads) {
   scene_t S = {N, center, size, vox_grid, grid_raw, sh, sh_degree};
   int W = (int)cam[0];
   int nb = (sh_degree + 1) * (sh_degree + 1);
@@ -360,7 +367,8 @@ int oracle_render(int64_t N, const double* center, const double* size, const int
   cam_origin(cam, o);
   grec_t** recs = NULL;
   int64_t* nrec = NULL;
-  if (g_rgba) {
+  if (!g_rgba) priority = NULL;
+  if (g_rgba || max_weight) {
     recs = (grec_t**)calloc((size_t)npix, sizeof(grec_t*));
     nrec = (int64_t*)calloc((size_t)npix, sizeof(int64_t));
   }
@@ -419,7 +427,7 @@ int oracle_render(int64_t N, const double* center, const double* size, const int
           if (seq) for (int64_t q = nc; q < max_seq; ++q) seq[p * max_seq + q] = -1;
           /* adjoint of the plain-rule result (eq. alpha_blend, Supp. A.2   */
           /* gradient of alpha): walk the composited hits back to front     */
-          if (g_rgba && nc > 0) {
+          if ((g_rgba || max_weight) && nc > 0) {
             grec_t* R = (grec_t*)malloc((size_t)nc * sizeof(grec_t));
             double* Ti = (double*)malloc((size_t)nc * sizeof(double));
             double* xs = (double*)malloc((size_t)nc * sizeof(double));
@@ -427,12 +435,15 @@ int oracle_render(int64_t N, const double* center, const double* size, const int
             for (int64_t h = 0; h < nc; ++h) {
               Ti[h] = Tt;
               xs[h] = segment_depth(&S, hits[h].id, o, d, hits[h].a, hits[h].b, K, act, NULL);
+              R[h].id = hits[h].id;
+              R[h].w = Tt * (1.0 - exp(-xs[h]));
+              R[h].prio = 0;
               Tt *= exp(-xs[h]);
             }
             double Tfin = Tt;
-            const double* g = g_rgba + p * 4;
+            const double* g = g_rgba ? g_rgba + p * 4 : NULL;
             double Sfx[3] = {0, 0, 0}; /* colour of the hits behind h, seen from just behind h */
-            for (int64_t h = nc - 1; h >= 0; --h) {
+            for (int64_t h = nc - 1; g && h >= 0; --h) {
               int64_t i = hits[h].id;
               double dxdV[8];
               double x = segment_depth(&S, i, o, d, hits[h].a, hits[h].b, K, act, dxdV);
@@ -449,6 +460,10 @@ int oracle_render(int64_t N, const double* center, const double* size, const int
               for (int ch = 0; ch < 3; ++ch) dot += g[ch] * (rgb[ch] - Sfx[ch]);
               double dLdx = Ti[h] * exp(-x) * dot + g[3] * Tfin;
               for (int m = 0; m < 8; ++m) R[h].g[m] = dLdx * dxdV[m];
+              /* subdivision priority term (Sec. 3.2.2 eq. priority) from the
+                 same dL/dalpha_h, with 1 - alpha_h = exp(-x_h) */
+              double dLdalpha = Ti[h] * dot + g[3] * Tfin / exp(-x);
+              R[h].prio = fabs(alpha * dLdalpha);
               for (int ch = 0; ch < 3; ++ch) Sfx[ch] = alpha * rgb[ch] + (1.0 - alpha) * Sfx[ch];
             }
             free(Ti);
@@ -468,13 +483,18 @@ int oracle_render(int64_t N, const double* center, const double* size, const int
     }
     free(hits);
   }
-  if (g_rgba) {
+  if (recs) {
     /* deterministic scatter in pixel order */
-    if (grad_grid) memset(grad_grid, 0, (size_t)M * sizeof(double));
-    if (grad_sh) memset(grad_sh, 0, (size_t)N * nb * 3 * sizeof(double));
+    if (g_rgba && grad_grid) memset(grad_grid, 0, (size_t)M * sizeof(double));
+    if (g_rgba && grad_sh) memset(grad_sh, 0, (size_t)N * nb * 3 * sizeof(double));
+    if (max_weight) memset(max_weight, 0, (size_t)N * sizeof(double));
+    if (priority) memset(priority, 0, (size_t)N * sizeof(double));
     for (int64_t p = 0; p < npix; ++p) {
       for (int64_t h = 0; h < nrec[p]; ++h) {
         grec_t* r = &recs[p][h];
+        if (max_weight && r->w > max_weight[r->id]) max_weight[r->id] = r->w;
+        if (priority) priority[r->id] += r->prio;
+        if (!g_rgba) continue;
         if (grad_grid)
           for (int m = 0; m < 8; ++m) grad_grid[vox_grid[r->id * 8 + m]] += r->g[m];
         if (grad_sh)

@@ -447,3 +447,78 @@ def test_tile_assignment_is_conservative(which):
     # the must set is inside the may set
     ok = r_must[:, 0] <= r_must[:, 1]
     assert np.all(r_may[ok, 0] <= r_must[ok, 0]) and np.all(r_may[ok, 1] >= r_must[ok, 1])
+
+
+# --------------------------------------------------------------------------
+# training statistics (Sec. 3.2.2 "Adaptive Pruning and Subdivision")
+# --------------------------------------------------------------------------
+def _column_scene(densities, cols):
+    """A column of level-3 voxels along +z at (1, 1, k), uniform raw density
+    per voxel (> 1.1: the linear branch of explin, so x = edge * density)."""
+    n = len(densities)
+    ijk = [[1, 1, k] for k in range(n)]
+
+    def raw(g):
+        k = np.clip(np.floor(g[:, 2] * 8 - 1e-9).astype(int), 0, n - 1)
+        return np.asarray(densities, np.float64)[k]
+    return S.scene_from_voxels((0.5, 0.5, 0.5), 1.0, 3, ijk, [3] * n, grid_raw=raw,
+                               sh=np.stack([_dc_sh(c)[0] for c in cols], 0))
+
+
+def _composite(alpha, cols, g):
+    """L = <g_rgb, sum T_i alpha_i c_i> + g_A (1 - prod(1 - alpha_i))."""
+    T, C = 1.0, np.zeros(3)
+    for a, c in zip(alpha, cols):
+        C += T * a * c
+        T *= 1 - a
+    return float(np.dot(g[:3], C) + g[3] * (1 - T))
+
+
+def test_max_weight_and_priority_closed_forms():
+    # densities are piecewise constant per voxel only when the corner values
+    # agree, so use one density for all voxels of the column
+    dens = [4.0, 4.0, 4.0, 4.0]
+    rng = np.random.default_rng(5)
+    cols = rng.random((4, 3)).astype(np.float32).astype(np.float64)
+    sc = _column_scene(dens, cols)
+    cam = _axis_camera(0.1875, 0.1875)
+    g = np.array([[0.3, -1.2, 0.7, 0.9]])
+    out = oracle.render(sc, cam, K=2, grad_rgba=g, train_stats=True)
+    x = 0.125 * 4.0                       # edge 1/8, explin linear branch
+    alpha = np.full(4, 1 - math.exp(-x))
+    T = np.cumprod(np.concatenate([[1.0], 1 - alpha[:-1]]))
+    assert np.allclose(out["max_weight"], T * alpha, rtol=1e-12)
+    # the colours the scene holds: the stored (fp32) DC coefficient times Y_00
+    col = sc.sh[:, 0, :].astype(np.float64) * (0.5 / math.sqrt(math.pi))
+    # alpha_i dL/dalpha_i by central differences of the compositing sum in
+    # alpha_i -> alpha_i (1 + e)
+    for i in range(4):
+        def L(e):
+            a = alpha.copy()
+            a[i] *= 1 + e
+            return _composite(a, col, g[0])
+        fd = (L(1e-6) - L(-1e-6)) / 2e-6
+        assert out["priority"][i] == pytest.approx(abs(fd), rel=1e-8, abs=1e-12)
+
+
+def test_max_weight_is_a_max_and_priority_a_sum_over_pixels():
+    # two pixels through the same column; the statistics combine per voxel
+    sc = _column_scene([2.0] * 3, np.random.default_rng(6).random((3, 3)))
+    cam = S.camera_from_pose(2, 1, 200.0, 200.0, 1.0, 0.5, np.eye(3), -np.array([0.1875, 0.1875, -1.0]))
+    g = np.random.default_rng(7).normal(size=(2, 4))
+    both = oracle.render(sc, cam, K=1, grad_rgba=g, train_stats=True)
+    one = [oracle.render(sc, cam, K=1, pixels=[p], grad_rgba=g[p:p + 1], train_stats=True)
+           for p in (0, 1)]
+    assert np.array_equal(both["max_weight"], np.maximum(one[0]["max_weight"], one[1]["max_weight"]))
+    assert np.allclose(both["priority"], one[0]["priority"] + one[1]["priority"], rtol=1e-14)
+    assert (both["max_weight"] > 0).all() and (both["priority"] > 0).all()
+
+
+def test_max_weight_respects_early_termination():
+    # opaque column (x = 2 per voxel): only the composited voxels get a weight
+    sc = _column_scene([16.0] * 8, np.random.default_rng(8).random((8, 3)))
+    out = oracle.render(sc, _axis_camera(0.1875, 0.1875), K=2, t_stop=1e-4, train_stats=True)
+    w = out["max_weight"]
+    Ts = np.exp(-2.0 * np.arange(5))
+    assert np.allclose(w[:5], Ts * (1 - math.exp(-2.0)), rtol=1e-12)
+    assert (w[5:] == 0).all()
