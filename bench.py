@@ -356,6 +356,25 @@ def main():
     elapsed_ms = min(elapsed_ms, ev0.elapsed_time(ev1))
     eager_ms_step = elapsed_ms / args.steps
 
+    # the same steps with the training statistics on (max blending weight in
+    # the forward, subdivision priority in the backward)
+    mw = torch.zeros(scene.n_voxels, dtype=torch.float32, device="cuda")
+    pr = torch.zeros_like(mw)
+
+    def step_stats(i):
+        rast.set_cameras([cams[i % len(cams)]])
+        rast.forward(max_weight=mw)
+        rast.backward(grad, priority=pr)
+
+    torch.cuda.synchronize()
+    ev0.record()
+    for i in range(args.steps):
+        step_stats(i)
+    ev1.record()
+    torch.cuda.synchronize()
+    stats_ms_step = ev0.elapsed_time(ev1) / args.steps
+    del mw, pr
+
     # the same frames replayed from one captured hipGraph per view (no host
     # launch overhead); this is the headline number
     gstream = torch.cuda.Stream()
@@ -423,6 +442,8 @@ def main():
         "frames_per_s": 1e3 / ms_step,
         "launch": "one hipGraph per view, replayed on one stream",
         "eager": {"ms_per_step": eager_ms_step, "mpix_s": P / (eager_ms_step / 1e3) / 1e6},
+        "with_train_stats": {"ms_per_step": stats_ms_step,
+                             "overhead": stats_ms_step / eager_ms_step - 1.0},
         "frame_hbm": {"bytes": fbytes, "achieved_GBs": frame_gbs, "peak_GBs": HBM_PEAK_GBS,
                       "frac": frame_gbs / HBM_PEAK_GBS},
         "roofline": roof,

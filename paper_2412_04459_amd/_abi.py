@@ -48,13 +48,17 @@ class svr_opts(ctypes.Structure):
                 ("entry_capacity", I64), ("persistent", I32), ("accumulate", I32)]
 
 
+class svr_train_stats(ctypes.Structure):
+    _fields_ = [("max_weight", ctypes.c_void_p), ("priority", ctypes.c_void_p)]
+
+
 _SIGS = {
     "svr_workspace_bytes": (ctypes.c_size_t, [P, P, ctypes.c_int, P]),
     "svr_workspace_parts": (ctypes.c_int, [P, P, ctypes.c_int, P, P, ctypes.c_int]),
     "svr_preprocess": (ctypes.c_int, [P, P, ctypes.c_int, P, P, ctypes.c_size_t, P, P]),
     "svr_sort": (ctypes.c_int, [P, P, ctypes.c_int, P, P, ctypes.c_size_t, I64, P]),
-    "svr_render_fwd": (ctypes.c_int, [P, P, ctypes.c_int, P, P, ctypes.c_size_t, P, P]),
-    "svr_render_bwd": (ctypes.c_int, [P, P, ctypes.c_int, P, P, ctypes.c_size_t, P, P, P, P]),
+    "svr_render_fwd": (ctypes.c_int, [P, P, ctypes.c_int, P, P, ctypes.c_size_t, P, P, P]),
+    "svr_render_bwd": (ctypes.c_int, [P, P, ctypes.c_int, P, P, ctypes.c_size_t, P, P, P, P, P]),
     "svr_check_overflow": (ctypes.c_int, [P, P, ctypes.c_int, P, P, ctypes.c_size_t, P, P]),
     "svr_copy_sorted": (ctypes.c_int, [P, P, ctypes.c_int, P, P, ctypes.c_size_t, P, P, I64, P]),
     "svr_radix_sort_scratch_bytes": (ctypes.c_size_t, [I64, ctypes.c_int]),
@@ -63,7 +67,7 @@ _SIGS = {
     "svr_timing_enable": (ctypes.c_int, [ctypes.c_int]),
     "svr_timing_read": (ctypes.c_int, [P, ctypes.c_int, P, P, ctypes.c_int, P]),
     "svr_graph_capture": (ctypes.c_int, [P, P, ctypes.c_int, P, P, ctypes.c_size_t, P, P, P, P, P,
-                                         P]),
+                                         P, P]),
     "svr_graph_launch": (ctypes.c_int, [P, P]),
     "svr_graph_destroy": (ctypes.c_int, [P]),
     "svr_grid_adjacency_scratch_bytes": (ctypes.c_size_t, [I64, I64]),
@@ -154,13 +158,15 @@ def svr_sort(scene, cams, n_cams, opts, ws, ws_bytes, n_entries_hint, stream):
                            stream)
 
 
-def svr_render_fwd(scene, cams, n_cams, opts, ws, ws_bytes, rgba, stream):
-    return load().svr_render_fwd(_ref(scene), cams, n_cams, _ref(opts), ws, ws_bytes, rgba, stream)
+def svr_render_fwd(scene, cams, n_cams, opts, ws, ws_bytes, rgba, train, stream):
+    return load().svr_render_fwd(_ref(scene), cams, n_cams, _ref(opts), ws, ws_bytes, rgba,
+                                 _ref(train), stream)
 
 
-def svr_render_bwd(scene, cams, n_cams, opts, ws, ws_bytes, grad_rgba, grad_grid, grad_sh, stream):
+def svr_render_bwd(scene, cams, n_cams, opts, ws, ws_bytes, grad_rgba, grad_grid, grad_sh, train,
+                   stream):
     return load().svr_render_bwd(_ref(scene), cams, n_cams, _ref(opts), ws, ws_bytes, grad_rgba,
-                                 grad_grid, grad_sh, stream)
+                                 grad_grid, grad_sh, _ref(train), stream)
 
 
 def svr_check_overflow(scene, cams, n_cams, opts, ws, ws_bytes, required_entries, stream):
@@ -212,9 +218,9 @@ def kernel_times():
 
 
 def svr_graph_capture(scene, cams, n_cams, opts, ws, ws_bytes, rgba, grad_rgba, grad_grid, grad_sh,
-                      stream, graph_out):
+                      train, stream, graph_out):
     return load().svr_graph_capture(_ref(scene), cams, n_cams, _ref(opts), ws, ws_bytes, rgba,
-                                    grad_rgba, grad_grid, grad_sh, stream, graph_out)
+                                    grad_rgba, grad_grid, grad_sh, _ref(train), stream, graph_out)
 
 
 def svr_graph_launch(graph, stream):

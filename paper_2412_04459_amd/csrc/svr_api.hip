@@ -303,7 +303,8 @@ int svr_sort(const svr_scene* scene, const svr_camera* cams, int n_cams, const s
 }
 
 int svr_render_fwd(const svr_scene* scene, const svr_camera* cams, int n_cams,
-                   const svr_opts* opts, void* ws, size_t ws_bytes, float* rgba, void* stream) {
+                   const svr_opts* opts, void* ws, size_t ws_bytes, float* rgba,
+                   const svr_train_stats* train, void* stream) {
   Layout L;
   CamSet cs;
   int st = make_layout(scene, cams, n_cams, opts, &L, &cs);
@@ -311,13 +312,16 @@ int svr_render_fwd(const svr_scene* scene, const svr_camera* cams, int n_cams,
   if ((st = check_ws(L, ws, ws_bytes)) != SVR_OK) return st;
   if (!rgba && L.P > 0) return fail(SVR_E_INVALID, "null rgba");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  SVR_HIP(launch_render_fwd(*scene, cs, *opts, L, ws, sorted_vals(L, ws), rgba, s), "render fwd");
+  SVR_HIP(launch_render_fwd(*scene, cs, *opts, L, ws, sorted_vals(L, ws), rgba,
+                            train ? train->max_weight : nullptr, s),
+          "render fwd");
   return SVR_OK;
 }
 
 int svr_render_bwd(const svr_scene* scene, const svr_camera* cams, int n_cams,
                    const svr_opts* opts, void* ws, size_t ws_bytes, const float* grad_rgba,
-                   float* grad_grid, float* grad_sh, void* stream) {
+                   float* grad_grid, float* grad_sh, const svr_train_stats* train,
+                   void* stream) {
   Layout L;
   CamSet cs;
   int st = make_layout(scene, cams, n_cams, opts, &L, &cs);
@@ -325,7 +329,8 @@ int svr_render_bwd(const svr_scene* scene, const svr_camera* cams, int n_cams,
   if ((st = check_ws(L, ws, ws_bytes)) != SVR_OK) return st;
   if (!grad_rgba && L.P > 0) return fail(SVR_E_INVALID, "null grad_rgba");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  SVR_HIP(launch_render_bwd(*scene, cs, *opts, L, ws, sorted_vals(L, ws), grad_rgba, s),
+  SVR_HIP(launch_render_bwd(*scene, cs, *opts, L, ws, sorted_vals(L, ws), grad_rgba,
+                            train ? train->priority : nullptr, s),
           "render bwd");
   SVR_HIP(launch_sh_bwd(*scene, cs, L, ws, grad_grid, grad_sh, opts->accumulate != 0, s),
           "pre-process adjoint");
@@ -501,8 +506,8 @@ struct SvrGraph {
 
 int svr_graph_capture(const svr_scene* scene, const svr_camera* cams, int n_cams,
                       const svr_opts* opts, void* ws, size_t ws_bytes, float* rgba,
-                      const float* grad_rgba, float* grad_grid, float* grad_sh, void* stream,
-                      void** graph_out) {
+                      const float* grad_rgba, float* grad_grid, float* grad_sh,
+                      const svr_train_stats* train, void* stream, void** graph_out) {
   if (!graph_out) return fail(SVR_E_INVALID, "null graph_out");
   *graph_out = nullptr;
   if (!stream) return fail(SVR_E_INVALID, "capture needs a non-default stream");
@@ -521,10 +526,11 @@ int svr_graph_capture(const svr_scene* scene, const svr_camera* cams, int n_cams
   SVR_HIP(hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal), "begin capture");
   st = svr_preprocess(scene, cams, n_cams, opts, ws, ws_bytes, nullptr, stream);
   if (st == SVR_OK) st = svr_sort(scene, cams, n_cams, opts, ws, ws_bytes, -1, stream);
-  if (st == SVR_OK) st = svr_render_fwd(scene, cams, n_cams, opts, ws, ws_bytes, rgba, stream);
+  if (st == SVR_OK)
+    st = svr_render_fwd(scene, cams, n_cams, opts, ws, ws_bytes, rgba, train, stream);
   if (st == SVR_OK && grad_rgba)
     st = svr_render_bwd(scene, cams, n_cams, opts, ws, ws_bytes, grad_rgba, grad_grid, grad_sh,
-                        stream);
+                        train, stream);
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamEndCapture(s, &g);
   {

@@ -172,10 +172,10 @@ size_t grid_adjacency_scratch_bytes(int64_t N, int64_t M);
 // render
 hipError_t launch_render_fwd(const svr_scene& sc, const CamSet& cams, const svr_opts& o,
                              const Layout& L, void* ws, const uint32_t* vals, float* rgba,
-                             hipStream_t s);
+                             float* max_weight, hipStream_t s);
 hipError_t launch_render_bwd(const svr_scene& sc, const CamSet& cams, const svr_opts& o,
                              const Layout& L, void* ws, const uint32_t* vals,
-                             const float* grad_rgba, hipStream_t s);
+                             const float* grad_rgba, float* priority, hipStream_t s);
 hipError_t launch_sh_bwd(const svr_scene& sc, const CamSet& cams, const Layout& L, void* ws,
                          float* grad_grid, float* grad_sh, bool accumulate, hipStream_t s);
 

@@ -25,8 +25,9 @@
 //   dL/dc_i = g_rgb T_i alpha_i
 //   dL/dx_i = <g_rgb, T_{i+1} c_i - U_{i+1}> + g_A T_final
 //   dL/dV_m = dL/dx_i (l/K) sum_k act'(v_k) w_m(q_k)    (Supp. A.2 gradient)
-// and U_i = U_{i+1} + T_i alpha_i c_i.  The 11 per-hit gradients are summed
-// over the wave and added with one 11-lane float atomic.  A tile with more
+// and U_i = U_{i+1} + T_i alpha_i c_i.  The 11 per-hit gradients (12 with the
+// subdivision priority |alpha_i dL/dalpha_i| of Sec. 3.2.2) are summed over
+// the wave and added with one float atomic per value.  A tile with more
 // than kBwdChunk entries is split into chunks of that many entries, one
 // workgroup each: the forward saves, per pixel, tau and the colour still to
 // come at every chunk boundary it passes, which is all a chunk's reverse walk
@@ -90,6 +91,7 @@ struct LdsBatch {
   uint32_t meta[NB];                   // sign bits | block mask << 3
   uint32_t vid[NB];
   uint32_t rx[NB], ry[NB];             // pixel rectangle: u0 | u1 << 16, v0 | v1 << 16
+  uint32_t mw[NB];                     // max blending weight in this tile (float bits)
 };
 
 // arguments shared by the render kernels
@@ -116,6 +118,8 @@ struct RenderArgs {
   const uint32_t* split_count;  // number of items
   float4* ckpt;                 // per slot and pixel: (tau, suffix colour) at the chunk's end
   int max_split, split_wgs;
+  uint32_t* max_weight;         // training statistics (bit patterns of non-negative floats)
+  float* priority;
 };
 
 // next position in the render order for a persistent workgroup (-1: none left)
@@ -165,6 +169,7 @@ __device__ __forceinline__ void stage_entry(LdsBatch<NB>& B, int slot, uint32_t 
   B.vid[slot] = vid;
   B.rx[slot] = rc.x;
   B.ry[slot] = rc.y;
+  B.mw[slot] = 0u;
 }
 
 // Ray-box slab test (Supp. A.2 listing "ray_aabb") against staged entry j, in
@@ -360,6 +365,7 @@ __device__ __forceinline__ void render_tile_fwd(const RenderArgs& A, int g,
           if (x >= 0.f) {
             const int j = WL.jl[k][lane];
             const float wgt = Tr * alpha_of(x);
+            if (A.max_weight) atomicMax(&B.mw[j], __float_as_uint(wgt));
             C0 = __fmaf_rn(wgt, B.cr[j], C0);
             C1 = __fmaf_rn(wgt, B.cg[j], C1);
             C2 = __fmaf_rn(wgt, B.cb[j], C2);
@@ -402,7 +408,11 @@ __device__ __forceinline__ void render_tile_fwd(const RenderArgs& A, int g,
         ++n_ck;
       }
     }
-    if (__syncthreads_and(done)) break;
+    const bool all_done = __syncthreads_and(done);
+    // the batch's maxima, one global atomic per entry with a composited hit
+    if (!STATS && A.max_weight && tid < n && B.mw[tid] != 0u)
+      atomicMax(A.max_weight + B.vid[tid], B.mw[tid]);
+    if (all_done) break;
   }
   // the backward wants the colour still to come: final minus so far
   for (uint32_t k = 0; k < n_ck; ++k) {
@@ -453,7 +463,7 @@ __global__ __launch_bounds__(TS * TS) void k_render_fwd(RenderArgs A) {
 }
 
 // ---------------------------------------------------------------------------
-// Wave sum of 11 per-lane values by recursive halving with gfx950 cross-lane
+// Wave sum of 12 per-lane values by recursive halving with gfx950 cross-lane
 // VALU operations (no LDS): at each step a lane keeps one half of its values
 // and adds its partner lane's copy of that half.
 //   step 1: v_permlane32_swap pairs lane L with L ^ 32  (8 pairs -> 8 values)
@@ -494,12 +504,12 @@ constexpr int kDppRowHalfMirror = 0x141;
 constexpr int kDppQuadXor1 = 0xB1;  // quad_perm [1,0,3,2]
 constexpr int kDppQuadXor2 = 0x4E;  // quad_perm [2,3,0,1]
 
-__device__ __forceinline__ float wave_reduce11(float g0, float g1, float g2, float g3, float g4,
+__device__ __forceinline__ float wave_reduce12(float g0, float g1, float g2, float g3, float g4,
                                                float g5, float g6, float g7, float g8, float g9,
-                                               float g10) {
+                                               float g10, float g11) {
   const int lane = threadIdx.x & 63;
   const float s0 = swap32_sum(g0, g8), s1 = swap32_sum(g1, g9), s2 = swap32_sum(g2, g10);
-  const float s3 = swap32_sum(g3, 0.f), s4 = swap32_sum(g4, 0.f), s5 = swap32_sum(g5, 0.f);
+  const float s3 = swap32_sum(g3, g11), s4 = swap32_sum(g4, 0.f), s5 = swap32_sum(g5, 0.f);
   const float s6 = swap32_sum(g6, 0.f), s7 = swap32_sum(g7, 0.f);
   const float t0 = swap16_sum(s0, s4), t1 = swap16_sum(s1, s5);
   const float t2 = swap16_sum(s2, s6), t3 = swap16_sum(s3, s7);
@@ -532,17 +542,19 @@ __device__ __forceinline__ void render_tile_bwd(const RenderArgs& A, int g, uint
   const int qu0 = tx * TS, qv0 = ty * TS;
   const PixelRay r = make_ray<TS>(c, qu0, qv0, w, lane);
   const int slot = (lane >> 2) & 15;  // reduced value this lane ends up holding
-  const bool writer = (lane & 3) == 0 && slot < 11;
+  const bool prio = A.priority != nullptr;
+  const bool writer = (lane & 3) == 0 && slot < (prio ? 12 : 11);
 
   const uint2 rg = A.range[g];
   const uint32_t e_lo = rg.x + m_lo * (uint32_t)kBwdChunk;
   const uint32_t e_hi = min(rg.x + m_hi * (uint32_t)kBwdChunk, rg.y);
-  float tau = 0.f, gr = 0.f, gg = 0.f, gb = 0.f, ga = 0.f, Tfin = 1.f;
+  float tau = 0.f, gr = 0.f, gg = 0.f, gb = 0.f, ga = 0.f, Tfin = 1.f, tau_end = 0.f;
   float U0 = 0.f, U1 = 0.f, U2 = 0.f;  // colour composited after the current entry
   uint32_t last = e_lo;
   if (r.inside) {
     const int64_t p = c.pix_off + (int64_t)r.v * c.W + r.u;
     const float tau_fin = A.px_tau[p];
+    tau_end = tau_fin;
     const uint32_t lp = A.px_last[p];
     const float4 gq = A.grad_rgba[p];
     gr = gq.x; gg = gq.y; gb = gq.z; ga = gq.w;
@@ -579,9 +591,9 @@ __device__ __forceinline__ void render_tile_bwd(const RenderArgs& A, int g, uint
       bool hit = (b0 + (uint32_t)j < last) && ((meta & 7u) == r.spat);
       if (hit) hit = slab(B, j, r.idx, r.idy, r.idz, a, bb);
       if (__ballot(hit) == 0ull) continue;
-      float gv[11];
+      float gv[12];
 #pragma unroll
-      for (int m = 0; m < 11; ++m) gv[m] = 0.f;
+      for (int m = 0; m < 12; ++m) gv[m] = 0.f;
       if (hit) {
         float dw[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
         const double lseg = bb - a;
@@ -595,6 +607,14 @@ __device__ __forceinline__ void render_tile_bwd(const RenderArgs& A, int g, uint
         gv[8] = gr * wgt; gv[9] = gg * wgt; gv[10] = gb * wgt;
         const float dLdx = gr * (Tnext * cr - U0) + gg * (Tnext * cg - U1) +
                            gb * (Tnext * cb - U2) + ga * Tfin;
+        if (prio) {
+          // |alpha dL/dalpha| (eq. priority) = |T_i alpha <g, c - S> + g_A (e^{-(tau_fin - x)}
+          // - T_fin)|, S = U / T_{i+1} the colour behind seen from just behind (0 when
+          // T_{i+1} underflows: then nothing is composited behind and U = 0)
+          const float iT = Tnext > 0.f ? 1.f / Tnext : 0.f;
+          gv[11] = fabsf(wgt * (gr * (cr - U0 * iT) + gg * (cg - U1 * iT) + gb * (cb - U2 * iT)) +
+                         ga * (__expf(x - tau_end) - Tfin));
+        }
         U0 = __fmaf_rn(wgt, cr, U0);
         U1 = __fmaf_rn(wgt, cg, U1);
         U2 = __fmaf_rn(wgt, cb, U2);
@@ -603,12 +623,13 @@ __device__ __forceinline__ void render_tile_bwd(const RenderArgs& A, int g, uint
 #pragma unroll
         for (int m = 0; m < 8; ++m) gv[m] = f * dw[m];
       }
-      const float tot = wave_reduce11(gv[0], gv[1], gv[2], gv[3], gv[4], gv[5], gv[6], gv[7],
-                                      gv[8], gv[9], gv[10]);
+      const float tot = wave_reduce12(gv[0], gv[1], gv[2], gv[3], gv[4], gv[5], gv[6], gv[7],
+                                      gv[8], gv[9], gv[10], gv[11]);
       if (writer) {
         const uint32_t vid = B.vid[j];
-        float* dst = slot < 8 ? A.g_corner + (int64_t)vid * 8 + slot
-                              : A.g_rgb + ((int64_t)vid * A.n_cams + ci) * 3 + (slot - 8);
+        float* dst = slot < 8    ? A.g_corner + (int64_t)vid * 8 + slot
+                     : slot < 11 ? A.g_rgb + ((int64_t)vid * A.n_cams + ci) * 3 + (slot - 8)
+                                 : A.priority + vid;
         unsafeAtomicAdd(dst, tot);
       }
     }
@@ -780,6 +801,8 @@ static RenderArgs render_args(const CamSet& cams, const svr_opts& o, const Layou
   A.ckpt = at<float4>(ws, L.ckpt);
   A.max_split = (int)L.max_split;
   A.split_wgs = (int)min((int64_t)kSplitWgs, L.max_split);
+  A.max_weight = nullptr;
+  A.priority = nullptr;
   return A;
 }
 
@@ -836,10 +859,11 @@ static hipError_t launch_render(RKind kind, const RenderArgs& A, const svr_opts&
 
 hipError_t launch_render_fwd(const svr_scene& sc, const CamSet& cams, const svr_opts& o,
                              const Layout& L, void* ws, const uint32_t* vals, float* rgba,
-                             hipStream_t s) {
+                             float* max_weight, hipStream_t s) {
   (void)sc;
   RenderArgs A = render_args(cams, o, L, ws, vals);
   A.rgba = reinterpret_cast<float4*>(rgba);
+  A.max_weight = reinterpret_cast<uint32_t*>(max_weight);
   return launch_render(RKind::kFwd, A, o, L, ws, s);
 }
 
@@ -855,7 +879,7 @@ hipError_t launch_render_stats(const svr_scene& sc, const CamSet& cams, const sv
 
 hipError_t launch_render_bwd(const svr_scene& sc, const CamSet& cams, const svr_opts& o,
                              const Layout& L, void* ws, const uint32_t* vals,
-                             const float* grad_rgba, hipStream_t s) {
+                             const float* grad_rgba, float* priority, hipStream_t s) {
   (void)sc;
   FillSet z;
   z.add(at<uint32_t>(ws, L.g_corner), L.N * 8);
@@ -864,6 +888,7 @@ hipError_t launch_render_bwd(const svr_scene& sc, const CamSet& cams, const svr_
   if (e != hipSuccess) return e;
   RenderArgs A = render_args(cams, o, L, ws, vals);
   A.grad_rgba = reinterpret_cast<const float4*>(grad_rgba);
+  A.priority = priority;
   return launch_render(RKind::kBwd, A, o, L, ws, s);
 }
 

@@ -21,6 +21,17 @@ def _ptr(t: Optional[torch.Tensor]):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
 
+def _train(max_weight, priority):
+    """svr_train_stats for the given float32 [n_voxels] tensors, or None."""
+    if max_weight is None and priority is None:
+        return None
+    for t in (max_weight, priority):
+        if t is not None and (t.dtype != torch.float32 or not t.is_contiguous()):
+            raise ValueError("training statistics must be contiguous float32 tensors")
+    return _abi.svr_train_stats(None if max_weight is None else max_weight.data_ptr(),
+                                None if priority is None else priority.data_ptr())
+
+
 def _stream():
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
@@ -195,21 +206,28 @@ class Rasterizer:
         check(_abi.svr_sort(st, self.cam_arr, self.n_cams, self.opts, self._ws_ptr(),
                             self.ws_bytes, self.n_entries, _stream()), "svr_sort")
 
-    def render_fwd(self, grid_raw=None, sh=None, out: Optional[torch.Tensor] = None):
+    def render_fwd(self, grid_raw=None, sh=None, out: Optional[torch.Tensor] = None,
+                   max_weight: Optional[torch.Tensor] = None):
+        """``max_weight`` (float32 [n_voxels], zeroed by the caller once per
+        statistics window): per-voxel maximum blending weight, updated."""
         st = self.ds.struct(grid_raw, sh)
         if out is None:
             out = torch.empty((self.n_pixels, 4), dtype=torch.float32, device=self.ds.device)
         check(_abi.svr_render_fwd(st, self.cam_arr, self.n_cams, self.opts, self._ws_ptr(),
-                                  self.ws_bytes, _ptr(out), _stream()), "svr_render_fwd")
+                                  self.ws_bytes, _ptr(out), _train(max_weight, None), _stream()),
+              "svr_render_fwd")
         return out
 
-    def forward(self, grid_raw=None, sh=None, out=None):
+    def forward(self, grid_raw=None, sh=None, out=None, max_weight=None):
         self.preprocess(grid_raw, sh)
         self.sort()
-        return self.render_fwd(grid_raw, sh, out)
+        return self.render_fwd(grid_raw, sh, out, max_weight)
 
     def backward(self, grad_rgba: torch.Tensor, grid_raw=None, sh=None, grad_grid=None,
-                 grad_sh=None, want_grid=True, want_sh=True):
+                 grad_sh=None, want_grid=True, want_sh=True,
+                 priority: Optional[torch.Tensor] = None):
+        """``priority`` (float32 [n_voxels]): per-voxel subdivision priority,
+        accumulated into."""
         st = self.ds.struct(grid_raw, sh)
         g = grad_rgba.contiguous().float()
         if g.numel() != self.n_pixels * 4:
@@ -220,7 +238,8 @@ class Rasterizer:
             grad_sh = torch.empty_like(self.ds.sh)
         check(_abi.svr_render_bwd(st, self.cam_arr, self.n_cams, self.opts, self._ws_ptr(),
                                   self.ws_bytes, _ptr(g), _ptr(grad_grid if want_grid else None),
-                                  _ptr(grad_sh if want_sh else None), _stream()),
+                                  _ptr(grad_sh if want_sh else None), _train(None, priority),
+                                  _stream()),
               "svr_render_bwd")
         return grad_grid, grad_sh
 
@@ -237,7 +256,7 @@ class Rasterizer:
         torch.cuda.synchronize()
         check(_abi.svr_graph_capture(st, self.cam_arr, self.n_cams, self.opts, self._ws_ptr(),
                                      self.ws_bytes, _ptr(rgba), _ptr(grad_rgba), _ptr(grad_grid),
-                                     _ptr(grad_sh), ctypes.c_void_p(stream.cuda_stream),
+                                     _ptr(grad_sh), None, ctypes.c_void_p(stream.cuda_stream),
                                      ctypes.byref(h)), "svr_graph_capture")
         self._graph = h
         self._graph_keep = (rgba, grad_rgba, grad_grid, grad_sh)
@@ -262,7 +281,7 @@ class Rasterizer:
             torch.cuda.synchronize()
             check(_abi.svr_graph_capture(st, self.cam_arr, self.n_cams, self.opts,
                                          self._ws_ptr(), self.ws_bytes, _ptr(rgba),
-                                         _ptr(grad_rgba), _ptr(grad_grid), _ptr(grad_sh),
+                                         _ptr(grad_rgba), _ptr(grad_grid), _ptr(grad_sh), None,
                                          ctypes.c_void_p(stream.cuda_stream), ctypes.byref(h)),
                   "svr_graph_capture")
             self._view_graphs.append(h)

@@ -84,7 +84,7 @@ def test_invalid_scene_is_rejected(field, value):
     assert _abi.svr_workspace_bytes(sc, cams, 1, o) == 0
     for fn in (lambda: _abi.svr_sort(sc, cams, 1, o, ctypes.c_void_p(0x100000), 1 << 30, -1, None),
                lambda: _abi.svr_render_fwd(sc, cams, 1, o, ctypes.c_void_p(0x100000), 1 << 30,
-                                           ctypes.c_void_p(0x1000), None)):
+                                           ctypes.c_void_p(0x1000), None, None)):
         assert fn() == _abi.SVR_E_INVALID
 
 
@@ -124,7 +124,7 @@ def test_graph_entry_points_check_arguments():
     h = ctypes.c_void_p(0)
     # the NULL stream cannot be captured
     rc = _abi.svr_graph_capture(sc, cams, 1, o, ctypes.c_void_p(0x100000), 1 << 30, None, None,
-                                None, None, None, ctypes.byref(h))
+                                None, None, None, None, ctypes.byref(h))
     assert rc == _abi.SVR_E_INVALID and h.value is None
     assert _abi.svr_graph_launch(None, None) == _abi.SVR_E_INVALID
     assert _abi.svr_graph_destroy(None) == _abi.SVR_OK
