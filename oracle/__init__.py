@@ -45,7 +45,7 @@ def _load():
         P = ctypes.c_void_p
         I64, I32, D = ctypes.c_int64, ctypes.c_int, ctypes.c_double
         _lib.oracle_render.argtypes = [I64, P, P, P, P, I64, P, I32, P, I32, D, I32, D, I64, P,
-                                       P, P, P, P, P, P, I32, P, P, P, P, P, I32]
+                                       P, P, P, P, P, P, I32, P, P, P, P, P, P, P, P, P, I32]
         _lib.oracle_render.restype = I32
         _lib.oracle_voxel_tiles.argtypes = [I64, P, P, P, I32, I32, D, D, P, P]
         _lib.oracle_voxel_tiles.restype = None
@@ -121,13 +121,17 @@ def morton_order(path: int, s: int) -> int:
 # --------------------------------------------------------------------------
 def render(scene, cam, K: int, t_stop: float = 1e-4, activation: int = 0, pixels=None,
            band: float = 1e-3, grad_rgba=None, max_seq: int = 0, nthreads: int = 0,
-           train_stats: bool = False) -> dict:
+           train_stats: bool = False, depth_normal: bool = False, grad_depth=None,
+           grad_normal=None) -> dict:
     """Brute-force FP64 render of the listed pixels (all when None).
 
     Returns dict(rgba, rgba_alt, flags, ncomp, nhit[, seq][, grad_grid, grad_sh]
     [, max_weight][, priority]).  ``grad_rgba`` (npix,4) gives dL/d rgba for
     L = sum <grad_rgba, rgba>.  ``train_stats`` adds the per-voxel maximum
-    blending weight and (with grad_rgba) the subdivision priority."""
+    blending weight and (with grad_rgba) the subdivision priority.
+    ``depth_normal`` adds the depth image [npix] and normal image [npix, 3];
+    with grad_rgba, ``grad_depth`` [npix] and ``grad_normal`` [npix, 3] add
+    <grad_depth, depth> + <grad_normal, normal> to L."""
     lib = _load()
     W, H = cam.W, cam.H
     if pixels is None:
@@ -156,15 +160,25 @@ def render(scene, cam, K: int, t_stop: float = 1e-4, activation: int = 0, pixels
         gs = np.zeros(sh.shape, np.float64)
     mw = np.zeros(N, np.float64) if train_stats else None
     pr = np.zeros(N, np.float64) if (train_stats and g is not None) else None
+    dep = np.zeros(npix, np.float64) if depth_normal else None
+    nrm = np.zeros((npix, 3), np.float64) if depth_normal else None
+    gd = None if (g is None or grad_depth is None) else \
+        np.ascontiguousarray(grad_depth, np.float64).reshape(npix)
+    gn = None if (g is None or grad_normal is None) else \
+        np.ascontiguousarray(grad_normal, np.float64).reshape(npix, 3)
     lib.oracle_render(N, _p(center), _p(size), _p(vg), _p(raw), M, _p(sh), int(scene.sh_degree),
                       _p(ca), int(K), float(t_stop), int(activation), float(band), npix,
                       _p(pixels), _p(rgba), _p(alt), _p(flags), _p(ncomp), _p(nhit), _p(seq),
-                      int(max_seq), _p(g), _p(gg), _p(gs), _p(mw), _p(pr), int(nthreads))
+                      int(max_seq), _p(g), _p(gg), _p(gs), _p(mw), _p(pr), _p(dep), _p(nrm),
+                      _p(gd), _p(gn), int(nthreads))
     out = dict(rgba=rgba, rgba_alt=alt, flags=flags, ncomp=ncomp, nhit=nhit, pixels=pixels)
     if mw is not None:
         out["max_weight"] = mw
     if pr is not None:
         out["priority"] = pr
+    if dep is not None:
+        out["depth"] = dep
+        out["normal"] = nrm
     if seq is not None:
         out["seq"] = seq
     if g is not None:

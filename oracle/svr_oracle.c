@@ -303,6 +303,84 @@ static double segment_depth(const scene_t* S, int64_t i, const double o[3], cons
   return l / (double)K * sum;
 }
 
+/* Voxel normal (Sec. 3.1.1 "Voxel normal"; Supp. "Details of Voxel Normal"):  */
+/* the gradient of the trilinear raw-density field at the voxel centre,      */
+/* g = 0.25 [ (V100+V101+V110+V111) - (V000+V001+V010+V011), ... ], normalised; */
+/* zero when g = 0.  With dLdn != NULL, adds dL/dV for dL/dn = dLdn:          */
+/* dn/dg = (I - n n^T) / |g| and dg_b/dV_ijk = 0.25 (2 bit_b - 1).            */
+static void voxel_normal(const scene_t* S, int64_t i, double n[3], const double* dLdn,
+                         double dLdV[8]) {
+  double V[8];
+  for (int k = 0; k < 8; ++k) V[k] = S->grid_raw[S->vox_grid[i * 8 + k]];
+  /* corner index c = 4x + 2y + z: V_xyz = V[4x + 2y + z] */
+  double g[3];
+  g[0] = 0.25 * ((V[4] + V[5] + V[6] + V[7]) - (V[0] + V[1] + V[2] + V[3]));
+  g[1] = 0.25 * ((V[2] + V[3] + V[6] + V[7]) - (V[0] + V[1] + V[4] + V[5]));
+  g[2] = 0.25 * ((V[1] + V[3] + V[5] + V[7]) - (V[0] + V[2] + V[4] + V[6]));
+  double len = sqrt(g[0] * g[0] + g[1] * g[1] + g[2] * g[2]);
+  for (int a = 0; a < 3; ++a) n[a] = len > 0 ? g[a] / len : 0.0;
+  if (!dLdn || !(len > 0)) return;
+  double dLdg[3];
+  double nd = n[0] * dLdn[0] + n[1] * dLdn[1] + n[2] * dLdn[2];
+  for (int b = 0; b < 3; ++b) dLdg[b] = (dLdn[b] - n[b] * nd) / len;
+  for (int c = 0; c < 8; ++c) {
+    int bit[3] = {(c >> 2) & 1, (c >> 1) & 1, c & 1};
+    for (int b = 0; b < 3; ++b) dLdV[c] += dLdg[b] * 0.25 * (2.0 * bit[b] - 1.0);
+  }
+}
+
+/* Voxel depth (Sec. 3.1.1 "Voxel depth"; Supp. "Details of Voxel Depth"):     */
+/* the K samples of the segment with their own alphas                          */
+/*   alpha_k = 1 - exp(-(l/K) act(v_k)),  t_k = a + (k - 1/2)/K (b - a)        */
+/* composited locally: d = sum_k prod_{j<k} (1 - alpha_j) alpha_k t_k.         */
+/* With dddV != NULL also dd/dV for the 8 corner raw densities, through        */
+/* dd/dalpha_k = P_k (t_k - E_{k+1}) (P_k the product before k, E_{k+1} the    */
+/* depth of the samples after k composited from k+1 on) and                    */
+/* dalpha_k/dv_k = (1 - alpha_k) (l/K) act'(v_k).                              */
+#define OR_MAX_K 64
+static double segment_local_depth(const scene_t* S, int64_t i, const double o[3],
+                                  const double d[3], double a, double b, int K, int act,
+                                  double dddV[8]) {
+  double c[3], s = S->size[i];
+  for (int ax = 0; ax < 3; ++ax) c[ax] = S->center[ax * S->N + i];
+  double V[8];
+  for (int k = 0; k < 8; ++k) V[k] = S->grid_raw[S->vox_grid[i * 8 + k]];
+  double dn = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+  double l = (b - a) * dn;
+  double al[OR_MAX_K], tk[OR_MAX_K], ag[OR_MAX_K], w[OR_MAX_K][8];
+  if (K > OR_MAX_K) K = OR_MAX_K;
+  for (int k = 1; k <= K; ++k) {
+    double t = a + ((double)k - 0.5) / (double)K * (b - a);
+    double q[3];
+    for (int ax = 0; ax < 3; ++ax) q[ax] = (o[ax] + t * d[ax] - (c[ax] - 0.5 * s)) / s;
+    trilinear_weights(q, w[k - 1]);
+    double v = 0;
+    for (int m = 0; m < 8; ++m) v += w[k - 1][m] * V[m];
+    al[k - 1] = 1.0 - exp(-l / (double)K * oracle_act(v, act));
+    ag[k - 1] = oracle_act_grad(v, act);
+    tk[k - 1] = t * dn;
+  }
+  double dep = 0, P = 1.0;
+  for (int k = 0; k < K; ++k) {
+    dep += P * al[k] * tk[k];
+    P *= 1.0 - al[k];
+  }
+  if (dddV) {
+    for (int m = 0; m < 8; ++m) dddV[m] = 0;
+    /* E after sample k, walking back */
+    double E = 0, Pk[OR_MAX_K];
+    P = 1.0;
+    for (int k = 0; k < K; ++k) { Pk[k] = P; P *= 1.0 - al[k]; }
+    for (int k = K - 1; k >= 0; --k) {
+      double dd_dal = Pk[k] * (tk[k] - E);
+      double dal_dv = (1.0 - al[k]) * l / (double)K * ag[k];
+      for (int m = 0; m < 8; ++m) dddV[m] += dd_dal * dal_dv * w[k][m];
+      E = al[k] * tk[k] + (1.0 - al[k]) * E;
+    }
+  }
+  return dep;
+}
+
 /* collect and order the hits of one ray */
 static int64_t collect_hits(const scene_t* S, const double o[3], const double d[3], hit_t** buf,
                             int64_t* cap) {
@@ -351,7 +429,15 @@ typedef struct {
  * Training statistics of Sec. 3.2.2 (NULL: not computed), per voxel over the
  * listed pixels' composited hits:
  *   max_weight[N]  max of the blending weight T_i alpha_i ("Pruning")
- *   priority[N]    sum of |alpha_i dL/dalpha_i| (eq. priority; needs g_rgba)
+ *   priority[N]    sum of |alpha_i dL/dalpha_i| (eq. priority; needs g_rgba;
+ *                  the loss here is the rgba term)
+ * Depth and normal images (Sec. 3.1.1 "Voxel normal", "Voxel depth"; NULL:
+ * not computed), plain rule:
+ *   depth[p]       D = sum_i T_i d_i, d_i the voxel's locally composited
+ *                  sample depth (ray distance)
+ *   normal[p*3..]  N = sum_i T_i alpha_i n_i
+ * and, with g_rgba != NULL, g_depth[p] / g_normal[p*3..] (NULL: zero) add
+ * <g_depth, D> + <g_normal, N> to L.
  */
 int oracle_render(int64_t N, const double* center, const double* size, const int32_t* vox_grid,
                   const double* grid_raw, int64_t M, const double* sh, int sh_degree,
@@ -359,6 +445,7 @@ int oracle_render(int64_t N, const double* center, const double* size, const int
                   const int64_t* pix, double* rgba, double* rgba_alt, uint8_t* flags,
                   int32_t* ncomp, int32_t* nhit, int32_t* seq, int max_seq, const double* g_rgba,
                   double* grad_grid, double* grad_sh, double* max_weight, double* priority,
+                  double* depth, double* normal, const double* g_depth, const double* g_normal,
                   int nthreads) {
   scene_t S = {N, center, size, vox_grid, grid_raw, sh, sh_degree};
   int W = (int)cam[0];
@@ -394,7 +481,7 @@ int oracle_render(int64_t N, const double* center, const double* size, const int
       /* two passes: pass 0 the plain rule, pass 1 with the first banded
          decision flipped */
       for (int pass = 0; pass < 2; ++pass) {
-        double C[3] = {0, 0, 0}, T = 1.0;
+        double C[3] = {0, 0, 0}, T = 1.0, Dp = 0, Np[3] = {0, 0, 0};
         int flipped = 0;
         int64_t nc = 0;
         for (int64_t h = 0; h < nh; ++h) {
@@ -410,6 +497,13 @@ int oracle_render(int64_t N, const double* center, const double* size, const int
           double rgb[3], pre[3], Y[16];
           voxel_color(&S, i, o, rgb, pre, Y);
           for (int ch = 0; ch < 3; ++ch) C[ch] += T * alpha * rgb[ch];
+          if (pass == 0 && depth)
+            Dp += T * segment_local_depth(&S, i, o, d, hits[h].a, hits[h].b, K, act, NULL);
+          if (pass == 0 && normal) {
+            double n[3];
+            voxel_normal(&S, i, n, NULL, NULL);
+            for (int ax = 0; ax < 3; ++ax) Np[ax] += T * alpha * n[ax];
+          }
           T *= exp(-x);
           if (pass == 0 && seq && nc < max_seq) seq[p * max_seq + nc] = (int32_t)i;
           ++nc;
@@ -422,6 +516,8 @@ int oracle_render(int64_t N, const double* center, const double* size, const int
           out[p * 4 + 3] = 1.0 - T;
         }
         if (pass == 0) {
+          if (depth) depth[p] = Dp;
+          if (normal) for (int ax = 0; ax < 3; ++ax) normal[p * 3 + ax] = Np[ax];
           if (ncomp) ncomp[p] = (int32_t)nc;
           if (nhit) nhit[p] = (int32_t)nh;
           if (seq) for (int64_t q = nc; q < max_seq; ++q) seq[p * max_seq + q] = -1;
@@ -443,6 +539,10 @@ int oracle_render(int64_t N, const double* center, const double* size, const int
             double Tfin = Tt;
             const double* g = g_rgba ? g_rgba + p * 4 : NULL;
             double Sfx[3] = {0, 0, 0}; /* colour of the hits behind h, seen from just behind h */
+            double SN[3] = {0, 0, 0};  /* the same for the normal */
+            double Q = 0;              /* depth of the hits behind h over T_{h+1} */
+            const double* gD = (g && g_depth) ? g_depth + p : NULL;
+            const double* gN = (g && g_normal) ? g_normal + p * 3 : NULL;
             for (int64_t h = nc - 1; g && h >= 0; --h) {
               int64_t i = hits[h].id;
               double dxdV[8];
@@ -459,12 +559,34 @@ int oracle_render(int64_t N, const double* center, const double* size, const int
               double dot = 0;
               for (int ch = 0; ch < 3; ++ch) dot += g[ch] * (rgb[ch] - Sfx[ch]);
               double dLdx = Ti[h] * exp(-x) * dot + g[3] * Tfin;
-              for (int m = 0; m < 8; ++m) R[h].g[m] = dLdx * dxdV[m];
+              double dLdV_extra[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+              double nrm[3] = {0, 0, 0};
+              if (gN) {
+                /* N = sum T_i alpha_i n_i: as the colour, plus dL/dn_h = T_h alpha_h g_N */
+                double dLdn[3];
+                for (int ax = 0; ax < 3; ++ax) dLdn[ax] = Ti[h] * alpha * gN[ax];
+                voxel_normal(&S, i, nrm, dLdn, dLdV_extra);
+                double dn_ = 0;
+                for (int ax = 0; ax < 3; ++ax) dn_ += gN[ax] * (nrm[ax] - SN[ax]);
+                dLdx += Ti[h] * exp(-x) * dn_;
+              }
+              double dloc = 0;
+              if (gD) {
+                /* D = sum T_i d_i: d_h through its own sample alphas, and the
+                   hits behind through T: dD/dx_h = -T_{h+1} Q */
+                double dddV[8];
+                dloc = segment_local_depth(&S, i, o, d, hits[h].a, hits[h].b, K, act, dddV);
+                for (int m = 0; m < 8; ++m) dLdV_extra[m] += gD[0] * Ti[h] * dddV[m];
+                dLdx += -gD[0] * Ti[h] * exp(-x) * Q;
+              }
+              for (int m = 0; m < 8; ++m) R[h].g[m] = dLdx * dxdV[m] + dLdV_extra[m];
               /* subdivision priority term (Sec. 3.2.2 eq. priority) from the
                  same dL/dalpha_h, with 1 - alpha_h = exp(-x_h) */
               double dLdalpha = Ti[h] * dot + g[3] * Tfin / exp(-x);
               R[h].prio = fabs(alpha * dLdalpha);
               for (int ch = 0; ch < 3; ++ch) Sfx[ch] = alpha * rgb[ch] + (1.0 - alpha) * Sfx[ch];
+              for (int ax = 0; ax < 3; ++ax) SN[ax] = alpha * nrm[ax] + (1.0 - alpha) * SN[ax];
+              Q = dloc + exp(-x) * Q;
             }
             free(Ti);
             free(xs);

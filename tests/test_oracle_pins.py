@@ -522,3 +522,99 @@ def test_max_weight_respects_early_termination():
     Ts = np.exp(-2.0 * np.arange(5))
     assert np.allclose(w[:5], Ts * (1 - math.exp(-2.0)), rtol=1e-12)
     assert (w[5:] == 0).all()
+
+
+# --------------------------------------------------------------------------
+# depth and normal images (Sec. 3.1.1 "Voxel normal", "Voxel depth")
+# --------------------------------------------------------------------------
+def test_normal_of_affine_field_is_its_gradient_direction():
+    # trilinear interpolation reproduces an affine raw-density field exactly,
+    # so the centre gradient is the field's gradient: n = b / |b|
+    rng = np.random.default_rng(11)
+    for _ in range(4):
+        b = rng.normal(size=3)
+        f = lambda g, b=b: 2.0 + 0.3 * (g - 0.5) @ b
+        sc = S.scene_from_voxels((0.5, 0.5, 0.5), 1.0, 1, [[0, 0, 0]], [1], grid_raw=f,
+                                 sh=_dc_sh([1, 1, 1]))
+        out = oracle.render(sc, _axis_camera(0.25, 0.25), K=2, depth_normal=True)
+        alpha = out["rgba"][0, 3]
+        assert alpha > 0
+        # the stored raw densities are fp32: compare at fp32 precision
+        assert np.allclose(out["normal"][0] / alpha, b / np.linalg.norm(b), atol=2e-7)
+
+
+@pytest.mark.parametrize("K", [1, 2, 3, 5])
+def test_uniform_voxel_depth_closed_form(K):
+    # uniform raw density r in one voxel, axis-aligned ray entering at
+    # distance 1 (camera at z = -1, voxel z in [0, 0.5]): every sample has
+    # alpha_s = 1 - exp(-(l/K) act(r)) and t_k = 1 + (k - 1/2)/K * l
+    r = 1.7
+    sc = S.scene_from_voxels((0.5, 0.5, 0.5), 1.0, 3, [[0, 0, 0]], [1],
+                             grid_raw=lambda g: np.full(len(g), r), sh=_dc_sh([1, 1, 1]))
+    out = oracle.render(sc, _axis_camera(0.25, 0.25), K=K, depth_normal=True)
+    l = 0.5
+    a_s = 1 - math.exp(-l / K * oracle.act(np.float32(r), 0))
+    t = 1.0 + (np.arange(1, K + 1) - 0.5) / K * l
+    d = sum((1 - a_s) ** (k - 1) * a_s * t[k - 1] for k in range(1, K + 1))
+    assert out["depth"][0] == pytest.approx(d, rel=1e-12)
+    if K == 1:
+        assert out["depth"][0] == pytest.approx(out["rgba"][0, 3] * t[0], rel=1e-12)
+    # the normal of a constant field is zero
+    assert np.all(out["normal"][0] == 0)
+
+
+def test_depth_composites_with_transmittance():
+    # two voxels in a row: D = d_1 + T_2 d_2 (T_2 = 1 - alpha_1)
+    sc = _column_scene([3.0, 3.0], np.ones((2, 3)))
+    one = S.scene_from_voxels((0.5, 0.5, 0.5), 1.0, 3, [[1, 1, 0]], [3],
+                              grid_raw=lambda g: np.full(len(g), 3.0), sh=_dc_sh([1, 1, 1]))
+    cam = _axis_camera(0.1875, 0.1875)
+    both = oracle.render(sc, cam, K=2, depth_normal=True)
+    first = oracle.render(one, cam, K=2, depth_normal=True)
+    a1 = first["rgba"][0, 3]
+    # the second voxel alone: the same local depth shifted by its edge 1/8
+    x = 0.125 * 3.0
+    a_s = 1 - math.exp(-x / 2)
+    t = 1.125 + np.array([0.25, 0.75]) * 0.125
+    d2 = a_s * t[0] + (1 - a_s) * a_s * t[1]
+    assert both["depth"][0] == pytest.approx(first["depth"][0] + (1 - a1) * d2, rel=1e-12)
+
+
+def _loss_dn(sc, cam, K, g, gd, gn, pixels, act=0):
+    out = oracle.render(sc, cam, K=K, pixels=pixels, activation=act, depth_normal=True)
+    return float(np.sum(out["rgba"] * g) + np.sum(out["depth"] * gd) + np.sum(out["normal"] * gn))
+
+
+@pytest.mark.parametrize("K,act,opaque", [(1, 0, False), (2, 0, True), (3, 1, False)])
+def test_depth_normal_adjoint_matches_central_differences(K, act, opaque):
+    import dataclasses
+    rng = np.random.default_rng(30 + K)
+    sc = S.tiny_random_scene(22, max_level=3, sh_degree=1,
+                             density_std=1.0 if not opaque else 0.5)
+    if opaque:
+        sc = dataclasses.replace(sc, grid_raw=(sc.grid_raw * 6.0).astype(np.float32))
+    sc = dataclasses.replace(sc, grid_raw=sc.grid_raw.astype(np.float64),
+                             sh=sc.sh.astype(np.float64))
+    cam = S.look_at(20, 20, 50.0, [1.9, 1.3, 1.1], target=(0.5, 0.5, 0.5))
+    pixels = np.arange(cam.W * cam.H)
+    g = rng.normal(size=(len(pixels), 4))
+    gd = rng.normal(size=len(pixels))
+    gn = rng.normal(size=(len(pixels), 3))
+    ref = oracle.render(sc, cam, K=K, pixels=pixels, activation=act, grad_rgba=g,
+                        depth_normal=True, grad_depth=gd, grad_normal=gn)
+    assert not np.any(ref["flags"] & 1)
+    # the depth and normal terms change the gradient
+    plain = oracle.render(sc, cam, K=K, pixels=pixels, activation=act, grad_rgba=g)
+    assert not np.allclose(plain["grad_grid"], ref["grad_grid"])
+    gg = ref["grad_grid"]
+    cand = np.nonzero(np.abs(gg) > 1e-3 * np.abs(gg).max())[0]
+    pick = rng.choice(cand, size=min(12, len(cand)), replace=False)
+    for m in pick:
+        h = 1e-6 * max(1.0, abs(sc.grid_raw[m]))
+        up = sc.grid_raw.copy(); up[m] += h
+        dn = sc.grid_raw.copy(); dn[m] -= h
+        fd = (_loss_dn(dataclasses.replace(sc, grid_raw=up), cam, K, g, gd, gn, pixels, act)
+              - _loss_dn(dataclasses.replace(sc, grid_raw=dn), cam, K, g, gd, gn, pixels, act)) / (2 * h)
+        assert gg[m] == pytest.approx(fd, rel=1e-5, abs=1e-8 * np.abs(gg).max())
+    # SH gradients see only the colour term
+    assert np.allclose(plain["grad_sh"], ref["grad_sh"], rtol=1e-12, atol=0)
