@@ -157,19 +157,37 @@ int svr_preprocess(const svr_scene* scene, const svr_camera* cams, int n_cams,
 int svr_sort(const svr_scene* scene, const svr_camera* cams, int n_cams, const svr_opts* opts,
              void* ws, size_t ws_bytes, int64_t n_entries_hint, void* stream);
 
-/* Per-voxel training statistics (Sec. 3.2.2 "Adaptive Pruning and
- * Subdivision"), optional outputs of the render calls.  Each pointer is a
- * caller-owned device array of n_voxels floats or NULL (statistic off).  The
- * calls accumulate into them across cameras and calls (maximum / sum), so
- * the caller zeroes them at the start of a statistics window.
- *   max_weight  svr_render_fwd: max over composited hits of the blending
- *               weight T_i alpha_i (the pruning test)
- *   priority    svr_render_bwd: sum over composited hits of
- *               |alpha_i dL/dalpha_i| (eq. priority, the subdivision order)  */
-typedef struct svr_train_stats {
+/* Optional extra outputs and inputs of the render calls.  Every pointer is
+ * caller-owned device memory or NULL (feature off).
+ * Per-voxel training statistics (Sec. 3.2.2 "Adaptive Pruning and
+ * Subdivision"), arrays of n_voxels floats that the calls accumulate into
+ * across cameras and calls (maximum / sum), so the caller zeroes them at the
+ * start of a statistics window:
+ *   max_weight   svr_render_fwd: max over composited hits of the blending
+ *                weight T_i alpha_i (the pruning test)
+ *   priority     svr_render_bwd: sum over composited hits of
+ *                |alpha_i dL/dalpha_i| (eq. priority, the subdivision order;
+ *                L is the rgba loss)
+ * Depth and normal images (Sec. 3.1.1 "Voxel normal", "Voxel depth";
+ * Supp. details of voxel normal and depth), overwritten:
+ *   depth        svr_render_fwd: [P] D = sum_i T_i d_i, d_i the voxel's K
+ *                samples composited with their own alphas at their ray
+ *                distances t_k
+ *   normal       svr_render_fwd: [P][3] N = sum_i T_i alpha_i n_i, n_i the
+ *                normalised gradient of the voxel's trilinear raw density at
+ *                its centre (as printed: it points to increasing density)
+ *   grad_depth   svr_render_bwd: [P] dL/dD (NULL: 0)
+ *   grad_normal  svr_render_bwd: [P][3] dL/dN (NULL: 0)
+ * A backward with grad_depth or grad_normal needs the frame's forward to have
+ * produced depth and normal (it saves their partial sums for the backward).  */
+typedef struct svr_extra {
   float* max_weight;
   float* priority;
-} svr_train_stats;
+  float* depth;
+  float* normal;
+  const float* grad_depth;
+  const float* grad_normal;
+} svr_extra;
 
 /* Render (Sec. 3.1 eq. alpha_blend; Sec. 3.1.1 eq. vox_alpha, eq. explin,
  * eq. vox_color; Supp. A.2 eq. K_samp_pts, eq. interp; Sec. 3.1.2 "Rendering
@@ -177,12 +195,12 @@ typedef struct svr_train_stats {
  * sign pattern and voxels its ray misses (ray-box slab test, entry distance
  * > 0) are skipped; a voxel is composited iff the transmittance before it is
  * >= t_stop.  Output rgba: [sum_c H_c W_c][4], cameras in order, row-major
- * pixels; premultiplied RGB and A = 1 - T_final (no background).  `train`
- * may be NULL; its max_weight is updated here.
+ * pixels; premultiplied RGB and A = 1 - T_final (no background).  `extra`
+ * may be NULL; its max_weight, depth and normal are written here.
  * Errors: SVR_E_INVALID, SVR_E_WORKSPACE, SVR_E_HIP.                         */
 int svr_render_fwd(const svr_scene* scene, const svr_camera* cams, int n_cams,
                    const svr_opts* opts, void* ws, size_t ws_bytes, float* rgba,
-                   const svr_train_stats* train, void* stream);
+                   const svr_extra* extra, void* stream);
 
 /* Adjoint of svr_render_fwd for L = sum <grad_rgba, rgba>.  The transmittance
  * is recomputed walking each pixel's list back to front from the saved final
@@ -190,11 +208,12 @@ int svr_render_fwd(const svr_scene* scene, const svr_camera* cams, int n_cams,
  * (added into when opts->accumulate is 1):
  *   grad_grid  [M]                 dL/d grid_raw            (may be NULL)
  *   grad_sh    [N][(D+1)^2][3]     dL/d sh                  (may be NULL)
- * `train` may be NULL; its priority is accumulated here.
+ * `extra` may be NULL; its grad_depth and grad_normal are read and its
+ * priority is accumulated here.
  * Errors: SVR_E_INVALID, SVR_E_WORKSPACE, SVR_E_HIP.                         */
 int svr_render_bwd(const svr_scene* scene, const svr_camera* cams, int n_cams,
                    const svr_opts* opts, void* ws, size_t ws_bytes, const float* grad_rgba,
-                   float* grad_grid, float* grad_sh, const svr_train_stats* train,
+                   float* grad_grid, float* grad_sh, const svr_extra* extra,
                    void* stream);
 
 /* After the frame (synchronises `stream`): *required_entries = E of the last
@@ -249,7 +268,7 @@ int svr_timing_read(char* names, int name_len, double* total_ms, int64_t* launch
  * launch per stage, no host synchronisation).  svr_graph_capture records, on
  * `stream` (must not be the NULL stream), svr_preprocess (without read-back),
  * svr_sort (sized by capacity), svr_render_fwd into `rgba` and, when
- * grad_rgba is not NULL, svr_render_bwd into grad_grid / grad_sh (`train` as
+ * grad_rgba is not NULL, svr_render_bwd into grad_grid / grad_sh (`extra` as
  * for those calls, NULL allowed); it returns
  * an executable graph in *graph_out.  Cameras and options are baked into the
  * graph; scene arrays, workspace and outputs are read and written through the
@@ -261,7 +280,7 @@ int svr_timing_read(char* names, int name_len, double* total_ms, int64_t* launch
 int svr_graph_capture(const svr_scene* scene, const svr_camera* cams, int n_cams,
                       const svr_opts* opts, void* ws, size_t ws_bytes, float* rgba,
                       const float* grad_rgba, float* grad_grid, float* grad_sh,
-                      const svr_train_stats* train, void* stream, void** graph_out);
+                      const svr_extra* extra, void* stream, void** graph_out);
 int svr_graph_launch(void* graph, void* stream);
 int svr_graph_destroy(void* graph);
 

@@ -48,8 +48,10 @@ class svr_opts(ctypes.Structure):
                 ("entry_capacity", I64), ("persistent", I32), ("accumulate", I32)]
 
 
-class svr_train_stats(ctypes.Structure):
-    _fields_ = [("max_weight", ctypes.c_void_p), ("priority", ctypes.c_void_p)]
+class svr_extra(ctypes.Structure):
+    _fields_ = [("max_weight", ctypes.c_void_p), ("priority", ctypes.c_void_p),
+                ("depth", ctypes.c_void_p), ("normal", ctypes.c_void_p),
+                ("grad_depth", ctypes.c_void_p), ("grad_normal", ctypes.c_void_p)]
 
 
 _SIGS = {
@@ -158,15 +160,15 @@ def svr_sort(scene, cams, n_cams, opts, ws, ws_bytes, n_entries_hint, stream):
                            stream)
 
 
-def svr_render_fwd(scene, cams, n_cams, opts, ws, ws_bytes, rgba, train, stream):
+def svr_render_fwd(scene, cams, n_cams, opts, ws, ws_bytes, rgba, extra, stream):
     return load().svr_render_fwd(_ref(scene), cams, n_cams, _ref(opts), ws, ws_bytes, rgba,
-                                 _ref(train), stream)
+                                 _ref(extra), stream)
 
 
-def svr_render_bwd(scene, cams, n_cams, opts, ws, ws_bytes, grad_rgba, grad_grid, grad_sh, train,
+def svr_render_bwd(scene, cams, n_cams, opts, ws, ws_bytes, grad_rgba, grad_grid, grad_sh, extra,
                    stream):
     return load().svr_render_bwd(_ref(scene), cams, n_cams, _ref(opts), ws, ws_bytes, grad_rgba,
-                                 grad_grid, grad_sh, _ref(train), stream)
+                                 grad_grid, grad_sh, _ref(extra), stream)
 
 
 def svr_check_overflow(scene, cams, n_cams, opts, ws, ws_bytes, required_entries, stream):
@@ -218,9 +220,9 @@ def kernel_times():
 
 
 def svr_graph_capture(scene, cams, n_cams, opts, ws, ws_bytes, rgba, grad_rgba, grad_grid, grad_sh,
-                      train, stream, graph_out):
+                      extra, stream, graph_out):
     return load().svr_graph_capture(_ref(scene), cams, n_cams, _ref(opts), ws, ws_bytes, rgba,
-                                    grad_rgba, grad_grid, grad_sh, _ref(train), stream, graph_out)
+                                    grad_rgba, grad_grid, grad_sh, _ref(extra), stream, graph_out)
 
 
 def svr_graph_launch(graph, stream):

@@ -193,8 +193,10 @@ int make_layout(const svr_scene* sc, const svr_camera* cams, int n_cams, const s
   l.px_tau = take((size_t)P * 4);
   l.px_last = take((size_t)P * 4);
   l.ckpt = take((size_t)l.max_split * l.tile * l.tile * 16);
+  l.ckpt_aux = take((size_t)l.max_split * l.tile * l.tile * 16);
   l.g_corner = take((size_t)l.N * 32);
   l.g_rgb = take((size_t)l.NV * 12);
+  l.g_nrm = take((size_t)l.N * 12);
   l.total = off;
   return SVR_OK;
 }
@@ -304,7 +306,7 @@ int svr_sort(const svr_scene* scene, const svr_camera* cams, int n_cams, const s
 
 int svr_render_fwd(const svr_scene* scene, const svr_camera* cams, int n_cams,
                    const svr_opts* opts, void* ws, size_t ws_bytes, float* rgba,
-                   const svr_train_stats* train, void* stream) {
+                   const svr_extra* extra, void* stream) {
   Layout L;
   CamSet cs;
   int st = make_layout(scene, cams, n_cams, opts, &L, &cs);
@@ -312,15 +314,14 @@ int svr_render_fwd(const svr_scene* scene, const svr_camera* cams, int n_cams,
   if ((st = check_ws(L, ws, ws_bytes)) != SVR_OK) return st;
   if (!rgba && L.P > 0) return fail(SVR_E_INVALID, "null rgba");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  SVR_HIP(launch_render_fwd(*scene, cs, *opts, L, ws, sorted_vals(L, ws), rgba,
-                            train ? train->max_weight : nullptr, s),
+  SVR_HIP(launch_render_fwd(*scene, cs, *opts, L, ws, sorted_vals(L, ws), rgba, extra, s),
           "render fwd");
   return SVR_OK;
 }
 
 int svr_render_bwd(const svr_scene* scene, const svr_camera* cams, int n_cams,
                    const svr_opts* opts, void* ws, size_t ws_bytes, const float* grad_rgba,
-                   float* grad_grid, float* grad_sh, const svr_train_stats* train,
+                   float* grad_grid, float* grad_sh, const svr_extra* extra,
                    void* stream) {
   Layout L;
   CamSet cs;
@@ -329,10 +330,10 @@ int svr_render_bwd(const svr_scene* scene, const svr_camera* cams, int n_cams,
   if ((st = check_ws(L, ws, ws_bytes)) != SVR_OK) return st;
   if (!grad_rgba && L.P > 0) return fail(SVR_E_INVALID, "null grad_rgba");
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  SVR_HIP(launch_render_bwd(*scene, cs, *opts, L, ws, sorted_vals(L, ws), grad_rgba,
-                            train ? train->priority : nullptr, s),
+  const bool aux = extra && (extra->grad_depth || extra->grad_normal);
+  SVR_HIP(launch_render_bwd(*scene, cs, *opts, L, ws, sorted_vals(L, ws), grad_rgba, extra, s),
           "render bwd");
-  SVR_HIP(launch_sh_bwd(*scene, cs, L, ws, grad_grid, grad_sh, opts->accumulate != 0, s),
+  SVR_HIP(launch_sh_bwd(*scene, cs, L, ws, grad_grid, grad_sh, opts->accumulate != 0, aux, s),
           "pre-process adjoint");
   return SVR_OK;
 }
@@ -507,7 +508,7 @@ struct SvrGraph {
 int svr_graph_capture(const svr_scene* scene, const svr_camera* cams, int n_cams,
                       const svr_opts* opts, void* ws, size_t ws_bytes, float* rgba,
                       const float* grad_rgba, float* grad_grid, float* grad_sh,
-                      const svr_train_stats* train, void* stream, void** graph_out) {
+                      const svr_extra* extra, void* stream, void** graph_out) {
   if (!graph_out) return fail(SVR_E_INVALID, "null graph_out");
   *graph_out = nullptr;
   if (!stream) return fail(SVR_E_INVALID, "capture needs a non-default stream");
@@ -527,10 +528,10 @@ int svr_graph_capture(const svr_scene* scene, const svr_camera* cams, int n_cams
   st = svr_preprocess(scene, cams, n_cams, opts, ws, ws_bytes, nullptr, stream);
   if (st == SVR_OK) st = svr_sort(scene, cams, n_cams, opts, ws, ws_bytes, -1, stream);
   if (st == SVR_OK)
-    st = svr_render_fwd(scene, cams, n_cams, opts, ws, ws_bytes, rgba, train, stream);
+    st = svr_render_fwd(scene, cams, n_cams, opts, ws, ws_bytes, rgba, extra, stream);
   if (st == SVR_OK && grad_rgba)
     st = svr_render_bwd(scene, cams, n_cams, opts, ws, ws_bytes, grad_rgba, grad_grid, grad_sh,
-                        train, stream);
+                        extra, stream);
   hipGraph_t g = nullptr;
   hipError_t e = hipStreamEndCapture(s, &g);
   {

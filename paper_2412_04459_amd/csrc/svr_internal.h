@@ -83,6 +83,8 @@ struct Layout {
   size_t hdr, count, offset, rect, rec, scan_part;
   size_t tile_mask, tile_sat, tile_range, tile_order, tile_rank;
   size_t split_base, split_items, ckpt;  // backward chunks of heavy tiles
+  size_t ckpt_aux;                       // the same for depth and normal
+  size_t g_nrm;                          // per voxel dL/dn (normal images)
   int64_t max_split;                     // capacity of the chunk list (>= sum of splits)
   size_t keys0, keys1, vals0, vals1;
   size_t sort_hist, sort_status0, sort_status1;
@@ -172,12 +174,13 @@ size_t grid_adjacency_scratch_bytes(int64_t N, int64_t M);
 // render
 hipError_t launch_render_fwd(const svr_scene& sc, const CamSet& cams, const svr_opts& o,
                              const Layout& L, void* ws, const uint32_t* vals, float* rgba,
-                             float* max_weight, hipStream_t s);
+                             const svr_extra* extra, hipStream_t s);
 hipError_t launch_render_bwd(const svr_scene& sc, const CamSet& cams, const svr_opts& o,
                              const Layout& L, void* ws, const uint32_t* vals,
-                             const float* grad_rgba, float* priority, hipStream_t s);
+                             const float* grad_rgba, const svr_extra* extra, hipStream_t s);
 hipError_t launch_sh_bwd(const svr_scene& sc, const CamSet& cams, const Layout& L, void* ws,
-                         float* grad_grid, float* grad_sh, bool accumulate, hipStream_t s);
+                         float* grad_grid, float* grad_sh, bool accumulate, bool aux,
+                         hipStream_t s);
 
 // ---- diagnostics: kernel timing ------------------------------------------
 // When enabled (svr_timing_enable), every launch is bracketed by HIP events

@@ -120,6 +120,14 @@ struct RenderArgs {
   int max_split, split_wgs;
   uint32_t* max_weight;         // training statistics (bit patterns of non-negative floats)
   float* priority;
+  // depth and normal images (aux kernels)
+  float* depth;
+  float* normal;
+  const float* grad_depth;
+  const float* grad_normal;
+  float4* ckpt_aux;             // per slot and pixel: (depth, normal) still to come
+  float* g_nrm;                 // per voxel dL/dn
+  int aux;
 };
 
 // next position in the render order for a persistent workgroup (-1: none left)
@@ -265,6 +273,110 @@ __device__ __forceinline__ float segment_x(const LdsBatch<NB>& B, int j, double 
   return x * ((float)lseg / (float)K);
 }
 
+// Voxel normal (Sec. 3.1.1 "Voxel normal"; Supp. details of voxel normal):
+// the gradient of the trilinear raw density at the voxel centre,
+//   g = 0.25 ((V_1jk summed) - (V_0jk summed), ...) for x, y, z,
+// normalised (zero when g = 0).  Corner c = 4x + 2y + z.
+__device__ __forceinline__ void centre_gradient(const float V[8], float g[3]) {
+  g[0] = 0.25f * ((V[4] + V[5] + V[6] + V[7]) - (V[0] + V[1] + V[2] + V[3]));
+  g[1] = 0.25f * ((V[2] + V[3] + V[6] + V[7]) - (V[0] + V[1] + V[4] + V[5]));
+  g[2] = 0.25f * ((V[1] + V[3] + V[5] + V[7]) - (V[0] + V[2] + V[4] + V[6]));
+}
+
+template <int NB>
+__device__ __forceinline__ void staged_normal(const LdsBatch<NB>& B, int j, float n[3]) {
+  float V[8], g[3];
+#pragma unroll
+  for (int m = 0; m < 8; ++m) V[m] = B.V[m][j];
+  centre_gradient(V, g);
+  const float g2 = g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
+  const float r = g2 > 0.f ? rsqrtf(g2) : 0.f;
+  n[0] = g[0] * r; n[1] = g[1] * r; n[2] = g[2] * r;
+}
+
+// optical depth x of staged entry j (as segment_x) and its local depth
+// (Supp. details of voxel depth): the K samples composited with their own
+// alphas alpha_k = 1 - exp(-(l/K) act(v_k)) at their ray distances t_k,
+//   d = sum_k prod_{j<k} (1 - alpha_j) alpha_k t_k
+template <int KT, int ACT, int NB>
+__device__ __forceinline__ float segment_xd(const LdsBatch<NB>& B, int j, double dx, double dy,
+                                            double dz, double a, double lseg, int Krt,
+                                            float& dloc) {
+  const int K = KT > 0 ? KT : Krt;
+  const double step = 1.0 / (double)K;
+  const float lK = (float)lseg / (float)K;
+  float x = 0.f, P = 1.f, d = 0.f;
+#pragma unroll
+  for (int k = 0; k < (KT > 0 ? KT : SVR_MAX_K); ++k) {
+    if (KT == 0 && k >= K) break;
+    const double t = fma(((double)k + 0.5) * step, lseg, a);
+    float qx, qy, qz;
+    local_coord(B, j, t, dx, dy, dz, qx, qy, qz);
+    const float xk = lK * act_f<ACT>(trilerp(B, j, qx, qy, qz));
+    const float ak = alpha_of(xk);
+    d = __fmaf_rn(P * ak, (float)t, d);
+    P *= 1.f - ak;
+    x += xk;
+  }
+  dloc = d;
+  return x;
+}
+
+// local depth d of staged entry j and dd/dV for its 8 corner raw densities:
+// dd/dalpha_k = P_k (t_k - E_{k+1}), P_k the product of (1 - alpha) before k
+// and E_{k+1} the samples after k composited from k + 1 on;
+// dalpha_k/dv_k = (1 - alpha_k) (l/K) act'(v_k); dv_k/dV_m = w_m(q_k)
+template <int KT, int ACT, int NB>
+__device__ __forceinline__ float segment_depth_grad(const LdsBatch<NB>& B, int j, double dx,
+                                                    double dy, double dz, double a, double lseg,
+                                                    int Krt, float dd[8]) {
+  constexpr int KM = KT > 0 ? KT : SVR_MAX_K;
+  const int K = KT > 0 ? KT : Krt;
+  const double step = 1.0 / (double)K;
+  const float lK = (float)lseg / (float)K;
+  float al[KM], tk[KM], Pk[KM], ck[KM];
+  float P = 1.f, d = 0.f;
+#pragma unroll
+  for (int k = 0; k < KM; ++k) {
+    al[k] = 0.f; tk[k] = 0.f; Pk[k] = 0.f; ck[k] = 0.f;
+    if (KT == 0 && k >= K) continue;
+    const double t = fma(((double)k + 0.5) * step, lseg, a);
+    float qx, qy, qz;
+    local_coord(B, j, t, dx, dy, dz, qx, qy, qz);
+    const float v = trilerp(B, j, qx, qy, qz);
+    al[k] = alpha_of(lK * act_f<ACT>(v));
+    ck[k] = (1.f - al[k]) * lK * act_df<ACT>(v);  // dalpha_k / dv_k
+    tk[k] = (float)t;
+    Pk[k] = P;
+    d = __fmaf_rn(P * al[k], tk[k], d);
+    P *= 1.f - al[k];
+  }
+  float E = 0.f;
+#pragma unroll
+  for (int k = KM - 1; k >= 0; --k) {
+    if (KT == 0 && k >= K) continue;
+    ck[k] *= Pk[k] * (tk[k] - E);
+    E = __fmaf_rn(al[k], tk[k] - E, E);
+  }
+#pragma unroll
+  for (int m = 0; m < 8; ++m) dd[m] = 0.f;
+#pragma unroll
+  for (int k = 0; k < KM; ++k) {
+    if (KT == 0 && k >= K) break;
+    const double t = fma(((double)k + 0.5) * step, lseg, a);
+    float qx, qy, qz;
+    local_coord(B, j, t, dx, dy, dz, qx, qy, qz);
+    const float c = ck[k];
+    const float px = 1.f - qx, py = 1.f - qy, pz = 1.f - qz;
+    const float a00 = c * px * py, a01 = c * px * qy, a10 = c * qx * py, a11 = c * qx * qy;
+    dd[0] = __fmaf_rn(a00, pz, dd[0]); dd[1] = __fmaf_rn(a00, qz, dd[1]);
+    dd[2] = __fmaf_rn(a01, pz, dd[2]); dd[3] = __fmaf_rn(a01, qz, dd[3]);
+    dd[4] = __fmaf_rn(a10, pz, dd[4]); dd[5] = __fmaf_rn(a10, qz, dd[5]);
+    dd[6] = __fmaf_rn(a11, pz, dd[6]); dd[7] = __fmaf_rn(a11, qz, dd[7]);
+  }
+  return d;
+}
+
 // ---------------------------------------------------------------------------
 // Forward, dense form.  Hits are sparse in a wave (a voxel a few pixels wide
 // covers a handful of the 64 pixels of a block), so the per-hit work is not
@@ -281,16 +393,18 @@ __device__ __forceinline__ float segment_x(const LdsBatch<NB>& B, int j, double 
 //      sequential part: a few operations per hit).
 // A lane list holding kListCap candidates triggers B and C early, so order
 // and early termination are those of the plain per-pixel walk.
-template <int TS>
+template <int TS, bool AUX = false>
 struct DenseCfg {
-  static constexpr int kListCap = 8;
+  // 32x32 tiles with depth and normal lists would exceed the LDS
+  static constexpr int kListCap = (TS == 32 && AUX) ? 4 : 8;
 };
 
-template <int CAP>
+template <int CAP, bool AUX>
 struct WaveLists {
   uint16_t queue[64 * CAP];  // task -> owner lane << 8 | list slot
   uint8_t jl[CAP][64];       // staged entry index of a lane's candidate
   float xl[CAP][64];         // its optical depth (< 0: the ray misses the box)
+  float dl[AUX ? CAP : 1][64];  // its local depth (depth images only)
   double d[3][64];           // lane ray direction (fp64)
   double id[3][64];          // and its reciprocal
 };
@@ -304,13 +418,13 @@ __device__ __forceinline__ uint32_t lane_rank(unsigned long long mask) {
 // STATS: count, per frame, the (pixel, entry) pairs of matching sign pattern
 // the method walks, the ray-box tests this kernel executes (candidates after
 // the rectangle test), and the composited hits (into stats[0..2]); no outputs.
-template <int TS, int KT, int ACT, bool STATS>
+template <int TS, int KT, int ACT, bool STATS, bool AUX>
 __device__ __forceinline__ void render_tile_fwd(const RenderArgs& A, int g,
                                                 LdsBatch<TileGeom<TS>::kBatch>& B,
-                                                WaveLists<DenseCfg<TS>::kListCap>* WLs) {
+                                                WaveLists<DenseCfg<TS, AUX>::kListCap, AUX>* WLs) {
   using G = TileGeom<TS>;
   constexpr int NB = G::kBatch;
-  constexpr int CAP = DenseCfg<TS>::kListCap;
+  constexpr int CAP = DenseCfg<TS, AUX>::kListCap;
   const int ci = find_cam_r(A.cams, g);
   const DevCam& c = A.cams.c[ci];
   const int tl = g - c.tile_off;
@@ -318,13 +432,14 @@ __device__ __forceinline__ void render_tile_fwd(const RenderArgs& A, int g,
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int qu0 = tx * TS, qv0 = ty * TS;
   const PixelRay r = make_ray<TS>(c, qu0, qv0, w, lane);
-  WaveLists<CAP>& WL = WLs[w];
+  WaveLists<CAP, AUX>& WL = WLs[w];
   WL.d[0][lane] = r.dx; WL.d[1][lane] = r.dy; WL.d[2][lane] = r.dz;
   WL.id[0][lane] = r.idx; WL.id[1][lane] = r.idy; WL.id[2][lane] = r.idz;
 
   const uint2 rg = A.range[g];
   const uint32_t start = rg.x, end = rg.y;
   float tau = 0.f, Tr = 1.f, C0 = 0.f, C1 = 0.f, C2 = 0.f;
+  float D = 0.f, N0 = 0.f, N1 = 0.f, N2 = 0.f;  // depth and normal images
   uint32_t last = start;
   bool done = !r.inside;
   uint32_t n_pairs = 0, n_tests = 0, n_hits = 0;
@@ -332,6 +447,7 @@ __device__ __forceinline__ void render_tile_fwd(const RenderArgs& A, int g,
   // heavy tile: record (tau, colour so far) at every chunk boundary passed
   const uint32_t sb = STATS ? kNoSplit : A.split_base[g];
   float4* const ck = A.ckpt + (int64_t)(sb == kNoSplit ? 0u : sb) * (TS * TS) + tid;
+  float4* const ck_aux = A.ckpt_aux + (int64_t)(sb == kNoSplit ? 0u : sb) * (TS * TS) + tid;
   uint32_t n_ck = 0;
 
   for (uint32_t b0 = start; b0 < end; b0 += NB) {
@@ -350,9 +466,17 @@ __device__ __forceinline__ void render_tile_fwd(const RenderArgs& A, int g,
         const int j = WL.jl[k][ow];
         double a, bb;
         float x = -1.f;
-        if (slab(B, j, WL.id[0][ow], WL.id[1][ow], WL.id[2][ow], a, bb))
-          x = segment_x<KT, ACT, false>(B, j, WL.d[0][ow], WL.d[1][ow], WL.d[2][ow], a, bb - a,
-                                        A.K, nullptr);
+        if (slab(B, j, WL.id[0][ow], WL.id[1][ow], WL.id[2][ow], a, bb)) {
+          if (AUX) {
+            float dloc;
+            x = segment_xd<KT, ACT>(B, j, WL.d[0][ow], WL.d[1][ow], WL.d[2][ow], a, bb - a, A.K,
+                                    dloc);
+            WL.dl[AUX ? k : 0][ow] = dloc;
+          } else {
+            x = segment_x<KT, ACT, false>(B, j, WL.d[0][ow], WL.d[1][ow], WL.d[2][ow], a, bb - a,
+                                          A.K, nullptr);
+          }
+        }
         WL.xl[k][ow] = x;
         if (STATS) ++n_tests;
       }
@@ -369,6 +493,14 @@ __device__ __forceinline__ void render_tile_fwd(const RenderArgs& A, int g,
             C0 = __fmaf_rn(wgt, B.cr[j], C0);
             C1 = __fmaf_rn(wgt, B.cg[j], C1);
             C2 = __fmaf_rn(wgt, B.cb[j], C2);
+            if (AUX) {
+              float nv[3];
+              staged_normal(B, j, nv);
+              D = __fmaf_rn(Tr, WL.dl[AUX ? k : 0][lane], D);
+              N0 = __fmaf_rn(wgt, nv[0], N0);
+              N1 = __fmaf_rn(wgt, nv[1], N1);
+              N2 = __fmaf_rn(wgt, nv[2], N2);
+            }
             tau += x;
             Tr = __expf(-tau);
             last = b0 + (uint32_t)j + 1u;
@@ -405,6 +537,7 @@ __device__ __forceinline__ void render_tile_fwd(const RenderArgs& A, int g,
       const uint32_t bend = b0 + NB;
       if (bend < end && ((bend - start) & (kBwdChunk - 1)) == 0) {
         ck[(int64_t)n_ck * (TS * TS)] = make_float4(tau, C0, C1, C2);
+        if (AUX) ck_aux[(int64_t)n_ck * (TS * TS)] = make_float4(D, N0, N1, N2);
         ++n_ck;
       }
     }
@@ -418,6 +551,10 @@ __device__ __forceinline__ void render_tile_fwd(const RenderArgs& A, int g,
   for (uint32_t k = 0; k < n_ck; ++k) {
     const float4 q = ck[(int64_t)k * (TS * TS)];
     ck[(int64_t)k * (TS * TS)] = make_float4(q.x, C0 - q.y, C1 - q.z, C2 - q.w);
+    if (AUX) {
+      const float4 e = ck_aux[(int64_t)k * (TS * TS)];
+      ck_aux[(int64_t)k * (TS * TS)] = make_float4(D - e.x, N0 - e.y, N1 - e.z, N2 - e.w);
+    }
   }
   if (STATS) {
     unsigned long long a0 = n_pairs, a1 = n_tests, a2 = n_hits;
@@ -439,16 +576,22 @@ __device__ __forceinline__ void render_tile_fwd(const RenderArgs& A, int g,
     A.rgba[p] = make_float4(C0, C1, C2, 1.f - Tr);
     A.px_tau[p] = tau;
     A.px_last[p] = last;
+    if (AUX && A.depth) A.depth[p] = D;
+    if (AUX && A.normal) {
+      A.normal[3 * p + 0] = N0;
+      A.normal[3 * p + 1] = N1;
+      A.normal[3 * p + 2] = N2;
+    }
   }
 }
 
-template <int TS, int KT, int ACT, bool STATS>
+template <int TS, int KT, int ACT, bool STATS, bool AUX>
 __global__ __launch_bounds__(TS * TS) void k_render_fwd(RenderArgs A) {
   __shared__ LdsBatch<TileGeom<TS>::kBatch> B;
-  __shared__ WaveLists<DenseCfg<TS>::kListCap> WL[TileGeom<TS>::kWaves];
+  __shared__ WaveLists<DenseCfg<TS, AUX>::kListCap, AUX> WL[TileGeom<TS>::kWaves];
   __shared__ int s_tile;
   if (!A.persistent) {
-    if ((int)blockIdx.x < A.T) render_tile_fwd<TS, KT, ACT, STATS>(A, A.order[blockIdx.x], B, WL);
+    if ((int)blockIdx.x < A.T) render_tile_fwd<TS, KT, ACT, STATS, AUX>(A, A.order[blockIdx.x], B, WL);
     return;
   }
   while (true) {
@@ -457,13 +600,13 @@ __global__ __launch_bounds__(TS * TS) void k_render_fwd(RenderArgs A) {
     const int p = s_tile;
     if (p < 0) break;
     const int g = A.order[p];
-    render_tile_fwd<TS, KT, ACT, STATS>(A, g, B, WL);
+    render_tile_fwd<TS, KT, ACT, STATS, AUX>(A, g, B, WL);
     __syncthreads();
   }
 }
 
 // ---------------------------------------------------------------------------
-// Wave sum of 12 per-lane values by recursive halving with gfx950 cross-lane
+// Wave sum of 16 per-lane values by recursive halving with gfx950 cross-lane
 // VALU operations (no LDS): at each step a lane keeps one half of its values
 // and adds its partner lane's copy of that half.
 //   step 1: v_permlane32_swap pairs lane L with L ^ 32  (8 pairs -> 8 values)
@@ -504,13 +647,12 @@ constexpr int kDppRowHalfMirror = 0x141;
 constexpr int kDppQuadXor1 = 0xB1;  // quad_perm [1,0,3,2]
 constexpr int kDppQuadXor2 = 0x4E;  // quad_perm [2,3,0,1]
 
-__device__ __forceinline__ float wave_reduce12(float g0, float g1, float g2, float g3, float g4,
-                                               float g5, float g6, float g7, float g8, float g9,
-                                               float g10, float g11) {
+__device__ __forceinline__ float wave_reduce16(const float (&g)[16]) {
   const int lane = threadIdx.x & 63;
-  const float s0 = swap32_sum(g0, g8), s1 = swap32_sum(g1, g9), s2 = swap32_sum(g2, g10);
-  const float s3 = swap32_sum(g3, g11), s4 = swap32_sum(g4, 0.f), s5 = swap32_sum(g5, 0.f);
-  const float s6 = swap32_sum(g6, 0.f), s7 = swap32_sum(g7, 0.f);
+  const float s0 = swap32_sum(g[0], g[8]), s1 = swap32_sum(g[1], g[9]);
+  const float s2 = swap32_sum(g[2], g[10]), s3 = swap32_sum(g[3], g[11]);
+  const float s4 = swap32_sum(g[4], g[12]), s5 = swap32_sum(g[5], g[13]);
+  const float s6 = swap32_sum(g[6], g[14]), s7 = swap32_sum(g[7], g[15]);
   const float t0 = swap16_sum(s0, s4), t1 = swap16_sum(s1, s5);
   const float t2 = swap16_sum(s2, s6), t3 = swap16_sum(s3, s7);
   const bool u8 = (lane & 8) != 0, u4 = (lane & 4) != 0;
@@ -527,7 +669,7 @@ __device__ __forceinline__ float wave_reduce12(float g0, float g1, float g2, flo
 // entry lies beyond the range starts from the forward's checkpoint at the
 // range's end (optical depth so far, colour still to come); the others start
 // from their final state.
-template <int TS, int KT, int ACT>
+template <int TS, int KT, int ACT, bool AUX>
 __device__ __forceinline__ void render_tile_bwd(const RenderArgs& A, int g, uint32_t m_lo,
                                                 uint32_t m_hi,
                                                 LdsBatch<TileGeom<TS>::kBatch>& B,
@@ -543,13 +685,17 @@ __device__ __forceinline__ void render_tile_bwd(const RenderArgs& A, int g, uint
   const PixelRay r = make_ray<TS>(c, qu0, qv0, w, lane);
   const int slot = (lane >> 2) & 15;  // reduced value this lane ends up holding
   const bool prio = A.priority != nullptr;
-  const bool writer = (lane & 3) == 0 && slot < (prio ? 12 : 11);
+  // values: 0-7 corners, 8-10 colour, 11 priority, 12-14 dL/dn (depth and normal)
+  const bool writer = (lane & 3) == 0 &&
+                      (slot < 11 || (slot == 11 && prio) || (AUX && slot >= 12 && slot < 15));
 
   const uint2 rg = A.range[g];
   const uint32_t e_lo = rg.x + m_lo * (uint32_t)kBwdChunk;
   const uint32_t e_hi = min(rg.x + m_hi * (uint32_t)kBwdChunk, rg.y);
   float tau = 0.f, gr = 0.f, gg = 0.f, gb = 0.f, ga = 0.f, Tfin = 1.f, tau_end = 0.f;
   float U0 = 0.f, U1 = 0.f, U2 = 0.f;  // colour composited after the current entry
+  float UD = 0.f, UN0 = 0.f, UN1 = 0.f, UN2 = 0.f;  // the same for depth and normal
+  float gD = 0.f, gN0 = 0.f, gN1 = 0.f, gN2 = 0.f;
   uint32_t last = e_lo;
   if (r.inside) {
     const int64_t p = c.pix_off + (int64_t)r.v * c.W + r.u;
@@ -558,10 +704,23 @@ __device__ __forceinline__ void render_tile_bwd(const RenderArgs& A, int g, uint
     const uint32_t lp = A.px_last[p];
     const float4 gq = A.grad_rgba[p];
     gr = gq.x; gg = gq.y; gb = gq.z; ga = gq.w;
+    if (AUX) {
+      if (A.grad_depth) gD = A.grad_depth[p];
+      if (A.grad_normal) {
+        gN0 = A.grad_normal[3 * p + 0];
+        gN1 = A.grad_normal[3 * p + 1];
+        gN2 = A.grad_normal[3 * p + 2];
+      }
+    }
     Tfin = __expf(-tau_fin);
     if (lp > e_hi) {  // only in a split chunk (e_hi < end), whose tile has checkpoints
-      const float4 q = A.ckpt[((int64_t)A.split_base[g] + m_hi - 1) * (TS * TS) + tid];
+      const int64_t slot_px = ((int64_t)A.split_base[g] + m_hi - 1) * (TS * TS) + tid;
+      const float4 q = A.ckpt[slot_px];
       tau = q.x; U0 = q.y; U1 = q.z; U2 = q.w;
+      if (AUX) {
+        const float4 e = A.ckpt_aux[slot_px];
+        UD = e.x; UN0 = e.y; UN1 = e.z; UN2 = e.w;
+      }
       last = e_hi;
     } else {
       tau = tau_fin;
@@ -591,9 +750,9 @@ __device__ __forceinline__ void render_tile_bwd(const RenderArgs& A, int g, uint
       bool hit = (b0 + (uint32_t)j < last) && ((meta & 7u) == r.spat);
       if (hit) hit = slab(B, j, r.idx, r.idy, r.idz, a, bb);
       if (__ballot(hit) == 0ull) continue;
-      float gv[12];
+      float gv[16];
 #pragma unroll
-      for (int m = 0; m < 12; ++m) gv[m] = 0.f;
+      for (int m = 0; m < 16; ++m) gv[m] = 0.f;
       if (hit) {
         float dw[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
         const double lseg = bb - a;
@@ -605,8 +764,20 @@ __device__ __forceinline__ void render_tile_bwd(const RenderArgs& A, int g, uint
         const float cr = B.cr[j], cg = B.cg[j], cb = B.cb[j];
         const float wgt = Ti * alpha;
         gv[8] = gr * wgt; gv[9] = gg * wgt; gv[10] = gb * wgt;
-        const float dLdx = gr * (Tnext * cr - U0) + gg * (Tnext * cg - U1) +
-                           gb * (Tnext * cb - U2) + ga * Tfin;
+        float dLdx = gr * (Tnext * cr - U0) + gg * (Tnext * cg - U1) +
+                     gb * (Tnext * cb - U2) + ga * Tfin;
+        float dd[8], dloc = 0.f, nv[3] = {0.f, 0.f, 0.f};
+        if (AUX) {
+          // depth: D = sum T_i d_i (d_i through its sample alphas; the hits
+          // behind through T); normal: N = sum T_i alpha_i n_i, as the colour
+          dloc = segment_depth_grad<KT, ACT>(B, j, r.dx, r.dy, r.dz, a, lseg, A.K, dd);
+          staged_normal(B, j, nv);
+          dLdx += -gD * UD + gN0 * (Tnext * nv[0] - UN0) + gN1 * (Tnext * nv[1] - UN1) +
+                  gN2 * (Tnext * nv[2] - UN2);
+          gv[12] = wgt * gN0;
+          gv[13] = wgt * gN1;
+          gv[14] = wgt * gN2;
+        }
         if (prio) {
           // |alpha dL/dalpha| (eq. priority) = |T_i alpha <g, c - S> + g_A (e^{-(tau_fin - x)}
           // - T_fin)|, S = U / T_{i+1} the colour behind seen from just behind (0 when
@@ -618,18 +789,29 @@ __device__ __forceinline__ void render_tile_bwd(const RenderArgs& A, int g, uint
         U0 = __fmaf_rn(wgt, cr, U0);
         U1 = __fmaf_rn(wgt, cg, U1);
         U2 = __fmaf_rn(wgt, cb, U2);
+        if (AUX) {
+          UD = __fmaf_rn(Ti, dloc, UD);
+          UN0 = __fmaf_rn(wgt, nv[0], UN0);
+          UN1 = __fmaf_rn(wgt, nv[1], UN1);
+          UN2 = __fmaf_rn(wgt, nv[2], UN2);
+        }
         Tnext = Ti;
         const float f = dLdx * lK;
 #pragma unroll
         for (int m = 0; m < 8; ++m) gv[m] = f * dw[m];
+        if (AUX) {
+          const float gt = gD * Ti;
+#pragma unroll
+          for (int m = 0; m < 8; ++m) gv[m] = __fmaf_rn(gt, dd[m], gv[m]);
+        }
       }
-      const float tot = wave_reduce12(gv[0], gv[1], gv[2], gv[3], gv[4], gv[5], gv[6], gv[7],
-                                      gv[8], gv[9], gv[10], gv[11]);
+      const float tot = wave_reduce16(gv);
       if (writer) {
         const uint32_t vid = B.vid[j];
         float* dst = slot < 8    ? A.g_corner + (int64_t)vid * 8 + slot
                      : slot < 11 ? A.g_rgb + ((int64_t)vid * A.n_cams + ci) * 3 + (slot - 8)
-                                 : A.priority + vid;
+                     : slot < 12 ? A.priority + vid
+                                 : A.g_nrm + (int64_t)vid * 3 + (slot - 12);
         unsafeAtomicAdd(dst, tot);
       }
     }
@@ -638,7 +820,7 @@ __device__ __forceinline__ void render_tile_bwd(const RenderArgs& A, int g, uint
 }
 
 // chunk item k: (tile, chunk), checked against the tile before use
-template <int TS, int KT, int ACT>
+template <int TS, int KT, int ACT, bool AUX>
 __device__ __forceinline__ void bwd_split_item(const RenderArgs& A, uint32_t k,
                                                LdsBatch<TileGeom<TS>::kBatch>& B,
                                                uint32_t& s_lmax) {
@@ -647,21 +829,21 @@ __device__ __forceinline__ void bwd_split_item(const RenderArgs& A, uint32_t k,
   const uint2 rg = A.range[it.x];
   const uint32_t nch = (rg.y - rg.x + kBwdChunk - 1) / kBwdChunk;
   if (it.y + 1 >= nch) return;
-  render_tile_bwd<TS, KT, ACT>(A, (int)it.x, it.y, it.y + 1, B, s_lmax);
+  render_tile_bwd<TS, KT, ACT, AUX>(A, (int)it.x, it.y, it.y + 1, B, s_lmax);
 }
 
 // a tile's whole range, or its last chunk when the others are chunk items
-template <int TS, int KT, int ACT>
+template <int TS, int KT, int ACT, bool AUX>
 __device__ __forceinline__ void bwd_tile_rest(const RenderArgs& A, int g,
                                               LdsBatch<TileGeom<TS>::kBatch>& B,
                                               uint32_t& s_lmax) {
   const uint2 rg = A.range[g];
   const uint32_t nch = (rg.y - rg.x + kBwdChunk - 1) / kBwdChunk;
   const uint32_t m_lo = (A.split_base[g] == kNoSplit || nch == 0) ? 0u : nch - 1;
-  render_tile_bwd<TS, KT, ACT>(A, g, m_lo, nch, B, s_lmax);
+  render_tile_bwd<TS, KT, ACT, AUX>(A, g, m_lo, nch, B, s_lmax);
 }
 
-template <int TS, int KT, int ACT>
+template <int TS, int KT, int ACT, bool AUX>
 __global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderArgs A) {
   __shared__ LdsBatch<TileGeom<TS>::kBatch> B;
   __shared__ uint32_t s_lmax;
@@ -673,11 +855,11 @@ __global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderArgs A) {
     const int b = (int)blockIdx.x;
     if (b < A.split_wgs) {
       for (uint32_t k = (uint32_t)b; k < ns; k += (uint32_t)A.split_wgs) {
-        bwd_split_item<TS, KT, ACT>(A, k, B, s_lmax);
+        bwd_split_item<TS, KT, ACT, AUX>(A, k, B, s_lmax);
         __syncthreads();
       }
     } else if (b - A.split_wgs < A.T) {
-      bwd_tile_rest<TS, KT, ACT>(A, (int)A.order[b - A.split_wgs], B, s_lmax);
+      bwd_tile_rest<TS, KT, ACT, AUX>(A, (int)A.order[b - A.split_wgs], B, s_lmax);
     }
     return;
   }
@@ -686,7 +868,7 @@ __global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderArgs A) {
     __syncthreads();
     const int k = s_tile;
     if (k < 0) break;
-    bwd_split_item<TS, KT, ACT>(A, (uint32_t)k, B, s_lmax);
+    bwd_split_item<TS, KT, ACT, AUX>(A, (uint32_t)k, B, s_lmax);
     __syncthreads();
   }
   __syncthreads();  // every thread has read the last s_tile before it is reused
@@ -695,7 +877,7 @@ __global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderArgs A) {
     __syncthreads();
     const int p = s_tile;
     if (p < 0) break;
-    bwd_tile_rest<TS, KT, ACT>(A, (int)A.order[p], B, s_lmax);
+    bwd_tile_rest<TS, KT, ACT, AUX>(A, (int)A.order[p], B, s_lmax);
     __syncthreads();
   }
 }
@@ -708,8 +890,9 @@ __global__ __launch_bounds__(kBlock) void k_sh_bwd(
     int64_t N, int n_cams, CamSet cams, const float* __restrict__ center,
     const int32_t* __restrict__ vox_grid, const uint32_t* __restrict__ count,
     const VoxRec* __restrict__ rec, const float* __restrict__ g_rgb,
-    const float* __restrict__ g_corner, float* __restrict__ grad_grid, float* __restrict__ grad_sh,
-    int accumulate, int scatter) {
+    float* __restrict__ g_corner, float* __restrict__ grad_grid, float* __restrict__ grad_sh,
+    const float* __restrict__ grid_raw, const float* __restrict__ g_nrm, int accumulate,
+    int scatter) {
   constexpr int NB = (D + 1) * (D + 1);
   constexpr int F = 3 * NB;
   constexpr int FP = F | 1;
@@ -755,6 +938,30 @@ __global__ __launch_bounds__(kBlock) void k_sh_bwd(
       for (int i = threadIdx.x; i < nv * F; i += kBlock) o[i] += stage[(i / F) * FP + (i % F)];
     } else {
       for (int i = threadIdx.x; i < nv * F; i += kBlock) o[i] = stage[(i / F) * FP + (i % F)];
+    }
+  }
+  if (g_nrm && vid < N) {
+    // normal images: dL/dn of the voxel to its corners, n = g / |g| with g the
+    // centre gradient; dL/dg = (dL/dn - n (n . dL/dn)) / |g| and
+    // dg/dV_ijk = 0.25 (2i - 1, 2j - 1, 2k - 1) (Supp. details of voxel normal)
+    const float gn0 = g_nrm[vid * 3 + 0], gn1 = g_nrm[vid * 3 + 1], gn2 = g_nrm[vid * 3 + 2];
+    if (gn0 != 0.f || gn1 != 0.f || gn2 != 0.f) {
+      float V[8], gc3[3];
+#pragma unroll
+      for (int m = 0; m < 8; ++m) V[m] = grid_raw[vox_grid[vid * 8 + m]];
+      centre_gradient(V, gc3);
+      const float g2 = gc3[0] * gc3[0] + gc3[1] * gc3[1] + gc3[2] * gc3[2];
+      if (g2 > 0.f) {
+        const float il = rsqrtf(g2);
+        const float n0 = gc3[0] * il, n1 = gc3[1] * il, n2 = gc3[2] * il;
+        const float nd = n0 * gn0 + n1 * gn1 + n2 * gn2;
+        const float q0 = 0.25f * (gn0 - n0 * nd) * il, q1 = 0.25f * (gn1 - n1 * nd) * il,
+                    q2 = 0.25f * (gn2 - n2 * nd) * il;
+#pragma unroll
+        for (int m = 0; m < 8; ++m)
+          g_corner[vid * 8 + m] += (((m >> 2) & 1) ? q0 : -q0) + (((m >> 1) & 1) ? q1 : -q1) +
+                                   ((m & 1) ? q2 : -q2);
+      }
     }
   }
   if (grad_grid && scatter && vid < N) {
@@ -803,27 +1010,44 @@ static RenderArgs render_args(const CamSet& cams, const svr_opts& o, const Layou
   A.split_wgs = (int)min((int64_t)kSplitWgs, L.max_split);
   A.max_weight = nullptr;
   A.priority = nullptr;
+  A.depth = A.normal = nullptr;
+  A.grad_depth = A.grad_normal = nullptr;
+  A.ckpt_aux = at<float4>(ws, L.ckpt_aux);
+  A.g_nrm = at<float>(ws, L.g_nrm);
+  A.aux = 0;
   return A;
 }
 
-template <int TS, int KT, int ACT>
+template <int TS, int KT, int ACT, bool AUX>
 static void launch_kind(RKind kind, const RenderArgs& A, unsigned grid, hipStream_t s) {
   const dim3 blk(TS * TS);
   switch (kind) {
     case RKind::kFwd:
-      SVR_LAUNCH("render_fwd", (k_render_fwd<TS, KT, ACT, false>), dim3(grid), blk, 0, s, A);
+      SVR_LAUNCH("render_fwd", (k_render_fwd<TS, KT, ACT, false, AUX>), dim3(grid), blk, 0, s, A);
       break;
     case RKind::kStats:
-      SVR_LAUNCH("render_stats", (k_render_fwd<TS, KT, ACT, true>), dim3(grid), blk, 0, s, A);
+      SVR_LAUNCH("render_stats", (k_render_fwd<TS, KT, ACT, true, false>), dim3(grid), blk, 0, s,
+                 A);
       break;
     case RKind::kBwd:
-      SVR_LAUNCH("render_bwd", (k_render_bwd<TS, KT, ACT>), dim3(grid), blk, 0, s, A);
+      SVR_LAUNCH("render_bwd", (k_render_bwd<TS, KT, ACT, AUX>), dim3(grid), blk, 0, s, A);
       break;
   }
 }
 
+template <int TS, int KT, int ACT>
+static void launch_kind(RKind kind, const RenderArgs& A, unsigned grid, hipStream_t s) {
+  launch_kind<TS, KT, ACT, false>(kind, A, grid, s);
+}
+
 template <int TS, int ACT>
 static void launch_k(RKind kind, const RenderArgs& A, unsigned grid, hipStream_t s) {
+  // depth and normal images: one kernel per tile size and activation, K at
+  // run time
+  if (A.aux && kind != RKind::kStats) {
+    launch_kind<TS, 0, ACT, true>(kind, A, grid, s);
+    return;
+  }
   switch (A.K) {
     case 1: launch_kind<TS, 1, ACT>(kind, A, grid, s); break;
     case 2: launch_kind<TS, 2, ACT>(kind, A, grid, s); break;
@@ -859,11 +1083,16 @@ static hipError_t launch_render(RKind kind, const RenderArgs& A, const svr_opts&
 
 hipError_t launch_render_fwd(const svr_scene& sc, const CamSet& cams, const svr_opts& o,
                              const Layout& L, void* ws, const uint32_t* vals, float* rgba,
-                             float* max_weight, hipStream_t s) {
+                             const svr_extra* extra, hipStream_t s) {
   (void)sc;
   RenderArgs A = render_args(cams, o, L, ws, vals);
   A.rgba = reinterpret_cast<float4*>(rgba);
-  A.max_weight = reinterpret_cast<uint32_t*>(max_weight);
+  if (extra) {
+    A.max_weight = reinterpret_cast<uint32_t*>(extra->max_weight);
+    A.depth = extra->depth;
+    A.normal = extra->normal;
+    A.aux = (extra->depth || extra->normal) ? 1 : 0;
+  }
   return launch_render(RKind::kFwd, A, o, L, ws, s);
 }
 
@@ -879,16 +1108,22 @@ hipError_t launch_render_stats(const svr_scene& sc, const CamSet& cams, const sv
 
 hipError_t launch_render_bwd(const svr_scene& sc, const CamSet& cams, const svr_opts& o,
                              const Layout& L, void* ws, const uint32_t* vals,
-                             const float* grad_rgba, float* priority, hipStream_t s) {
+                             const float* grad_rgba, const svr_extra* extra, hipStream_t s) {
   (void)sc;
+  RenderArgs A = render_args(cams, o, L, ws, vals);
+  A.grad_rgba = reinterpret_cast<const float4*>(grad_rgba);
+  if (extra) {
+    A.priority = extra->priority;
+    A.grad_depth = extra->grad_depth;
+    A.grad_normal = extra->grad_normal;
+    A.aux = (extra->grad_depth || extra->grad_normal) ? 1 : 0;
+  }
   FillSet z;
   z.add(at<uint32_t>(ws, L.g_corner), L.N * 8);
   z.add(at<uint32_t>(ws, L.g_rgb), L.NV * 3);
+  if (A.aux) z.add(at<uint32_t>(ws, L.g_nrm), L.N * 3);
   hipError_t e = launch_zero_u32(z, s);
   if (e != hipSuccess) return e;
-  RenderArgs A = render_args(cams, o, L, ws, vals);
-  A.grad_rgba = reinterpret_cast<const float4*>(grad_rgba);
-  A.priority = priority;
   return launch_render(RKind::kBwd, A, o, L, ws, s);
 }
 
@@ -911,7 +1146,8 @@ __global__ __launch_bounds__(kBlock) void k_grid_gather(int64_t M, const int32_t
 }
 
 hipError_t launch_sh_bwd(const svr_scene& sc, const CamSet& cams, const Layout& L, void* ws,
-                         float* grad_grid, float* grad_sh, bool accumulate, hipStream_t s) {
+                         float* grad_grid, float* grad_sh, bool accumulate, bool aux,
+                         hipStream_t s) {
   const bool gather = sc.grid_adj_off != nullptr && sc.grid_adj != nullptr;
   if (grad_grid && !accumulate && !gather) {
     hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(grad_grid), 0u, sc.n_grid, s);
@@ -923,7 +1159,8 @@ hipError_t launch_sh_bwd(const svr_scene& sc, const CamSet& cams, const Layout& 
   SVR_LAUNCH("sh_bwd", k_sh_bwd<D>, grid, dim3(kBlock), 0, s, L.N, L.n_cams, cams, sc.center,   \
              sc.vox_grid, at<uint32_t>(ws, L.count), at<VoxRec>(ws, L.rec),                     \
              at<float>(ws, L.g_rgb), at<float>(ws, L.g_corner), grad_grid, grad_sh,            \
-             accumulate ? 1 : 0, gather ? 0 : 1)
+             sc.grid_raw, aux ? at<float>(ws, L.g_nrm) : nullptr, accumulate ? 1 : 0,          \
+             gather ? 0 : 1)
     switch (sc.sh_degree) {
       case 0: SVR_SHB(0); break;
       case 1: SVR_SHB(1); break;

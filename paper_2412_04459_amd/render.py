@@ -21,15 +21,19 @@ def _ptr(t: Optional[torch.Tensor]):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
 
-def _train(max_weight, priority):
-    """svr_train_stats for the given float32 [n_voxels] tensors, or None."""
-    if max_weight is None and priority is None:
+def _extra(**tensors):
+    """svr_extra for the given tensors (float32, contiguous; None: off), or
+    None when all are None."""
+    if all(t is None for t in tensors.values()):
         return None
-    for t in (max_weight, priority):
-        if t is not None and (t.dtype != torch.float32 or not t.is_contiguous()):
-            raise ValueError("training statistics must be contiguous float32 tensors")
-    return _abi.svr_train_stats(None if max_weight is None else max_weight.data_ptr(),
-                                None if priority is None else priority.data_ptr())
+    ex = _abi.svr_extra()
+    for name, t in tensors.items():
+        if t is None:
+            continue
+        if t.dtype != torch.float32 or not t.is_contiguous():
+            raise ValueError("%s must be a contiguous float32 tensor" % name)
+        setattr(ex, name, t.data_ptr())
+    return ex
 
 
 def _stream():
@@ -207,27 +211,34 @@ class Rasterizer:
                             self.ws_bytes, self.n_entries, _stream()), "svr_sort")
 
     def render_fwd(self, grid_raw=None, sh=None, out: Optional[torch.Tensor] = None,
-                   max_weight: Optional[torch.Tensor] = None):
+                   max_weight: Optional[torch.Tensor] = None,
+                   depth: Optional[torch.Tensor] = None, normal: Optional[torch.Tensor] = None):
         """``max_weight`` (float32 [n_voxels], zeroed by the caller once per
-        statistics window): per-voxel maximum blending weight, updated."""
+        statistics window): per-voxel maximum blending weight, updated.
+        ``depth`` [n_pixels] / ``normal`` [n_pixels, 3]: depth and normal
+        images, written."""
         st = self.ds.struct(grid_raw, sh)
         if out is None:
             out = torch.empty((self.n_pixels, 4), dtype=torch.float32, device=self.ds.device)
+        ex = _extra(max_weight=max_weight, depth=depth, normal=normal)
         check(_abi.svr_render_fwd(st, self.cam_arr, self.n_cams, self.opts, self._ws_ptr(),
-                                  self.ws_bytes, _ptr(out), _train(max_weight, None), _stream()),
-              "svr_render_fwd")
+                                  self.ws_bytes, _ptr(out), ex, _stream()), "svr_render_fwd")
         return out
 
-    def forward(self, grid_raw=None, sh=None, out=None, max_weight=None):
+    def forward(self, grid_raw=None, sh=None, out=None, max_weight=None, depth=None,
+                normal=None):
         self.preprocess(grid_raw, sh)
         self.sort()
-        return self.render_fwd(grid_raw, sh, out, max_weight)
+        return self.render_fwd(grid_raw, sh, out, max_weight, depth, normal)
 
     def backward(self, grad_rgba: torch.Tensor, grid_raw=None, sh=None, grad_grid=None,
                  grad_sh=None, want_grid=True, want_sh=True,
-                 priority: Optional[torch.Tensor] = None):
+                 priority: Optional[torch.Tensor] = None,
+                 grad_depth: Optional[torch.Tensor] = None,
+                 grad_normal: Optional[torch.Tensor] = None):
         """``priority`` (float32 [n_voxels]): per-voxel subdivision priority,
-        accumulated into."""
+        accumulated into.  ``grad_depth`` / ``grad_normal``: upstream gradients
+        of the depth and normal images (the forward must have produced them)."""
         st = self.ds.struct(grid_raw, sh)
         g = grad_rgba.contiguous().float()
         if g.numel() != self.n_pixels * 4:
@@ -238,7 +249,9 @@ class Rasterizer:
             grad_sh = torch.empty_like(self.ds.sh)
         check(_abi.svr_render_bwd(st, self.cam_arr, self.n_cams, self.opts, self._ws_ptr(),
                                   self.ws_bytes, _ptr(g), _ptr(grad_grid if want_grid else None),
-                                  _ptr(grad_sh if want_sh else None), _train(None, priority),
+                                  _ptr(grad_sh if want_sh else None),
+                                  _extra(priority=priority, grad_depth=grad_depth,
+                                         grad_normal=grad_normal),
                                   _stream()),
               "svr_render_bwd")
         return grad_grid, grad_sh

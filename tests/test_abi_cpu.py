@@ -150,9 +150,10 @@ def test_workspace_parts_sum_to_total():
         # count, offset, rect (4 + 8 + 8 B) and a 64-byte record per (voxel, camera)
         nv = 5000 * n_cams
         assert 84 * nv <= parts["per_voxel_camera_records"] <= 84 * nv + 4 * 256
-        # 8 B per pixel, plus a 16 B checkpoint per pixel of a 16x16 tile for
-        # each possible backward chunk (capacity / 256 + 1)
-        ck = (70000 // 256 + 1) * 256 * 16
+        # 8 B per pixel, plus two 16 B checkpoints (colour, depth and normal)
+        # per pixel of a 16x16 tile for each possible backward chunk
+        # (capacity / 256 + 1)
+        ck = 2 * (70000 // 256 + 1) * 256 * 16
         assert 8 * 6000 * n_cams + ck <= parts["per_pixel_state"] <= 8 * 6000 * n_cams + ck + 768
     with pytest.raises(ValueError):
         o.K = 0

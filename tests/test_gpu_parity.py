@@ -457,3 +457,51 @@ def test_training_statistics_leave_image_and_gradients_unchanged(torch_dev):
     assert torch.equal(a, b)
     # gradients go through float atomics: equal up to summation order
     assert torch.allclose(ga, gb, rtol=1e-5, atol=1e-7) and torch.allclose(sa, sb, rtol=1e-5, atol=1e-7)
+
+
+# ---------------------------------------------------------------------------
+# depth and normal images (Sec. 3.1.1 "Voxel normal", "Voxel depth") and
+# their adjoint
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("case,K,act,tile", [("shell_opaque", 2, 0, 16), ("shell", 3, 0, 8),
+                                             ("tiny", 2, 1, 8), ("shell_opaque", 1, 0, 32)])
+def test_depth_normal_match_oracle(torch_dev, case, K, act, tile):
+    torch = torch_dev
+    from paper_2412_04459_amd.render import DeviceScene, Rasterizer
+    if case.startswith("shell"):
+        scene, cams = S.sphere_shell_scene(opaque=case.endswith("opaque")), [S.sphere_shell_camera()]
+    else:
+        scene = S.tiny_random_scene(9, max_level=4, sh_degree=3)
+        cams = [S.look_at(90, 70, 80.0, [1.7, 1.4, 1.2], target=(0.5, 0.5, 0.5))]
+    _say("depth and normal %s K=%d act=%d tile %d" % (case, K, act, tile))
+    P = cams[0].W * cams[0].H
+    rng = np.random.default_rng(40 + K)
+    g = S.upstream_grads(P, 10)
+    gd = rng.normal(size=P).astype(np.float32)
+    gn = rng.normal(size=(P, 3)).astype(np.float32)
+    ref0 = oracle.render(scene, cams[0], K=K, activation=act, depth_normal=True)
+    ok = ref0["flags"] == 0
+    g[~ok] = 0.0
+    gd[~ok] = 0.0
+    gn[~ok] = 0.0
+    ref = oracle.render(scene, cams[0], K=K, activation=act, grad_rgba=g.astype(np.float64),
+                        depth_normal=True, grad_depth=gd.astype(np.float64),
+                        grad_normal=gn.astype(np.float64))
+    ds = DeviceScene(scene)
+    rast = Rasterizer(ds, cams, K=K, activation=act, tile=tile)
+    dep = torch.empty(P, dtype=torch.float32, device="cuda")
+    nrm = torch.empty((P, 3), dtype=torch.float32, device="cuda")
+    rgba = rast.forward(depth=dep, normal=nrm)
+    gg, gs = rast.backward(torch.from_numpy(g).cuda(), grad_depth=torch.from_numpy(gd).cuda(),
+                           grad_normal=torch.from_numpy(gn).cuda())
+    torch.cuda.synchronize()
+    _check_rgba(rgba.cpu().numpy().astype(np.float64), ref0)
+    d = dep.cpu().numpy().astype(np.float64)
+    n = nrm.cpu().numpy().astype(np.float64)
+    ed = np.abs(d - ref0["depth"])[ok]
+    en = np.abs(n - ref0["normal"]).max(1)[ok]
+    assert ed.max() <= RGBA_TOL * max(1.0, np.abs(ref0["depth"]).max()), "depth off by %.3g" % ed.max()
+    assert en.max() <= RGBA_TOL, "normal off by %.3g" % en.max()
+    assert np.abs(ref0["depth"]).max() > 0.1 and np.abs(ref0["normal"]).max() > 0.01
+    _check_grad(gg.cpu().numpy().astype(np.float64), ref["grad_grid"], "grad_grid")
+    _check_grad(gs.cpu().numpy().astype(np.float64), ref["grad_sh"], "grad_sh")
