@@ -375,6 +375,28 @@ def main():
     stats_ms_step = ev0.elapsed_time(ev1) / args.steps
     del mw, pr
 
+    # the same steps rendering and differentiating depth and normal images too
+    dep = torch.empty(P, dtype=torch.float32, device="cuda")
+    nrm = torch.empty((P, 3), dtype=torch.float32, device="cuda")
+    gdep = torch.from_numpy(np.random.default_rng(3).normal(size=P).astype(np.float32)).cuda()
+    gnrm = torch.from_numpy(np.random.default_rng(4).normal(size=(P, 3)).astype(np.float32)).cuda()
+
+    def step_aux(i):
+        rast.set_cameras([cams[i % len(cams)]])
+        rast.forward(depth=dep, normal=nrm)
+        rast.backward(grad, grad_depth=gdep, grad_normal=gnrm)
+
+    for i in range(2):
+        step_aux(i)
+    torch.cuda.synchronize()
+    ev0.record()
+    for i in range(args.steps):
+        step_aux(i)
+    ev1.record()
+    torch.cuda.synchronize()
+    aux_ms_step = ev0.elapsed_time(ev1) / args.steps
+    del dep, nrm, gdep, gnrm
+
     # the same frames replayed from one captured hipGraph per view (no host
     # launch overhead); this is the headline number
     gstream = torch.cuda.Stream()
@@ -444,6 +466,8 @@ def main():
         "eager": {"ms_per_step": eager_ms_step, "mpix_s": P / (eager_ms_step / 1e3) / 1e6},
         "with_train_stats": {"ms_per_step": stats_ms_step,
                              "overhead": stats_ms_step / eager_ms_step - 1.0},
+        "with_depth_normal": {"ms_per_step": aux_ms_step,
+                              "overhead": aux_ms_step / eager_ms_step - 1.0},
         "frame_hbm": {"bytes": fbytes, "achieved_GBs": frame_gbs, "peak_GBs": HBM_PEAK_GBS,
                       "frac": frame_gbs / HBM_PEAK_GBS},
         "roofline": roof,
