@@ -48,6 +48,8 @@ def _load():
                                        P, P, P, P, P, P, I32, P, P, P, P, P, P, P, P, P, I32]
         _lib.oracle_render.restype = I32
         _lib.oracle_voxel_tiles.argtypes = [I64, P, P, P, I32, I32, D, D, P, P]
+        _lib.oracle_downsample.argtypes = [P, I32, I32, P, I32, I32, P]
+        _lib.oracle_downsample.restype = None
         _lib.oracle_voxel_tiles.restype = None
         _lib.oracle_tile_masks.argtypes = [P, I32, I32, D, P, P]
         _lib.oracle_tile_masks.restype = None
@@ -269,4 +271,19 @@ def expected_entries(scene, cam, tile_w=16, tile_h=16, z_near=Z_NEAR, band=0.02,
         kp, kc, val = keys(t + tile_offset, v, s, scene.octpath, scene.max_level)
         order = np.lexsort((val, kp))
         out[name] = (kc[order], val[order], kp[order])
+    return out
+
+
+# --------------------------------------------------------------------------
+# anti-aliased downsampling and background (Sec. 3.1.2 "Anti-aliasing")
+# --------------------------------------------------------------------------
+def downsample(img, w_out: int, h_out: int, bg=None):
+    """img [h_in, w_in, 4] (or [h_in * w_in, 4] with w_in given by shape) ->
+    [h_out, w_out, 4]: separable tent filter of half-width n_in / n_out, then
+    rgb += (1 - A) bg when bg is given."""
+    img = np.ascontiguousarray(img, np.float64)
+    h_in, w_in = img.shape[0], img.shape[1]
+    out = np.zeros((h_out, w_out, 4), np.float64)
+    b = None if bg is None else np.ascontiguousarray(bg, np.float64).reshape(3)
+    _load().oracle_downsample(_p(img), int(w_in), int(h_in), _p(out), int(w_out), int(h_out), _p(b))
     return out

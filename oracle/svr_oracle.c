@@ -731,3 +731,55 @@ void oracle_tile_masks(const double* cam, int tile_w, int tile_h, double rel_ban
         if ((f & ~amb) == 0) may[t] |= (uint8_t)(1u << (s ^ f));
     }
 }
+
+/* ------------------------------------------------------------------------ */
+/* Anti-aliased downsampling (Sec. 3.1.2 "Anti-aliasing": render ss times    */
+/* larger, then downsample with an anti-aliasing filter) and background      */
+/* (Supp. implementation details: a background colour fills the remaining   */
+/* transmittance).  Reading for the unspecified filter: the separable tent   */
+/* of half-width s = n_in / n_out per axis, centred at (i + 1/2) s - 1/2 in  */
+/* input pixel coordinates, weights normalised over the in-image taps.       */
+/*   out[y][x][c] = sum_{j,k} wy(y,j) wx(x,k) in[j][k][c]                    */
+/*   out rgb += (1 - out A) * bg                                             */
+/* img layout [h][w][4].                                                     */
+/* ------------------------------------------------------------------------ */
+static void tent_weights(int n_in, int n_out, int i, int* j0, int* j1, double* w) {
+  double s = (double)n_in / (double)n_out;
+  double c = (i + 0.5) * s - 0.5;
+  int lo = (int)floor(c - s), hi = (int)ceil(c + s);
+  if (lo < 0) lo = 0;
+  if (hi > n_in - 1) hi = n_in - 1;
+  double tot = 0;
+  for (int j = lo; j <= hi; ++j) {
+    double t = 1.0 - fabs((double)j - c) / s;
+    w[j - lo] = t > 0 ? t : 0;
+    tot += w[j - lo];
+  }
+  for (int j = lo; j <= hi; ++j) w[j - lo] /= tot;
+  *j0 = lo;
+  *j1 = hi;
+}
+
+void oracle_downsample(const double* in, int w_in, int h_in, double* out, int w_out, int h_out,
+                       const double* bg) {
+  double* wx = (double*)malloc((size_t)(2 * w_in + 4) * sizeof(double));
+  double* wy = (double*)malloc((size_t)(2 * h_in + 4) * sizeof(double));
+  for (int y = 0; y < h_out; ++y) {
+    int y0, y1;
+    tent_weights(h_in, h_out, y, &y0, &y1, wy);
+    for (int x = 0; x < w_out; ++x) {
+      int x0, x1;
+      tent_weights(w_in, w_out, x, &x0, &x1, wx);
+      double acc[4] = {0, 0, 0, 0};
+      for (int j = y0; j <= y1; ++j)
+        for (int k = x0; k <= x1; ++k)
+          for (int c = 0; c < 4; ++c)
+            acc[c] += wy[j - y0] * wx[k - x0] * in[((size_t)j * w_in + k) * 4 + c];
+      if (bg)
+        for (int c = 0; c < 3; ++c) acc[c] += (1.0 - acc[3]) * bg[c];
+      for (int c = 0; c < 4; ++c) out[((size_t)y * w_out + x) * 4 + c] = acc[c];
+    }
+  }
+  free(wx);
+  free(wy);
+}

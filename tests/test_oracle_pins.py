@@ -618,3 +618,32 @@ def test_depth_normal_adjoint_matches_central_differences(K, act, opaque):
         assert gg[m] == pytest.approx(fd, rel=1e-5, abs=1e-8 * np.abs(gg).max())
     # SH gradients see only the colour term
     assert np.allclose(plain["grad_sh"], ref["grad_sh"], rtol=1e-12, atol=0)
+
+
+# --------------------------------------------------------------------------
+# anti-aliased downsampling (Sec. 3.1.2 "Anti-aliasing") and background
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("src,dst", [((33, 21), (30, 19)), ((64, 48), (32, 24)),
+                                     ((40, 30), (27, 20)), ((17, 9), (17, 9))])
+def test_downsample_equals_antialiased_bilinear(src, dst):
+    # the tent filter of half-width n_in / n_out is what antialiased bilinear
+    # resizing computes; compare with the library routine in float64
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(src[0] * 100 + dst[0])
+    img = rng.random((src[1], src[0], 4))
+    ours = oracle.downsample(img, dst[0], dst[1])
+    t = torch.from_numpy(img).permute(2, 0, 1)[None]
+    ref = torch.nn.functional.interpolate(t, size=(dst[1], dst[0]), mode="bilinear",
+                                          antialias=True, align_corners=False)
+    ref = ref[0].permute(1, 2, 0).numpy()
+    assert np.allclose(ours, ref, atol=1e-12, rtol=0)
+
+
+def test_downsample_preserves_constants_and_adds_background():
+    img = np.zeros((30, 45, 4))
+    img[..., :3] = [0.2, 0.4, 0.6]
+    img[..., 3] = 0.75
+    out = oracle.downsample(img, 30, 20, bg=[1.0, 0.5, 0.0])
+    assert np.allclose(out[..., 3], 0.75, atol=1e-14)
+    assert np.allclose(out[..., :3], np.array([0.2, 0.4, 0.6]) + 0.25 * np.array([1.0, 0.5, 0.0]),
+                       atol=1e-14)
