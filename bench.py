@@ -115,6 +115,62 @@ def measured_traffic(kernel_prefix):
     return None, None
 
 
+def supersampled_run(ds, cams, K, tile, grad, steps, log):
+    """Anti-aliased frames (Sec. 3.1.2): each view rendered at ss times its
+    resolution, downsampled by the tent filter with a background colour, and
+    differentiated through both; ms per frame and target Mpix/s."""
+    import torch
+    from paper_2412_04459_amd.render import Rasterizer, downsample, supersampled_camera
+    out = {}
+    W, H = cams[0].W, cams[0].H
+    bg = [0.5, 0.5, 0.5]
+    for ss in (1.1, 1.5):
+        hi = [supersampled_camera(c, ss) for c in cams]
+        probe = Rasterizer(ds, [hi[0]], K=K, sync_count=True, tile=tile)
+        e_max = 0
+        for c in hi[:8]:
+            probe.set_cameras([c])
+            probe.preprocess()
+            e_max = max(e_max, probe.n_entries)
+        del probe
+        r = Rasterizer(ds, [hi[0]], K=K, capacity=int(e_max * 1.2) + 4096, sync_count=False,
+                       tile=tile)
+        Wh, Hh = hi[0].W, hi[0].H
+        rgba = torch.empty((Wh * Hh, 4), dtype=torch.float32, device="cuda")
+        lo = torch.empty((W * H, 4), dtype=torch.float32, device="cuda")
+        from paper_2412_04459_amd import _abi
+        from paper_2412_04459_amd.render import _bg_arr, _ptr, _stream
+        g_hi = torch.empty_like(rgba)
+        bga = _bg_arr(bg)
+
+        def step(i):
+            r.set_cameras([hi[i % len(hi)]])
+            r.forward(out=rgba)
+            _abi.svr_downsample(_ptr(rgba), Wh, Hh, _ptr(lo), W, H, bga, _stream())
+            _abi.svr_downsample_bwd(_ptr(grad), W, H, _ptr(g_hi), Wh, Hh, bga, _stream())
+            r.backward(g_hi)
+
+        for i in range(3):
+            step(i)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for i in range(steps):
+            step(i)
+        e1.record()
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / steps
+        over = r.check_overflow()
+        out["ss%.1f" % ss] = {"render_resolution": "%dx%d" % (Wh, Hh), "ms_per_frame": ms,
+                              "target_mpix_s": W * H / (ms / 1e3) / 1e6,
+                              "overflow": over > r.capacity}
+        log("supersampled ss=%.1f (%dx%d): %.3f ms per fwd+bwd frame" % (ss, Wh, Hh, ms))
+        del r, rgba, lo, g_hi
+        torch.cuda.empty_cache()
+    return out
+
+
 def large_scene_run(log):
     """~8M voxels (max level 14), 16 views at 1920x1080, K = 1, fwd+bwd of all
     16 views in one batched graph (16x16 tiles, one launch per stage), plus
@@ -473,6 +529,7 @@ def main():
         "roofline": roof,
         "kernels": per_kernel,
     }
+    out["supersampled"] = supersampled_run(ds, cams, K, tile, grad, min(args.steps, 24), log)
     if not args.no_batched:
         out["batched"] = batched_comparison(ds, K, log)
     if args.large:

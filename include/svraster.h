@@ -284,6 +284,23 @@ int svr_graph_capture(const svr_scene* scene, const svr_camera* cams, int n_cams
 int svr_graph_launch(void* graph, void* stream);
 int svr_graph_destroy(void* graph);
 
+/* Anti-aliasing (Sec. 3.1.2 "Anti-aliasing": render ss times larger, then
+ * downsample with an anti-aliasing filter) and background colour (the
+ * supplementary implementation details use the average frame colour).
+ * svr_downsample: out[h_out][w_out][4] from in[h_in][w_in][4] (device, rgba as
+ * svr_render_fwd writes it) by the separable tent of half-width
+ * n_in / n_out per axis, centred at (i + 1/2) n_in / n_out - 1/2, weights
+ * normalised over the in-image taps; then rgb += (1 - A) bg (bg: HOST
+ * float[3], NULL for black).  svr_downsample_bwd: the adjoint, grad_in from
+ * grad_out (overwritten).  Render at w_in x h_in with the intrinsics scaled by
+ * w_in / w_out and h_in / h_out.
+ * Errors: SVR_E_INVALID (sizes: 1 <= out <= in <= 65536, null pointers),
+ * SVR_E_HIP.                                                                 */
+int svr_downsample(const float* in, int w_in, int h_in, float* out, int w_out, int h_out,
+                   const float* bg, void* stream);
+int svr_downsample_bwd(const float* grad_out, int w_out, int h_out, float* grad_in, int w_in,
+                       int h_in, const float* bg, void* stream);
+
 /* Corner adjacency of the grid points, a property of the scene topology
  * (build once per vox_grid): for grid point m, adj[adj_off[m] .. adj_off[m+1])
  * lists, in increasing order, the corner slots 8 v + c whose vox_grid entry is

@@ -50,6 +50,8 @@ def _load():
         _lib.oracle_voxel_tiles.argtypes = [I64, P, P, P, I32, I32, D, D, P, P]
         _lib.oracle_downsample.argtypes = [P, I32, I32, P, I32, I32, P]
         _lib.oracle_downsample.restype = None
+        _lib.oracle_downsample_adjoint.argtypes = [P, I32, I32, P, I32, I32, P]
+        _lib.oracle_downsample_adjoint.restype = None
         _lib.oracle_voxel_tiles.restype = None
         _lib.oracle_tile_masks.argtypes = [P, I32, I32, D, P, P]
         _lib.oracle_tile_masks.restype = None
@@ -287,3 +289,14 @@ def downsample(img, w_out: int, h_out: int, bg=None):
     b = None if bg is None else np.ascontiguousarray(bg, np.float64).reshape(3)
     _load().oracle_downsample(_p(img), int(w_in), int(h_in), _p(out), int(w_out), int(h_out), _p(b))
     return out
+
+
+def downsample_adjoint(gout, w_in: int, h_in: int, bg=None):
+    """D^T gout: gout [h_out, w_out, 4] -> [h_in, w_in, 4]."""
+    gout = np.ascontiguousarray(gout, np.float64)
+    h_out, w_out = gout.shape[0], gout.shape[1]
+    gin = np.zeros((h_in, w_in, 4), np.float64)
+    b = None if bg is None else np.ascontiguousarray(bg, np.float64).reshape(3)
+    _load().oracle_downsample_adjoint(_p(gout), int(w_out), int(h_out), _p(gin), int(w_in),
+                                      int(h_in), _p(b))
+    return gin

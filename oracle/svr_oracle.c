@@ -783,3 +783,30 @@ void oracle_downsample(const double* in, int w_in, int h_in, double* out, int w_
   free(wx);
   free(wy);
 }
+
+/* adjoint of oracle_downsample: grad_in = D^T grad_out for the linear map D  */
+/* above (the background term makes out rgb depend on out A: its gradient   */
+/* adds -<g_rgb, bg> to the alpha channel before the transpose)             */
+void oracle_downsample_adjoint(const double* gout, int w_out, int h_out, double* gin, int w_in,
+                               int h_in, const double* bg) {
+  double* wx = (double*)malloc((size_t)(2 * w_in + 4) * sizeof(double));
+  double* wy = (double*)malloc((size_t)(2 * h_in + 4) * sizeof(double));
+  memset(gin, 0, (size_t)w_in * h_in * 4 * sizeof(double));
+  for (int y = 0; y < h_out; ++y) {
+    int y0, y1;
+    tent_weights(h_in, h_out, y, &y0, &y1, wy);
+    for (int x = 0; x < w_out; ++x) {
+      int x0, x1;
+      tent_weights(w_in, w_out, x, &x0, &x1, wx);
+      const double* g = gout + ((size_t)y * w_out + x) * 4;
+      double ge[4] = {g[0], g[1], g[2], g[3]};
+      if (bg) ge[3] -= g[0] * bg[0] + g[1] * bg[1] + g[2] * bg[2];
+      for (int j = y0; j <= y1; ++j)
+        for (int k = x0; k <= x1; ++k)
+          for (int c = 0; c < 4; ++c)
+            gin[((size_t)j * w_in + k) * 4 + c] += wy[j - y0] * wx[k - x0] * ge[c];
+    }
+  }
+  free(wx);
+  free(wy);
+}

@@ -71,6 +71,10 @@ _SIGS = {
     "svr_graph_capture": (ctypes.c_int, [P, P, ctypes.c_int, P, P, ctypes.c_size_t, P, P, P, P, P,
                                          P, P]),
     "svr_graph_launch": (ctypes.c_int, [P, P]),
+    "svr_downsample": (ctypes.c_int, [P, ctypes.c_int, ctypes.c_int, P, ctypes.c_int, ctypes.c_int,
+                                      P, P]),
+    "svr_downsample_bwd": (ctypes.c_int, [P, ctypes.c_int, ctypes.c_int, P, ctypes.c_int,
+                                          ctypes.c_int, P, P]),
     "svr_graph_destroy": (ctypes.c_int, [P]),
     "svr_grid_adjacency_scratch_bytes": (ctypes.c_size_t, [I64, I64]),
     "svr_build_grid_adjacency": (ctypes.c_int, [P, I64, I64, P, P, P, ctypes.c_size_t, P]),
@@ -249,3 +253,11 @@ def svr_status_string(status):
 
 def svr_last_error():
     return load().svr_last_error().decode()
+
+
+def svr_downsample(img_in, w_in, h_in, img_out, w_out, h_out, bg, stream):
+    return load().svr_downsample(img_in, w_in, h_in, img_out, w_out, h_out, bg, stream)
+
+
+def svr_downsample_bwd(grad_out, w_out, h_out, grad_in, w_in, h_in, bg, stream):
+    return load().svr_downsample_bwd(grad_out, w_out, h_out, grad_in, w_in, h_in, bg, stream)

@@ -600,6 +600,32 @@ int svr_build_grid_adjacency(const int32_t* vox_grid, int64_t n_voxels, int64_t 
   return SVR_OK;
 }
 
+int svr_downsample(const float* in, int w_in, int h_in, float* out, int w_out, int h_out,
+                   const float* bg, void* stream) {
+  if (w_out < 1 || h_out < 1 || w_in < w_out || h_in < h_out || w_in > 65536 || h_in > 65536)
+    return fail(SVR_E_INVALID, "sizes %dx%d -> %dx%d: need 1 <= out <= in <= 65536", w_in, h_in,
+                w_out, h_out);
+  if (!in || !out) return fail(SVR_E_INVALID, "null image");
+  const float zero[3] = {0.f, 0.f, 0.f};
+  SVR_HIP(launch_downsample(in, w_in, h_in, out, w_out, h_out, bg ? bg : zero,
+                            reinterpret_cast<hipStream_t>(stream)),
+          "downsample");
+  return SVR_OK;
+}
+
+int svr_downsample_bwd(const float* grad_out, int w_out, int h_out, float* grad_in, int w_in,
+                       int h_in, const float* bg, void* stream) {
+  if (w_out < 1 || h_out < 1 || w_in < w_out || h_in < h_out || w_in > 65536 || h_in > 65536)
+    return fail(SVR_E_INVALID, "sizes %dx%d -> %dx%d: need 1 <= out <= in <= 65536", w_in, h_in,
+                w_out, h_out);
+  if (!grad_out || !grad_in) return fail(SVR_E_INVALID, "null image");
+  const float zero[3] = {0.f, 0.f, 0.f};
+  SVR_HIP(launch_downsample_bwd(grad_out, w_out, h_out, grad_in, w_in, h_in, bg ? bg : zero,
+                                reinterpret_cast<hipStream_t>(stream)),
+          "downsample adjoint");
+  return SVR_OK;
+}
+
 const char* svr_status_string(int status) {
   switch (status) {
     case SVR_OK: return "ok";

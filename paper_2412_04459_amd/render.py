@@ -457,3 +457,52 @@ def radix_sort_pairs(keys: torch.Tensor, vals: torch.Tensor, bits: int = 64):
     check(_abi.svr_radix_sort_pairs(_ptr(keys), _ptr(vals), _ptr(kt), _ptr(vt), n, bits,
                                     ctypes.c_void_p(p), nb, _stream()), "svr_radix_sort_pairs")
     return keys, vals
+
+
+# -- anti-aliasing (Sec. 3.1.2 "Anti-aliasing") and background -----------------------
+def supersampled_camera(cam, ss: float):
+    """The camera rendering ``cam``'s view at ss times its resolution
+    (rounded), intrinsics scaled with the image so that pixel centres map
+    onto each other: (u + 1/2) W' / W."""
+    import dataclasses
+    W2 = max(cam.W, int(round(cam.W * ss)))
+    H2 = max(cam.H, int(round(cam.H * ss)))
+    sx, sy = W2 / cam.W, H2 / cam.H
+    return dataclasses.replace(cam, W=W2, H=H2, fx=cam.fx * sx, fy=cam.fy * sy, cx=cam.cx * sx,
+                               cy=cam.cy * sy)
+
+
+def _bg_arr(bg):
+    if bg is None:
+        return None
+    a = (ctypes.c_float * 3)(*[float(x) for x in bg])
+    return a
+
+
+class DownsampleFunction(torch.autograd.Function):
+    """rgba at (w_out, h_out) from a supersampled rgba (svr_downsample), with
+    the background colour bg composited behind; differentiable in the input."""
+
+    @staticmethod
+    def forward(ctx, rgba_in, w_in, h_in, w_out, h_out, bg):
+        x = rgba_in.contiguous()
+        out = torch.empty((w_out * h_out, 4), dtype=torch.float32, device=x.device)
+        check(_abi.svr_downsample(_ptr(x), w_in, h_in, _ptr(out), w_out, h_out, _bg_arr(bg),
+                                  _stream()), "svr_downsample")
+        ctx.sizes = (w_in, h_in, w_out, h_out)
+        ctx.bg = bg
+        return out
+
+    @staticmethod
+    def backward(ctx, grad_out):
+        w_in, h_in, w_out, h_out = ctx.sizes
+        g = grad_out.contiguous().float()
+        gin = torch.empty((w_in * h_in, 4), dtype=torch.float32, device=g.device)
+        check(_abi.svr_downsample_bwd(_ptr(g), w_out, h_out, _ptr(gin), w_in, h_in,
+                                      _bg_arr(ctx.bg), _stream()), "svr_downsample_bwd")
+        return gin, None, None, None, None, None
+
+
+def downsample(rgba_in: torch.Tensor, w_in: int, h_in: int, w_out: int, h_out: int, bg=None):
+    """Anti-aliased downsample of a supersampled render plus background."""
+    return DownsampleFunction.apply(rgba_in, w_in, h_in, w_out, h_out, bg)

@@ -158,3 +158,12 @@ def test_workspace_parts_sum_to_total():
     with pytest.raises(ValueError):
         o.K = 0
         _abi.svr_workspace_parts(sc, cams, 1, o)
+
+
+def test_downsample_rejects_bad_sizes():
+    _lib()
+    p = ctypes.c_void_p(0x100000)
+    for (wi, hi, wo, ho) in ((10, 10, 11, 5), (10, 10, 0, 5), (10, 10, 5, 11), (70000, 10, 5, 5)):
+        assert _abi.svr_downsample(p, wi, hi, p, wo, ho, None, None) == _abi.SVR_E_INVALID
+        assert _abi.svr_downsample_bwd(p, wo, ho, p, wi, hi, None, None) == _abi.SVR_E_INVALID
+    assert _abi.svr_downsample(None, 10, 10, p, 5, 5, None, None) == _abi.SVR_E_INVALID

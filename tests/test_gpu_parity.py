@@ -505,3 +505,61 @@ def test_depth_normal_match_oracle(torch_dev, case, K, act, tile):
     assert np.abs(ref0["depth"]).max() > 0.1 and np.abs(ref0["normal"]).max() > 0.01
     _check_grad(gg.cpu().numpy().astype(np.float64), ref["grad_grid"], "grad_grid")
     _check_grad(gs.cpu().numpy().astype(np.float64), ref["grad_sh"], "grad_sh")
+
+
+# ---------------------------------------------------------------------------
+# anti-aliasing (Sec. 3.1.2): supersampled render, anti-aliased downsample,
+# background colour; and the adjoint
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("src,dst", [((71, 53), (64, 48)), ((96, 96), (64, 64)),
+                                     ((128, 90), (64, 45)), ((31, 17), (31, 17)),
+                                     ((1412, 924), (1284, 840))])
+def test_downsample_and_adjoint_match_oracle(torch_dev, src, dst):
+    torch = torch_dev
+    from paper_2412_04459_amd.render import downsample
+    rng = np.random.default_rng(src[0] + dst[1])
+    bg = [0.25, 0.5, 0.75]
+    x = rng.random((src[1], src[0], 4)).astype(np.float32)
+    y = rng.normal(size=(dst[1], dst[0], 4)).astype(np.float32)
+    xt = torch.from_numpy(x.reshape(-1, 4)).cuda().requires_grad_(True)
+    out = downsample(xt, src[0], src[1], dst[0], dst[1], bg)
+    (out * torch.from_numpy(y.reshape(-1, 4)).cuda()).sum().backward()
+    torch.cuda.synchronize()
+    ref = oracle.downsample(x.astype(np.float64), dst[0], dst[1], bg)
+    assert np.abs(out.detach().cpu().numpy().reshape(ref.shape) - ref).max() <= 1e-5
+    gref = oracle.downsample_adjoint(y.astype(np.float64), src[0], src[1], bg)
+    g = xt.grad.cpu().numpy().reshape(gref.shape)
+    assert np.abs(g - gref).max() <= 1e-5 * max(1.0, np.abs(gref).max())
+
+
+def test_supersampled_render_with_background_matches_oracle(torch_dev):
+    """The view rendered at 1.5x, downsampled with the tent filter and given a
+    background colour; gradients through both (autograd) against the oracle's
+    render at 1.5x with the oracle's transpose of the filter."""
+    torch = torch_dev
+    from paper_2412_04459_amd.render import (DeviceScene, Rasterizer, downsample, render,
+                                              supersampled_camera)
+    scene, cam = S.sphere_shell_scene(opaque=True), S.sphere_shell_camera()
+    hi = supersampled_camera(cam, 1.5)
+    assert (hi.W, hi.H) == (96, 96)
+    bg = [0.2, 0.3, 0.4]
+    ds = DeviceScene(scene)
+    rast = Rasterizer(ds, [hi], K=2, tile=8)
+    grid = ds.grid_raw.clone().requires_grad_(True)
+    sh = ds.sh.clone().requires_grad_(True)
+    img = downsample(render(rast, grid, sh), hi.W, hi.H, cam.W, cam.H, bg)
+    g = S.upstream_grads(cam.W * cam.H, 11)
+    ref_hi = oracle.render(scene, hi, K=2)
+    # pixels of the low-res image whose filter taps reach a flagged pixel
+    flag_lo = oracle.downsample(np.repeat((ref_hi["flags"] != 0).astype(np.float64), 4)
+                                .reshape(hi.H, hi.W, 4), cam.W, cam.H)[..., 0] > 0
+    g[flag_lo.reshape(-1)] = 0.0
+    (img * torch.from_numpy(g).cuda()).sum().backward()
+    torch.cuda.synchronize()
+    ref_img = oracle.downsample(ref_hi["rgba"].reshape(hi.H, hi.W, 4), cam.W, cam.H, bg)
+    err = np.abs(img.detach().cpu().numpy().reshape(ref_img.shape) - ref_img).max(-1)
+    assert err[~flag_lo].max() <= RGBA_TOL
+    g_hi = oracle.downsample_adjoint(g.reshape(cam.H, cam.W, 4).astype(np.float64), hi.W, hi.H, bg)
+    ref = oracle.render(scene, hi, K=2, grad_rgba=g_hi.reshape(-1, 4))
+    _check_grad(grid.grad.cpu().numpy().astype(np.float64), ref["grad_grid"], "grad_grid")
+    _check_grad(sh.grad.cpu().numpy().astype(np.float64), ref["grad_sh"], "grad_sh")

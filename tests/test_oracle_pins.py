@@ -647,3 +647,17 @@ def test_downsample_preserves_constants_and_adds_background():
     assert np.allclose(out[..., 3], 0.75, atol=1e-14)
     assert np.allclose(out[..., :3], np.array([0.2, 0.4, 0.6]) + 0.25 * np.array([1.0, 0.5, 0.0]),
                        atol=1e-14)
+
+
+def test_downsample_adjoint_is_the_transpose():
+    # <D x, y> = <x, D^T y> for the affine-free part; with a background the
+    # map is affine, so compare on differences D(x1) - D(x2)
+    rng = np.random.default_rng(12)
+    bg = [0.3, 0.1, 0.8]
+    for (wi, hi), (wo, ho) in (((37, 23), (25, 16)), ((20, 20), (10, 10)), ((13, 7), (13, 7))):
+        x1 = rng.random((hi, wi, 4))
+        x2 = rng.random((hi, wi, 4))
+        y = rng.normal(size=(ho, wo, 4))
+        lhs = np.sum((oracle.downsample(x1, wo, ho, bg) - oracle.downsample(x2, wo, ho, bg)) * y)
+        rhs = np.sum((x1 - x2) * oracle.downsample_adjoint(y, wi, hi, bg))
+        assert lhs == pytest.approx(rhs, rel=1e-12)
