@@ -81,6 +81,8 @@ typedef struct svr_scene {
   int32_t max_level;       /* deepest level present, 1..16                             */
   const int32_t* grid_adj_off; /* [M+1] optional (NULL: atomics): corner adjacency of   */
   const int32_t* grid_adj;     /* [8N]  the grid points, see svr_build_grid_adjacency   */
+  const uint32_t* order_rank;  /* [N][8] optional (NULL: keys from octpath): order ranks
+                                  of the (voxel, sign) pairs, see svr_build_order_ranks */
 } svr_scene;
 
 /* Pinhole camera (host memory). */
@@ -224,7 +226,9 @@ int svr_check_overflow(const svr_scene* scene, const svr_camera* cams, int n_cam
                        int64_t* required_entries, void* stream);
 
 /* Read back the sorted list of the frame (debug / parity): keys[E], values[E]
- * device pointers of capacity >= E.  Asynchronous. */
+ * device pointers of capacity >= E.  Keys are tile << (3L + 3) | (top 3L path
+ * bits XOR s * 0b001..001) << 3 | s, or tile << ceil(log2(8N)) | rank when the
+ * scene carries order ranks; values are s << 29 | voxel id.  Asynchronous. */
 int svr_copy_sorted(const svr_scene* scene, const svr_camera* cams, int n_cams,
                     const svr_opts* opts, void* ws, size_t ws_bytes, uint64_t* keys,
                     uint32_t* values, int64_t n, void* stream);
@@ -300,6 +304,19 @@ int svr_downsample(const float* in, int w_in, int h_in, float* out, int w_out, i
                    const float* bg, void* stream);
 int svr_downsample_bwd(const float* grad_out, int w_out, int h_out, float* grad_in, int w_in,
                        int h_in, const float* bg, void* stream);
+
+/* Order ranks of the scene (build once per octpath set; Supp. B.1, B.2): the
+ * sort key orders a tile's entries by (top 3L path bits XOR s * 0b001..001,
+ * s).  rank[v*8 + s] is the position of pair (v, s) in that order over all 8N
+ * pairs.  With it in svr_scene the per-frame key is tile << ceil(log2(8N)) |
+ * rank: the same order (unique pair keys for max_level <= 15) in fewer radix
+ * passes; svr_copy_sorted then returns keys of that form.
+ * rank: device uint32 [8N].  scratch: device, 256-byte aligned,
+ * >= svr_order_rank_scratch_bytes(n_voxels, max_level) (0 on invalid sizes).
+ * Errors: SVR_E_INVALID, SVR_E_WORKSPACE, SVR_E_HIP.                         */
+size_t svr_order_rank_scratch_bytes(int64_t n_voxels, int max_level);
+int svr_build_order_ranks(const uint64_t* octpath, int64_t n_voxels, int max_level,
+                          uint32_t* rank, void* scratch, size_t scratch_bytes, void* stream);
 
 /* Corner adjacency of the grid points, a property of the scene topology
  * (build once per vox_grid): for grid point m, adj[adj_off[m] .. adj_off[m+1])

@@ -35,7 +35,7 @@ I32 = ctypes.c_int32
 class svr_scene(ctypes.Structure):
     _fields_ = [("n_voxels", I64), ("n_grid", I64), ("center", P), ("size", P), ("octpath", P),
                 ("vox_grid", P), ("grid_raw", P), ("sh", P), ("sh_degree", I32),
-                ("max_level", I32), ("grid_adj_off", P), ("grid_adj", P)]
+                ("max_level", I32), ("grid_adj_off", P), ("grid_adj", P), ("order_rank", P)]
 
 
 class svr_camera(ctypes.Structure):
@@ -71,6 +71,8 @@ _SIGS = {
     "svr_graph_capture": (ctypes.c_int, [P, P, ctypes.c_int, P, P, ctypes.c_size_t, P, P, P, P, P,
                                          P, P]),
     "svr_graph_launch": (ctypes.c_int, [P, P]),
+    "svr_order_rank_scratch_bytes": (ctypes.c_size_t, [I64, ctypes.c_int]),
+    "svr_build_order_ranks": (ctypes.c_int, [P, I64, ctypes.c_int, P, P, ctypes.c_size_t, P]),
     "svr_downsample": (ctypes.c_int, [P, ctypes.c_int, ctypes.c_int, P, ctypes.c_int, ctypes.c_int,
                                       P, P]),
     "svr_downsample_bwd": (ctypes.c_int, [P, ctypes.c_int, ctypes.c_int, P, ctypes.c_int,
@@ -261,3 +263,12 @@ def svr_downsample(img_in, w_in, h_in, img_out, w_out, h_out, bg, stream):
 
 def svr_downsample_bwd(grad_out, w_out, h_out, grad_in, w_in, h_in, bg, stream):
     return load().svr_downsample_bwd(grad_out, w_out, h_out, grad_in, w_in, h_in, bg, stream)
+
+
+def svr_order_rank_scratch_bytes(n_voxels, max_level):
+    return load().svr_order_rank_scratch_bytes(n_voxels, max_level)
+
+
+def svr_build_order_ranks(octpath, n_voxels, max_level, rank, scratch, scratch_bytes, stream):
+    return load().svr_build_order_ranks(octpath, n_voxels, max_level, rank, scratch,
+                                        scratch_bytes, stream)

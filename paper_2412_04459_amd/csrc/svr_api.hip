@@ -154,7 +154,8 @@ int make_layout(const svr_scene* sc, const svr_camera* cams, int n_cams, const s
   l.P = P;
   l.sat_total = (int32_t)sat;
   cs->total_tiles = l.T;
-  l.key_bits = bits_for(T - 1) + 3 * l.L + 3;
+  l.key_low = sc->order_rank ? bits_for(8 * l.N - 1) : 3 * l.L + 3;
+  l.key_bits = bits_for(T - 1) + l.key_low;
   if (l.key_bits > 64)
     return fail(SVR_E_INVALID, "sort key needs %d bits (> 64): too many tiles for max_level %d",
                 l.key_bits, l.L);
@@ -575,6 +576,32 @@ size_t svr_grid_adjacency_scratch_bytes(int64_t n_voxels, int64_t n_grid) {
   if (n_voxels < 0 || n_voxels >= (int64_t)SVR_MAX_VOXELS || n_grid < 0 || n_grid >= ((int64_t)1 << 31))
     return 0;
   return grid_adjacency_scratch_bytes(n_voxels, n_grid) + 256;
+}
+
+size_t svr_order_rank_scratch_bytes(int64_t n_voxels, int max_level) {
+  if (n_voxels < 0 || n_voxels >= (int64_t)SVR_MAX_VOXELS || max_level < 1 ||
+      max_level > SVR_MAX_LEVELS)
+    return 0;
+  return order_rank_scratch_bytes(n_voxels, max_level) + 256;
+}
+
+int svr_build_order_ranks(const uint64_t* octpath, int64_t n_voxels, int max_level,
+                          uint32_t* rank, void* scratch, size_t scratch_bytes, void* stream) {
+  if (n_voxels < 0 || n_voxels >= (int64_t)SVR_MAX_VOXELS)
+    return fail(SVR_E_INVALID, "n_voxels outside [0, 2^29)");
+  if (max_level < 1 || max_level > SVR_MAX_LEVELS)
+    return fail(SVR_E_INVALID, "max_level=%d outside 1..16", max_level);
+  if (n_voxels > 0 && (!octpath || !rank || !scratch)) return fail(SVR_E_INVALID, "null pointer");
+  if ((reinterpret_cast<uintptr_t>(scratch) & 255u) != 0)
+    return fail(SVR_E_INVALID, "scratch must be 256-byte aligned");
+  const size_t need = svr_order_rank_scratch_bytes(n_voxels, max_level);
+  if (scratch_bytes < need)
+    return fail(SVR_E_WORKSPACE, "scratch has %zu bytes, %zu needed", scratch_bytes, need);
+  if (n_voxels == 0) return SVR_OK;
+  SVR_HIP(launch_order_ranks(octpath, n_voxels, max_level, rank, scratch,
+                             reinterpret_cast<hipStream_t>(stream)),
+          "order ranks");
+  return SVR_OK;
 }
 
 int svr_build_grid_adjacency(const int32_t* vox_grid, int64_t n_voxels, int64_t n_grid,

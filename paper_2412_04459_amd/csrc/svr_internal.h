@@ -77,6 +77,7 @@ struct Layout {
   // sizes
   int64_t N, NV, cap, P;
   int32_t n_cams, T, sat_total, key_bits, passes, L;
+  int32_t key_low;  // bits below the tile id: 3L + 3 (path key) or log2 of the rank range
   int32_t tile, tshift, persistent;
   int64_t scan_blocks, sort_parts;
   // byte offsets into the workspace
@@ -168,6 +169,9 @@ hipError_t launch_radix_sort(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t*
                              uint32_t* hist, uint32_t* st0, uint32_t* st1, uint32_t* tickets,
                              uint32_t* err, bool* result_in_1, hipStream_t s);
 hipError_t launch_tile_ranges(const Layout& L, void* ws, const uint64_t* keys, hipStream_t s);
+size_t order_rank_scratch_bytes(int64_t N, int L);
+hipError_t launch_order_ranks(const uint64_t* octpath, int64_t N, int L, uint32_t* rank,
+                              void* scratch, hipStream_t s);
 hipError_t launch_grid_adjacency(const int32_t* vox_grid, int64_t N, int64_t M, int32_t* adj_off,
                                  int32_t* adj, void* scratch, hipStream_t s);
 size_t grid_adjacency_scratch_bytes(int64_t N, int64_t M);

@@ -557,6 +557,7 @@ struct EmitCtx {
   uint64_t top, rep;
   int sh;
   uint32_t vid;
+  const uint32_t* rank;  // the voxel's 8 order ranks, or null (key from the path)
 };
 
 __device__ __forceinline__ void emit_tile(const EmitCtx& e, int gt, uint32_t m,
@@ -566,7 +567,9 @@ __device__ __forceinline__ void emit_tile(const EmitCtx& e, int gt, uint32_t m,
     const int sgn = __ffs(m) - 1;
     m &= m - 1;
     if (o < (unsigned long long)cap) {
-      keys[o] = ((uint64_t)gt << e.sh) | ((e.top ^ ((uint64_t)sgn * e.rep)) << 3) | (uint64_t)sgn;
+      const uint64_t low = e.rank ? (uint64_t)e.rank[sgn]
+                                  : ((e.top ^ ((uint64_t)sgn * e.rep)) << 3) | (uint64_t)sgn;
+      keys[o] = ((uint64_t)gt << e.sh) | low;
       vals[o] = ((uint32_t)sgn << kVidBits) | e.vid;
     }
     ++o;
@@ -577,15 +580,16 @@ __global__ __launch_bounds__(kBlock) void k_emit(
     int64_t NV, int n_cams, CamSet cams, const uint64_t* __restrict__ octpath,
     const uint32_t* __restrict__ count, const unsigned long long* __restrict__ off,
     const uint2* __restrict__ rect, const uint8_t* __restrict__ mask,
-    const uint32_t* __restrict__ sat, int L, int64_t cap, uint64_t* __restrict__ keys,
-    uint32_t* __restrict__ vals, WsHeader* __restrict__ hdr) {
+    const uint32_t* __restrict__ sat, int L, int key_low, const uint32_t* __restrict__ rank,
+    int64_t cap, uint64_t* __restrict__ keys, uint32_t* __restrict__ vals,
+    WsHeader* __restrict__ hdr) {
   __shared__ int s_nbig;
   __shared__ int64_t s_big[kBlock];
   if (threadIdx.x == 0) s_nbig = 0;
   __syncthreads();
   const int64_t vv = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t cnt = vv < NV ? count[vv] : 0u;
-  const int sh = 3 * L + 3;
+  const int sh = key_low;
   const uint64_t rep = ((1ull << (3 * L)) - 1ull) / 7ull;  // 001 001 ... 001 (L triplets)
   if (cnt > 0) {
     if (off[vv] + cnt > (unsigned long long)cap) atomicOr(&hdr->overflow, 1u);
@@ -594,7 +598,8 @@ __global__ __launch_bounds__(kBlock) void k_emit(
     } else {
       const int64_t vid = vv / n_cams;
       const DevCam& c = cams.c[(int)(vv - vid * n_cams)];
-      const EmitCtx e{octpath[vid] >> (3 * (SVR_MAX_LEVELS - L)), rep, sh, (uint32_t)vid};
+      const EmitCtx e{octpath[vid] >> (3 * (SVR_MAX_LEVELS - L)), rep, sh, (uint32_t)vid,
+                      rank ? rank + vid * 8 : nullptr};
       unsigned long long o = off[vv];
       const uint2 r = rect[vv];
       const int tx0 = (int)(r.x & 0xffffu) >> cams.tshift, tx1 = (int)(r.x >> 16) >> cams.tshift;
@@ -615,7 +620,8 @@ __global__ __launch_bounds__(kBlock) void k_emit(
     const int64_t bv = s_big[b];
     const int64_t vid = bv / n_cams;
     const DevCam& c = cams.c[(int)(bv - vid * n_cams)];
-    const EmitCtx e{octpath[vid] >> (3 * (SVR_MAX_LEVELS - L)), rep, sh, (uint32_t)vid};
+    const EmitCtx e{octpath[vid] >> (3 * (SVR_MAX_LEVELS - L)), rep, sh, (uint32_t)vid,
+                    rank ? rank + vid * 8 : nullptr};
     const uint2 r = rect[bv];
     const int tx0 = (int)(r.x & 0xffffu) >> cams.tshift, tx1 = (int)(r.x >> 16) >> cams.tshift;
     const int ty0 = (int)(r.y & 0xffffu) >> cams.tshift, ty1 = (int)(r.y >> 16) >> cams.tshift;
@@ -641,7 +647,8 @@ hipError_t launch_emit(const svr_scene& sc, const CamSet& cams, const Layout& L,
   SVR_LAUNCH("emit", k_emit, dim3((unsigned)((L.NV + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
              L.NV, L.n_cams, cams, sc.octpath, at<uint32_t>(ws, L.count),
              at<unsigned long long>(ws, L.offset), at<uint2>(ws, L.rect),
-             at<uint8_t>(ws, L.tile_mask), at<uint32_t>(ws, L.tile_sat), L.L, L.cap,
+             at<uint8_t>(ws, L.tile_mask), at<uint32_t>(ws, L.tile_sat), L.L, L.key_low,
+             sc.order_rank, L.cap,
              at<uint64_t>(ws, L.keys0), at<uint32_t>(ws, L.vals0), at<WsHeader>(ws, L.hdr));
   return hipGetLastError();
 }

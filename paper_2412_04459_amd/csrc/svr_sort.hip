@@ -369,7 +369,7 @@ hipError_t launch_tile_ranges(const Layout& L, void* ws, const uint64_t* keys, h
   uint32_t* split_count = counts + kOrderBuckets;
   if (L.cap > 0)
     SVR_LAUNCH("tile_ranges", k_tile_ranges, dim3((unsigned)((L.cap + kBlock - 1) / kBlock)),
-               dim3(kBlock), 0, s, keys, &at<WsHeader>(ws, L.hdr)->n_entries, L.cap, 3 * L.L + 3,
+               dim3(kBlock), 0, s, keys, &at<WsHeader>(ws, L.hdr)->n_entries, L.cap, L.key_low,
                (uint32_t)L.T, range);
   const dim3 tg((unsigned)((L.T + kBlock - 1) / kBlock));
   SVR_LAUNCH("tile_order", k_tile_bucket, tg, dim3(kBlock), 0, s, range, (uint32_t)L.T, counts,
@@ -439,6 +439,73 @@ hipError_t launch_grid_adjacency(const int32_t* vox_grid, int64_t N, int64_t M, 
   }
   SVR_LAUNCH("adj_offsets", k_adj_offsets, dim3((unsigned)((n8 + kBlock) / kBlock)), dim3(kBlock),
              0, s, ks, n8, M, adj_off);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// Per-scene order ranks.  Within a tile the sort key orders entries by
+// (top 3L path bits XOR s * 0b001..001, s) (Supp. B.1, B.2).  That order over
+// all (voxel, sign pattern) pairs is a property of the scene, so it is sorted
+// once and each pair gets its rank; the per-frame key tile | rank then has
+// ceil(log2(8N)) low bits instead of 3L + 3 and orders the entries exactly as
+// before (the pair keys are distinct for L <= 15; at L = 16 equal keys keep
+// the pair index order).
+__global__ __launch_bounds__(kBlock) void k_rank_keys(const uint64_t* __restrict__ octpath,
+                                                      int64_t n8, int L,
+                                                      uint64_t* __restrict__ keys,
+                                                      uint32_t* __restrict__ vals) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n8) return;
+  const uint64_t top = octpath[i >> 3] >> (3 * (SVR_MAX_LEVELS - L));
+  const uint64_t rep = ((1ull << (3 * L)) - 1ull) / 7ull;  // 001 001 ... 001 (L triplets)
+  const uint64_t sgn = (uint64_t)(i & 7);
+  keys[i] = ((top ^ (sgn * rep)) << 3) | sgn;
+  vals[i] = (uint32_t)i;
+}
+
+__global__ __launch_bounds__(kBlock) void k_rank_scatter(const uint32_t* __restrict__ vals,
+                                                         int64_t n8, uint32_t* __restrict__ rank) {
+  const int64_t p = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (p < n8) rank[vals[p]] = (uint32_t)p;
+}
+
+size_t order_rank_scratch_bytes(int64_t N, int L) {
+  const int64_t n8 = 8 * N;
+  const size_t r = 256;
+  auto up = [&](size_t b) { return (b + r - 1) / r * r; };
+  return up((size_t)n8 * 8) * 2 + up((size_t)n8 * 4) * 2 +
+         up(sort_scratch_bytes(n8, 3 * L + 3, nullptr) + 256);
+}
+
+hipError_t launch_order_ranks(const uint64_t* octpath, int64_t N, int L, uint32_t* rank,
+                              void* scratch, hipStream_t s) {
+  const int64_t n8 = 8 * N;
+  const int bits = 3 * L + 3;
+  int64_t parts = 0;
+  const size_t sb = sort_scratch_bytes(n8, bits, &parts);
+  char* p = reinterpret_cast<char*>(scratch);
+  auto take = [&](size_t b) { char* q = p; p += (b + 255) / 256 * 256; return q; };
+  uint64_t* k0 = reinterpret_cast<uint64_t*>(take((size_t)n8 * 8));
+  uint64_t* k1 = reinterpret_cast<uint64_t*>(take((size_t)n8 * 8));
+  uint32_t* v0 = reinterpret_cast<uint32_t*>(take((size_t)n8 * 4));
+  uint32_t* v1 = reinterpret_cast<uint32_t*>(take((size_t)n8 * 4));
+  uint32_t* base = reinterpret_cast<uint32_t*>(take(sb + 256));
+  auto* n_dev = reinterpret_cast<unsigned long long*>(base);
+  uint32_t* hist = base + 64;
+  uint32_t* st0 = hist + 8 * kRadix;
+  uint32_t* st1 = st0 + (parts > 0 ? parts : 1) * kRadix;
+  hipError_t e;
+  if ((e = launch_fill_u32(base, 0u, 64, s)) != hipSuccess) return e;
+  if ((e = launch_fill_u32(base, (uint32_t)(n8 & 0xffffffffu), 1, s)) != hipSuccess) return e;
+  if ((e = launch_fill_u32(base + 1, (uint32_t)(n8 >> 32), 1, s)) != hipSuccess) return e;
+  const unsigned grid = (unsigned)((n8 + kBlock - 1) / kBlock);
+  SVR_LAUNCH("rank_keys", k_rank_keys, dim3(grid), dim3(kBlock), 0, s, octpath, n8, L, k0, v0);
+  bool in1 = false;
+  if ((e = launch_radix_sort(k0, v0, k1, v1, n_dev, n8, bits, hist, st0, st1, base + 2, base + 18,
+                             &in1, s)) != hipSuccess)
+    return e;
+  SVR_LAUNCH("rank_scatter", k_rank_scatter, dim3(grid), dim3(kBlock), 0, s, in1 ? v1 : v0, n8,
+             rank);
   return hipGetLastError();
 }
 

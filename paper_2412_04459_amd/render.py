@@ -43,7 +43,8 @@ def _stream():
 class DeviceScene:
     """Scene arrays resident in device memory (layouts as in svr_scene)."""
 
-    def __init__(self, scene, device="cuda", grid_adjacency: bool = True):
+    def __init__(self, scene, device="cuda", grid_adjacency: bool = True,
+                 order_ranks: bool = True):
         if not torch.cuda.is_available():
             raise RuntimeError("DeviceScene needs a HIP device")
         dev = torch.device(device)
@@ -62,6 +63,24 @@ class DeviceScene:
         self.adj_off = self.adj = None
         if grid_adjacency:
             self.build_adjacency()
+        self.rank = None
+        if order_ranks:
+            self.build_order_ranks()
+
+    def build_order_ranks(self):
+        """Order ranks of the (voxel, sign) pairs (svr_build_order_ranks): the
+        per-frame sort key then needs ceil(log2(8N)) bits below the tile id
+        instead of 3 max_level + 3."""
+        rank = torch.empty(max(1, 8 * self.n_voxels), dtype=torch.int32, device=self.device)
+        nb = _abi.svr_order_rank_scratch_bytes(self.n_voxels, self.max_level)
+        scratch = torch.empty(nb + 256, dtype=torch.uint8, device=self.device)
+        p = (scratch.data_ptr() + 255) // 256 * 256
+        check(_abi.svr_build_order_ranks(_ptr(self.octpath), self.n_voxels, self.max_level,
+                                         _ptr(rank), ctypes.c_void_p(p), nb, _stream()),
+              "svr_build_order_ranks")
+        torch.cuda.current_stream().synchronize()
+        del scratch
+        self.rank = rank
 
     def build_adjacency(self):
         """Corner adjacency of the grid points (svr_build_grid_adjacency): makes the
@@ -81,7 +100,7 @@ class DeviceScene:
     def nbytes(self) -> int:
         """Device bytes of the scene arrays (adjacency included)."""
         ts = [self.center, self.size, self.octpath, self.vox_grid, self.grid_raw, self.sh,
-              self.adj_off, self.adj]
+              self.adj_off, self.adj, self.rank]
         return int(sum(t.numel() * t.element_size() for t in ts if t is not None))
 
     def struct(self, grid_raw: Optional[torch.Tensor] = None,
@@ -107,6 +126,8 @@ class DeviceScene:
         if self.adj_off is not None:
             st.grid_adj_off = self.adj_off.data_ptr()
             st.grid_adj = self.adj.data_ptr()
+        if self.rank is not None:
+            st.order_rank = self.rank.data_ptr()
         return st
 
 

@@ -34,9 +34,10 @@ def _say(msg):
     print(msg, flush=True)
 
 
-def _gpu_frame(torch, scene, cams, K, t_stop=1e-4, act=0, grad=None, sync=True, tile=16):
+def _gpu_frame(torch, scene, cams, K, t_stop=1e-4, act=0, grad=None, sync=True, tile=16,
+               ranks=True):
     from paper_2412_04459_amd.render import DeviceScene, Rasterizer
-    ds = DeviceScene(scene)
+    ds = DeviceScene(scene, order_ranks=ranks)
     rast = Rasterizer(ds, cams, K=K, t_stop=t_stop, activation=act, sync_count=sync, tile=tile)
     rgba = rast.forward()
     out = {"rast": rast, "rgba": rgba.cpu().numpy().astype(np.float64)}
@@ -109,37 +110,61 @@ def _key_cases():
                                                    target=(0.9, 0.8, 0.7))]))]
 
 
-@pytest.mark.parametrize("name", [c[0] for c in _key_cases()])
-def test_sorted_entries_bit_exact(torch_dev, name):
-    torch = torch_dev
-    make = dict(_key_cases())[name]
-    scene, cams = make()
-    _say("sorted entries: %s N=%d %dx%d" % (name, scene.n_voxels, cams[0].W, cams[0].H))
-    out = _gpu_frame(torch, scene, cams, K=1)
-    rast = out["rast"]
-    E = rast.n_entries
-    keys, vals = rast.sorted_entries(E)
-    gk = keys.cpu().numpy().view(np.uint64)
-    gv = vals.cpu().numpy().view(np.uint32)
-    assert rast.check_overflow() == E
-    exp = oracle.expected_entries(scene, cams[0])
+def _cpu_order_ranks(scene):
+    """Rank of every (voxel, sign) pair in the oracle's within-tile key order."""
+    n8 = 8 * scene.n_voxels
+    vid = np.repeat(np.arange(scene.n_voxels, dtype=np.int64), 8)
+    sgn = np.tile(np.arange(8, dtype=np.uint8), scene.n_voxels)
+    _, kc, _ = oracle.keys(np.zeros(n8, np.int64), vid, sgn, scene.octpath, scene.max_level)
+    order = np.argsort(kc, kind="stable")
+    rank = np.empty(n8, np.int64)
+    rank[order] = np.arange(n8)
+    return rank
+
+
+def _check_sorted_list(scene, cam, gk, gv, ranks):
+    """The GPU's sorted list against the oracle: strictly ascending keys; each
+    entry's value and, for its (tile, voxel, s), the oracle's key; those keys
+    strictly ascending too (the list is in the paper's key order); the key's
+    low bits are the order rank (ranks) or the compact key itself (no ranks);
+    every required entry present and none outside the tolerance band."""
     L = scene.max_level
-    sh = np.uint64(3 * L + 3)
-    # strictly ascending keys (unique keys, fully determined order)
+    key_low = int(8 * scene.n_voxels - 1).bit_length() if ranks else 3 * L + 3
     assert np.all(gk[1:] > gk[:-1])
-    # each entry's key equals the oracle's key for the same triple
-    tile = (gk >> sh).astype(np.int64)
+    tile = (gk >> np.uint64(key_low)).astype(np.int64)
     vid = (gv & np.uint32((1 << 29) - 1)).astype(np.int64)
     sgn = (gv >> np.uint32(29)).astype(np.uint8)
     _, kc, val = oracle.keys(tile, vid, sgn, scene.octpath, L)
-    assert np.array_equal(kc, gk)
     assert np.array_equal(val, gv)
-    # set bounds
+    assert np.all(kc[1:] > kc[:-1])
+    if ranks:
+        low = (gk & np.uint64((1 << key_low) - 1)).astype(np.int64)
+        assert np.array_equal(low, _cpu_order_ranks(scene)[vid * 8 + sgn])
+    else:
+        assert np.array_equal(kc, gk)
+    exp = oracle.expected_entries(scene, cam)
     must_k, _, _ = exp["must"]
     may_k, _, _ = exp["may"]
-    assert np.all(np.isin(must_k, gk)), "missing %d required entries" % int((~np.isin(must_k, gk)).sum())
-    assert np.all(np.isin(gk, may_k)), "%d entries outside the band" % int((~np.isin(gk, may_k)).sum())
+    assert np.all(np.isin(must_k, kc)), "missing %d required entries" % int((~np.isin(must_k, kc)).sum())
+    assert np.all(np.isin(kc, may_k)), "%d entries outside the band" % int((~np.isin(kc, may_k)).sum())
     assert len(must_k) > 0
+
+
+@pytest.mark.parametrize("name,ranks", [(c[0], True) for c in _key_cases()] + [("shell", False),
+                                                                             ("tiny_multisign", False)])
+def test_sorted_entries_bit_exact(torch_dev, name, ranks):
+    torch = torch_dev
+    make = dict(_key_cases())[name]
+    scene, cams = make()
+    _say("sorted entries: %s N=%d %dx%d ranks=%d" % (name, scene.n_voxels, cams[0].W, cams[0].H,
+                                                     ranks))
+    out = _gpu_frame(torch, scene, cams, K=1, ranks=ranks)
+    rast = out["rast"]
+    E = rast.n_entries
+    keys, vals = rast.sorted_entries(E)
+    assert rast.check_overflow() == E
+    _check_sorted_list(scene, cams[0], keys.cpu().numpy().view(np.uint64),
+                       vals.cpu().numpy().view(np.uint32), ranks)
 
 
 # ---------------------------------------------------------------------------
@@ -225,7 +250,7 @@ def test_render_bwd_split_heavy_tiles(torch_dev, tile, K, act):
     out = _gpu_frame(torch, scene, cams, K=K, act=act, grad=g, tile=tile)
     rast = out["rast"]
     keys, _ = rast.sorted_entries(rast.n_entries)
-    tiles = keys.cpu().numpy().view(np.uint64) >> np.uint64(3 * scene.max_level + 3)
+    tiles = keys.cpu().numpy().view(np.uint64) >> np.uint64(int(8 * scene.n_voxels - 1).bit_length())
     per_tile = np.bincount(tiles.astype(np.int64))
     assert per_tile.max() > 2 * 256, "no tile of three or more chunks"
     _check_rgba(out["rgba"], ref0)
@@ -318,17 +343,8 @@ def test_bench_scene_sorted_entries_bit_exact(torch_dev, bench_scene):
     out = _gpu_frame(torch, scene, cams, K=2)
     rast = out["rast"]
     keys, vals = rast.sorted_entries(rast.n_entries)
-    gk = keys.cpu().numpy().view(np.uint64)
-    gv = vals.cpu().numpy().view(np.uint32)
-    assert np.all(gk[1:] > gk[:-1])
-    sh = np.uint64(3 * scene.max_level + 3)
-    _, kc, val = oracle.keys((gk >> sh).astype(np.int64),
-                             (gv & np.uint32((1 << 29) - 1)).astype(np.int64),
-                             (gv >> np.uint32(29)).astype(np.uint8), scene.octpath, scene.max_level)
-    assert np.array_equal(kc, gk) and np.array_equal(val, gv)
-    exp = oracle.expected_entries(scene, cams[0])
-    assert np.all(np.isin(exp["must"][0], gk))
-    assert np.all(np.isin(gk, exp["may"][0]))
+    _check_sorted_list(scene, cams[0], keys.cpu().numpy().view(np.uint64),
+                       vals.cpu().numpy().view(np.uint32), True)
 
 
 def test_autograd_central_differences_bench_scene(torch_dev, bench_scene):
