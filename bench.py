@@ -95,9 +95,21 @@ def cpu_baseline(scene, cam, K, seconds_target=15.0):
                       "(%.1f s; CPU: %s)" % (done, scene.n_voxels, t_used, model)}
 
 
-def measured_traffic(kernel_prefix):
-    """HBM bytes per dispatch of a kernel from a committed rocprofv3 summary
-    under profiles/, if that summary was taken on the current HIP sources."""
+def kernel_symbol(kind, tile, K, act=0):
+    """Name rocprofv3 gives the render kernel instantiation the library
+    launches for this tile size, K (templated for K <= 3) and activation."""
+    kt = K if K <= 3 else 0
+    if kind == "render_fwd":
+        return "k_render_fwd<%d, %d, %d, false, false>" % (tile, kt, act)
+    if kind == "render_bwd":
+        return "k_render_bwd<%d, %d, %d, false>" % (tile, kt, act)
+    return {"project": "k_project<3>", "sh_bwd": "k_sh_bwd<3>"}.get(kind, "k_" + kind)
+
+
+def measured_traffic(kernel):
+    """HBM bytes per dispatch of one kernel (its exact profiled name) from a
+    committed rocprofv3 summary under profiles/, if that summary was taken on
+    the current HIP sources."""
     import glob
     import re as _re
     from paper_2412_04459_amd.profsum import source_hash
@@ -110,7 +122,7 @@ def measured_traffic(kernel_prefix):
         if blk.get("source_hash") != h:
             continue
         for k, v in blk.get("traffic", {}).items():
-            if k.startswith(kernel_prefix) and blk.get("fetch_factor"):
+            if k == kernel and blk.get("fetch_factor"):
                 return v["bytes_scaled"], os.path.relpath(f, ROOT)
     return None, None
 
@@ -279,6 +291,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=8)
     ap.add_argument("--views", type=int, default=36)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--main-only", action="store_true",
+                    help="time only the headline frames (profiled runs: every launch of the "
+                         "headline kernels then belongs to the headline workload)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the 24-camera batched comparison")
@@ -412,46 +427,52 @@ def main():
     elapsed_ms = min(elapsed_ms, ev0.elapsed_time(ev1))
     eager_ms_step = elapsed_ms / args.steps
 
-    # the same steps with the training statistics on (max blending weight in
-    # the forward, subdivision priority in the backward)
-    mw = torch.zeros(scene.n_voxels, dtype=torch.float32, device="cuda")
-    pr = torch.zeros_like(mw)
+    def optional_timings():
+        """The same steps with the training statistics on (max blending weight
+        in the forward, subdivision priority in the backward), then rendering
+        and differentiating depth and normal images too; ms per step each."""
+        mw = torch.zeros(scene.n_voxels, dtype=torch.float32, device="cuda")
+        pr = torch.zeros_like(mw)
 
-    def step_stats(i):
-        rast.set_cameras([cams[i % len(cams)]])
-        rast.forward(max_weight=mw)
-        rast.backward(grad, priority=pr)
+        def step_stats(i):
+            rast.set_cameras([cams[i % len(cams)]])
+            rast.forward(max_weight=mw)
+            rast.backward(grad, priority=pr)
 
-    torch.cuda.synchronize()
-    ev0.record()
-    for i in range(args.steps):
-        step_stats(i)
-    ev1.record()
-    torch.cuda.synchronize()
-    stats_ms_step = ev0.elapsed_time(ev1) / args.steps
-    del mw, pr
+        torch.cuda.synchronize()
+        ev0.record()
+        for i in range(args.steps):
+            step_stats(i)
+        ev1.record()
+        torch.cuda.synchronize()
+        stats_ms_step = ev0.elapsed_time(ev1) / args.steps
+        del mw, pr
 
-    # the same steps rendering and differentiating depth and normal images too
-    dep = torch.empty(P, dtype=torch.float32, device="cuda")
-    nrm = torch.empty((P, 3), dtype=torch.float32, device="cuda")
-    gdep = torch.from_numpy(np.random.default_rng(3).normal(size=P).astype(np.float32)).cuda()
-    gnrm = torch.from_numpy(np.random.default_rng(4).normal(size=(P, 3)).astype(np.float32)).cuda()
+        # the same steps rendering and differentiating depth and normal images too
+        dep = torch.empty(P, dtype=torch.float32, device="cuda")
+        nrm = torch.empty((P, 3), dtype=torch.float32, device="cuda")
+        gdep = torch.from_numpy(np.random.default_rng(3).normal(size=P).astype(np.float32)).cuda()
+        gnrm = torch.from_numpy(np.random.default_rng(4).normal(size=(P, 3)).astype(np.float32)).cuda()
 
-    def step_aux(i):
-        rast.set_cameras([cams[i % len(cams)]])
-        rast.forward(depth=dep, normal=nrm)
-        rast.backward(grad, grad_depth=gdep, grad_normal=gnrm)
+        def step_aux(i):
+            rast.set_cameras([cams[i % len(cams)]])
+            rast.forward(depth=dep, normal=nrm)
+            rast.backward(grad, grad_depth=gdep, grad_normal=gnrm)
 
-    for i in range(2):
-        step_aux(i)
-    torch.cuda.synchronize()
-    ev0.record()
-    for i in range(args.steps):
-        step_aux(i)
-    ev1.record()
-    torch.cuda.synchronize()
-    aux_ms_step = ev0.elapsed_time(ev1) / args.steps
-    del dep, nrm, gdep, gnrm
+        for i in range(2):
+            step_aux(i)
+        torch.cuda.synchronize()
+        ev0.record()
+        for i in range(args.steps):
+            step_aux(i)
+        ev1.record()
+        torch.cuda.synchronize()
+        aux_ms_step = ev0.elapsed_time(ev1) / args.steps
+        del dep, nrm, gdep, gnrm
+
+        return stats_ms_step, aux_ms_step
+
+    stats_ms_step, aux_ms_step = (None, None) if args.main_only else optional_timings()
 
     # the same frames replayed from one captured hipGraph per view (no host
     # launch overhead); this is the headline number
@@ -491,7 +512,8 @@ def main():
         roof = {"kernel": dom, "bound": "hbm", "achieved": ach, "peak": HBM_PEAK_GBS,
                 "unit": "GB/s", "frac": ach / HBM_PEAK_GBS, "traffic": None,
                 "bytes_per_launch": b}
-    tb, tsrc = measured_traffic("k_" + dom)
+    roof["symbol"] = kernel_symbol(dom, tile, K)
+    tb, tsrc = measured_traffic(roof["symbol"])
     if tb is not None:
         roof["traffic"] = tb
         roof["traffic_source"] = tsrc
@@ -520,23 +542,24 @@ def main():
         "frames_per_s": 1e3 / ms_step,
         "launch": "one hipGraph per view, replayed on one stream",
         "eager": {"ms_per_step": eager_ms_step, "mpix_s": P / (eager_ms_step / 1e3) / 1e6},
-        "with_train_stats": {"ms_per_step": stats_ms_step,
-                             "overhead": stats_ms_step / eager_ms_step - 1.0},
-        "with_depth_normal": {"ms_per_step": aux_ms_step,
-                              "overhead": aux_ms_step / eager_ms_step - 1.0},
+        "with_train_stats": None if stats_ms_step is None else {
+            "ms_per_step": stats_ms_step, "overhead": stats_ms_step / eager_ms_step - 1.0},
+        "with_depth_normal": None if aux_ms_step is None else {
+            "ms_per_step": aux_ms_step, "overhead": aux_ms_step / eager_ms_step - 1.0},
         "frame_hbm": {"bytes": fbytes, "achieved_GBs": frame_gbs, "peak_GBs": HBM_PEAK_GBS,
                       "frac": frame_gbs / HBM_PEAK_GBS},
         "roofline": roof,
         "kernels": per_kernel,
     }
-    out["supersampled"] = supersampled_run(ds, cams, K, tile, grad, min(args.steps, 24), log)
-    if not args.no_batched:
+    if not args.main_only:
+        out["supersampled"] = supersampled_run(ds, cams, K, tile, grad, min(args.steps, 24), log)
+    if not (args.no_batched or args.main_only):
         out["batched"] = batched_comparison(ds, K, log)
-    if args.large:
+    if args.large and not args.main_only:
         del rast
         torch.cuda.empty_cache()
         out["large"] = large_scene_run(log)
-    if not args.no_cpu:
+    if not (args.no_cpu or args.main_only):
         log("timing the oracle on the host ...")
         out["cpu_baseline"] = cpu_baseline(scene, cams[0], K, args.cpu_seconds)
     print(json.dumps(out), flush=True)
