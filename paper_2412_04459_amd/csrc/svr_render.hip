@@ -46,6 +46,10 @@
 
 namespace svr {
 
+// backward walk: entries grouped by disjoint pixel sets (true) or one entry
+// at a time (false)
+constexpr bool kGroupedBwd = true;
+
 // Sec. 3.1.1 eq. explin:  x for x > 1.1, else exp(x / 1.1 - 1 + ln 1.1)
 constexpr float kInv11 = 1.f / 1.1f;
 constexpr float kExplinOff = 0.09531017980432486f - 1.f;  // ln(1.1) - 1
@@ -85,11 +89,10 @@ template <int NB>
 struct LdsBatch {
   double lo[3][NB];                    // box min - camera centre (fp64)
   double hi[3][NB];                    // box max - camera centre (fp64)
+  float4 col[NB];                      // colour rgb, voxel id (bits) in w
   float isz[NB];                       // 1 / edge
   float V[8][NB];                      // corner raw densities
-  float cr[NB], cg[NB], cb[NB];        // colour
   uint32_t meta[NB];                   // sign bits | block mask << 3
-  uint32_t vid[NB];
   uint32_t rx[NB], ry[NB];             // pixel rectangle: u0 | u1 << 16, v0 | v1 << 16
   uint32_t mw[NB];                     // max blending weight in this tile (float bits)
 };
@@ -172,9 +175,8 @@ __device__ __forceinline__ void stage_entry(LdsBatch<NB>& B, int slot, uint32_t 
   B.isz[slot] = 1.f / R.q0.w;
   B.V[0][slot] = R.q1.x; B.V[1][slot] = R.q1.y; B.V[2][slot] = R.q1.z; B.V[3][slot] = R.q1.w;
   B.V[4][slot] = R.q2.x; B.V[5][slot] = R.q2.y; B.V[6][slot] = R.q2.z; B.V[7][slot] = R.q2.w;
-  B.cr[slot] = R.q3.x; B.cg[slot] = R.q3.y; B.cb[slot] = R.q3.z;
+  B.col[slot] = make_float4(R.q3.x, R.q3.y, R.q3.z, __uint_as_float(vid));
   B.meta[slot] = (val >> kVidBits) | (qm << 3);
-  B.vid[slot] = vid;
   B.rx[slot] = rc.x;
   B.ry[slot] = rc.y;
   B.mw[slot] = 0u;
@@ -384,13 +386,17 @@ __device__ __forceinline__ float segment_depth_grad(const LdsBatch<NB>& B, int j
 //   A. walks the entries touching its block once: lanes whose pixel lies in
 //      the voxel's projected rectangle (and whose sign pattern matches, and
 //      which have not terminated) append the entry to their own list, and a
-//      wave-wide task queue records (lane, list slot) in entry order;
+//      wave-wide task queue records (lane, list slot, entry) in entry order.
+//      The entries' sign/block word and rectangle come from registers (one
+//      LDS read per 64 entries, then v_readlane), so the walk has no LDS
+//      round trip per entry;
 //   B. takes the queued candidates 64 at a time, one per lane: the fp64
 //      ray-box test with the owning pixel's ray and, for a hit, the optical
 //      depth x over K samples (written back to the owner's list, -1 on a
 //      miss);
 //   C. lets every lane composite its own list in entry order (the only
-//      sequential part: a few operations per hit).
+//      sequential part: a few operations per hit), after loading the whole
+//      list (optical depths, entries, colours) at once.
 // A lane list holding kListCap candidates triggers B and C early, so order
 // and early termination are those of the plain per-pixel walk.
 template <int TS, bool AUX = false>
@@ -400,13 +406,14 @@ struct DenseCfg {
 };
 
 template <int CAP, bool AUX>
-struct WaveLists {
-  uint16_t queue[64 * CAP];  // task -> owner lane << 8 | list slot
-  uint8_t jl[CAP][64];       // staged entry index of a lane's candidate
-  float xl[CAP][64];         // its optical depth (< 0: the ray misses the box)
-  float dl[AUX ? CAP : 1][64];  // its local depth (depth images only)
+struct alignas(16) WaveLists {
+  static_assert(CAP == 4 || CAP == 8, "list slots are loaded 4 at a time");
+  uint32_t queue[64 * CAP];  // task -> owner lane | list slot << 8 | staged entry << 16
   double d[3][64];           // lane ray direction (fp64)
   double id[3][64];          // and its reciprocal
+  float xl[64][CAP];         // per lane: optical depth of each candidate (< 0: a miss)
+  float dl[64][AUX ? CAP : 1];  // its local depth (depth images only)
+  uint8_t jl[64][CAP];       // per lane: staged entry index of each candidate
 };
 
 __device__ __forceinline__ uint32_t lane_rank(unsigned long long mask) {
@@ -462,8 +469,7 @@ __device__ __forceinline__ void render_tile_fwd(const RenderArgs& A, int g,
       // B: candidates, one per lane
       for (uint32_t t = lane; t < nq; t += 64) {
         const uint32_t q = WL.queue[t];
-        const int ow = (int)(q >> 8), k = (int)(q & 0xffu);
-        const int j = WL.jl[k][ow];
+        const int ow = (int)(q & 63u), k = (int)((q >> 8) & 0xffu), j = (int)(q >> 16);
         double a, bb;
         float x = -1.f;
         if (slab(B, j, WL.id[0][ow], WL.id[1][ow], WL.id[2][ow], a, bb)) {
@@ -471,32 +477,46 @@ __device__ __forceinline__ void render_tile_fwd(const RenderArgs& A, int g,
             float dloc;
             x = segment_xd<KT, ACT>(B, j, WL.d[0][ow], WL.d[1][ow], WL.d[2][ow], a, bb - a, A.K,
                                     dloc);
-            WL.dl[AUX ? k : 0][ow] = dloc;
+            WL.dl[ow][AUX ? k : 0] = dloc;
           } else {
             x = segment_x<KT, ACT, false>(B, j, WL.d[0][ow], WL.d[1][ow], WL.d[2][ow], a, bb - a,
                                           A.K, nullptr);
           }
         }
-        WL.xl[k][ow] = x;
+        WL.xl[ow][k] = x;
         if (STATS) ++n_tests;
       }
       wave_sync_lds();
-      // C: each lane composites its own list in entry order
+      // C: each lane composites its own list in entry order; the list is
+      // loaded first (4 slots per LDS read) so the loop waits on LDS once
+      float xs[CAP];
+      uint32_t jw[CAP / 4];
+#pragma unroll
+      for (int h = 0; h < CAP / 4; ++h) {
+        const float4 xv = reinterpret_cast<const float4*>(&WL.xl[lane][0])[h];
+        xs[4 * h + 0] = xv.x; xs[4 * h + 1] = xv.y; xs[4 * h + 2] = xv.z; xs[4 * h + 3] = xv.w;
+        jw[h] = reinterpret_cast<const uint32_t*>(&WL.jl[lane][0])[h];
+      }
+      float4 cc[CAP];
+#pragma unroll
+      for (int k = 0; k < CAP; ++k)
+        cc[k] = B.col[(jw[k >> 2] >> (8 * (k & 3))) & (uint32_t)(NB - 1)];
+#pragma unroll
       for (int k = 0; k < CAP; ++k) {
         if (__ballot(k < cnt) == 0ull) break;
         if (k < cnt && !done) {
-          const float x = WL.xl[k][lane];
+          const float x = xs[k];
           if (x >= 0.f) {
-            const int j = WL.jl[k][lane];
+            const int j = (int)((jw[k >> 2] >> (8 * (k & 3))) & (uint32_t)(NB - 1));
             const float wgt = Tr * alpha_of(x);
             if (A.max_weight) atomicMax(&B.mw[j], __float_as_uint(wgt));
-            C0 = __fmaf_rn(wgt, B.cr[j], C0);
-            C1 = __fmaf_rn(wgt, B.cg[j], C1);
-            C2 = __fmaf_rn(wgt, B.cb[j], C2);
+            C0 = __fmaf_rn(wgt, cc[k].x, C0);
+            C1 = __fmaf_rn(wgt, cc[k].y, C1);
+            C2 = __fmaf_rn(wgt, cc[k].z, C2);
             if (AUX) {
               float nv[3];
               staged_normal(B, j, nv);
-              D = __fmaf_rn(Tr, WL.dl[AUX ? k : 0][lane], D);
+              D = __fmaf_rn(Tr, WL.dl[lane][AUX ? k : 0], D);
               N0 = __fmaf_rn(wgt, nv[0], N0);
               N1 = __fmaf_rn(wgt, nv[1], N1);
               N2 = __fmaf_rn(wgt, nv[2], N2);
@@ -513,24 +533,31 @@ __device__ __forceinline__ void render_tile_fwd(const RenderArgs& A, int g,
       cnt = 0;
       nq = 0;
     };
-    // A: candidate lists
-    for (int j = 0; j < n; ++j) {
-      const uint32_t meta = __builtin_amdgcn_readfirstlane(B.meta[j]);
-      if (STATS && !done && (meta & 7u) == r.spat) ++n_pairs;
-      if (!((meta >> (3 + w)) & 1u)) continue;
-      const uint32_t rx = __builtin_amdgcn_readfirstlane(B.rx[j]);
-      const uint32_t ry = __builtin_amdgcn_readfirstlane(B.ry[j]);
-      const bool cand = !done && (meta & 7u) == r.spat && u >= (rx & 0xffffu) && u <= (rx >> 16) &&
-                        v >= (ry & 0xffffu) && v <= (ry >> 16);
-      const unsigned long long m = __ballot(cand);
-      if (m == 0ull) continue;
-      if (cand) {
-        WL.queue[nq + lane_rank(m)] = (uint16_t)((lane << 8) | cnt);
-        WL.jl[cnt][lane] = (uint8_t)j;
-        ++cnt;
+    // A: candidate lists; 64 entries' words at a time in registers
+    for (int jb = 0; jb < n; jb += 64) {
+      const int jn = min(64, n - jb);
+      const uint32_t meta_v = lane < jn ? B.meta[jb + lane] : 0u;
+      const uint32_t rx_v = lane < jn ? B.rx[jb + lane] : 0u;
+      const uint32_t ry_v = lane < jn ? B.ry[jb + lane] : 0u;
+      for (int jj = 0; jj < jn; ++jj) {
+        const uint32_t meta = (uint32_t)__builtin_amdgcn_readlane((int)meta_v, jj);
+        if (STATS && !done && (meta & 7u) == r.spat) ++n_pairs;
+        if (!((meta >> (3 + w)) & 1u)) continue;
+        const uint32_t rx = (uint32_t)__builtin_amdgcn_readlane((int)rx_v, jj);
+        const uint32_t ry = (uint32_t)__builtin_amdgcn_readlane((int)ry_v, jj);
+        const bool cand = !done && (meta & 7u) == r.spat && u >= (rx & 0xffffu) &&
+                          u <= (rx >> 16) && v >= (ry & 0xffffu) && v <= (ry >> 16);
+        const unsigned long long m = __ballot(cand);
+        if (m == 0ull) continue;
+        const int j = jb + jj;
+        if (cand) {
+          WL.queue[nq + lane_rank(m)] = (uint32_t)lane | ((uint32_t)cnt << 8) | ((uint32_t)j << 16);
+          WL.jl[lane][cnt] = (uint8_t)j;
+          ++cnt;
+        }
+        nq += (uint32_t)__popcll(m);
+        if (__ballot(cnt == CAP) != 0ull) flush();
       }
-      nq += (uint32_t)__popcll(m);
-      if (__ballot(cnt == CAP) != 0ull) flush();
     }
     if (nq > 0) flush();
     if (sb != kNoSplit) {
@@ -544,7 +571,7 @@ __device__ __forceinline__ void render_tile_fwd(const RenderArgs& A, int g,
     const bool all_done = __syncthreads_and(done);
     // the batch's maxima, one global atomic per entry with a composited hit
     if (!STATS && A.max_weight && tid < n && B.mw[tid] != 0u)
-      atomicMax(A.max_weight + B.vid[tid], B.mw[tid]);
+      atomicMax(A.max_weight + __float_as_uint(B.col[tid].w), B.mw[tid]);
     if (all_done) break;
   }
   // the backward wants the colour still to come: final minus so far
@@ -643,9 +670,23 @@ __device__ __forceinline__ float dpp_pair_sum(float lo, float hi, bool upper) {
 }
 
 constexpr int kDppRowMirror = 0x140;
+constexpr int kDppRowShr1 = 0x111;
+constexpr int kDppRowShr2 = 0x112;
+constexpr int kDppRowShr4 = 0x114;
+constexpr int kDppRowShr8 = 0x118;
+constexpr int kDppWaveShr1 = 0x138;   // whole wave, lane L takes lane L - 1
+constexpr int kDppRowBcast15 = 0x142;  // lane 15 of a row to the next row
+constexpr int kDppRowBcast31 = 0x143;  // lane 31 to rows 2 and 3
 constexpr int kDppRowHalfMirror = 0x141;
 constexpr int kDppQuadXor1 = 0xB1;  // quad_perm [1,0,3,2]
 constexpr int kDppQuadXor2 = 0x4E;  // quad_perm [2,3,0,1]
+
+// DPP move of a 32-bit value; lanes with no source (and rows outside
+// ROW_MASK) read 0
+template <int CTRL, int ROW_MASK = 0xf>
+__device__ __forceinline__ uint32_t dpp_u(uint32_t x) {
+  return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)x, CTRL, ROW_MASK, 0xf, true);
+}
 
 __device__ __forceinline__ float wave_reduce16(const float (&g)[16]) {
   const int lane = threadIdx.x & 63;
@@ -743,76 +784,167 @@ __device__ __forceinline__ void render_tile_bwd(const RenderArgs& A, int g, uint
     bend = b0;
     if (tid < n) stage_entry<TS>(B, tid, A.vals[b0 + tid], ci, A.n_cams, c, A.rec, A.rect, qu0, qv0);
     __syncthreads();
-    for (int j = n - 1; j >= 0; --j) {
-      const uint32_t meta = __builtin_amdgcn_readfirstlane(B.meta[j]);
-      if (!((meta >> (3 + w)) & 1u)) continue;
-      double a = 0.0, bb = 0.0;
-      bool hit = (b0 + (uint32_t)j < last) && ((meta & 7u) == r.spat);
-      if (hit) hit = slab(B, j, r.idx, r.idy, r.idz, a, bb);
-      if (__ballot(hit) == 0ull) continue;
-      float gv[16];
-#pragma unroll
-      for (int m = 0; m < 16; ++m) gv[m] = 0.f;
-      if (hit) {
-        float dw[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-        const double lseg = bb - a;
-        const float x = segment_x<KT, ACT, true>(B, j, r.dx, r.dy, r.dz, a, lseg, A.K, dw);
-        const float lK = (float)lseg / (float)(KT > 0 ? KT : A.K);
-        const float alpha = alpha_of(x);
-        tau -= x;
-        const float Ti = __expf(-tau);
-        const float cr = B.cr[j], cg = B.cg[j], cb = B.cb[j];
-        const float wgt = Ti * alpha;
-        gv[8] = gr * wgt; gv[9] = gg * wgt; gv[10] = gb * wgt;
-        float dLdx = gr * (Tnext * cr - U0) + gg * (Tnext * cg - U1) +
-                     gb * (Tnext * cb - U2) + ga * Tfin;
-        float dd[8], dloc = 0.f, nv[3] = {0.f, 0.f, 0.f};
-        if (AUX) {
-          // depth: D = sum T_i d_i (d_i through its sample alphas; the hits
-          // behind through T); normal: N = sum T_i alpha_i n_i, as the colour
-          dloc = segment_depth_grad<KT, ACT>(B, j, r.dx, r.dy, r.dz, a, lseg, A.K, dd);
-          staged_normal(B, j, nv);
-          dLdx += -gD * UD + gN0 * (Tnext * nv[0] - UN0) + gN1 * (Tnext * nv[1] - UN1) +
-                  gN2 * (Tnext * nv[2] - UN2);
-          gv[12] = wgt * gN0;
-          gv[13] = wgt * gN1;
-          gv[14] = wgt * gN2;
-        }
-        if (prio) {
-          // |alpha dL/dalpha| (eq. priority) = |T_i alpha <g, c - S> + g_A (e^{-(tau_fin - x)}
-          // - T_fin)|, S = U / T_{i+1} the colour behind seen from just behind (0 when
-          // T_{i+1} underflows: then nothing is composited behind and U = 0)
-          const float iT = Tnext > 0.f ? 1.f / Tnext : 0.f;
-          gv[11] = fabsf(wgt * (gr * (cr - U0 * iT) + gg * (cg - U1 * iT) + gb * (cb - U2 * iT)) +
-                         ga * (__expf(x - tau_end) - Tfin));
-        }
-        U0 = __fmaf_rn(wgt, cr, U0);
-        U1 = __fmaf_rn(wgt, cg, U1);
-        U2 = __fmaf_rn(wgt, cb, U2);
-        if (AUX) {
-          UD = __fmaf_rn(Ti, dloc, UD);
-          UN0 = __fmaf_rn(wgt, nv[0], UN0);
-          UN1 = __fmaf_rn(wgt, nv[1], UN1);
-          UN2 = __fmaf_rn(wgt, nv[2], UN2);
-        }
-        Tnext = Ti;
-        const float f = dLdx * lK;
-#pragma unroll
-        for (int m = 0; m < 8; ++m) gv[m] = f * dw[m];
-        if (AUX) {
-          const float gt = gD * Ti;
-#pragma unroll
-          for (int m = 0; m < 8; ++m) gv[m] = __fmaf_rn(gt, dd[m], gv[m]);
-        }
+    // one hit: step the pixel's reverse state over staged entry j (hit on
+    // [a, bb]) and write its gradients into gv[0..14]
+    auto hit_grads = [&](int j, double a, double bb, float (&gv)[16]) {
+      float dw[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+      const double lseg = bb - a;
+      const float x = segment_x<KT, ACT, true>(B, j, r.dx, r.dy, r.dz, a, lseg, A.K, dw);
+      const float lK = (float)lseg / (float)(KT > 0 ? KT : A.K);
+      const float alpha = alpha_of(x);
+      tau -= x;
+      const float Ti = __expf(-tau);
+      const float4 cj = B.col[j];
+      const float cr = cj.x, cg = cj.y, cb = cj.z;
+      const float wgt = Ti * alpha;
+      gv[8] = gr * wgt; gv[9] = gg * wgt; gv[10] = gb * wgt;
+      float dLdx = gr * (Tnext * cr - U0) + gg * (Tnext * cg - U1) +
+                   gb * (Tnext * cb - U2) + ga * Tfin;
+      float dd[8], dloc = 0.f, nv[3] = {0.f, 0.f, 0.f};
+      if (AUX) {
+        // depth: D = sum T_i d_i (d_i through its sample alphas; the hits
+        // behind through T); normal: N = sum T_i alpha_i n_i, as the colour
+        dloc = segment_depth_grad<KT, ACT>(B, j, r.dx, r.dy, r.dz, a, lseg, A.K, dd);
+        staged_normal(B, j, nv);
+        dLdx += -gD * UD + gN0 * (Tnext * nv[0] - UN0) + gN1 * (Tnext * nv[1] - UN1) +
+                gN2 * (Tnext * nv[2] - UN2);
+        gv[12] = wgt * gN0;
+        gv[13] = wgt * gN1;
+        gv[14] = wgt * gN2;
       }
-      const float tot = wave_reduce16(gv);
+      if (prio) {
+        // |alpha dL/dalpha| (eq. priority) = |T_i alpha <g, c - S> + g_A (e^{-(tau_fin - x)}
+        // - T_fin)|, S = U / T_{i+1} the colour behind seen from just behind (0 when
+        // T_{i+1} underflows: then nothing is composited behind and U = 0)
+        const float iT = Tnext > 0.f ? 1.f / Tnext : 0.f;
+        gv[11] = fabsf(wgt * (gr * (cr - U0 * iT) + gg * (cg - U1 * iT) + gb * (cb - U2 * iT)) +
+                       ga * (__expf(x - tau_end) - Tfin));
+      }
+      U0 = __fmaf_rn(wgt, cr, U0);
+      U1 = __fmaf_rn(wgt, cg, U1);
+      U2 = __fmaf_rn(wgt, cb, U2);
+      if (AUX) {
+        UD = __fmaf_rn(Ti, dloc, UD);
+        UN0 = __fmaf_rn(wgt, nv[0], UN0);
+        UN1 = __fmaf_rn(wgt, nv[1], UN1);
+        UN2 = __fmaf_rn(wgt, nv[2], UN2);
+      }
+      Tnext = Ti;
+      const float f = dLdx * lK;
+#pragma unroll
+      for (int m = 0; m < 8; ++m) gv[m] = f * dw[m];
+      if (AUX) {
+        const float gt = gD * Ti;
+#pragma unroll
+        for (int m = 0; m < 8; ++m) gv[m] = __fmaf_rn(gt, dd[m], gv[m]);
+      }
+    };
+    // the wave total of reduced value `slot` of voxel vid goes to its gradient
+    auto flush_grads = [&](float tot, uint32_t vid) {
       if (writer) {
-        const uint32_t vid = B.vid[j];
         float* dst = slot < 8    ? A.g_corner + (int64_t)vid * 8 + slot
                      : slot < 11 ? A.g_rgb + ((int64_t)vid * A.n_cams + ci) * 3 + (slot - 8)
                      : slot < 12 ? A.priority + vid
                                  : A.g_nrm + (int64_t)vid * 3 + (slot - 12);
         unsafeAtomicAdd(dst, tot);
+      }
+    };
+    if (!kGroupedBwd) {
+      // 64 entries' voxel ids at a time in registers (a scalar base address
+      // for the gradient atomics)
+      uint32_t vid_v = 0u;
+      for (int j = n - 1; j >= 0; --j) {
+        if (j == n - 1 || (j & 63) == 63) {
+          const int jb = j & ~63;
+          vid_v = jb + lane < n ? __float_as_uint(B.col[jb + lane].w) : 0u;
+        }
+        const uint32_t meta = __builtin_amdgcn_readfirstlane(B.meta[j]);
+        if (!((meta >> (3 + w)) & 1u)) continue;
+        double a = 0.0, bb = 0.0;
+        bool hit = (b0 + (uint32_t)j < last) && ((meta & 7u) == r.spat);
+        if (hit) hit = slab(B, j, r.idx, r.idy, r.idz, a, bb);
+        if (__ballot(hit) == 0ull) continue;
+        float gv[16];
+#pragma unroll
+        for (int m = 0; m < 16; ++m) gv[m] = 0.f;
+        if (hit) hit_grads(j, a, bb, gv);
+        flush_grads(wave_reduce16(gv), (uint32_t)__builtin_amdgcn_readlane((int)vid_v, j & 63));
+      }
+    } else {
+      // Grouped walk: 64 entries at a time, entry e of the chunk held by
+      // lane e (entry top - e, so lane order is the reverse walk order) with
+      // the mask of the block's pixels inside its projected rectangle.  An
+      // entry whose mask is disjoint from the masks of every entry still
+      // pending before it is the next entry of each of its pixels, so all
+      // such entries are walked together, one per pixel lane: the hit path
+      // runs once per group instead of once per entry (groups hold about
+      // two entries on the benchmark scenes), and each entry's gradients are
+      // then summed over its own lanes.
+      const int bu0 = qu0 + (w % G::kBpr) * 8, bv0 = qv0 + (w / G::kBpr) * 8;
+      for (int top = n - 1; top >= 0; top -= 64) {
+        const int j_e = top - lane;  // this lane's entry (as an entry lane)
+        uint32_t mlo = 0u, mhi = 0u, vid_e = 0u;
+        if (j_e >= 0) {
+          const uint32_t meta = B.meta[j_e];
+          if ((meta >> (3 + w)) & 1u) {
+            const uint32_t rx = B.rx[j_e], ry = B.ry[j_e];
+            const int cu0 = max((int)(rx & 0xffffu) - bu0, 0), cu1 = min((int)(rx >> 16) - bu0, 7);
+            const int cv0 = max((int)(ry & 0xffffu) - bv0, 0), cv1 = min((int)(ry >> 16) - bv0, 7);
+            if (cu0 <= cu1 && cv0 <= cv1) {
+              uint32_t row = ((2u << cu1) - 1u) & ~((1u << cu0) - 1u);
+              row |= row << 8;
+              row |= row << 16;
+              const unsigned long long rows =
+                  (cv1 == 7 ? ~0ull : ((1ull << (8 * (cv1 + 1))) - 1ull)) & ~((1ull << (8 * cv0)) - 1ull);
+              mlo = row & (uint32_t)rows;
+              mhi = row & (uint32_t)(rows >> 32);
+            }
+          }
+          vid_e = __float_as_uint(B.col[j_e].w);
+        }
+        while (__ballot((mlo | mhi) != 0u) != 0ull) {
+          // inclusive prefix OR of the masks in lane order, then exclusive
+          uint32_t ilo = mlo, ihi = mhi;
+          ilo |= dpp_u<kDppRowShr1>(ilo); ihi |= dpp_u<kDppRowShr1>(ihi);
+          ilo |= dpp_u<kDppRowShr2>(ilo); ihi |= dpp_u<kDppRowShr2>(ihi);
+          ilo |= dpp_u<kDppRowShr4>(ilo); ihi |= dpp_u<kDppRowShr4>(ihi);
+          ilo |= dpp_u<kDppRowShr8>(ilo); ihi |= dpp_u<kDppRowShr8>(ihi);
+          ilo |= dpp_u<kDppRowBcast15, 0xa>(ilo); ihi |= dpp_u<kDppRowBcast15, 0xa>(ihi);
+          ilo |= dpp_u<kDppRowBcast31, 0xc>(ilo); ihi |= dpp_u<kDppRowBcast31, 0xc>(ihi);
+          const uint32_t elo = dpp_u<kDppWaveShr1>(ilo), ehi = dpp_u<kDppWaveShr1>(ihi);
+          const bool elig = (mlo | mhi) != 0u && ((mlo & elo) | (mhi & ehi)) == 0u;
+          const unsigned long long E = __ballot(elig);
+          // the group entry (lane) that holds this pixel, -1 if none
+          int my = -1;
+          for (unsigned long long es = E; es != 0ull; es &= es - 1ull) {
+            const int e = __builtin_ctzll(es);
+            const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)mlo, e);
+            const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)mhi, e);
+            if ((((lane < 32 ? lo : hi) >> (lane & 31)) & 1u) != 0u) my = e;
+          }
+          if (elig) { mlo = 0u; mhi = 0u; }
+          const int j = top - my;
+          double a = 0.0, bb = 0.0;
+          bool hit = false;
+          if (my >= 0) {
+            hit = (b0 + (uint32_t)j < last) && ((B.meta[j] & 7u) == r.spat);
+            if (hit) hit = slab(B, j, r.idx, r.idy, r.idz, a, bb);
+          }
+          if (__ballot(hit) == 0ull) continue;
+          float gv[16];
+#pragma unroll
+          for (int m = 0; m < 16; ++m) gv[m] = 0.f;
+          if (hit) hit_grads(j, a, bb, gv);
+          for (unsigned long long es = E; es != 0ull; es &= es - 1ull) {
+            const int e = __builtin_ctzll(es);
+            const bool mine = hit && my == e;
+            if (__ballot(mine) == 0ull) continue;
+            float ge[16];
+#pragma unroll
+            for (int m = 0; m < 16; ++m) ge[m] = mine ? gv[m] : 0.f;
+            flush_grads(wave_reduce16(ge), (uint32_t)__builtin_amdgcn_readlane((int)vid_e, e));
+          }
+        }
       }
     }
     __syncthreads();
