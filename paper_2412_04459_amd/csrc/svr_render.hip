@@ -41,6 +41,8 @@
 // started last would set the kernel's length.  Either one workgroup per
 // position of that order, or a persistent grid whose workgroups take the next
 // position from one counter.
+#include <type_traits>
+
 #include "svr_internal.h"
 #include "svr_sh.h"
 
@@ -88,8 +90,8 @@ struct TileGeom {
 template <int NB>
 struct LdsBatch {
   double lo[3][NB];                    // box min - camera centre (fp64)
-  double hi[3][NB];                    // box max - camera centre (fp64)
   float4 col[NB];                      // colour rgb, voxel id (bits) in w
+  float edge[NB];                      // box edge (box max = min + edge)
   float isz[NB];                       // 1 / edge
   float V[8][NB];                      // corner raw densities
   uint32_t meta[NB];                   // sign bits | block mask << 3
@@ -169,9 +171,7 @@ __device__ __forceinline__ void stage_entry(LdsBatch<NB>& B, int slot, uint32_t 
   B.lo[0][slot] = ((double)R.q0.x - h) - c.od[0];
   B.lo[1][slot] = ((double)R.q0.y - h) - c.od[1];
   B.lo[2][slot] = ((double)R.q0.z - h) - c.od[2];
-  B.hi[0][slot] = ((double)R.q0.x + h) - c.od[0];
-  B.hi[1][slot] = ((double)R.q0.y + h) - c.od[1];
-  B.hi[2][slot] = ((double)R.q0.z + h) - c.od[2];
+  B.edge[slot] = R.q0.w;
   B.isz[slot] = 1.f / R.q0.w;
   B.V[0][slot] = R.q1.x; B.V[1][slot] = R.q1.y; B.V[2][slot] = R.q1.z; B.V[3][slot] = R.q1.w;
   B.V[4][slot] = R.q2.x; B.V[5][slot] = R.q2.y; B.V[6][slot] = R.q2.z; B.V[7][slot] = R.q2.w;
@@ -187,9 +187,11 @@ __device__ __forceinline__ void stage_entry(LdsBatch<NB>& B, int slot, uint32_t 
 template <int NB>
 __device__ __forceinline__ bool slab(const LdsBatch<NB>& B, int j, double idx, double idy,
                                      double idz, double& a, double& b) {
-  const double t0x = B.lo[0][j] * idx, t1x = B.hi[0][j] * idx;
-  const double t0y = B.lo[1][j] * idy, t1y = B.hi[1][j] * idy;
-  const double t0z = B.lo[2][j] * idz, t1z = B.hi[2][j] * idz;
+  const double e = (double)B.edge[j];
+  const double lx = B.lo[0][j], ly = B.lo[1][j], lz = B.lo[2][j];
+  const double t0x = lx * idx, t1x = (lx + e) * idx;
+  const double t0y = ly * idy, t1y = (ly + e) * idy;
+  const double t0z = lz * idz, t1z = (lz + e) * idz;
   a = fmax(fmax(fmin(t0x, t1x), fmin(t0y, t1y)), fmin(t0z, t1z));
   b = fmin(fmin(fmax(t0x, t1x), fmax(t0y, t1y)), fmax(t0z, t1z));
   return (a <= b) && (a > 0.0);
@@ -405,16 +407,32 @@ struct DenseCfg {
   static constexpr int kListCap = (TS == 32 && AUX) ? 4 : 8;
 };
 
-template <int CAP, bool AUX>
+// queue word: owner lane | list slot (3 bits) << kSlotShift | staged entry
+// << kEntryShift; 16 bits when a batch holds at most 64 entries, else 32
+template <int NB>
+struct QueueWord {
+  static constexpr bool kSmall = NB <= 64;
+  using T = typename std::conditional<kSmall, uint16_t, uint32_t>::type;
+  static constexpr int kSlotShift = kSmall ? 6 : 8;
+  static constexpr int kEntryShift = kSmall ? 9 : 16;
+};
+
+template <int CAP, bool AUX, int NB>
 struct alignas(16) WaveLists {
   static_assert(CAP == 4 || CAP == 8, "list slots are loaded 4 at a time");
-  uint32_t queue[64 * CAP];  // task -> owner lane | list slot << 8 | staged entry << 16
-  double d[3][64];           // lane ray direction (fp64)
-  double id[3][64];          // and its reciprocal
+  typename QueueWord<NB>::T queue[64 * CAP];  // task -> (owner lane, list slot, entry)
   float xl[64][CAP];         // per lane: optical depth of each candidate (< 0: a miss)
-  float dl[64][AUX ? CAP : 1];  // its local depth (depth images only)
+  float dl[AUX ? 64 : 1][AUX ? CAP : 1];  // its local depth (depth images only)
   uint8_t jl[64][CAP];       // per lane: staged entry index of each candidate
 };
+
+// value of v in lane src (all lanes of the wave must execute this)
+__device__ __forceinline__ double lane_f64(double v, int src) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(v);
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_ds_bpermute(src << 2, (int)(uint32_t)b);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_ds_bpermute(src << 2, (int)(uint32_t)(b >> 32));
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
 
 __device__ __forceinline__ uint32_t lane_rank(unsigned long long mask) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
@@ -428,7 +446,7 @@ __device__ __forceinline__ uint32_t lane_rank(unsigned long long mask) {
 template <int TS, int KT, int ACT, bool STATS, bool AUX>
 __device__ __forceinline__ void render_tile_fwd(const RenderArgs& A, int g,
                                                 LdsBatch<TileGeom<TS>::kBatch>& B,
-                                                WaveLists<DenseCfg<TS, AUX>::kListCap, AUX>* WLs) {
+                                                WaveLists<DenseCfg<TS, AUX>::kListCap, AUX, TileGeom<TS>::kBatch>* WLs) {
   using G = TileGeom<TS>;
   constexpr int NB = G::kBatch;
   constexpr int CAP = DenseCfg<TS, AUX>::kListCap;
@@ -439,9 +457,8 @@ __device__ __forceinline__ void render_tile_fwd(const RenderArgs& A, int g,
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int qu0 = tx * TS, qv0 = ty * TS;
   const PixelRay r = make_ray<TS>(c, qu0, qv0, w, lane);
-  WaveLists<CAP, AUX>& WL = WLs[w];
-  WL.d[0][lane] = r.dx; WL.d[1][lane] = r.dy; WL.d[2][lane] = r.dz;
-  WL.id[0][lane] = r.idx; WL.id[1][lane] = r.idy; WL.id[2][lane] = r.idz;
+  using QW = QueueWord<NB>;
+  WaveLists<CAP, AUX, NB>& WL = WLs[w];
 
   const uint2 rg = A.range[g];
   const uint32_t start = rg.x, end = rg.y;
@@ -466,25 +483,31 @@ __device__ __forceinline__ void render_tile_fwd(const RenderArgs& A, int g,
     uint32_t nq = 0;  // queue length (wave-uniform)
     auto flush = [&]() {
       wave_sync_lds();
-      // B: candidates, one per lane
-      for (uint32_t t = lane; t < nq; t += 64) {
-        const uint32_t q = WL.queue[t];
-        const int ow = (int)(q & 63u), k = (int)((q >> 8) & 0xffu), j = (int)(q >> 16);
-        double a, bb;
-        float x = -1.f;
-        if (slab(B, j, WL.id[0][ow], WL.id[1][ow], WL.id[2][ow], a, bb)) {
-          if (AUX) {
-            float dloc;
-            x = segment_xd<KT, ACT>(B, j, WL.d[0][ow], WL.d[1][ow], WL.d[2][ow], a, bb - a, A.K,
-                                    dloc);
-            WL.dl[ow][AUX ? k : 0] = dloc;
-          } else {
-            x = segment_x<KT, ACT, false>(B, j, WL.d[0][ow], WL.d[1][ow], WL.d[2][ow], a, bb - a,
-                                          A.K, nullptr);
+      // B: candidates, one per lane; the owner's ray comes from its lane
+      // (ds_bpermute, with every lane of the wave taking part)
+      for (uint32_t tb = 0; tb < nq; tb += 64) {
+        const bool act = tb + lane < nq;
+        const uint32_t q = act ? (uint32_t)WL.queue[tb + lane] : 0u;
+        const int ow = (int)(q & 63u), k = (int)((q >> QW::kSlotShift) & 7u);
+        const int j = (int)(q >> QW::kEntryShift);
+        const double dx = lane_f64(r.dx, ow), dy = lane_f64(r.dy, ow), dz = lane_f64(r.dz, ow);
+        const double idx = lane_f64(r.idx, ow), idy = lane_f64(r.idy, ow);
+        const double idz = lane_f64(r.idz, ow);
+        if (act) {
+          double a, bb;
+          float x = -1.f;
+          if (slab(B, j, idx, idy, idz, a, bb)) {
+            if (AUX) {
+              float dloc;
+              x = segment_xd<KT, ACT>(B, j, dx, dy, dz, a, bb - a, A.K, dloc);
+              WL.dl[AUX ? ow : 0][AUX ? k : 0] = dloc;
+            } else {
+              x = segment_x<KT, ACT, false>(B, j, dx, dy, dz, a, bb - a, A.K, nullptr);
+            }
           }
+          WL.xl[ow][k] = x;
+          if (STATS) ++n_tests;
         }
-        WL.xl[ow][k] = x;
-        if (STATS) ++n_tests;
       }
       wave_sync_lds();
       // C: each lane composites its own list in entry order; the list is
@@ -516,7 +539,7 @@ __device__ __forceinline__ void render_tile_fwd(const RenderArgs& A, int g,
             if (AUX) {
               float nv[3];
               staged_normal(B, j, nv);
-              D = __fmaf_rn(Tr, WL.dl[lane][AUX ? k : 0], D);
+              D = __fmaf_rn(Tr, WL.dl[AUX ? lane : 0][AUX ? k : 0], D);
               N0 = __fmaf_rn(wgt, nv[0], N0);
               N1 = __fmaf_rn(wgt, nv[1], N1);
               N2 = __fmaf_rn(wgt, nv[2], N2);
@@ -551,7 +574,9 @@ __device__ __forceinline__ void render_tile_fwd(const RenderArgs& A, int g,
         if (m == 0ull) continue;
         const int j = jb + jj;
         if (cand) {
-          WL.queue[nq + lane_rank(m)] = (uint32_t)lane | ((uint32_t)cnt << 8) | ((uint32_t)j << 16);
+          WL.queue[nq + lane_rank(m)] =
+              (typename QW::T)((uint32_t)lane | ((uint32_t)cnt << QW::kSlotShift) |
+                               ((uint32_t)j << QW::kEntryShift));
           WL.jl[lane][cnt] = (uint8_t)j;
           ++cnt;
         }
@@ -615,7 +640,7 @@ __device__ __forceinline__ void render_tile_fwd(const RenderArgs& A, int g,
 template <int TS, int KT, int ACT, bool STATS, bool AUX>
 __global__ __launch_bounds__(TS * TS) void k_render_fwd(RenderArgs A) {
   __shared__ LdsBatch<TileGeom<TS>::kBatch> B;
-  __shared__ WaveLists<DenseCfg<TS, AUX>::kListCap, AUX> WL[TileGeom<TS>::kWaves];
+  __shared__ WaveLists<DenseCfg<TS, AUX>::kListCap, AUX, TileGeom<TS>::kBatch> WL[TileGeom<TS>::kWaves];
   __shared__ int s_tile;
   if (!A.persistent) {
     if ((int)blockIdx.x < A.T) render_tile_fwd<TS, KT, ACT, STATS, AUX>(A, A.order[blockIdx.x], B, WL);
