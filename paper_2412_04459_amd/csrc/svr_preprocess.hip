@@ -557,8 +557,34 @@ struct EmitCtx {
   uint64_t top, rep;
   int sh;
   uint32_t vid;
-  const uint32_t* rank;  // the voxel's 8 order ranks, or null (key from the path)
+  bool ranked;    // key low bits from the order ranks (else from the path)
+  uint4 r03, r47;  // the voxel's 8 order ranks, loaded together up front
 };
+
+__device__ __forceinline__ EmitCtx emit_ctx(const uint64_t* __restrict__ octpath,
+                                            const uint32_t* __restrict__ rank, int64_t vid, int L,
+                                            uint64_t rep, int sh) {
+  EmitCtx e;
+  e.top = octpath[vid] >> (3 * (SVR_MAX_LEVELS - L));
+  e.rep = rep;
+  e.sh = sh;
+  e.vid = (uint32_t)vid;
+  e.ranked = rank != nullptr;
+  if (e.ranked) {
+    const uint4* r = reinterpret_cast<const uint4*>(rank + vid * 8);
+    e.r03 = r[0];
+    e.r47 = r[1];
+  } else {
+    e.r03 = e.r47 = make_uint4(0u, 0u, 0u, 0u);
+  }
+  return e;
+}
+
+__device__ __forceinline__ uint32_t rank_of(const EmitCtx& e, int sgn) {
+  const uint4 q = sgn < 4 ? e.r03 : e.r47;
+  const int i = sgn & 3;
+  return i < 2 ? (i == 0 ? q.x : q.y) : (i == 2 ? q.z : q.w);
+}
 
 __device__ __forceinline__ void emit_tile(const EmitCtx& e, int gt, uint32_t m,
                                           unsigned long long o, int64_t cap,
@@ -567,8 +593,8 @@ __device__ __forceinline__ void emit_tile(const EmitCtx& e, int gt, uint32_t m,
     const int sgn = __ffs(m) - 1;
     m &= m - 1;
     if (o < (unsigned long long)cap) {
-      const uint64_t low = e.rank ? (uint64_t)e.rank[sgn]
-                                  : ((e.top ^ ((uint64_t)sgn * e.rep)) << 3) | (uint64_t)sgn;
+      const uint64_t low = e.ranked ? (uint64_t)rank_of(e, sgn)
+                                    : ((e.top ^ ((uint64_t)sgn * e.rep)) << 3) | (uint64_t)sgn;
       keys[o] = ((uint64_t)gt << e.sh) | low;
       vals[o] = ((uint32_t)sgn << kVidBits) | e.vid;
     }
@@ -598,8 +624,7 @@ __global__ __launch_bounds__(kBlock) void k_emit(
     } else {
       const int64_t vid = vv / n_cams;
       const DevCam& c = cams.c[(int)(vv - vid * n_cams)];
-      const EmitCtx e{octpath[vid] >> (3 * (SVR_MAX_LEVELS - L)), rep, sh, (uint32_t)vid,
-                      rank ? rank + vid * 8 : nullptr};
+      const EmitCtx e = emit_ctx(octpath, rank, vid, L, rep, sh);
       unsigned long long o = off[vv];
       const uint2 r = rect[vv];
       const int tx0 = (int)(r.x & 0xffffu) >> cams.tshift, tx1 = (int)(r.x >> 16) >> cams.tshift;
@@ -620,8 +645,7 @@ __global__ __launch_bounds__(kBlock) void k_emit(
     const int64_t bv = s_big[b];
     const int64_t vid = bv / n_cams;
     const DevCam& c = cams.c[(int)(bv - vid * n_cams)];
-    const EmitCtx e{octpath[vid] >> (3 * (SVR_MAX_LEVELS - L)), rep, sh, (uint32_t)vid,
-                    rank ? rank + vid * 8 : nullptr};
+    const EmitCtx e = emit_ctx(octpath, rank, vid, L, rep, sh);
     const uint2 r = rect[bv];
     const int tx0 = (int)(r.x & 0xffffu) >> cams.tshift, tx1 = (int)(r.x >> 16) >> cams.tshift;
     const int ty0 = (int)(r.y & 0xffffu) >> cams.tshift, ty1 = (int)(r.y >> 16) >> cams.tshift;
