@@ -34,16 +34,22 @@ hipError_t launch_fill_u32(uint32_t* p, uint32_t v, int64_t n, hipStream_t s) {
   return hipGetLastError();
 }
 
-// zero up to kFillRegions arrays in one launch: the grid-stride index runs
-// over their concatenation
+// zero up to kFillRegions arrays in one launch: each workgroup takes a share
+// of every array; 16-byte stores over the 16-byte aligned middle of an array
 __global__ void k_zero_u32(FillSet f) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t tid = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  int r = 0;
-  int64_t base = 0;
-  for (; i < f.total; i += stride) {
-    while (i >= base + f.n[r]) base += f.n[r++];
-    f.p[r][i - base] = 0u;
+  for (int r = 0; r < f.k; ++r) {
+    uint32_t* p = f.p[r];
+    const int64_t n = f.n[r];
+    // head up to the first 16-byte boundary, then uint4 stores, then the tail
+    const int64_t head = min(n, (int64_t)(((16u - ((uintptr_t)p & 15u)) & 15u) >> 2));
+    const int64_t n4 = (n - head) >> 2;
+    if (tid < head) p[tid] = 0u;
+    uint4* q = reinterpret_cast<uint4*>(p + head);
+    for (int64_t i = tid; i < n4; i += stride) q[i] = make_uint4(0u, 0u, 0u, 0u);
+    const int64_t t0 = head + 4 * n4;
+    if (tid < n - t0) p[t0 + tid] = 0u;
   }
 }
 
@@ -175,10 +181,18 @@ __global__ __launch_bounds__(kBlock) void k_sat_cols(CamSet cams, uint32_t* __re
   const int tx = (int)blk * 64 + lane;
   if (tx >= W1) return;
   uint32_t* S = sat + c.sat_off + tx;
+  // 16 rows per step: the loads are issued together, then summed and stored
+  constexpr int kRows = 16;
   uint32_t acc = 0;
-  for (int ty = 0; ty <= c.nty; ++ty) {
-    acc += S[(int64_t)ty * W1];
-    S[(int64_t)ty * W1] = acc;
+  for (int y0 = 0; y0 <= c.nty; y0 += kRows) {
+    uint32_t v[kRows];
+#pragma unroll
+    for (int k = 0; k < kRows; ++k) v[k] = y0 + k <= c.nty ? S[(int64_t)(y0 + k) * W1] : 0u;
+#pragma unroll
+    for (int k = 0; k < kRows; ++k) {
+      acc += v[k];
+      if (y0 + k <= c.nty) S[(int64_t)(y0 + k) * W1] = acc;
+    }
   }
 }
 
