@@ -730,6 +730,32 @@ __device__ __forceinline__ float wave_reduce16(const float (&g)[16]) {
   return x;
 }
 
+// The same for 12 values (no depth/normal gradients): 6 permlane32 swaps,
+// 3 permlane16 swaps, then the row mirrors on 3 values (one slot padded with
+// zero) and the quad adds; about 29 VALU instructions.  Lane L ends up with
+// value red12_slot(L) (see there); lanes with (L >> 2) & 3 == 3 hold nothing.
+__device__ __forceinline__ float wave_reduce12(const float (&g)[16]) {
+  const int lane = threadIdx.x & 63;
+  const float s0 = swap32_sum(g[0], g[6]), s1 = swap32_sum(g[1], g[7]);
+  const float s2 = swap32_sum(g[2], g[8]), s3 = swap32_sum(g[3], g[9]);
+  const float s4 = swap32_sum(g[4], g[10]), s5 = swap32_sum(g[5], g[11]);
+  const float t0 = swap16_sum(s0, s3), t1 = swap16_sum(s1, s4), t2 = swap16_sum(s2, s5);
+  const bool u8 = (lane & 8) != 0, u4 = (lane & 4) != 0;
+  const float w0 = dpp_pair_sum<kDppRowMirror>(t0, t2, u8);
+  const float w1 = dpp_pair_sum<kDppRowMirror>(t1, 0.f, u8);
+  float x = dpp_pair_sum<kDppRowHalfMirror>(w0, w1, u4);
+  x += dpp<kDppQuadXor1>(x);
+  x += dpp<kDppQuadXor2>(x);
+  return x;
+}
+
+// value index lane L holds after wave_reduce12: 6 (L >> 5) + 3 ((L >> 4) & 1)
+// + i, i = 0, 1, 2 for (L >> 2) & 3 = 0, 1, 2 (and 3: none, returned as 15)
+__device__ __forceinline__ int red12_slot(int lane) {
+  const int q = (lane >> 2) & 3;
+  return q == 3 ? 15 : 6 * (lane >> 5) + 3 * ((lane >> 4) & 1) + q;
+}
+
 // Backward of chunks [m_lo, m_hi) of tile g (entries [start + m_lo C,
 // min(start + m_hi C, end)), C = kBwdChunk).  A pixel whose last composited
 // entry lies beyond the range starts from the forward's checkpoint at the
@@ -749,11 +775,14 @@ __device__ __forceinline__ void render_tile_bwd(const RenderArgs& A, int g, uint
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   const int qu0 = tx * TS, qv0 = ty * TS;
   const PixelRay r = make_ray<TS>(c, qu0, qv0, w, lane);
-  const int slot = (lane >> 2) & 15;  // reduced value this lane ends up holding
+  // reduced value this lane ends up holding: 12 values without depth and
+  // normal images, 16 with them
+  const int slot = AUX ? (lane >> 2) & 15 : red12_slot(lane);
   const bool prio = A.priority != nullptr;
   // values: 0-7 corners, 8-10 colour, 11 priority, 12-14 dL/dn (depth and normal)
   const bool writer = (lane & 3) == 0 &&
                       (slot < 11 || (slot == 11 && prio) || (AUX && slot >= 12 && slot < 15));
+  auto reduce = [&](const float (&g)[16]) { return AUX ? wave_reduce16(g) : wave_reduce12(g); };
 
   const uint2 rg = A.range[g];
   const uint32_t e_lo = rg.x + m_lo * (uint32_t)kBwdChunk;
@@ -893,7 +922,7 @@ __device__ __forceinline__ void render_tile_bwd(const RenderArgs& A, int g, uint
 #pragma unroll
         for (int m = 0; m < 16; ++m) gv[m] = 0.f;
         if (hit) hit_grads(j, a, bb, gv);
-        flush_grads(wave_reduce16(gv), (uint32_t)__builtin_amdgcn_readlane((int)vid_v, j & 63));
+        flush_grads(reduce(gv), (uint32_t)__builtin_amdgcn_readlane((int)vid_v, j & 63));
       }
     } else {
       // Grouped walk: 64 entries at a time, entry e of the chunk held by
@@ -960,6 +989,11 @@ __device__ __forceinline__ void render_tile_bwd(const RenderArgs& A, int g, uint
 #pragma unroll
           for (int m = 0; m < 16; ++m) gv[m] = 0.f;
           if (hit) hit_grads(j, a, bb, gv);
+          if ((E & (E - 1ull)) == 0ull) {
+            // one entry: the lanes that did not hit it hold zeros already
+            flush_grads(reduce(gv), (uint32_t)__builtin_amdgcn_readlane((int)vid_e, __builtin_ctzll(E)));
+            continue;
+          }
           for (unsigned long long es = E; es != 0ull; es &= es - 1ull) {
             const int e = __builtin_ctzll(es);
             const bool mine = hit && my == e;
@@ -967,7 +1001,7 @@ __device__ __forceinline__ void render_tile_bwd(const RenderArgs& A, int g, uint
             float ge[16];
 #pragma unroll
             for (int m = 0; m < 16; ++m) ge[m] = mine ? gv[m] : 0.f;
-            flush_grads(wave_reduce16(ge), (uint32_t)__builtin_amdgcn_readlane((int)vid_e, e));
+            flush_grads(reduce(ge), (uint32_t)__builtin_amdgcn_readlane((int)vid_e, e));
           }
         }
       }
