@@ -439,6 +439,24 @@ __device__ __forceinline__ uint32_t lane_rank(unsigned long long mask) {
                                    __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
+// 64-bit mask of the pixels of the 8x8 block at (bu0, bv0) (bit 8 y + x)
+// that lie in the pixel rectangle rx = u0 | u1 << 16, ry = v0 | v1 << 16
+__device__ __forceinline__ void block_rect_mask(uint32_t rx, uint32_t ry, int bu0, int bv0,
+                                                uint32_t& mlo, uint32_t& mhi) {
+  mlo = mhi = 0u;
+  const int cu0 = max((int)(rx & 0xffffu) - bu0, 0), cu1 = min((int)(rx >> 16) - bu0, 7);
+  const int cv0 = max((int)(ry & 0xffffu) - bv0, 0), cv1 = min((int)(ry >> 16) - bv0, 7);
+  if (cu0 <= cu1 && cv0 <= cv1) {
+    uint32_t row = ((2u << cu1) - 1u) & ~((1u << cu0) - 1u);
+    row |= row << 8;
+    row |= row << 16;
+    const unsigned long long rows =
+        (cv1 == 7 ? ~0ull : ((1ull << (8 * (cv1 + 1))) - 1ull)) & ~((1ull << (8 * cv0)) - 1ull);
+    mlo = row & (uint32_t)rows;
+    mhi = row & (uint32_t)(rows >> 32);
+  }
+}
+
 
 // STATS: count, per frame, the (pixel, entry) pairs of matching sign pattern
 // the method walks, the ray-box tests this kernel executes (candidates after
@@ -459,6 +477,7 @@ __device__ __forceinline__ void render_tile_fwd(const RenderArgs& A, int g,
   const PixelRay r = make_ray<TS>(c, qu0, qv0, w, lane);
   using QW = QueueWord<NB>;
   WaveLists<CAP, AUX, NB>& WL = WLs[w];
+  const int bu0 = qu0 + (w % G::kBpr) * 8, bv0 = qv0 + (w / G::kBpr) * 8;  // this wave's block
 
   const uint2 rg = A.range[g];
   const uint32_t start = rg.x, end = rg.y;
@@ -467,7 +486,6 @@ __device__ __forceinline__ void render_tile_fwd(const RenderArgs& A, int g,
   uint32_t last = start;
   bool done = !r.inside;
   uint32_t n_pairs = 0, n_tests = 0, n_hits = 0;
-  const uint32_t u = (uint32_t)r.u, v = (uint32_t)r.v;
   // heavy tile: record (tau, colour so far) at every chunk boundary passed
   const uint32_t sb = STATS ? kNoSplit : A.split_base[g];
   float4* const ck = A.ckpt + (int64_t)(sb == kNoSplit ? 0u : sb) * (TS * TS) + tid;
@@ -556,22 +574,28 @@ __device__ __forceinline__ void render_tile_fwd(const RenderArgs& A, int g,
       cnt = 0;
       nq = 0;
     };
-    // A: candidate lists; 64 entries' words at a time in registers
+    // A: candidate lists.  64 entries at a time, entry jb + e held by lane e
+    // with its sign/block word and the mask of this wave's pixels inside its
+    // rectangle; per entry the candidates are that mask & the pixels of its
+    // sign pattern & the pixels still compositing
     for (int jb = 0; jb < n; jb += 64) {
       const int jn = min(64, n - jb);
-      const uint32_t meta_v = lane < jn ? B.meta[jb + lane] : 0u;
-      const uint32_t rx_v = lane < jn ? B.rx[jb + lane] : 0u;
-      const uint32_t ry_v = lane < jn ? B.ry[jb + lane] : 0u;
+      uint32_t meta_v = 0u, mlo = 0u, mhi = 0u;
+      if (lane < jn) {
+        meta_v = B.meta[jb + lane];
+        if ((meta_v >> (3 + w)) & 1u) block_rect_mask(B.rx[jb + lane], B.ry[jb + lane], bu0, bv0, mlo, mhi);
+      }
+      unsigned long long live = __ballot(!done);
       for (int jj = 0; jj < jn; ++jj) {
         const uint32_t meta = (uint32_t)__builtin_amdgcn_readlane((int)meta_v, jj);
         if (STATS && !done && (meta & 7u) == r.spat) ++n_pairs;
-        if (!((meta >> (3 + w)) & 1u)) continue;
-        const uint32_t rx = (uint32_t)__builtin_amdgcn_readlane((int)rx_v, jj);
-        const uint32_t ry = (uint32_t)__builtin_amdgcn_readlane((int)ry_v, jj);
-        const bool cand = !done && (meta & 7u) == r.spat && u >= (rx & 0xffffu) &&
-                          u <= (rx >> 16) && v >= (ry & 0xffffu) && v <= (ry >> 16);
-        const unsigned long long m = __ballot(cand);
+        const unsigned long long rm =
+            ((unsigned long long)(uint32_t)__builtin_amdgcn_readlane((int)mhi, jj) << 32) |
+            (uint32_t)__builtin_amdgcn_readlane((int)mlo, jj);
+        if ((rm & live) == 0ull) continue;
+        const unsigned long long m = rm & live & __ballot(r.spat == (meta & 7u));
         if (m == 0ull) continue;
+        const bool cand = ((m >> lane) & 1ull) != 0ull;
         const int j = jb + jj;
         if (cand) {
           WL.queue[nq + lane_rank(m)] =
@@ -581,7 +605,10 @@ __device__ __forceinline__ void render_tile_fwd(const RenderArgs& A, int g,
           ++cnt;
         }
         nq += (uint32_t)__popcll(m);
-        if (__ballot(cnt == CAP) != 0ull) flush();
+        if (__ballot(cnt == CAP) != 0ull) {
+          flush();
+          live = __ballot(!done);
+        }
       }
     }
     if (nq > 0) flush();
@@ -939,21 +966,7 @@ __device__ __forceinline__ void render_tile_bwd(const RenderArgs& A, int g, uint
         const int j_e = top - lane;  // this lane's entry (as an entry lane)
         uint32_t mlo = 0u, mhi = 0u, vid_e = 0u;
         if (j_e >= 0) {
-          const uint32_t meta = B.meta[j_e];
-          if ((meta >> (3 + w)) & 1u) {
-            const uint32_t rx = B.rx[j_e], ry = B.ry[j_e];
-            const int cu0 = max((int)(rx & 0xffffu) - bu0, 0), cu1 = min((int)(rx >> 16) - bu0, 7);
-            const int cv0 = max((int)(ry & 0xffffu) - bv0, 0), cv1 = min((int)(ry >> 16) - bv0, 7);
-            if (cu0 <= cu1 && cv0 <= cv1) {
-              uint32_t row = ((2u << cu1) - 1u) & ~((1u << cu0) - 1u);
-              row |= row << 8;
-              row |= row << 16;
-              const unsigned long long rows =
-                  (cv1 == 7 ? ~0ull : ((1ull << (8 * (cv1 + 1))) - 1ull)) & ~((1ull << (8 * cv0)) - 1ull);
-              mlo = row & (uint32_t)rows;
-              mhi = row & (uint32_t)(rows >> 32);
-            }
-          }
+          if ((B.meta[j_e] >> (3 + w)) & 1u) block_rect_mask(B.rx[j_e], B.ry[j_e], bu0, bv0, mlo, mhi);
           vid_e = __float_as_uint(B.col[j_e].w);
         }
         while (__ballot((mlo | mhi) != 0u) != 0ull) {
