@@ -114,7 +114,7 @@ size_t svr_workspace_bytes(const svr_scene* scene, const svr_camera* cams, int n
  * written to parts[0 .. min(n_parts, SVR_WS_PARTS) - 1]:
  *   [0] header, tile masks, tile summed-area table, tile ranges, render order
  *       and the backward chunk list of heavy tiles
- *   [1] per (voxel, camera): count, offset, tile rectangle and render record
+ *   [1] per (voxel, camera): count, tile rectangle and render record
  *   [2] scan partial sums
  *   [3] sort keys and values, both buffers of the double-buffered sort
  *   [4] radix-sort digit histograms and look-back status

@@ -160,7 +160,7 @@ int make_layout(const svr_scene* sc, const svr_camera* cams, int n_cams, const s
     return fail(SVR_E_INVALID, "sort key needs %d bits (> 64): too many tiles for max_level %d",
                 l.key_bits, l.L);
   l.passes = (l.key_bits + 7) / 8;
-  l.scan_blocks = (l.NV + kScanTile - 1) / kScanTile;
+  l.scan_blocks = (l.NV + kBlock - 1) / kBlock;  // one partial per project/emit workgroup
   l.sort_parts = (l.cap + kSortPart - 1) / kSortPart;
   size_t off = 0;
   auto take = [&](size_t bytes) {
@@ -170,7 +170,6 @@ int make_layout(const svr_scene* sc, const svr_camera* cams, int n_cams, const s
   };
   l.hdr = take(sizeof(WsHeader));
   l.count = take((size_t)l.NV * 4);
-  l.offset = take((size_t)l.NV * 8);
   l.rect = take((size_t)l.NV * 8);
   l.rec = take((size_t)l.NV * sizeof(VoxRec));
   l.scan_part = take((size_t)(l.scan_blocks > 0 ? l.scan_blocks : 1) * 8);

@@ -81,7 +81,7 @@ struct Layout {
   int32_t tile, tshift, persistent;
   int64_t scan_blocks, sort_parts;
   // byte offsets into the workspace
-  size_t hdr, count, offset, rect, rec, scan_part;
+  size_t hdr, count, rect, rec, scan_part;
   size_t tile_mask, tile_sat, tile_range, tile_order, tile_rank;
   size_t split_base, split_items, ckpt;  // backward chunks of heavy tiles
   size_t ckpt_aux;                       // the same for depth and normal

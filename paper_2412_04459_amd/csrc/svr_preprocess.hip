@@ -288,13 +288,41 @@ __device__ __forceinline__ uint32_t sat_rect(const uint32_t* __restrict__ S, int
          S[ty0 * W1 + tx0];
 }
 
+__device__ __forceinline__ unsigned long long wave_incl_scan(unsigned long long v) {
+  const int lane = threadIdx.x & 63;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    unsigned long long t = __shfl_up(v, d, 64);
+    if (lane >= d) v += t;
+  }
+  return v;
+}
+
+__device__ __forceinline__ unsigned long long block_excl_scan(unsigned long long v,
+                                                              unsigned long long& excl) {
+  __shared__ unsigned long long wsum[kBlock / 64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  unsigned long long inc = wave_incl_scan(v);
+  if (lane == 63) wsum[w] = inc;
+  __syncthreads();
+  unsigned long long base = 0, tot = 0;
+#pragma unroll
+  for (int i = 0; i < kBlock / 64; ++i) {
+    if (i < w) base += wsum[i];
+    tot += wsum[i];
+  }
+  excl = base + inc - v;
+  __syncthreads();
+  return tot;
+}
+
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_project(
     int64_t NV, int n_cams, CamSet cams, const float* __restrict__ center,
     const float* __restrict__ size, const int32_t* __restrict__ vox_grid,
     const float* __restrict__ grid_raw, const float* __restrict__ sh, int64_t N,
     const uint32_t* __restrict__ sat, uint32_t* __restrict__ count, uint2* __restrict__ rect,
-    VoxRec* __restrict__ rec) {
+    VoxRec* __restrict__ rec, unsigned long long* __restrict__ part) {
   __shared__ float4 shs[D == 3 ? kBlock / 64 : 1][D == 3 ? kShStageVox * kShRow : 1];
   const int64_t vv0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool active = vv0 < NV;
@@ -363,6 +391,12 @@ __global__ __launch_bounds__(kBlock) void k_project(
     }
   }
   if (!active) cnt = 0;
+  {
+    // the workgroup's entry total, for the scan of the offsets
+    unsigned long long ex;
+    const unsigned long long tot = block_excl_scan(cnt, ex);
+    if (threadIdx.x == 0) part[blockIdx.x] = tot;
+  }
   if (active) {
     count[vv] = cnt;
     rect[vv] = cnt == 0 ? make_uint2(1u, 0u)
@@ -446,9 +480,10 @@ hipError_t launch_project(const svr_scene& sc, const CamSet& cams, const Layout&
   auto* count = at<uint32_t>(ws, L.count);
   auto* rect = at<uint2>(ws, L.rect);
   auto* rec = at<VoxRec>(ws, L.rec);
+  auto* part = at<unsigned long long>(ws, L.scan_part);
 #define SVR_PROJ(D)                                                                             \
   SVR_LAUNCH("project", k_project<D>, grid, dim3(kBlock), 0, s, L.NV, L.n_cams, cams, sc.center, \
-                     sc.size, sc.vox_grid, sc.grid_raw, sc.sh, L.N, sat, count, rect, rec)
+                     sc.size, sc.vox_grid, sc.grid_raw, sc.sh, L.N, sat, count, rect, rec, part)
   switch (sc.sh_degree) {
     case 0: SVR_PROJ(0); break;
     case 1: SVR_PROJ(1); break;
@@ -462,58 +497,31 @@ hipError_t launch_project(const svr_scene& sc, const CamSet& cams, const Layout&
 // ---------------------------------------------------------------------------
 // exclusive scan of the per view-voxel counts into 64-bit offsets
 
-__device__ __forceinline__ unsigned long long wave_incl_scan(unsigned long long v) {
-  const int lane = threadIdx.x & 63;
-#pragma unroll
-  for (int d = 1; d < 64; d <<= 1) {
-    unsigned long long t = __shfl_up(v, d, 64);
-    if (lane >= d) v += t;
-  }
-  return v;
-}
 
 // block-wide exclusive scan of one value per thread; returns the block total
-__device__ __forceinline__ unsigned long long block_excl_scan(unsigned long long v,
-                                                              unsigned long long& excl) {
-  __shared__ unsigned long long wsum[kBlock / 64];
-  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-  unsigned long long inc = wave_incl_scan(v);
-  if (lane == 63) wsum[w] = inc;
-  __syncthreads();
-  unsigned long long base = 0, tot = 0;
-#pragma unroll
-  for (int i = 0; i < kBlock / 64; ++i) {
-    if (i < w) base += wsum[i];
-    tot += wsum[i];
-  }
-  excl = base + inc - v;
-  __syncthreads();
-  return tot;
-}
 
-__global__ __launch_bounds__(kBlock) void k_scan_reduce(const uint32_t* __restrict__ cnt, int64_t n,
-                                                        unsigned long long* __restrict__ part) {
-  const int64_t base = (int64_t)blockIdx.x * kScanTile;
-  unsigned long long acc = 0;
-#pragma unroll
-  for (int i = 0; i < kScanItems; ++i) {
-    int64_t j = base + i * kBlock + threadIdx.x;
-    if (j < n) acc += cnt[j];
-  }
-  unsigned long long ex;
-  unsigned long long tot = block_excl_scan(acc, ex);
-  if (threadIdx.x == 0) part[blockIdx.x] = tot;
-}
-
+// exclusive scan of the per-workgroup entry totals (in place), kScanItems
+// consecutive totals per thread and round; the grand total is the entry count
 __global__ __launch_bounds__(kBlock) void k_scan_top(unsigned long long* __restrict__ part, int64_t nb,
                                                      WsHeader* __restrict__ hdr) {
   unsigned long long carry = 0;
-  for (int64_t b0 = 0; b0 < nb; b0 += kBlock) {
-    int64_t j = b0 + threadIdx.x;
-    unsigned long long v = j < nb ? part[j] : 0ull;
+  for (int64_t b0 = 0; b0 < nb; b0 += kScanTile) {
+    const int64_t j0 = b0 + (int64_t)threadIdx.x * kScanItems;
+    unsigned long long v[kScanItems];
+    unsigned long long acc = 0;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+      v[i] = j0 + i < nb ? part[j0 + i] : 0ull;
+      acc += v[i];
+    }
     unsigned long long ex;
-    unsigned long long tot = block_excl_scan(v, ex);
-    if (j < nb) part[j] = carry + ex;
+    const unsigned long long tot = block_excl_scan(acc, ex);
+    ex += carry;
+#pragma unroll
+    for (int i = 0; i < kScanItems; ++i) {
+      if (j0 + i < nb) part[j0 + i] = ex;
+      ex += v[i];
+    }
     carry += tot;
   }
   if (threadIdx.x == 0) {
@@ -522,38 +530,10 @@ __global__ __launch_bounds__(kBlock) void k_scan_top(unsigned long long* __restr
   }
 }
 
-__global__ __launch_bounds__(kBlock) void k_scan_down(const uint32_t* __restrict__ cnt, int64_t n,
-                                                      const unsigned long long* __restrict__ part,
-                                                      unsigned long long* __restrict__ off) {
-  const int64_t base = (int64_t)blockIdx.x * kScanTile + (int64_t)threadIdx.x * kScanItems;
-  uint32_t v[kScanItems];
-  unsigned long long acc = 0;
-#pragma unroll
-  for (int i = 0; i < kScanItems; ++i) {
-    v[i] = (base + i < n) ? cnt[base + i] : 0u;
-    acc += v[i];
-  }
-  unsigned long long ex;
-  block_excl_scan(acc, ex);
-  ex += part[blockIdx.x];
-#pragma unroll
-  for (int i = 0; i < kScanItems; ++i) {
-    if (base + i < n) off[base + i] = ex;
-    ex += v[i];
-  }
-}
-
 hipError_t launch_scan(const Layout& L, void* ws, hipStream_t s) {
-  auto* cnt = at<uint32_t>(ws, L.count);
   auto* part = at<unsigned long long>(ws, L.scan_part);
-  auto* off = at<unsigned long long>(ws, L.offset);
   auto* hdr = at<WsHeader>(ws, L.hdr);
-  const int64_t nb = L.scan_blocks;
-  if (nb > 0)
-    SVR_LAUNCH("scan_reduce", k_scan_reduce, dim3((unsigned)nb), dim3(kBlock), 0, s, cnt, L.NV, part);
-  SVR_LAUNCH("scan_top", k_scan_top, dim3(1), dim3(kBlock), 0, s, part, nb, hdr);
-  if (nb > 0)
-    SVR_LAUNCH("scan_down", k_scan_down, dim3((unsigned)nb), dim3(kBlock), 0, s, cnt, L.NV, part, off);
+  SVR_LAUNCH("scan_top", k_scan_top, dim3(1), dim3(kBlock), 0, s, part, L.scan_blocks, hdr);
   return hipGetLastError();
 }
 
@@ -618,28 +598,35 @@ __device__ __forceinline__ void emit_tile(const EmitCtx& e, int gt, uint32_t m,
 
 __global__ __launch_bounds__(kBlock) void k_emit(
     int64_t NV, int n_cams, CamSet cams, const uint64_t* __restrict__ octpath,
-    const uint32_t* __restrict__ count, const unsigned long long* __restrict__ off,
+    const uint32_t* __restrict__ count, const unsigned long long* __restrict__ part,
     const uint2* __restrict__ rect, const uint8_t* __restrict__ mask,
     const uint32_t* __restrict__ sat, int L, int key_low, const uint32_t* __restrict__ rank,
     int64_t cap, uint64_t* __restrict__ keys, uint32_t* __restrict__ vals,
     WsHeader* __restrict__ hdr) {
   __shared__ int s_nbig;
   __shared__ int64_t s_big[kBlock];
+  __shared__ unsigned long long s_big_off[kBlock];
   if (threadIdx.x == 0) s_nbig = 0;
-  __syncthreads();
   const int64_t vv = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t cnt = vv < NV ? count[vv] : 0u;
+  // first output position: the workgroup's prefix plus the counts before
+  // this thread in the workgroup
+  unsigned long long off_vv;
+  block_excl_scan(cnt, off_vv);
+  off_vv += part[blockIdx.x];
   const int sh = key_low;
   const uint64_t rep = ((1ull << (3 * L)) - 1ull) / 7ull;  // 001 001 ... 001 (L triplets)
   if (cnt > 0) {
-    if (off[vv] + cnt > (unsigned long long)cap) atomicOr(&hdr->overflow, 1u);
+    if (off_vv + cnt > (unsigned long long)cap) atomicOr(&hdr->overflow, 1u);
     if (cnt > kBigEmit) {
-      s_big[atomicAdd(&s_nbig, 1)] = vv;
+      const int q = atomicAdd(&s_nbig, 1);
+      s_big[q] = vv;
+      s_big_off[q] = off_vv;
     } else {
       const int64_t vid = vv / n_cams;
       const DevCam& c = cams.c[(int)(vv - vid * n_cams)];
       const EmitCtx e = emit_ctx(octpath, rank, vid, L, rep, sh);
-      unsigned long long o = off[vv];
+      unsigned long long o = off_vv;
       const uint2 r = rect[vv];
       const int tx0 = (int)(r.x & 0xffffu) >> cams.tshift, tx1 = (int)(r.x >> 16) >> cams.tshift;
       const int ty0 = (int)(r.y & 0xffffu) >> cams.tshift, ty1 = (int)(r.y >> 16) >> cams.tshift;
@@ -667,7 +654,7 @@ __global__ __launch_bounds__(kBlock) void k_emit(
     const int ntiles = wdt * (ty1 - ty0 + 1);
     const uint32_t* S = sat + c.sat_off;
     const int W1 = c.ntx + 1;
-    const unsigned long long o0 = off[bv];
+    const unsigned long long o0 = s_big_off[b];
     for (int jt = threadIdx.x; jt < ntiles; jt += kBlock) {
       const int tx = tx0 + jt % wdt, ty = ty0 + jt / wdt;
       unsigned long long o = o0;
@@ -684,7 +671,7 @@ hipError_t launch_emit(const svr_scene& sc, const CamSet& cams, const Layout& L,
   if (L.NV == 0) return hipSuccess;
   SVR_LAUNCH("emit", k_emit, dim3((unsigned)((L.NV + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
              L.NV, L.n_cams, cams, sc.octpath, at<uint32_t>(ws, L.count),
-             at<unsigned long long>(ws, L.offset), at<uint2>(ws, L.rect),
+             at<unsigned long long>(ws, L.scan_part), at<uint2>(ws, L.rect),
              at<uint8_t>(ws, L.tile_mask), at<uint32_t>(ws, L.tile_sat), L.L, L.key_low,
              sc.order_rank, L.cap,
              at<uint64_t>(ws, L.keys0), at<uint32_t>(ws, L.vals0), at<WsHeader>(ws, L.hdr));

@@ -147,9 +147,11 @@ def test_workspace_parts_sum_to_total():
         assert sum(parts.values()) == _abi.svr_workspace_bytes(sc, cams, n_cams, o)
         # keys (8 B) + values (4 B), two buffers, 256-byte aligned each
         assert 24 * 70000 <= parts["keys_values_x2"] <= 24 * 70000 + 4 * 256
-        # count, offset, rect (4 + 8 + 8 B) and a 64-byte record per (voxel, camera)
+        # count, rect (4 + 8 B) and a 64-byte record per (voxel, camera)
         nv = 5000 * n_cams
-        assert 84 * nv <= parts["per_voxel_camera_records"] <= 84 * nv + 4 * 256
+        assert 76 * nv <= parts["per_voxel_camera_records"] <= 76 * nv + 3 * 256
+        # one 8-byte partial entry total per 256 (voxel, camera) pairs
+        assert 8 * ((nv + 255) // 256) <= parts["scan_partials"] <= 8 * ((nv + 255) // 256) + 256
         # 8 B per pixel, plus two 16 B checkpoints (colour, depth and normal)
         # per pixel of a 16x16 tile for each possible backward chunk
         # (capacity / 256 + 1)
