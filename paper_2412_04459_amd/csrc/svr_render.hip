@@ -153,7 +153,8 @@ template <int TS, int NB>
 __device__ __forceinline__ void stage_entry(LdsBatch<NB>& B, int slot, uint32_t val, int ci,
                                             int n_cams, const DevCam& c,
                                             const VoxRec* __restrict__ rec,
-                                            const uint2* __restrict__ rect, int qu0, int qv0) {
+                                            const uint2* __restrict__ rect, int qu0, int qv0,
+                                            double (*hi)[NB] = nullptr) {
   using G = TileGeom<TS>;
   const uint32_t vid = val & kVidMask;
   const int64_t vv = (int64_t)vid * n_cams + ci;
@@ -168,10 +169,19 @@ __device__ __forceinline__ void stage_entry(LdsBatch<NB>& B, int slot, uint32_t 
     if (u0 <= a0 + 7 && u1 >= a0 && v0 <= b0 + 7 && v1 >= b0) qm |= 1u << q;
   }
   const double h = 0.5 * (double)R.q0.w;
-  B.lo[0][slot] = ((double)R.q0.x - h) - c.od[0];
-  B.lo[1][slot] = ((double)R.q0.y - h) - c.od[1];
-  B.lo[2][slot] = ((double)R.q0.z - h) - c.od[2];
+  const double lx = ((double)R.q0.x - h) - c.od[0];
+  const double ly = ((double)R.q0.y - h) - c.od[1];
+  const double lz = ((double)R.q0.z - h) - c.od[2];
+  B.lo[0][slot] = lx;
+  B.lo[1][slot] = ly;
+  B.lo[2][slot] = lz;
   B.edge[slot] = R.q0.w;
+  if (hi) {
+    const double e = (double)R.q0.w;
+    hi[0][slot] = lx + e;
+    hi[1][slot] = ly + e;
+    hi[2][slot] = lz + e;
+  }
   B.isz[slot] = 1.f / R.q0.w;
   B.V[0][slot] = R.q1.x; B.V[1][slot] = R.q1.y; B.V[2][slot] = R.q1.z; B.V[3][slot] = R.q1.w;
   B.V[4][slot] = R.q2.x; B.V[5][slot] = R.q2.y; B.V[6][slot] = R.q2.z; B.V[7][slot] = R.q2.w;
@@ -192,6 +202,19 @@ __device__ __forceinline__ bool slab(const LdsBatch<NB>& B, int j, double idx, d
   const double t0x = lx * idx, t1x = (lx + e) * idx;
   const double t0y = ly * idy, t1y = (ly + e) * idy;
   const double t0z = lz * idz, t1z = (lz + e) * idz;
+  a = fmax(fmax(fmin(t0x, t1x), fmin(t0y, t1y)), fmin(t0z, t1z));
+  b = fmin(fmin(fmax(t0x, t1x), fmax(t0y, t1y)), fmax(t0z, t1z));
+  return (a <= b) && (a > 0.0);
+}
+
+// the same test with the box max staged as well (min + edge, formed as in
+// slab, so both passes take the same decisions)
+template <int NB>
+__device__ __forceinline__ bool slab_hi(const LdsBatch<NB>& B, const double (&hi)[3][NB], int j,
+                                        double idx, double idy, double idz, double& a, double& b) {
+  const double t0x = B.lo[0][j] * idx, t1x = hi[0][j] * idx;
+  const double t0y = B.lo[1][j] * idy, t1y = hi[1][j] * idy;
+  const double t0z = B.lo[2][j] * idz, t1z = hi[2][j] * idz;
   a = fmax(fmax(fmin(t0x, t1x), fmin(t0y, t1y)), fmin(t0z, t1z));
   b = fmin(fmin(fmax(t0x, t1x), fmax(t0y, t1y)), fmax(t0z, t1z));
   return (a <= b) && (a > 0.0);
@@ -275,6 +298,47 @@ __device__ __forceinline__ float segment_x(const LdsBatch<NB>& B, int j, double 
     }
   }
   return x * ((float)lseg / (float)K);
+}
+
+// Backward form of segment_x for a compile-time K: the optical depth, and
+// per sample its local coordinate and act'(v_k), so that the corner
+// gradients f sum_k act'(v_k) w_m(q_k) can be formed once f = dL/dx (l/K) is
+// known, with f folded into each sample's factor
+template <int KT, int ACT, int NB>
+__device__ __forceinline__ float segment_samples(const LdsBatch<NB>& B, int j, double dx, double dy,
+                                                 double dz, double a, double lseg, float (&q)[KT][3],
+                                                 float (&dk)[KT]) {
+  const double step = 1.0 / (double)KT;
+  float x = 0.f;
+#pragma unroll
+  for (int k = 0; k < KT; ++k) {
+    const double t = fma(((double)k + 0.5) * step, lseg, a);
+    local_coord(B, j, t, dx, dy, dz, q[k][0], q[k][1], q[k][2]);
+    const float vk = trilerp(B, j, q[k][0], q[k][1], q[k][2]);
+    x += act_f<ACT>(vk);
+    dk[k] = act_df<ACT>(vk);
+  }
+  return x * ((float)lseg / (float)KT);
+}
+
+// g[m] = sum_k f dk_k w_m(q_k) for the 8 corners (trilinear weights w_m)
+template <int KT>
+__device__ __forceinline__ void corner_grads(const float (&q)[KT][3], const float (&dk)[KT], float f,
+                                             float (&g)[16]) {
+#pragma unroll
+  for (int m = 0; m < 8; ++m) g[m] = 0.f;
+#pragma unroll
+  for (int k = 0; k < KT; ++k) {
+    const float fk = f * dk[k];
+    const float qx = q[k][0], qy = q[k][1], qz = q[k][2];
+    const float px = 1.f - qx, py = 1.f - qy, pz = 1.f - qz;
+    const float bx0 = fk * px, bx1 = fk * qx;
+    const float a00 = bx0 * py, a01 = bx0 * qy, a10 = bx1 * py, a11 = bx1 * qy;
+    g[0] = __fmaf_rn(a00, pz, g[0]); g[1] = __fmaf_rn(a00, qz, g[1]);
+    g[2] = __fmaf_rn(a01, pz, g[2]); g[3] = __fmaf_rn(a01, qz, g[3]);
+    g[4] = __fmaf_rn(a10, pz, g[4]); g[5] = __fmaf_rn(a10, qz, g[5]);
+    g[6] = __fmaf_rn(a11, pz, g[6]); g[7] = __fmaf_rn(a11, qz, g[7]);
+  }
 }
 
 // Voxel normal (Sec. 3.1.1 "Voxel normal"; Supp. details of voxel normal):
@@ -437,6 +501,14 @@ __device__ __forceinline__ double lane_f64(double v, int src) {
 __device__ __forceinline__ uint32_t lane_rank(unsigned long long mask) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
                                    __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// b in the lanes whose bit is set in the wave-uniform mask m, a elsewhere
+// (one v_cndmask with m as its lane mask)
+__device__ __forceinline__ int select_lanes(int a, int b, unsigned long long m) {
+  int r;
+  asm("v_cndmask_b32_e64 %0, %1, %2, %3" : "=v"(r) : "v"(a), "v"(b), "s"(m));
+  return r;
 }
 
 // 64-bit mask of the pixels of the 8x8 block at (bu0, bv0) (bit 8 y + x)
@@ -792,6 +864,7 @@ template <int TS, int KT, int ACT, bool AUX>
 __device__ __forceinline__ void render_tile_bwd(const RenderArgs& A, int g, uint32_t m_lo,
                                                 uint32_t m_hi,
                                                 LdsBatch<TileGeom<TS>::kBatch>& B,
+                                                double (&hi)[3][TileGeom<TS>::kBatch],
                                                 uint32_t& s_lmax) {
   using G = TileGeom<TS>;
   constexpr int NB = G::kBatch;
@@ -863,14 +936,20 @@ __device__ __forceinline__ void render_tile_bwd(const RenderArgs& A, int g, uint
     const uint32_t b0 = bend - min((uint32_t)NB, bend - e_lo);
     const int n = (int)(bend - b0);
     bend = b0;
-    if (tid < n) stage_entry<TS>(B, tid, A.vals[b0 + tid], ci, A.n_cams, c, A.rec, A.rect, qu0, qv0);
+    if (tid < n)
+      stage_entry<TS>(B, tid, A.vals[b0 + tid], ci, A.n_cams, c, A.rec, A.rect, qu0, qv0, hi);
     __syncthreads();
     // one hit: step the pixel's reverse state over staged entry j (hit on
     // [a, bb]) and write its gradients into gv[0..14]
     auto hit_grads = [&](int j, double a, double bb, float (&gv)[16]) {
+      constexpr bool kTwoPhase = KT > 0 && !AUX;
+      constexpr int KQ = KT > 0 ? KT : 1;
       float dw[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+      float qs[KQ][3], dks[KQ];
       const double lseg = bb - a;
-      const float x = segment_x<KT, ACT, true>(B, j, r.dx, r.dy, r.dz, a, lseg, A.K, dw);
+      const float x = kTwoPhase
+                          ? segment_samples<KQ, ACT>(B, j, r.dx, r.dy, r.dz, a, lseg, qs, dks)
+                          : segment_x<KT, ACT, true>(B, j, r.dx, r.dy, r.dz, a, lseg, A.K, dw);
       const float lK = (float)lseg / (float)(KT > 0 ? KT : A.K);
       const float alpha = alpha_of(x);
       tau -= x;
@@ -912,8 +991,12 @@ __device__ __forceinline__ void render_tile_bwd(const RenderArgs& A, int g, uint
       }
       Tnext = Ti;
       const float f = dLdx * lK;
+      if (kTwoPhase) {
+        corner_grads<KQ>(qs, dks, f, gv);
+      } else {
 #pragma unroll
-      for (int m = 0; m < 8; ++m) gv[m] = f * dw[m];
+        for (int m = 0; m < 8; ++m) gv[m] = f * dw[m];
+      }
       if (AUX) {
         const float gt = gD * Ti;
 #pragma unroll
@@ -943,7 +1026,7 @@ __device__ __forceinline__ void render_tile_bwd(const RenderArgs& A, int g, uint
         if (!((meta >> (3 + w)) & 1u)) continue;
         double a = 0.0, bb = 0.0;
         bool hit = (b0 + (uint32_t)j < last) && ((meta & 7u) == r.spat);
-        if (hit) hit = slab(B, j, r.idx, r.idy, r.idz, a, bb);
+        if (hit) hit = slab_hi(B, hi, j, r.idx, r.idy, r.idz, a, bb);
         if (__ballot(hit) == 0ull) continue;
         float gv[16];
 #pragma unroll
@@ -985,9 +1068,10 @@ __device__ __forceinline__ void render_tile_bwd(const RenderArgs& A, int g, uint
           int my = -1;
           for (unsigned long long es = E; es != 0ull; es &= es - 1ull) {
             const int e = __builtin_ctzll(es);
-            const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)mlo, e);
-            const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)mhi, e);
-            if ((((lane < 32 ? lo : hi) >> (lane & 31)) & 1u) != 0u) my = e;
+            const unsigned long long me =
+                ((unsigned long long)(uint32_t)__builtin_amdgcn_readlane((int)mhi, e) << 32) |
+                (uint32_t)__builtin_amdgcn_readlane((int)mlo, e);
+            my = select_lanes(my, e, me);
           }
           if (elig) { mlo = 0u; mhi = 0u; }
           const int j = top - my;
@@ -995,7 +1079,7 @@ __device__ __forceinline__ void render_tile_bwd(const RenderArgs& A, int g, uint
           bool hit = false;
           if (my >= 0) {
             hit = (b0 + (uint32_t)j < last) && ((B.meta[j] & 7u) == r.spat);
-            if (hit) hit = slab(B, j, r.idx, r.idy, r.idz, a, bb);
+            if (hit) hit = slab_hi(B, hi, j, r.idx, r.idy, r.idz, a, bb);
           }
           if (__ballot(hit) == 0ull) continue;
           float gv[16];
@@ -1027,29 +1111,32 @@ __device__ __forceinline__ void render_tile_bwd(const RenderArgs& A, int g, uint
 template <int TS, int KT, int ACT, bool AUX>
 __device__ __forceinline__ void bwd_split_item(const RenderArgs& A, uint32_t k,
                                                LdsBatch<TileGeom<TS>::kBatch>& B,
+                                               double (&hi)[3][TileGeom<TS>::kBatch],
                                                uint32_t& s_lmax) {
   const uint2 it = A.split_items[k];
   if (it.x >= (uint32_t)A.T || A.split_base[it.x] == kNoSplit) return;
   const uint2 rg = A.range[it.x];
   const uint32_t nch = (rg.y - rg.x + kBwdChunk - 1) / kBwdChunk;
   if (it.y + 1 >= nch) return;
-  render_tile_bwd<TS, KT, ACT, AUX>(A, (int)it.x, it.y, it.y + 1, B, s_lmax);
+  render_tile_bwd<TS, KT, ACT, AUX>(A, (int)it.x, it.y, it.y + 1, B, hi, s_lmax);
 }
 
 // a tile's whole range, or its last chunk when the others are chunk items
 template <int TS, int KT, int ACT, bool AUX>
 __device__ __forceinline__ void bwd_tile_rest(const RenderArgs& A, int g,
                                               LdsBatch<TileGeom<TS>::kBatch>& B,
+                                              double (&hi)[3][TileGeom<TS>::kBatch],
                                               uint32_t& s_lmax) {
   const uint2 rg = A.range[g];
   const uint32_t nch = (rg.y - rg.x + kBwdChunk - 1) / kBwdChunk;
   const uint32_t m_lo = (A.split_base[g] == kNoSplit || nch == 0) ? 0u : nch - 1;
-  render_tile_bwd<TS, KT, ACT, AUX>(A, g, m_lo, nch, B, s_lmax);
+  render_tile_bwd<TS, KT, ACT, AUX>(A, g, m_lo, nch, B, hi, s_lmax);
 }
 
 template <int TS, int KT, int ACT, bool AUX>
 __global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderArgs A) {
   __shared__ LdsBatch<TileGeom<TS>::kBatch> B;
+  __shared__ double hi[3][TileGeom<TS>::kBatch];  // staged box max
   __shared__ uint32_t s_lmax;
   __shared__ int s_tile;
   const uint32_t ns = min(*A.split_count, (uint32_t)A.max_split);
@@ -1059,11 +1146,11 @@ __global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderArgs A) {
     const int b = (int)blockIdx.x;
     if (b < A.split_wgs) {
       for (uint32_t k = (uint32_t)b; k < ns; k += (uint32_t)A.split_wgs) {
-        bwd_split_item<TS, KT, ACT, AUX>(A, k, B, s_lmax);
+        bwd_split_item<TS, KT, ACT, AUX>(A, k, B, hi, s_lmax);
         __syncthreads();
       }
     } else if (b - A.split_wgs < A.T) {
-      bwd_tile_rest<TS, KT, ACT, AUX>(A, (int)A.order[b - A.split_wgs], B, s_lmax);
+      bwd_tile_rest<TS, KT, ACT, AUX>(A, (int)A.order[b - A.split_wgs], B, hi, s_lmax);
     }
     return;
   }
@@ -1072,7 +1159,7 @@ __global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderArgs A) {
     __syncthreads();
     const int k = s_tile;
     if (k < 0) break;
-    bwd_split_item<TS, KT, ACT, AUX>(A, (uint32_t)k, B, s_lmax);
+    bwd_split_item<TS, KT, ACT, AUX>(A, (uint32_t)k, B, hi, s_lmax);
     __syncthreads();
   }
   __syncthreads();  // every thread has read the last s_tile before it is reused
@@ -1081,7 +1168,7 @@ __global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderArgs A) {
     __syncthreads();
     const int p = s_tile;
     if (p < 0) break;
-    bwd_tile_rest<TS, KT, ACT, AUX>(A, (int)A.order[p], B, s_lmax);
+    bwd_tile_rest<TS, KT, ACT, AUX>(A, (int)A.order[p], B, hi, s_lmax);
     __syncthreads();
   }
 }
