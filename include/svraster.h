@@ -150,9 +150,10 @@ int svr_preprocess(const svr_scene* scene, const svr_camera* cams, int n_cams,
                    void* stream);
 
 /* Sort the duplicated list by key (ascending; keys are unique whenever
- * max_level <= 15, so the order is fully determined) with an LSD radix sort
- * over the significant key bits, then find each tile's [start, end) range
- * (Sec. 3.1.2 "Sorting voxels").  `n_entries_hint` is E when known (it sizes
+ * max_level <= 15, so the order is fully determined) (Sec. 3.1.2 "Sorting
+ * voxels"): an LSD radix sort over the key's tile bits (entries of one tile
+ * keep their emission order), each tile's [start, end) range, then every
+ * range sorted by the key's low bits (the direction-dependent order).  `n_entries_hint` is E when known (it sizes
  * the launches) or -1 to size them by capacity; the device-side count is
  * authoritative either way.
  * Errors: SVR_E_INVALID, SVR_E_WORKSPACE, SVR_E_HIP.                         */

@@ -159,7 +159,8 @@ int make_layout(const svr_scene* sc, const svr_camera* cams, int n_cams, const s
   if (l.key_bits > 64)
     return fail(SVR_E_INVALID, "sort key needs %d bits (> 64): too many tiles for max_level %d",
                 l.key_bits, l.L);
-  l.passes = (l.key_bits + 7) / 8;
+  // radix passes over the tile bits (the low key bits are sorted per tile)
+  l.passes = (l.key_bits - l.key_low + 7) / 8;
   l.scan_blocks = (l.NV + kBlock - 1) / kBlock;  // one partial per project/emit workgroup
   l.sort_parts = (l.cap + kSortPart - 1) / kSortPart;
   size_t off = 0;
@@ -294,13 +295,21 @@ int svr_sort(const svr_scene* scene, const svr_camera* cams, int n_cams, const s
   const int64_t n_max = (n_entries_hint >= 0 && n_entries_hint < L.cap) ? n_entries_hint : L.cap;
   WsHeader* hdr = at<WsHeader>(ws, L.hdr);
   bool in1 = false;
+  // radix sort by tile (the key bits above key_low), then each tile's range
+  // by the low bits
   SVR_HIP(launch_radix_sort(at<uint64_t>(ws, L.keys0), at<uint32_t>(ws, L.vals0),
                             at<uint64_t>(ws, L.keys1), at<uint32_t>(ws, L.vals1), &hdr->n_entries,
-                            n_max, L.key_bits, at<uint32_t>(ws, L.sort_hist),
+                            n_max, L.key_bits, L.key_low, at<uint32_t>(ws, L.sort_hist),
                             at<uint32_t>(ws, L.sort_status0), at<uint32_t>(ws, L.sort_status1),
                             hdr->tickets, &hdr->error, &in1, s),
           "radix sort");
   SVR_HIP(launch_tile_ranges(L, ws, sorted_keys(L, ws), s), "tile ranges");
+  const bool res1 = (L.passes & 1) != 0;
+  SVR_HIP(launch_tile_sort(L, ws, res1 ? at<uint64_t>(ws, L.keys1) : at<uint64_t>(ws, L.keys0),
+                           res1 ? at<uint32_t>(ws, L.vals1) : at<uint32_t>(ws, L.vals0),
+                           res1 ? at<uint64_t>(ws, L.keys0) : at<uint64_t>(ws, L.keys1),
+                           res1 ? at<uint32_t>(ws, L.vals0) : at<uint32_t>(ws, L.vals1), s),
+          "tile sort");
   return SVR_OK;
 }
 
@@ -411,7 +420,7 @@ int svr_radix_sort_pairs(uint64_t* keys, uint32_t* values, uint64_t* keys_tmp,
   SVR_HIP(launch_fill_u32(base, 0u, 64, s), "clear scratch");
   SVR_HIP(launch_fill_u32(base, (uint32_t)(n & 0xffffffffu), 1, s), "store n");
   bool in1 = false;
-  SVR_HIP(launch_radix_sort(keys, values, keys_tmp, values_tmp, n_dev, n, bits, hist, st0, st1,
+  SVR_HIP(launch_radix_sort(keys, values, keys_tmp, values_tmp, n_dev, n, bits, 0, hist, st0, st1,
                             tickets, err, &in1, s),
           "radix sort");
   if (in1) {

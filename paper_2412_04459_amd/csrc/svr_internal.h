@@ -165,9 +165,11 @@ hipError_t launch_emit(const svr_scene& sc, const CamSet& cams, const Layout& L,
 // sort
 size_t sort_scratch_bytes(int64_t n, int bits, int64_t* parts_out);
 hipError_t launch_radix_sort(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1,
-                             const unsigned long long* n_dev, int64_t n_max, int bits,
+                             const unsigned long long* n_dev, int64_t n_max, int key_bits, int lo,
                              uint32_t* hist, uint32_t* st0, uint32_t* st1, uint32_t* tickets,
                              uint32_t* err, bool* result_in_1, hipStream_t s);
+hipError_t launch_tile_sort(const Layout& L, void* ws, uint64_t* keys, uint32_t* vals, uint64_t* ktmp,
+                            uint32_t* vtmp, hipStream_t s);
 hipError_t launch_tile_ranges(const Layout& L, void* ws, const uint64_t* keys, hipStream_t s);
 size_t order_rank_scratch_bytes(int64_t N, int L);
 hipError_t launch_order_ranks(const uint64_t* octpath, int64_t N, int L, uint32_t* rank,

@@ -14,6 +14,8 @@
 // sort on the tile / Morton key).  Look-back waits are bounded: a workgroup
 // that spins past the limit sets an error bit and finishes, so no launch can
 // hang.
+#include <type_traits>
+
 #include "svr_internal.h"
 
 namespace svr {
@@ -32,9 +34,10 @@ __device__ __forceinline__ unsigned long long lane_mask_lt() {
 }
 
 // ---------------------------------------------------------------------------
+// digit histograms of key bits [lo, lo + bits), 8 bits per pass
 __global__ __launch_bounds__(kBlock) void k_sort_hist(const uint64_t* __restrict__ keys,
                                                       const unsigned long long* __restrict__ n_dev,
-                                                      int64_t n_max, int bits,
+                                                      int64_t n_max, int bits, int lo,
                                                       uint32_t* __restrict__ hist) {
   const int passes = (bits + 7) / 8;
   __shared__ uint32_t h[8 * kRadix];
@@ -46,7 +49,7 @@ __global__ __launch_bounds__(kBlock) void k_sort_hist(const uint64_t* __restrict
     const uint64_t k = keys[i];
     for (int p = 0; p < passes; ++p) {
       const uint32_t dmask = (bits - 8 * p >= 8) ? 255u : ((1u << (bits - 8 * p)) - 1u);
-      atomicAdd(&h[p * kRadix + (int)((k >> (8 * p)) & dmask)], 1u);
+      atomicAdd(&h[p * kRadix + (int)((k >> (lo + 8 * p)) & dmask)], 1u);
     }
   }
   __syncthreads();
@@ -242,9 +245,11 @@ size_t sort_scratch_bytes(int64_t n, int bits, int64_t* parts_out) {
 }
 
 hipError_t launch_radix_sort(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t* v1,
-                             const unsigned long long* n_dev, int64_t n_max, int bits,
+                             const unsigned long long* n_dev, int64_t n_max, int key_bits, int lo,
                              uint32_t* hist, uint32_t* st0, uint32_t* st1, uint32_t* tickets,
                              uint32_t* err, bool* result_in_1, hipStream_t s) {
+  // sort by key bits [lo, key_bits); the order of equal digits is kept
+  const int bits = key_bits > lo ? key_bits - lo : 0;
   const int passes = (bits + 7) / 8;
   *result_in_1 = (passes & 1) != 0;
   if (n_max <= 0 || passes == 0) {
@@ -264,7 +269,7 @@ hipError_t launch_radix_sort(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t*
   if (hb > 256) hb = 256;
   if (hb < 1) hb = 1;
   SVR_LAUNCH("sort_hist", k_sort_hist, dim3((unsigned)hb), dim3(kBlock), 0, s, k0, n_dev, n_max, bits,
-                     hist);
+                     lo, hist);
   SVR_LAUNCH("sort_hist_scan", k_sort_hist_scan, dim3(1), dim3(kRadix), 0, s, hist, passes);
   for (int p = 0; p < passes; ++p) {
     const uint64_t* ki = (p & 1) ? k1 : k0;
@@ -274,8 +279,8 @@ hipError_t launch_radix_sort(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t*
     uint32_t* st = (p & 1) ? st1 : st0;
     uint32_t* stn = (p & 1) ? st0 : st1;
     const uint32_t dmask = (bits - 8 * p >= 8) ? 255u : ((1u << (bits - 8 * p)) - 1u);
-    SVR_LAUNCH("sort_pass", k_sort_pass, dim3((unsigned)parts), dim3(kBlock), 0, s, 8 * p, dmask, ki, vi, ko,
-                       vo, n_dev, n_max, hist + p * kRadix, st, stn, tickets + p, err);
+    SVR_LAUNCH("sort_pass", k_sort_pass, dim3((unsigned)parts), dim3(kBlock), 0, s, lo + 8 * p, dmask, ki,
+                       vi, ko, vo, n_dev, n_max, hist + p * kRadix, st, stn, tickets + p, err);
   }
   return hipGetLastError();
 }
@@ -381,6 +386,272 @@ hipError_t launch_tile_ranges(const Layout& L, void* ws, const uint64_t* keys, h
 }
 
 // ---------------------------------------------------------------------------
+// Order within each tile.  The radix sort orders the entries by tile only
+// (the key's high bits) and keeps the emission order within a tile; these
+// kernels then sort every tile's range [start, end) in place by the key's low
+// bits (the tile bits are equal), which gives exactly the order of a full
+// sort of the keys.  Short ranges take a counting rank, one wave per tile;
+// long ones LSD radix passes over the low key bits, in LDS up to SEG
+// entries, else through the other key/value buffer.  Low key bits are held
+// as K (32 bits when they fit).
+
+
+// tiles of fewer than kSmallSeg entries: one wave each, rank = number of
+// smaller keys in the range.  Order ranks are unique within a tile; 64-bit
+// low keys (at most 3 * 16 + 3 = 51 bits) carry the entry's index in the
+// range below them (kIdxBits), so equal keys keep their order as in a
+// stable sort.
+constexpr int kSmallSeg = 256;
+constexpr int kIdxBits = 13;
+
+template <typename K>
+__device__ __forceinline__ K seg_key(uint64_t key, uint64_t lowmask, int i) {
+  if (sizeof(K) == 8) return (K)(((key & lowmask) << kIdxBits) | (uint64_t)i);
+  return (K)(key & lowmask);
+}
+
+template <typename K>
+__device__ __forceinline__ uint64_t seg_low(K k) {
+  return sizeof(K) == 8 ? (uint64_t)k >> kIdxBits : (uint64_t)k;
+}
+
+template <typename K>
+__global__ __launch_bounds__(kBlock) void k_tile_sort_small(uint64_t* __restrict__ keys,
+                                                            uint32_t* __restrict__ vals,
+                                                            const uint2* __restrict__ range,
+                                                            const uint32_t* __restrict__ order,
+                                                            uint32_t T, int lo_bits) {
+  constexpr int kWaves = kBlock / 64;
+  __shared__ K sk[kWaves][kSmallSeg];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const uint32_t pos = blockIdx.x * kWaves + w;
+  if (pos >= T) return;
+  const uint32_t t = order[pos];
+  if (t >= T) return;
+  const uint2 r = range[t];
+  const int n = (int)(r.y - r.x);
+  if (n <= 1 || n >= kSmallSeg) return;
+  const uint64_t lowmask = lo_bits >= 64 ? ~0ull : ((1ull << lo_bits) - 1ull);
+  const uint64_t high = keys[r.x] & ~lowmask;
+  if (n <= 64) {
+    // one entry per lane; the keys come from the other lanes' registers
+    const bool valid = lane < n;
+    const K k0 = valid ? seg_key<K>(keys[r.x + lane], lowmask, lane) : (K)~(K)0;
+    const uint32_t v0 = valid ? vals[r.x + lane] : 0u;
+    int rank0 = 0;
+    for (int j = 0; j < n; ++j) {
+      K kj;
+      if (sizeof(K) == 8) {
+        const uint64_t u = (uint64_t)k0;
+        kj = (K)(((uint64_t)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(u >> 32), j) << 32) |
+                 (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)u, j));
+      } else {
+        kj = (K)(uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)k0, j);
+      }
+      rank0 += kj < k0 ? 1 : 0;
+    }
+    if (valid) {
+      keys[r.x + rank0] = high | seg_low<K>(k0);
+      vals[r.x + rank0] = v0;
+    }
+    return;
+  }
+  // up to P entries per lane (entry lane + 64 e), each compared with every
+  // key of the range (LDS broadcast reads)
+  auto count_rank = [&](auto per) {
+    constexpr int P = decltype(per)::value;
+    K k[P];
+    uint32_t v[P];
+    int rank[P];
+#pragma unroll
+    for (int e = 0; e < P; ++e) {
+      const int i = lane + 64 * e;
+      k[e] = i < n ? seg_key<K>(keys[r.x + i], lowmask, i) : (K)0;
+      v[e] = i < n ? vals[r.x + i] : 0u;
+      if (i < n) sk[w][i] = k[e];
+      rank[e] = 0;
+    }
+    wave_sync_lds();
+    for (int j = 0; j < n; ++j) {
+      const K kj = sk[w][j];
+#pragma unroll
+      for (int e = 0; e < P; ++e) rank[e] += kj < k[e] ? 1 : 0;
+    }
+#pragma unroll
+    for (int e = 0; e < P; ++e) {
+      if (lane + 64 * e < n) {
+        keys[r.x + rank[e]] = high | seg_low<K>(k[e]);
+        vals[r.x + rank[e]] = v[e];
+      }
+    }
+  };
+  if (n <= 128) count_rank(std::integral_constant<int, 2>());
+  else count_rank(std::integral_constant<int, kSmallSeg / 64>());
+}
+
+
+
+// tiles of kSmallSeg or more entries: they open the render order (heaviest
+// first, bucketed by floor(log2 n)), so the workgroups walk the order from
+// the front, one tile at a time, and stop at the first shorter tile
+// one LSD radix pass (digit (key >> shift) & dmask) of n entries from
+// (ka, va) to (kb, vb), stable, by a workgroup of kBlock threads; base and wc
+// are LDS scratch (base: kRadix words, wc: one kRadix row per wave)
+template <typename KA, typename KB>
+__device__ __forceinline__ void radix_pass_wg(const KA* ka, const uint32_t* va, KB* kb, uint32_t* vb,
+                                              int n, int shift, uint32_t dmask, uint32_t* base,
+                                              uint32_t (*wc)[kRadix]) {
+  constexpr int kWaves = kBlock / 64;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const unsigned long long lt = (1ull << lane) - 1ull;
+  // digit counts, then their exclusive scan
+  base[tid] = 0u;
+  __syncthreads();
+  for (int i = tid; i < n; i += kBlock) atomicAdd(&base[(uint32_t)((uint64_t)ka[i] >> shift) & dmask], 1u);
+  __syncthreads();
+  {
+    const uint32_t v = base[tid];
+    uint32_t inc = v;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t u = __shfl_up(inc, d, 64);
+      if (lane >= d) inc += u;
+    }
+    if (lane == 63) wc[w][0] = inc;
+    __syncthreads();
+    uint32_t wb = 0;
+    for (int i = 0; i < w; ++i) wb += wc[i][0];
+    __syncthreads();
+    base[tid] = wb + inc - v;
+#pragma unroll
+    for (int i = 0; i < kWaves; ++i) wc[i][tid] = 0u;
+    __syncthreads();
+  }
+  // stable scatter, kBlock entries at a time in index order
+  for (int c0 = 0; c0 < n; c0 += kBlock) {
+    const int i = c0 + tid;
+    const bool valid = i < n;
+    const KA kk = valid ? ka[i] : (KA)0;
+    const uint32_t v = valid ? va[i] : 0u;
+    const uint32_t d = (uint32_t)((uint64_t)kk >> shift) & dmask;
+    unsigned long long peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const bool bit = (d >> b) & 1u;
+      const unsigned long long bb = __ballot(bit);
+      peers &= bit ? bb : ~bb;
+    }
+    const uint32_t below = (uint32_t)__popcll(peers & lt);
+    if (valid && below == 0) wc[w][d] = (uint32_t)__popcll(peers);
+    __syncthreads();
+    if (valid) {
+      uint32_t off = base[d] + below;
+      for (int q = 0; q < w; ++q) off += wc[q][d];
+      kb[off] = (KB)kk;
+      vb[off] = v;
+    }
+    __syncthreads();
+    uint32_t add = 0;
+#pragma unroll
+    for (int q = 0; q < kWaves; ++q) {
+      add += wc[q][tid];
+      wc[q][tid] = 0u;
+    }
+    base[tid] += add;
+    __syncthreads();
+  }
+}
+
+// tiles of kSmallSeg or more entries: they open the render order (heaviest
+// first, bucketed by floor(log2 n)), so the workgroups walk the order from
+// the front, one tile at a time, and stop at the first shorter tile.  Up to
+// SEG entries: LSD radix passes in LDS (ping-pong); longer: the same passes
+// through the other key/value buffer.
+template <typename K, int SEG>
+__global__ __launch_bounds__(kBlock) void k_tile_sort_big(uint64_t* __restrict__ keys,
+                                                          uint32_t* __restrict__ vals,
+                                                          uint64_t* __restrict__ ktmp,
+                                                          uint32_t* __restrict__ vtmp,
+                                                          const uint2* __restrict__ range,
+                                                          const uint32_t* __restrict__ order,
+                                                          uint32_t T, int lo_bits) {
+  constexpr int kWaves = kBlock / 64;
+  __shared__ K sk[2][SEG];
+  __shared__ uint32_t sv[2][SEG];
+  __shared__ uint32_t base[kRadix];
+  __shared__ uint32_t wc[kWaves][kRadix];
+  const int tid = threadIdx.x;
+  const uint64_t lowmask = lo_bits >= 64 ? ~0ull : ((1ull << lo_bits) - 1ull);
+  const int passes = (lo_bits + 7) / 8;
+  for (uint32_t pos = blockIdx.x; pos < T; pos += gridDim.x) {
+    const uint32_t t = order[pos];
+    if (t >= T) break;
+    const uint2 r = range[t];
+    const int n = (int)(r.y - r.x);
+    if (n < kSmallSeg) break;  // every later tile is shorter too
+    if (n <= SEG) {
+      const uint64_t high = keys[r.x] & ~lowmask;
+      for (int i = tid; i < n; i += kBlock) {
+        sk[0][i] = (K)(keys[r.x + i] & lowmask);
+        sv[0][i] = vals[r.x + i];
+      }
+      for (int p = 0; p < passes; ++p) {
+        const uint32_t dmask = (lo_bits - 8 * p >= 8) ? 255u : ((1u << (lo_bits - 8 * p)) - 1u);
+        radix_pass_wg(sk[p & 1], sv[p & 1], sk[(p + 1) & 1], sv[(p + 1) & 1], n, 8 * p, dmask, base,
+                      wc);
+      }
+      for (int i = tid; i < n; i += kBlock) {
+        keys[r.x + i] = high | (uint64_t)sk[passes & 1][i];
+        vals[r.x + i] = sv[passes & 1][i];
+      }
+      __syncthreads();
+      continue;
+    }
+    // long range: the passes through the other key/value buffer
+    uint64_t* ks = keys + r.x;
+    uint32_t* vs = vals + r.x;
+    uint64_t* kd = ktmp + r.x;
+    uint32_t* vd = vtmp + r.x;
+    for (int p = 0; p < passes; ++p) {
+      const uint32_t dmask = (lo_bits - 8 * p >= 8) ? 255u : ((1u << (lo_bits - 8 * p)) - 1u);
+      radix_pass_wg(ks, vs, kd, vd, n, 8 * p, dmask, base, wc);
+      uint64_t* tk = ks; ks = kd; kd = tk;
+      uint32_t* tv = vs; vs = vd; vd = tv;
+    }
+    if (passes & 1) {
+      for (int i = tid; i < n; i += kBlock) {
+        keys[r.x + i] = ks[i];
+        vals[r.x + i] = vs[i];
+      }
+    }
+    __syncthreads();
+  }
+}
+
+hipError_t launch_tile_sort(const Layout& L, void* ws, uint64_t* keys, uint32_t* vals, uint64_t* ktmp,
+                            uint32_t* vtmp, hipStream_t s) {
+  if (L.T == 0) return hipSuccess;
+  const uint2* range = at<uint2>(ws, L.tile_range);
+  const uint32_t* order = at<uint32_t>(ws, L.tile_order);
+  const dim3 small_grid((unsigned)((L.T + kBlock / 64 - 1) / (kBlock / 64)));
+  // at most cap / kSmallSeg tiles are long; a few workgroups per CU
+  const int64_t nbig = min((int64_t)L.T, min(L.cap / kSmallSeg + 1, (int64_t)2048));
+  const dim3 big_grid((unsigned)nbig);
+  if (L.key_low <= 32) {
+    SVR_LAUNCH("tile_sort_small", k_tile_sort_small<uint32_t>, small_grid, dim3(kBlock), 0, s, keys, vals,
+               range, order, (uint32_t)L.T, L.key_low);
+    SVR_LAUNCH("tile_sort_big", (k_tile_sort_big<uint32_t, 2048>), big_grid, dim3(kBlock), 0, s, keys,
+               vals, ktmp, vtmp, range, order, (uint32_t)L.T, L.key_low);
+  } else {
+    SVR_LAUNCH("tile_sort_small", k_tile_sort_small<uint64_t>, small_grid, dim3(kBlock), 0, s, keys, vals,
+               range, order, (uint32_t)L.T, L.key_low);
+    SVR_LAUNCH("tile_sort_big", (k_tile_sort_big<uint64_t, 1024>), big_grid, dim3(kBlock), 0, s, keys,
+               vals, ktmp, vtmp, range, order, (uint32_t)L.T, L.key_low);
+  }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
 // corner adjacency of the grid points: sort (grid index, corner slot) pairs by
 // grid index (stable, so slots stay increasing), then mark where each grid
 // point's run starts
@@ -429,7 +700,7 @@ hipError_t launch_grid_adjacency(const int32_t* vox_grid, int64_t N, int64_t M, 
   const unsigned grid = (unsigned)((n8 + kBlock - 1) / kBlock);
   SVR_LAUNCH("adj_pairs", k_adj_pairs, dim3(grid), dim3(kBlock), 0, s, vox_grid, n8, k0, v0);
   bool in1 = false;
-  if ((e = launch_radix_sort(k0, v0, k1, v1, n_dev, n8, bits, hist, st0, st1, base + 2, base + 18,
+  if ((e = launch_radix_sort(k0, v0, k1, v1, n_dev, n8, bits, 0, hist, st0, st1, base + 2, base + 18,
                              &in1, s)) != hipSuccess)
     return e;
   const uint64_t* ks = in1 ? k1 : k0;
@@ -501,7 +772,7 @@ hipError_t launch_order_ranks(const uint64_t* octpath, int64_t N, int L, uint32_
   const unsigned grid = (unsigned)((n8 + kBlock - 1) / kBlock);
   SVR_LAUNCH("rank_keys", k_rank_keys, dim3(grid), dim3(kBlock), 0, s, octpath, n8, L, k0, v0);
   bool in1 = false;
-  if ((e = launch_radix_sort(k0, v0, k1, v1, n_dev, n8, bits, hist, st0, st1, base + 2, base + 18,
+  if ((e = launch_radix_sort(k0, v0, k1, v1, n_dev, n8, bits, 0, hist, st0, st1, base + 2, base + 18,
                              &in1, s)) != hipSuccess)
     return e;
   SVR_LAUNCH("rank_scatter", k_rank_scatter, dim3(grid), dim3(kBlock), 0, s, in1 ? v1 : v0, n8,

@@ -107,7 +107,18 @@ def _key_cases():
             ("spheres_plane", lambda: (S.spheres_plane_scene(), [S.spheres_plane_camera()])),
             ("tiny_multisign", lambda: (S.tiny_random_scene(4, max_level=4),
                                         [S.look_at(90, 70, 100.0, [0.5, 0.45, 0.55],
-                                                   target=(0.9, 0.8, 0.7))]))]
+                                                   target=(0.9, 0.8, 0.7))])),
+            # a single 16x16 tile over a dense 32^3 block of voxels: ~16k
+            # entries in one range, past the in-LDS sort of a tile's range
+            ("one_tile", lambda: (_dense_cube(5), [S.look_at(16, 16, 20.0, [1.9, 1.7, 1.5],
+                                                             target=(0.5, 0.5, 0.5))]))]
+
+
+def _dense_cube(level):
+    """Every voxel of level `level` in the unit cube (zero densities)."""
+    n = 1 << level
+    g = np.stack(np.meshgrid(np.arange(n), np.arange(n), np.arange(n), indexing="ij"), -1).reshape(-1, 3)
+    return S.scene_from_voxels((0.5, 0.5, 0.5), 1.0, level, g, np.full(len(g), level))
 
 
 def _cpu_order_ranks(scene):
@@ -151,7 +162,8 @@ def _check_sorted_list(scene, cam, gk, gv, ranks):
 
 
 @pytest.mark.parametrize("name,ranks", [(c[0], True) for c in _key_cases()] + [("shell", False),
-                                                                             ("tiny_multisign", False)])
+                                                                             ("tiny_multisign", False),
+                                                                             ("one_tile", False)])
 def test_sorted_entries_bit_exact(torch_dev, name, ranks):
     torch = torch_dev
     make = dict(_key_cases())[name]
@@ -163,6 +175,8 @@ def test_sorted_entries_bit_exact(torch_dev, name, ranks):
     E = rast.n_entries
     keys, vals = rast.sorted_entries(E)
     assert rast.check_overflow() == E
+    if name == "one_tile":
+        assert E > 2048  # the range is sorted by the radix fallback
     _check_sorted_list(scene, cams[0], keys.cpu().numpy().view(np.uint64),
                        vals.cpu().numpy().view(np.uint32), ranks)
 
