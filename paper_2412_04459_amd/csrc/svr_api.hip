@@ -264,8 +264,8 @@ int svr_preprocess(const svr_scene* scene, const svr_camera* cams, int n_cams,
   if (st != SVR_OK) return st;
   if ((st = check_ws(L, ws, ws_bytes)) != SVR_OK) return st;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  SVR_HIP(launch_fill_u32(at<uint32_t>(ws, L.hdr), 0u, sizeof(WsHeader) / 4, s), "clear header");
-  SVR_HIP(launch_tile_masks(cs, at<uint8_t>(ws, L.tile_mask), s), "tile masks");
+  SVR_HIP(launch_tile_masks(cs, at<uint8_t>(ws, L.tile_mask), at<uint2>(ws, L.tile_range), s),
+          "tile masks");
   SVR_HIP(launch_tile_sat(cs, at<uint8_t>(ws, L.tile_mask), at<uint32_t>(ws, L.tile_sat), s),
           "tile table");
   SVR_HIP(launch_project(*scene, cs, L, ws, s), "project");

@@ -155,7 +155,7 @@ struct FillSet {
   void add(uint32_t* ptr, int64_t count);
 };
 hipError_t launch_zero_u32(const FillSet& f, hipStream_t s);
-hipError_t launch_tile_masks(const CamSet& cams, uint8_t* mask, hipStream_t s);
+hipError_t launch_tile_masks(const CamSet& cams, uint8_t* mask, uint2* range, hipStream_t s);
 hipError_t launch_tile_sat(const CamSet& cams, const uint8_t* mask, uint32_t* sat, hipStream_t s);
 hipError_t launch_project(const svr_scene& sc, const CamSet& cams, const Layout& L, void* ws,
                           hipStream_t s);

@@ -80,7 +80,8 @@ __device__ __forceinline__ int find_cam(const CamSet& cams, int gtile) {
 // Per tile, the OR of 1 << sign_bits over its in-image pixel centres.  A
 // workgroup covers kBlock pixels: 4 tiles of 8x8, one of 16x16, or one of
 // 32x32 with 4 pixels per thread.
-__global__ __launch_bounds__(kBlock) void k_tile_masks(CamSet cams, uint8_t* __restrict__ mask) {
+__global__ __launch_bounds__(kBlock) void k_tile_masks(CamSet cams, uint8_t* __restrict__ mask,
+                                                       uint2* __restrict__ range) {
   __shared__ uint32_t m[4];
   const int ts = cams.tile;
   const int tiles_per_wg = ts == 8 ? 4 : 1;
@@ -110,14 +111,17 @@ __global__ __launch_bounds__(kBlock) void k_tile_masks(CamSet cams, uint8_t* __r
   __syncthreads();
   if (threadIdx.x < (unsigned)tiles_per_wg) {
     const int gt = (int)blockIdx.x * tiles_per_wg + (int)threadIdx.x;
-    if (gt < cams.total_tiles) mask[gt] = (uint8_t)m[threadIdx.x];
+    if (gt < cams.total_tiles) {
+      mask[gt] = (uint8_t)m[threadIdx.x];
+      range[gt] = make_uint2(0u, 0u);  // tiles without entries keep an empty range
+    }
   }
 }
 
-hipError_t launch_tile_masks(const CamSet& cams, uint8_t* mask, hipStream_t s) {
+hipError_t launch_tile_masks(const CamSet& cams, uint8_t* mask, uint2* range, hipStream_t s) {
   const int per = cams.tile == 8 ? 4 : 1;
   SVR_LAUNCH("tile_masks", k_tile_masks, dim3((cams.total_tiles + per - 1) / per), dim3(kBlock), 0,
-             s, cams, mask);
+             s, cams, mask, range);
   return hipGetLastError();
 }
 
@@ -420,7 +424,12 @@ __global__ __launch_bounds__(kBlock) void k_project(
     float4* S = shs[w];
     for (int64_t vb = vlo; vb <= vhi; vb += kShStageVox) {
       const int nv = (int)min((int64_t)kShStageVox, vhi - vb + 1);
-      for (int q = lane; q < nv * 12; q += 64) S[(q / 12) * kShRow + q % 12] = sh4[vb * 12 + q];
+      // with one camera, lane L holds voxel vlo + L: rows of voxels that
+      // emit nothing are not read
+      const unsigned long long rows =
+          n_cams == 1 ? (needm >> (vb - vlo)) : ~0ull;
+      for (int q = lane; q < nv * 12; q += 64)
+        if ((rows >> (q / 12)) & 1ull) S[(q / 12) * kShRow + q % 12] = sh4[vb * 12 + q];
       wave_sync_lds();
       if (need && vid >= vb && vid < vb + nv)
         sh_color3_lds(S + (vid - vb) * kShRow, rx * rn, ry * rn, rz * rn, rgb, bits);
@@ -527,6 +536,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_top(unsigned long long* __restr
   if (threadIdx.x == 0) {
     hdr->n_entries = carry;
     hdr->overflow = 0;
+    hdr->error = 0;  // the frame's sort and tile order report into it
   }
 }
 

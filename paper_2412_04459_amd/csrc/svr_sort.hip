@@ -289,7 +289,9 @@ hipError_t launch_radix_sort(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t*
 __global__ __launch_bounds__(kBlock) void k_tile_ranges(const uint64_t* __restrict__ keys,
                                                         const unsigned long long* __restrict__ n_dev,
                                                         int64_t cap, int shift, uint32_t T,
-                                                        uint2* __restrict__ range) {
+                                                        uint2* __restrict__ range,
+                                                        uint32_t* __restrict__ counters) {
+  if (blockIdx.x == 0 && threadIdx.x <= (unsigned)kOrderBuckets) counters[threadIdx.x] = 0u;
   const int64_t n = min((int64_t)*n_dev, cap);
   const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
   if (i >= n) return;
@@ -365,17 +367,15 @@ __global__ __launch_bounds__(kBlock) void k_tile_scatter(const uint2* __restrict
 }
 
 hipError_t launch_tile_ranges(const Layout& L, void* ws, const uint64_t* keys, hipStream_t s) {
-  // ranges and the bucket and chunk counters behind them are cleared together
-  hipError_t e = launch_fill_u32(at<uint32_t>(ws, L.tile_range), 0u,
-                                 2 * (int64_t)L.T + kOrderBuckets + 1, s);
-  if (e != hipSuccess) return e;
+  // the ranges start empty (cleared with the tile masks); the bucket and
+  // chunk counters behind them are cleared by the first workgroup here
   uint2* range = at<uint2>(ws, L.tile_range);
   uint32_t* counts = at<uint32_t>(ws, L.tile_range) + 2 * (int64_t)L.T;
   uint32_t* split_count = counts + kOrderBuckets;
-  if (L.cap > 0)
-    SVR_LAUNCH("tile_ranges", k_tile_ranges, dim3((unsigned)((L.cap + kBlock - 1) / kBlock)),
-               dim3(kBlock), 0, s, keys, &at<WsHeader>(ws, L.hdr)->n_entries, L.cap, L.key_low,
-               (uint32_t)L.T, range);
+  // at least one workgroup: the first one clears the counters
+  SVR_LAUNCH("tile_ranges", k_tile_ranges,
+             dim3((unsigned)max((L.cap + kBlock - 1) / kBlock, (int64_t)1)), dim3(kBlock), 0, s, keys,
+             &at<WsHeader>(ws, L.hdr)->n_entries, L.cap, L.key_low, (uint32_t)L.T, range, counts);
   const dim3 tg((unsigned)((L.T + kBlock - 1) / kBlock));
   SVR_LAUNCH("tile_order", k_tile_bucket, tg, dim3(kBlock), 0, s, range, (uint32_t)L.T, counts,
              at<uint32_t>(ws, L.tile_rank), split_count, at<uint32_t>(ws, L.split_base),
