@@ -1333,10 +1333,15 @@ static void launch_kind(RKind kind, const RenderArgs& A, unsigned grid, hipStrea
 
 template <int TS, int ACT>
 static void launch_k(RKind kind, const RenderArgs& A, unsigned grid, hipStream_t s) {
-  // depth and normal images: one kernel per tile size and activation, K at
-  // run time
+  // depth and normal images: kernels of their own (K = 1, 2, 3 compiled in,
+  // other K at run time)
   if (A.aux && kind != RKind::kStats) {
-    launch_kind<TS, 0, ACT, true>(kind, A, grid, s);
+    switch (A.K) {
+      case 1: launch_kind<TS, 1, ACT, true>(kind, A, grid, s); break;
+      case 2: launch_kind<TS, 2, ACT, true>(kind, A, grid, s); break;
+      case 3: launch_kind<TS, 3, ACT, true>(kind, A, grid, s); break;
+      default: launch_kind<TS, 0, ACT, true>(kind, A, grid, s); break;
+    }
     return;
   }
   switch (A.K) {
