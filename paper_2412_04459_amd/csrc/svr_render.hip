@@ -1435,9 +1435,23 @@ __global__ __launch_bounds__(kBlock) void k_grid_gather(int64_t M, const int32_t
   const int64_t nb = (M + kBlock - 1) / kBlock;
   const int64_t m = xcd_block(blockIdx.x, nb) * kBlock + threadIdx.x;
   if (m >= M) return;
+  // a grid point is a corner of at most 8 voxels: the slots are loaded
+  // together, then their gradients, then summed in slot order
+  const int32_t e0 = off[m], e1 = off[m + 1];
   float acc = 0.f;
-  const int32_t e1 = off[m + 1];
-  for (int32_t e = off[m]; e < e1; ++e) acc += g_corner[adj[e]];
+  if (e1 - e0 <= 8) {
+    int32_t a[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) a[k] = e0 + k < e1 ? adj[e0 + k] : -1;
+    float g[8];
+#pragma unroll
+    for (int k = 0; k < 8; ++k) g[k] = a[k] >= 0 ? g_corner[a[k]] : 0.f;
+#pragma unroll
+    for (int k = 0; k < 8; ++k)
+      if (e0 + k < e1) acc += g[k];
+  } else {
+    for (int32_t e = e0; e < e1; ++e) acc += g_corner[adj[e]];
+  }
   grad_grid[m] = accumulate ? grad_grid[m] + acc : acc;
 }
 
