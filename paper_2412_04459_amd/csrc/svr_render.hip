@@ -1195,16 +1195,18 @@ __global__ __launch_bounds__(kBlock) void k_sh_bwd(
 #pragma unroll
     for (int j = 0; j < NB; ++j) acc[j][0] = acc[j][1] = acc[j][2] = 0.f;
     if (vid < N) {
+      const float cx = center[vid], cy = center[N + vid], cz = center[2 * N + vid];
       for (int ci = 0; ci < n_cams; ++ci) {
         const int64_t vv = vid * n_cams + ci;
-        if (count[vv] == 0) continue;
-        const DevCam& c = cams.c[ci];
+        // the record and colour gradient are read with the count (both are
+        // only used when it is non-zero)
+        const uint32_t cnt = count[vv];
         const uint32_t bits = __float_as_uint(rec[vv].q3.w);
-        float g3[3];
-#pragma unroll
-        for (int ch = 0; ch < 3; ++ch) g3[ch] = ((bits >> ch) & 1u) ? g_rgb[vv * 3 + ch] : 0.f;
-        const float rx = center[vid] - c.o[0], ry = center[N + vid] - c.o[1],
-                    rz = center[2 * N + vid] - c.o[2];
+        const float gr0 = g_rgb[vv * 3 + 0], gr1 = g_rgb[vv * 3 + 1], gr2 = g_rgb[vv * 3 + 2];
+        if (cnt == 0) continue;
+        const DevCam& c = cams.c[ci];
+        const float g3[3] = {(bits & 1u) ? gr0 : 0.f, (bits & 2u) ? gr1 : 0.f, (bits & 4u) ? gr2 : 0.f};
+        const float rx = cx - c.o[0], ry = cy - c.o[1], rz = cz - c.o[2];
         const float rn = rsqrtf(rx * rx + ry * ry + rz * rz);
         float Y[16];
         sh_basis<D>(rx * rn, ry * rn, rz * rn, Y);
