@@ -306,6 +306,62 @@ int svr_downsample(const float* in, int w_in, int h_in, float* out, int w_out, i
 int svr_downsample_bwd(const float* grad_out, int w_out, int h_out, float* grad_in, int w_in,
                        int h_in, const float* bg, void* stream);
 
+/* Mesh extraction (Sec. 3.2.4 "Sparse-voxel TSDF Fusion and Marching Cubes").
+ *
+ * svr_tsdf_fuse: truncated signed distances at the grid points fused from
+ * depth images.  For grid point p and camera i: when p projects (by
+ * p_cam = R p + t of w2c as given) in front of the camera into pixel
+ * (floor u, floor v) of the image (pixel centres at
+ * +1/2) and that pixel holds depth D > 0 (distance along the unit ray;
+ * D <= 0 marks no depth), sdf = D - |p - o_i|;
+ * sdf >= -trunc adds min(sdf / trunc, 1) with weight 1.  tsdf[m] is the mean
+ * of the added values (1 when none), weight[m] their count.
+ * grid_pos: device float [3][n_grid] (x row, y row, z row); cams: host
+ * [n_cams], any number >= 1 (one launch per SVR_MAX_CAMERAS of them, tsdf
+ * holding running sums in between); depth: device float, the cameras'
+ * [H][W] images concatenated in
+ * camera order.  rgba: NULL (depth holds distances), or the frame's rgba
+ * [P][4] with depth as svr_render_fwd writes it (the composited sum): then
+ * D = depth / A where A >= min_alpha and A > 0, else no depth.
+ * tsdf, weight: device float [n_grid], overwritten.  Points
+ * and depths are read in fp32, projections and distances computed in fp64.
+ * Errors: SVR_E_INVALID (n_grid outside [0, 2^31), trunc not finite > 0,
+ * min_alpha not finite,
+ * camera checks as for svr_preprocess, null arrays), SVR_E_HIP.
+ *
+ * svr_marching_cubes: triangles of the iso-surface field = iso over the
+ * scene's voxels, each voxel one cell whose corner values are the field at
+ * its 8 grid points (vox_grid).  A corner is above when field > iso; every
+ * cell edge between an above and a below corner carries a vertex, keyed by
+ * its two grid points (smaller index first) so that neighbouring cells share
+ * it, at the linear interpolation of the corner positions (centre +- size/2)
+ * at iso.  In each cell the crossings on every face are joined in pairs (four
+ * crossings: two segments, each cutting off one above corner), oriented so
+ * that the polygons' right-hand normals point to increasing field; each
+ * polygon is a fan from its vertex with the smallest corner pair.  Cells with
+ * a grid point of weight 0 (weight device float [n_grid], NULL: none) give no
+ * triangles.  Uses scene->center, size, vox_grid, n_voxels, n_grid only.
+ * field: device float [n_grid]; tri_keys: device int32 [max_triangles][3][2]
+ * grid point pairs; tri_pos: device float [max_triangles][3][3];
+ * n_triangles: device, receives the total count (which may exceed
+ * max_triangles: then a cell whose triangles do not all fit writes none and
+ * the caller retries with room for the count).  Triangle order varies from
+ * call to call; each cell's triangles are consecutive and in table order.
+ * Grid indices must lie in [0, n_grid) (not checked).
+ * Errors: SVR_E_INVALID (sizes, non-finite iso, null arrays), SVR_E_HIP.   */
+int svr_tsdf_fuse(const float* grid_pos, int64_t n_grid, const svr_camera* cams, int n_cams,
+                  const float* depth, const float* rgba, float min_alpha, float trunc, float* tsdf,
+                  float* weight, void* stream);
+int svr_marching_cubes(const svr_scene* scene, const float* field, const float* weight, float iso,
+                       int64_t max_triangles, int32_t* tri_keys, float* tri_pos,
+                       unsigned long long* n_triangles, void* stream);
+/* The cell table svr_marching_cubes uses (host memory, no GPU needed):
+ * counts[case] triangles for case = sum over above corners c of 2^c;
+ * verts[case][3 t + j] vertex j of triangle t as its corner pair a << 3 | b
+ * (a < b).  counts: uint8 [256]; verts: uint8 [256][36].
+ * Errors: SVR_E_INVALID (null arrays).                                     */
+int svr_mesh_case_table(uint8_t* counts, uint8_t* verts);
+
 /* Order ranks of the scene (build once per octpath set; Supp. B.1, B.2): the
  * sort key orders a tile's entries by (top 3L path bits XOR s * 0b001..001,
  * s).  rank[v*8 + s] is the position of pair (v, s) in that order over all 8N

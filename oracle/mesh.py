@@ -13,7 +13,11 @@ TSDF fusion (readings, the paper gives the method by reference only):
       sdf = D(pixel) - |p - o|.
   Observations with sdf >= -trunc are integrated as min(sdf / trunc, 1) with
   weight 1; the fused value is their mean (weight = their count).  Points
-  never observed keep the value 1 and weight 0.
+  never observed keep the value 1 and weight 0.  When the rendered opacity A
+  is given with the depth (the renderer's depth is the composited sum
+  sum_i T_i d_i), the distance is that sum divided by A where A >= min_alpha
+  and A > 0, taken in float32 as the renderer's images are; other pixels
+  carry no depth.
 
 Marching cubes over the voxels (one cell per voxel, its 8 corner grid
 points; corner c = 4x + 2y + z):
@@ -157,13 +161,20 @@ def marching_cubes(center, size, vox_grid, field, iso=0.0, weight=None):
     return (np.asarray(keys, np.int64).reshape(-1, 3, 2), np.asarray(pos, np.float64).reshape(-1, 3, 3))
 
 
-def tsdf_fuse(grid_pos, cams, depths, trunc):
-    """Fused truncated signed distances of the grid points (values, weights)."""
+def tsdf_fuse(grid_pos, cams, depths, trunc, alphas=None, min_alpha=0.5):
+    """Fused truncated signed distances of the grid points (values, weights).
+    grid_pos [M][3]; depths / alphas: per camera [H*W] (alphas None: the
+    depths are distances already)."""
     p = np.asarray(grid_pos, np.float64)
     M = p.shape[0]
     acc = np.zeros(M)
     w = np.zeros(M)
-    for cam, D in zip(cams, depths):
+    for ci, (cam, D) in enumerate(zip(cams, depths)):
+        if alphas is not None:
+            A = np.asarray(alphas[ci], np.float32).reshape(-1)
+            D32 = np.asarray(D, np.float32).reshape(-1)
+            ok_a = (A >= np.float32(min_alpha)) & (A > 0)
+            D = np.where(ok_a, D32 / np.where(ok_a, A, np.float32(1)), np.float32(0))
         D = np.asarray(D, np.float64).reshape(cam.H, cam.W)
         R = np.asarray(cam.w2c, np.float64)[:, :3]
         t = np.asarray(cam.w2c, np.float64)[:, 3]

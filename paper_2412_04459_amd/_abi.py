@@ -78,6 +78,10 @@ _SIGS = {
     "svr_downsample_bwd": (ctypes.c_int, [P, ctypes.c_int, ctypes.c_int, P, ctypes.c_int,
                                           ctypes.c_int, P, P]),
     "svr_graph_destroy": (ctypes.c_int, [P]),
+    "svr_tsdf_fuse": (ctypes.c_int, [P, I64, P, ctypes.c_int, P, P, ctypes.c_float, ctypes.c_float,
+                                     P, P, P]),
+    "svr_marching_cubes": (ctypes.c_int, [P, P, P, ctypes.c_float, I64, P, P, P, P]),
+    "svr_mesh_case_table": (ctypes.c_int, [P, P]),
     "svr_grid_adjacency_scratch_bytes": (ctypes.c_size_t, [I64, I64]),
     "svr_build_grid_adjacency": (ctypes.c_int, [P, I64, I64, P, P, P, ctypes.c_size_t, P]),
     "svr_status_string": (ctypes.c_char_p, [ctypes.c_int]),
@@ -272,3 +276,20 @@ def svr_order_rank_scratch_bytes(n_voxels, max_level):
 def svr_build_order_ranks(octpath, n_voxels, max_level, rank, scratch, scratch_bytes, stream):
     return load().svr_build_order_ranks(octpath, n_voxels, max_level, rank, scratch,
                                         scratch_bytes, stream)
+
+
+def svr_tsdf_fuse(grid_pos, n_grid, cams, n_cams, depth, rgba, min_alpha, trunc, tsdf, weight,
+                  stream):
+    return load().svr_tsdf_fuse(grid_pos, n_grid, cams, n_cams, depth, rgba, min_alpha, trunc,
+                                tsdf, weight, stream)
+
+
+def svr_marching_cubes(scene, field, weight, iso, max_triangles, tri_keys, tri_pos, n_triangles,
+                       stream):
+    return load().svr_marching_cubes(_ref(scene), field, weight, iso, max_triangles, tri_keys,
+                                     tri_pos,
+                                     n_triangles, stream)
+
+
+def svr_mesh_case_table(counts, verts):
+    return load(with_torch=False).svr_mesh_case_table(counts, verts)

@@ -80,6 +80,52 @@ int bits_for(int64_t x) {  // bits needed to hold values 0..x
   return b;
 }
 
+// Device camera records (fp64 centre, rotation, intrinsics, tile and pixel
+// offsets of the concatenated images) for n_cams host cameras.
+int fill_cams(const svr_camera* cams, int n_cams, int tile, CamSet* cs, int64_t* T_out,
+              int64_t* P_out, int64_t* sat_out) {
+  if (!cams) return fail(SVR_E_INVALID, "null camera pointer");
+  if (n_cams < 1 || n_cams > SVR_MAX_CAMERAS)
+    return fail(SVR_E_INVALID, "n_cams=%d outside 1..%d", n_cams, SVR_MAX_CAMERAS);
+  const int tshift = tile == 8 ? 3 : (tile == 16 ? 4 : 5);
+  int64_t T = 0, P = 0, sat = 0;
+  cs->n = n_cams;
+  cs->tile = tile;
+  cs->tshift = tshift;
+  for (int i = 0; i < n_cams; ++i) {
+    const svr_camera& c = cams[i];
+    if (c.width < 1 || c.height < 1 || c.width > 16384 || c.height > 16384)
+      return fail(SVR_E_INVALID, "camera %d: size %dx%d outside 1..16384", i, c.width, c.height);
+    if (!(c.fx > 0.f) || !(c.fy > 0.f) || !isfinite(c.cx) || !isfinite(c.cy))
+      return fail(SVR_E_INVALID, "camera %d: bad intrinsics", i);
+    for (int k = 0; k < 12; ++k)
+      if (!isfinite(c.w2c[k])) return fail(SVR_E_INVALID, "camera %d: non-finite pose", i);
+    DevCam& d = cs->c[i];
+    for (int r = 0; r < 3; ++r)
+      for (int j = 0; j < 3; ++j) d.r[3 * r + j] = c.w2c[4 * r + j];
+    for (int j = 0; j < 3; ++j) {
+      double acc = 0;
+      for (int r = 0; r < 3; ++r) acc += (double)c.w2c[4 * r + j] * (double)c.w2c[4 * r + 3];
+      d.od[j] = -acc;
+      d.o[j] = (float)(-acc);
+    }
+    d.fx = c.fx; d.fy = c.fy; d.cx = c.cx; d.cy = c.cy;
+    d.W = c.width; d.H = c.height;
+    d.ntx = (c.width + tile - 1) / tile;
+    d.nty = (c.height + tile - 1) / tile;
+    d.tile_off = (int32_t)T;
+    d.sat_off = (int32_t)sat;
+    d.pix_off = P;
+    T += (int64_t)d.ntx * d.nty;
+    sat += (int64_t)(d.ntx + 1) * (d.nty + 1);
+    P += (int64_t)c.width * c.height;
+  }
+  *T_out = T;
+  *P_out = P;
+  *sat_out = sat;
+  return SVR_OK;
+}
+
 int make_layout(const svr_scene* sc, const svr_camera* cams, int n_cams, const svr_opts* o,
                 Layout* L, CamSet* cs) {
   if (!sc || !cams || !o || !L) return fail(SVR_E_INVALID, "null scene, camera or options pointer");
@@ -118,37 +164,8 @@ int make_layout(const svr_scene* sc, const svr_camera* cams, int n_cams, const s
   l.tshift = l.tile == 8 ? 3 : (l.tile == 16 ? 4 : 5);
   l.persistent = o->persistent;
   int64_t T = 0, P = 0, sat = 0;
-  cs->n = n_cams;
-  cs->tile = l.tile;
-  cs->tshift = l.tshift;
-  for (int i = 0; i < n_cams; ++i) {
-    const svr_camera& c = cams[i];
-    if (c.width < 1 || c.height < 1 || c.width > 16384 || c.height > 16384)
-      return fail(SVR_E_INVALID, "camera %d: size %dx%d outside 1..16384", i, c.width, c.height);
-    if (!(c.fx > 0.f) || !(c.fy > 0.f) || !isfinite(c.cx) || !isfinite(c.cy))
-      return fail(SVR_E_INVALID, "camera %d: bad intrinsics", i);
-    for (int k = 0; k < 12; ++k)
-      if (!isfinite(c.w2c[k])) return fail(SVR_E_INVALID, "camera %d: non-finite pose", i);
-    DevCam& d = cs->c[i];
-    for (int r = 0; r < 3; ++r)
-      for (int j = 0; j < 3; ++j) d.r[3 * r + j] = c.w2c[4 * r + j];
-    for (int j = 0; j < 3; ++j) {
-      double acc = 0;
-      for (int r = 0; r < 3; ++r) acc += (double)c.w2c[4 * r + j] * (double)c.w2c[4 * r + 3];
-      d.od[j] = -acc;
-      d.o[j] = (float)(-acc);
-    }
-    d.fx = c.fx; d.fy = c.fy; d.cx = c.cx; d.cy = c.cy;
-    d.W = c.width; d.H = c.height;
-    d.ntx = (c.width + l.tile - 1) / l.tile;
-    d.nty = (c.height + l.tile - 1) / l.tile;
-    d.tile_off = (int32_t)T;
-    d.sat_off = (int32_t)sat;
-    d.pix_off = P;
-    T += (int64_t)d.ntx * d.nty;
-    sat += (int64_t)(d.ntx + 1) * (d.nty + 1);
-    P += (int64_t)c.width * c.height;
-  }
+  int st = fill_cams(cams, n_cams, l.tile, cs, &T, &P, &sat);
+  if (st != SVR_OK) return st;
   if (T >= ((int64_t)1 << 31)) return fail(SVR_E_INVALID, "too many tiles");
   l.T = (int32_t)T;
   l.P = P;
@@ -658,6 +675,80 @@ int svr_downsample_bwd(const float* grad_out, int w_out, int h_out, float* grad_
   SVR_HIP(launch_downsample_bwd(grad_out, w_out, h_out, grad_in, w_in, h_in, bg ? bg : zero,
                                 reinterpret_cast<hipStream_t>(stream)),
           "downsample adjoint");
+  return SVR_OK;
+}
+
+int svr_tsdf_fuse(const float* grid_pos, int64_t n_grid, const svr_camera* cams, int n_cams,
+                  const float* depth, const float* rgba, float min_alpha, float trunc, float* tsdf,
+                  float* weight, void* stream) {
+  if (n_grid < 0 || n_grid >= ((int64_t)1 << 31))
+    return fail(SVR_E_INVALID, "n_grid=%lld outside [0, 2^31)", (long long)n_grid);
+  if (!(trunc > 0.f) || !isfinite(trunc)) return fail(SVR_E_INVALID, "trunc must be finite and > 0");
+  if (!isfinite(min_alpha)) return fail(SVR_E_INVALID, "min_alpha must be finite");
+  if (!cams || n_cams < 1) return fail(SVR_E_INVALID, "need at least one camera");
+  // cameras in groups of SVR_MAX_CAMERAS, one launch each; the depth images
+  // stay one concatenated array
+  const int n_groups = (n_cams + SVR_MAX_CAMERAS - 1) / SVR_MAX_CAMERAS;
+  std::vector<FuseCamSet> groups((size_t)n_groups);
+  int64_t pix_base = 0;
+  for (int gi = 0; gi < n_groups; ++gi) {
+    const int c0 = gi * SVR_MAX_CAMERAS;
+    const int nc = std::min(SVR_MAX_CAMERAS, n_cams - c0);
+    CamSet cs;  // validation, centres and pixel offsets
+    memset(&cs, 0, sizeof(cs));
+    int64_t T = 0, P = 0, sat = 0;
+    int st = fill_cams(cams + c0, nc, SVR_TILE, &cs, &T, &P, &sat);
+    if (st != SVR_OK) return st;
+    FuseCamSet& fs = groups[(size_t)gi];
+    memset(&fs, 0, sizeof(fs));
+    fs.n = nc;
+    for (int i = 0; i < nc; ++i) {
+      const svr_camera& c = cams[c0 + i];
+      FuseCam& f = fs.c[i];
+      for (int j = 0; j < 3; ++j) f.od[j] = cs.c[i].od[j];
+      for (int r = 0; r < 3; ++r) {
+        for (int j = 0; j < 3; ++j) f.r[3 * r + j] = c.w2c[4 * r + j];
+        f.t[r] = c.w2c[4 * r + 3];
+      }
+      f.fx = c.fx; f.fy = c.fy; f.cx = c.cx; f.cy = c.cy;
+      f.W = c.width; f.H = c.height;
+      f.pix_off = pix_base + cs.c[i].pix_off;
+    }
+    pix_base += P;
+  }
+  if (n_grid == 0) return SVR_OK;
+  if (!grid_pos || !depth || !tsdf || !weight) return fail(SVR_E_INVALID, "null array");
+  for (int gi = 0; gi < n_groups; ++gi)
+    SVR_HIP(launch_tsdf_fuse(grid_pos, n_grid, groups[(size_t)gi], depth, rgba, min_alpha, trunc,
+                             tsdf, weight, gi == 0, gi == n_groups - 1,
+                             reinterpret_cast<hipStream_t>(stream)),
+            "tsdf fusion");
+  return SVR_OK;
+}
+
+int svr_mesh_case_table(uint8_t* counts, uint8_t* verts) {
+  if (!counts || !verts) return fail(SVR_E_INVALID, "null table array");
+  mesh_case_table(counts, verts);
+  return SVR_OK;
+}
+
+int svr_marching_cubes(const svr_scene* scene, const float* field, const float* weight, float iso,
+                       int64_t max_triangles, int32_t* tri_keys, float* tri_pos,
+                       unsigned long long* n_triangles, void* stream) {
+  if (!scene) return fail(SVR_E_INVALID, "null scene");
+  if (scene->n_voxels < 0 || scene->n_voxels >= (int64_t)SVR_MAX_VOXELS)
+    return fail(SVR_E_INVALID, "n_voxels=%lld outside [0, 2^29)", (long long)scene->n_voxels);
+  if (scene->n_grid < 0 || scene->n_grid >= ((int64_t)1 << 31))
+    return fail(SVR_E_INVALID, "n_grid=%lld outside [0, 2^31)", (long long)scene->n_grid);
+  if (!isfinite(iso)) return fail(SVR_E_INVALID, "iso must be finite");
+  if (max_triangles < 0) return fail(SVR_E_INVALID, "max_triangles < 0");
+  if (!n_triangles) return fail(SVR_E_INVALID, "null triangle counter");
+  if (max_triangles > 0 && (!tri_keys || !tri_pos)) return fail(SVR_E_INVALID, "null triangle arrays");
+  if (scene->n_voxels > 0 && (!scene->center || !scene->size || !scene->vox_grid || !field))
+    return fail(SVR_E_INVALID, "null scene array or field");
+  SVR_HIP(launch_mesh_cells(*scene, field, weight, iso, max_triangles, tri_keys, tri_pos,
+                            n_triangles, reinterpret_cast<hipStream_t>(stream)),
+          "marching cubes");
   return SVR_OK;
 }
 

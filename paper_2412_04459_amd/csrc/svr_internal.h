@@ -206,6 +206,29 @@ hipError_t launch_downsample(const float* in, int w_in, int h_in, float* out, in
                              int h_out, const float bg[3], hipStream_t s);
 hipError_t launch_downsample_bwd(const float* gout, int w_out, int h_out, float* gin, int w_in,
                                  int h_in, const float bg[3], hipStream_t s);
+
+// svr_mesh.hip
+// Camera of the TSDF fusion: projection by the world-to-camera matrix as
+// given (R p + t), distances from the fp64 centre -R^T t.
+struct FuseCam {
+  double od[3];
+  float r[9];
+  float t[3];
+  float fx, fy, cx, cy;
+  int32_t W, H;
+  int64_t pix_off;
+};
+struct FuseCamSet {
+  int32_t n;
+  FuseCam c[SVR_MAX_CAMERAS];
+};
+hipError_t launch_tsdf_fuse(const float* grid_pos, int64_t M, const FuseCamSet& cams, const float* depth,
+                            const float* rgba, float min_alpha, float trunc, float* tsdf,
+                            float* weight, bool first, bool last, hipStream_t s);
+hipError_t launch_mesh_cells(const svr_scene& sc, const float* field, const float* weight, float iso,
+                             int64_t max_tris, int32_t* keys, float* pos, unsigned long long* count,
+                             hipStream_t s);
+void mesh_case_table(uint8_t* counts, uint8_t* verts);  // [256], [256][36]
 hipError_t launch_render_stats(const svr_scene& sc, const CamSet& cams, const svr_opts& o,
                                const Layout& L, void* ws, const uint32_t* vals, hipStream_t s);
 

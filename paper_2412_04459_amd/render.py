@@ -60,6 +60,9 @@ class DeviceScene:
         self.grid_raw = torch.from_numpy(np.ascontiguousarray(scene.grid_raw, np.float32)).to(dev)
         self.sh = torch.from_numpy(np.ascontiguousarray(scene.sh, np.float32)).to(dev)
         self.device = self.grid_raw.device
+        gp = getattr(scene, "grid_pos", None)
+        self.grid_pos = None if gp is None else torch.from_numpy(
+            np.ascontiguousarray(np.asarray(gp, np.float32).T)).to(dev)  # [3][M]
         self.adj_off = self.adj = None
         if grid_adjacency:
             self.build_adjacency()
@@ -527,3 +530,91 @@ class DownsampleFunction(torch.autograd.Function):
 def downsample(rgba_in: torch.Tensor, w_in: int, h_in: int, w_out: int, h_out: int, bg=None):
     """Anti-aliased downsample of a supersampled render plus background."""
     return DownsampleFunction.apply(rgba_in, w_in, h_in, w_out, h_out, bg)
+
+
+# ---------------------------------------------------------------------------
+# Mesh extraction (Sec. 3.2.4): TSDF fusion of rendered depths at the grid
+# points, then marching cubes over the voxels.
+
+def _f32_dev(t, name, n=None):
+    if t.dtype != torch.float32 or not t.is_contiguous() or t.device.type != "cuda":
+        raise ValueError("%s must be a contiguous float32 device tensor" % name)
+    if n is not None and t.numel() != n:
+        raise ValueError("%s has %d elements, expected %d" % (name, t.numel(), n))
+    return t
+
+
+def tsdf_fuse(grid_pos: torch.Tensor, cams: Sequence, depth: torch.Tensor, trunc: float,
+              rgba: Optional[torch.Tensor] = None, min_alpha: float = 0.5,
+              tsdf: Optional[torch.Tensor] = None, weight: Optional[torch.Tensor] = None):
+    """Fused truncated signed distances (svr_tsdf_fuse).  grid_pos float32
+    [3, M]; depth [sum H*W] of the cameras in order (with ``rgba``: the
+    renderer's composited depth, divided by the opacity where it reaches
+    ``min_alpha``).  Returns (tsdf [M], weight [M])."""
+    M = grid_pos.shape[-1]
+    _f32_dev(grid_pos, "grid_pos", 3 * M)
+    P = int(sum(c.W * c.H for c in cams))
+    _f32_dev(depth, "depth", P)
+    if rgba is not None:
+        _f32_dev(rgba, "rgba", 4 * P)
+    if tsdf is None:
+        tsdf = torch.empty(M, dtype=torch.float32, device=grid_pos.device)
+    if weight is None:
+        weight = torch.empty(M, dtype=torch.float32, device=grid_pos.device)
+    _f32_dev(tsdf, "tsdf", M)
+    _f32_dev(weight, "weight", M)
+    arr = camera_structs(cams)
+    check(_abi.svr_tsdf_fuse(_ptr(grid_pos), M, arr, len(cams), _ptr(depth), _ptr(rgba),
+                             float(min_alpha), float(trunc), _ptr(tsdf), _ptr(weight),
+                             _stream()), "svr_tsdf_fuse")
+    return tsdf, weight
+
+
+def marching_cubes_into(ds: DeviceScene, field: torch.Tensor, keys: torch.Tensor,
+                        pos: torch.Tensor, count: torch.Tensor, iso: float = 0.0,
+                        weight: Optional[torch.Tensor] = None):
+    """svr_marching_cubes into preallocated keys int32 [cap, 3, 2], pos float32
+    [cap, 3, 3] and count int64 [1] (the total, which may exceed cap); no
+    host synchronisation."""
+    _f32_dev(field, "field", ds.n_grid)
+    if weight is not None:
+        _f32_dev(weight, "weight", ds.n_grid)
+    cap = keys.shape[0]
+    if keys.dtype != torch.int32 or tuple(keys.shape[1:]) != (3, 2) or not keys.is_contiguous():
+        raise ValueError("keys must be a contiguous int32 [cap, 3, 2] tensor")
+    if pos.dtype != torch.float32 or tuple(pos.shape) != (cap, 3, 3) or not pos.is_contiguous():
+        raise ValueError("pos must be a contiguous float32 [cap, 3, 3] tensor")
+    if count.dtype != torch.int64 or count.numel() != 1:
+        raise ValueError("count must be an int64 tensor of one element")
+    st = ds.struct()
+    check(_abi.svr_marching_cubes(st, _ptr(field), _ptr(weight), float(iso), cap, _ptr(keys),
+                                  _ptr(pos), _ptr(count), _stream()), "svr_marching_cubes")
+
+
+def marching_cubes(ds: DeviceScene, field: torch.Tensor, iso: float = 0.0,
+                   weight: Optional[torch.Tensor] = None, capacity: Optional[int] = None):
+    """Iso-surface triangles over the voxels (svr_marching_cubes): (keys int32
+    [n, 3, 2] grid point pairs per vertex, pos float32 [n, 3, 3]).  The
+    triangle order is not deterministic."""
+    dev = ds.device
+    cap = max(1024, ds.n_voxels // 2) if capacity is None else int(capacity)
+    count = torch.zeros(1, dtype=torch.int64, device=dev)
+    for _ in range(2):
+        keys = torch.empty((cap, 3, 2), dtype=torch.int32, device=dev)
+        pos = torch.empty((cap, 3, 3), dtype=torch.float32, device=dev)
+        marching_cubes_into(ds, field, keys, pos, count, iso, weight)
+        n = int(count.item())
+        if n <= cap:
+            return keys[:n], pos[:n]
+        cap = n
+    raise RuntimeError("marching cubes: triangle count changed between calls")
+
+
+def mesh_case_table():
+    """The cell table of svr_marching_cubes: (counts uint8 [256], verts uint8
+    [256, 36]) with vertices as corner pairs a << 3 | b."""
+    counts = (ctypes.c_uint8 * 256)()
+    verts = (ctypes.c_uint8 * (256 * 36))()
+    check(_abi.svr_mesh_case_table(counts, verts), "svr_mesh_case_table")
+    return (np.frombuffer(counts, np.uint8).copy(),
+            np.frombuffer(verts, np.uint8).reshape(256, 36).copy())

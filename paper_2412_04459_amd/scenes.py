@@ -494,6 +494,37 @@ def scene_from_voxels(world_center, world_size, max_level, ijk, level, grid_raw=
                  sh=np.asarray(sh, np.float32).reshape(ijk.shape[0], nb, 3), sh_degree=sh_degree)
 
 
+def sphere_depth_images(cams, spheres, hole_p=0.0, seed=0) -> List[np.ndarray]:
+    """Synthetic depth images: per camera [H*W] float32, the distance along
+    each pixel's unit ray (through the pixel centre) to the nearest of the
+    spheres ((centre, radius) pairs), 0 where the ray misses them all or, with
+    probability hole_p, at random pixels."""
+    rng = np.random.default_rng(np.random.SeedSequence(seed).spawn(6)[5])
+    out = []
+    for cam in cams:
+        R = np.asarray(cam.w2c, np.float64)[:, :3]
+        t = np.asarray(cam.w2c, np.float64)[:, 3]
+        o = -R.T @ t
+        u, v = np.meshgrid(np.arange(cam.W) + 0.5, np.arange(cam.H) + 0.5)
+        dc = np.stack([(u - cam.cx) / cam.fx, (v - cam.cy) / cam.fy, np.ones_like(u)], -1)
+        d = dc.reshape(-1, 3) @ R
+        d /= np.linalg.norm(d, axis=1, keepdims=True)
+        best = np.full(d.shape[0], np.inf)
+        for c, r in spheres:
+            oc = o - np.asarray(c, np.float64)
+            b = d @ oc
+            disc = b * b - (oc @ oc - r * r)
+            hit = disc >= 0
+            tq = -b - np.sqrt(np.where(hit, disc, 0.0))
+            hit &= tq > 0
+            best = np.where(hit & (tq < best), tq, best)
+        img = np.where(np.isfinite(best), best, 0.0)
+        if hole_p > 0:
+            img[rng.random(img.shape[0]) < hole_p] = 0.0
+        out.append(img.astype(np.float32))
+    return out
+
+
 def camera_from_pose(W, H, fx, fy, cx, cy, R, t) -> Camera:
     w2c = np.concatenate([np.asarray(R, np.float64), np.asarray(t, np.float64)[:, None]], 1)
     f32 = lambda x: float(np.float32(x))

@@ -169,3 +169,48 @@ def test_downsample_rejects_bad_sizes():
         assert _abi.svr_downsample(p, wi, hi, p, wo, ho, None, None) == _abi.SVR_E_INVALID
         assert _abi.svr_downsample_bwd(p, wo, ho, p, wi, hi, None, None) == _abi.SVR_E_INVALID
     assert _abi.svr_downsample(None, 10, 10, p, 5, 5, None, None) == _abi.SVR_E_INVALID
+
+
+def test_mesh_case_table_matches_the_oracle_cell_rule():
+    """The library's compile-time cell table against the oracle's face-traced
+    loops (Sec. 3.2.4 marching cubes), case by case and triangle by triangle."""
+    _lib()
+    from oracle import mesh as om
+    counts = (ctypes.c_uint8 * 256)()
+    verts = (ctypes.c_uint8 * (256 * 36))()
+    assert _abi.svr_mesh_case_table(counts, verts) == _abi.SVR_OK
+    v = np.frombuffer(verts, np.uint8).reshape(256, 36)
+    for case in range(256):
+        above = [bool((case >> c) & 1) for c in range(8)]
+        tris = om.cell_triangles(above) if 0 < case < 255 else []
+        assert counts[case] == len(tris), case
+        got = [tuple((int(v[case, 3 * t + j]) >> 3, int(v[case, 3 * t + j]) & 7) for j in range(3))
+               for t in range(len(tris))]
+        assert got == [tuple(tuple(e) for e in tri) for tri in tris], case
+    assert max(counts) <= 12
+    assert _abi.svr_mesh_case_table(None, verts) == _abi.SVR_E_INVALID
+
+
+def test_mesh_entry_points_check_arguments():
+    _lib()
+    sc, cams, _ = _host_args()
+    p = ctypes.c_void_p(0x100000)
+    # TSDF fusion: sizes, truncation, opacity threshold, cameras, null arrays
+    assert _abi.svr_tsdf_fuse(p, -1, cams, 1, p, None, 0.5, 0.1, p, p, None) == _abi.SVR_E_INVALID
+    assert _abi.svr_tsdf_fuse(p, 10, cams, 1, p, None, 0.5, 0.0, p, p, None) == _abi.SVR_E_INVALID
+    assert _abi.svr_tsdf_fuse(p, 10, cams, 1, p, None, float("nan"), 0.1, p, p,
+                              None) == _abi.SVR_E_INVALID
+    assert _abi.svr_tsdf_fuse(p, 10, cams, 0, p, None, 0.5, 0.1, p, p, None) == _abi.SVR_E_INVALID
+    assert _abi.svr_tsdf_fuse(None, 10, cams, 1, p, None, 0.5, 0.1, p, p,
+                              None) == _abi.SVR_E_INVALID
+    assert _abi.svr_tsdf_fuse(None, 0, cams, 1, None, None, 0.5, 0.1, None, None,
+                              None) == _abi.SVR_OK
+    # marching cubes: counter, arrays, iso, sizes
+    assert _abi.svr_marching_cubes(sc, p, None, 0.0, 10, p, p, None, None) == _abi.SVR_E_INVALID
+    assert _abi.svr_marching_cubes(sc, p, None, 0.0, 10, None, p, p, None) == _abi.SVR_E_INVALID
+    assert _abi.svr_marching_cubes(sc, p, None, float("inf"), 10, p, p, p,
+                                   None) == _abi.SVR_E_INVALID
+    assert _abi.svr_marching_cubes(sc, p, None, 0.0, -1, p, p, p, None) == _abi.SVR_E_INVALID
+    assert _abi.svr_marching_cubes(sc, None, None, 0.0, 10, p, p, p, None) == _abi.SVR_E_INVALID
+    sc.n_grid = 1 << 31
+    assert _abi.svr_marching_cubes(sc, p, None, 0.0, 10, p, p, p, None) == _abi.SVR_E_INVALID

@@ -1,0 +1,284 @@
+"""GPU parity of mesh extraction (Sec. 3.2.4): svr_tsdf_fuse and
+svr_marching_cubes, called through the C ABI, against the FP64 oracle in
+oracle/mesh.py.
+
+Bars: triangle vertex keys (grid point pairs) bit-exact as a set of triangles
+(the order of triangles is not fixed; each triangle's vertex order is);
+vertex positions within 2e-6 of the world size (fp32 corner positions and
+interpolation against fp64); triangle counts exact, also beyond the output
+capacity.  TSDF weights exact and values within 2e-5 absolute (fp32 mean of
+at most n_cams terms), away from projections that land within 1e-7 pixels of
+a pixel edge (where fp32/fp64 rounding may pick the neighbouring pixel).
+"""
+import numpy as np
+import pytest
+
+from oracle import mesh as om
+from paper_2412_04459_amd import scenes as S
+
+pytestmark = pytest.mark.gpu
+
+POS_REL = 2e-6
+TSDF_TOL = 2e-5
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    torch = pytest.importorskip("torch")
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _device_scene(scene):
+    from paper_2412_04459_amd.render import DeviceScene
+    return DeviceScene(scene, grid_adjacency=False, order_ranks=False)
+
+
+def _gpu_mesh(torch, ds, field, iso, weight=None, capacity=None):
+    from paper_2412_04459_amd.render import marching_cubes
+    f = torch.from_numpy(np.ascontiguousarray(field, np.float32)).cuda()
+    w = None if weight is None else torch.from_numpy(np.ascontiguousarray(weight, np.float32)).cuda()
+    keys, pos = marching_cubes(ds, f, iso, w, capacity)
+    torch.cuda.synchronize()
+    return keys.cpu().numpy().astype(np.int64), pos.cpu().numpy().astype(np.float64)
+
+
+def _sorted(keys, pos):
+    flat = keys.reshape(-1, 6)
+    order = np.lexsort(flat.T[::-1])
+    return flat[order], pos.reshape(-1, 9)[order]
+
+
+def _compare_meshes(gk, gp, ok, op, world_size):
+    assert gk.shape[0] == ok.shape[0], "triangles: gpu %d, oracle %d" % (gk.shape[0], ok.shape[0])
+    a, ap = _sorted(gk, gp)
+    b, bp = _sorted(ok, op)
+    assert np.array_equal(a, b), "triangle key sets differ"
+    if a.shape[0]:
+        err = np.abs(ap - bp).max()
+        assert err <= POS_REL * world_size, "max |d pos| = %.3g" % err
+
+
+def _random_field(scene, seed):
+    rng = np.random.default_rng(seed)
+    return rng.normal(0.0, 1.0, size=scene.n_grid).astype(np.float32)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_marching_cubes_matches_oracle_on_random_octrees(torch_dev, seed):
+    """Random corner values reach every cell case, the ambiguous ones too."""
+    sc = S.tiny_random_scene(seed, max_level=4, p_sub=0.55)
+    field = _random_field(sc, 100 + seed)
+    _say("mc random octree seed=%d N=%d M=%d" % (seed, sc.n_voxels, sc.n_grid))
+    ds = _device_scene(sc)
+    gk, gp = _gpu_mesh(torch_dev, ds, field, 0.0)
+    ok, op = om.marching_cubes(sc.center, sc.size, sc.vox_grid, field, 0.0)
+    assert ok.shape[0] > 100
+    _compare_meshes(gk, gp, ok, op, sc.world_size)
+
+
+def test_marching_cubes_sphere_distance_and_iso_offset(torch_dev):
+    sc = S.sphere_shell_scene()
+    c = sc.center.T.astype(np.float64).mean(0)
+    r = float(np.median(np.linalg.norm(sc.center.T - c[None, :], axis=1)))
+    field = (np.linalg.norm(sc.grid_pos - c[None, :], axis=1) - r).astype(np.float32)
+    _say("mc sphere N=%d" % sc.n_voxels)
+    ds = _device_scene(sc)
+    for iso in (0.0, 0.02):
+        gk, gp = _gpu_mesh(torch_dev, ds, field, iso)
+        ok, op = om.marching_cubes(sc.center, sc.size, sc.vox_grid, field, iso)
+        assert ok.shape[0] > 300
+        _compare_meshes(gk, gp, ok, op, sc.world_size)
+
+
+def test_marching_cubes_skips_cells_with_unobserved_corners(torch_dev):
+    sc = S.tiny_random_scene(7, max_level=4, p_sub=0.55)
+    field = _random_field(sc, 107)
+    rng = np.random.default_rng(7)
+    weight = (rng.random(sc.n_grid) > 0.1).astype(np.float32) * rng.integers(1, 5, sc.n_grid)
+    ds = _device_scene(sc)
+    gk, gp = _gpu_mesh(torch_dev, ds, field, 0.0, weight=weight)
+    ok, op = om.marching_cubes(sc.center, sc.size, sc.vox_grid, field, 0.0, weight=weight)
+    ok_all, _ = om.marching_cubes(sc.center, sc.size, sc.vox_grid, field, 0.0)
+    assert 0 < ok.shape[0] < ok_all.shape[0]
+    _compare_meshes(gk, gp, ok, op, sc.world_size)
+
+
+def test_marching_cubes_reports_the_full_count_beyond_capacity(torch_dev):
+    from paper_2412_04459_amd.render import marching_cubes_into
+    torch = torch_dev
+    sc = S.tiny_random_scene(3, max_level=4, p_sub=0.55)
+    field = _random_field(sc, 103)
+    ok, op = om.marching_cubes(sc.center, sc.size, sc.vox_grid, field, 0.0)
+    n = ok.shape[0]
+    cap = n // 2
+    ds = _device_scene(sc)
+    keys = torch.full((cap, 3, 2), -1, dtype=torch.int32, device="cuda")
+    pos = torch.zeros((cap, 3, 3), dtype=torch.float32, device="cuda")
+    count = torch.zeros(1, dtype=torch.int64, device="cuda")
+    f = torch.from_numpy(field).cuda()
+    marching_cubes_into(ds, f, keys, pos, count, 0.0)
+    torch.cuda.synchronize()
+    assert int(count.item()) == n
+    k = keys.cpu().numpy().astype(np.int64).reshape(cap, 6)
+    written = k[k[:, 0] >= 0]
+    assert written.shape[0] > 0
+    oracle_set = {tuple(r) for r in ok.reshape(-1, 6)}
+    assert all(tuple(r) in oracle_set for r in written)
+    # a second call into a buffer with room for all: the complete set
+    keys2 = torch.empty((n, 3, 2), dtype=torch.int32, device="cuda")
+    pos2 = torch.empty((n, 3, 3), dtype=torch.float32, device="cuda")
+    marching_cubes_into(ds, f, keys2, pos2, count, 0.0)
+    torch.cuda.synchronize()
+    assert int(count.item()) == n
+    _compare_meshes(keys2.cpu().numpy().astype(np.int64), pos2.cpu().numpy().astype(np.float64),
+                    ok, op, sc.world_size)
+
+
+def test_marching_cubes_degenerate_inputs(torch_dev):
+    torch = torch_dev
+    sc = S.tiny_random_scene(4, max_level=3)
+    field = _random_field(sc, 104)
+    ds = _device_scene(sc)
+    # every corner below (iso above all values) or above: no triangles
+    for iso in (10.0, -10.0):
+        gk, _ = _gpu_mesh(torch, ds, field, iso)
+        assert gk.shape[0] == 0
+    # corners exactly at iso count as below
+    flat = np.zeros(sc.n_grid, np.float32)
+    gk, _ = _gpu_mesh(torch, ds, flat, 0.0)
+    assert gk.shape[0] == 0
+    # no voxels
+    empty = sc.subset(np.zeros(0, np.int64))
+    gk, _ = _gpu_mesh(torch, _device_scene(empty), field, 0.0)
+    assert gk.shape[0] == 0
+
+
+def _cams_around(n, W, H, radius, seed):
+    rng = np.random.default_rng(seed)
+    cams = []
+    for _ in range(n):
+        eye = S.random_direction(rng) * radius
+        cams.append(S.look_at(W, H, 55.0, eye, target=tuple(rng.normal(0, 0.05, 3))))
+    return cams
+
+
+def _tie_free(points, cams, band=1e-7):
+    """Points whose projections lie at least `band` pixels from every pixel
+    edge in every camera (elsewhere fp32 and fp64 may pick different pixels)."""
+    p = np.asarray(points, np.float64)
+    keep = np.ones(p.shape[0], bool)
+    for cam in cams:
+        R = cam.w2c[:, :3]
+        t = cam.w2c[:, 3]
+        pc = p @ R.T + t
+        z = np.where(pc[:, 2] > 0, pc[:, 2], 1.0)
+        for q in (cam.fx * pc[:, 0] / z + cam.cx, cam.fy * pc[:, 1] / z + cam.cy):
+            keep &= np.abs(q - np.round(q)) > band
+    return keep
+
+
+def _gpu_tsdf(torch, points, cams, depths, trunc, alphas=None, min_alpha=0.5):
+    from paper_2412_04459_amd.render import tsdf_fuse
+    gp = torch.from_numpy(np.ascontiguousarray(np.asarray(points, np.float32).T)).cuda()
+    d = torch.from_numpy(np.concatenate(depths).astype(np.float32)).cuda()
+    rgba = None
+    if alphas is not None:
+        a = np.concatenate(alphas).astype(np.float32)
+        r = np.zeros((a.shape[0], 4), np.float32)
+        r[:, 3] = a
+        rgba = torch.from_numpy(r).cuda()
+    val, w = tsdf_fuse(gp, cams, d, trunc, rgba, min_alpha)
+    torch.cuda.synchronize()
+    return val.cpu().numpy().astype(np.float64), w.cpu().numpy().astype(np.float64)
+
+
+def _check_tsdf(gv, gw, ov, ow, keep):
+    assert np.array_equal(gw[keep], ow[keep]), "weights differ at %d points" % int(
+        (gw[keep] != ow[keep]).sum())
+    err = np.abs(gv[keep] - ov[keep]).max()
+    assert err <= TSDF_TOL, "max |d tsdf| = %.3g" % err
+
+
+SPHERES = [((0.0, 0.0, 0.0), 0.45), ((0.25, -0.15, 0.1), 0.3)]
+
+
+@pytest.mark.parametrize("n_cams,hole_p", [(1, 0.0), (5, 0.05), (40, 0.02)])
+def test_tsdf_fusion_matches_oracle(torch_dev, n_cams, hole_p):
+    rng = np.random.default_rng(11 + n_cams)
+    pts = rng.uniform(-0.8, 0.8, size=(40000, 3)).astype(np.float32).astype(np.float64)
+    cams = _cams_around(n_cams, 160, 120, 2.2, 21 + n_cams)
+    depths = S.sphere_depth_images(cams, SPHERES, hole_p=hole_p, seed=n_cams)
+    trunc = 0.08
+    _say("tsdf cams=%d points=%d" % (n_cams, pts.shape[0]))
+    gv, gw = _gpu_tsdf(torch_dev, pts, cams, depths, trunc)
+    ov, ow = om.tsdf_fuse(pts, cams, depths, trunc)
+    keep = _tie_free(pts, cams)
+    assert keep.mean() > 0.99
+    assert (ow > 0).sum() > 1000 and (ow == 0).sum() > 1000
+    _check_tsdf(gv, gw, ov, ow, keep)
+
+
+def test_tsdf_fusion_from_composited_depth_and_opacity(torch_dev):
+    """Renderer-style input: depth is the composited sum, divided by the
+    opacity where it reaches the threshold."""
+    rng = np.random.default_rng(5)
+    pts = rng.uniform(-0.8, 0.8, size=(30000, 3)).astype(np.float32).astype(np.float64)
+    cams = _cams_around(3, 128, 96, 2.0, 33)
+    dist = S.sphere_depth_images(cams, SPHERES, seed=3)
+    alphas = [rng.uniform(0.0, 1.0, size=d.shape[0]).astype(np.float32) for d in dist]
+    comp = [(d * a).astype(np.float32) for d, a in zip(dist, alphas)]
+    trunc = 0.1
+    gv, gw = _gpu_tsdf(torch_dev, pts, cams, comp, trunc, alphas, 0.4)
+    ov, ow = om.tsdf_fuse(pts, cams, comp, trunc, alphas=alphas, min_alpha=0.4)
+    keep = _tie_free(pts, cams)
+    assert (ow > 0).sum() > 500
+    _check_tsdf(gv, gw, ov, ow, keep)
+
+
+def test_mesh_at_the_orbit_scene_size(torch_dev):
+    """The 1.07M-voxel orbit scene and its 36 views at 1297x840: TSDF on
+    sampled grid points, marching cubes counted exactly over all voxels and
+    checked triangle by triangle on sampled voxels."""
+    torch = torch_dev
+    wl = S.workload("orbit_1m_1297x840")
+    sc, cams = wl.scene, wl.cameras
+    _say("mesh full size N=%d M=%d cams=%d" % (sc.n_voxels, sc.n_grid, len(cams)))
+    depths = S.sphere_depth_images(cams, [((0.0, 0.0, 0.0), 1.0), ((0.4, 0.2, -0.1), 0.6)],
+                                   hole_p=0.01, seed=9)
+    gv, gw = _gpu_tsdf(torch, sc.grid_pos, cams, depths, 0.02)
+    rng = np.random.default_rng(9)
+    pts32 = sc.grid_pos.astype(np.float32).astype(np.float64)
+    idx = rng.choice(sc.n_grid, size=20000, replace=False)
+    near = np.argsort(np.abs(np.linalg.norm(pts32, axis=1) - 1.0))[:20000]
+    idx = np.unique(np.concatenate([idx, near]))
+    ov, ow = om.tsdf_fuse(pts32[idx], cams, depths, 0.02)
+    keep = _tie_free(pts32[idx], cams)
+    assert (ow > 0).sum() > 1000
+    _check_tsdf(gv[idx], gw[idx], ov, ow, keep)
+
+    # marching cubes over a smooth synthetic field
+    g = sc.grid_pos
+    field = (np.sin(5.0 * g[:, 0]) + np.sin(5.0 * g[:, 1]) + np.sin(5.0 * g[:, 2])).astype(
+        np.float32)
+    ds = _device_scene(sc)
+    gk, gp = _gpu_mesh(torch, ds, field, 0.3)
+    counts = np.array([0] + [len(om.cell_triangles([bool((c >> i) & 1) for i in range(8)]))
+                             for c in range(1, 255)] + [0])
+    above = (field[sc.vox_grid] > np.float32(0.3)).astype(np.int64)
+    case = (above << np.arange(8)[None, :]).sum(1)
+    assert gk.shape[0] == int(counts[case].sum()) > 10000
+    sample = rng.choice(sc.n_voxels, size=3000, replace=False)
+    sub = sc.subset(sample)
+    ok, op = om.marching_cubes(sub.center, sub.size, sub.vox_grid, field, 0.3)
+    got = {tuple(r): p for r, p in zip(gk.reshape(-1, 6), gp.reshape(-1, 9))}
+    assert ok.shape[0] > 0
+    for r, p in zip(ok.reshape(-1, 6), op.reshape(-1, 9)):
+        q = got.get(tuple(r))
+        assert q is not None, "oracle triangle %s missing" % (tuple(r),)
+        assert np.abs(q - p).max() <= POS_REL * sc.world_size
