@@ -183,6 +183,74 @@ def supersampled_run(ds, cams, K, tile, grad, steps, log):
     return out
 
 
+def mesh_run(cams, K, tile, reps, log):
+    """Mesh extraction (Sec. 3.2.4) on the opaque variant of the orbit scene
+    (same octree, surfaces opaque, as meshing assumes): the views' rgba and
+    depth rendered, then TSDF fusion of all views at the grid points and
+    marching cubes over the voxels at iso 0, each timed on its own; ms per
+    call and HBM rates from
+    the algorithmic bytes (TSDF: 12 B position + 8 B outputs per grid point
+    and 8 B depth + opacity per accepted observation; marching cubes: 48 B
+    of voxel record + 8 B field and weight per grid point + 60 B per
+    triangle)."""
+    import torch
+    from paper_2412_04459_amd import scenes as S
+    from paper_2412_04459_amd.render import (DeviceScene, Rasterizer, marching_cubes,
+                                             marching_cubes_into, tsdf_fuse)
+    scene = S.spheres_background_scene(opaque=True)
+    ds = DeviceScene(scene)
+    rast = Rasterizer(ds, [cams[0]], K=K, tile=tile)
+    P = sum(c.W * c.H for c in cams)
+    rgba = torch.empty((P, 4), dtype=torch.float32, device="cuda")
+    dep = torch.empty(P, dtype=torch.float32, device="cuda")
+    off = 0
+    for c in cams:
+        n = c.W * c.H
+        rast.set_cameras([c])
+        rast.forward(out=rgba[off:off + n], depth=dep[off:off + n])
+        off += n
+    torch.cuda.synchronize()
+    trunc = 4.0 * scene.world_size / 2 ** scene.max_level
+    tsdf, w = tsdf_fuse(ds.grid_pos, cams, dep, trunc, rgba, 0.5)
+    keys, pos = marching_cubes(ds, tsdf, 0.0, w)
+    n_tri = keys.shape[0]
+    cap = n_tri + 1024
+    keys = torch.empty((cap, 3, 2), dtype=torch.int32, device="cuda")
+    pos = torch.empty((cap, 3, 3), dtype=torch.float32, device="cuda")
+    count = torch.zeros(1, dtype=torch.int64, device="cuda")
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+
+    def timed(fn):
+        fn()
+        torch.cuda.synchronize()
+        e0.record()
+        for _ in range(reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    t_ms = timed(lambda: tsdf_fuse(ds.grid_pos, cams, dep, trunc, rgba, 0.5, tsdf, w))
+    m_ms = timed(lambda: marching_cubes_into(ds, tsdf, keys, pos, count, 0.0, w))
+    assert int(count.item()) == n_tri
+    M, N = scene.n_grid, scene.n_voxels
+    obs = float(w.double().sum().item())
+    t_bytes = 20.0 * M + 8.0 * obs
+    m_bytes = 48.0 * N + 8.0 * M + 60.0 * n_tri
+    observed = int((w > 0).sum().item())
+    log("mesh: tsdf %.3f ms (%d views, %d grid points), marching cubes %.3f ms, %d triangles"
+        % (t_ms, len(cams), M, m_ms, n_tri))
+    del rast, ds
+    return {"scene": "orbit scene, opaque surfaces", "views": len(cams), "grid_points": M,
+            "voxels": N, "trunc": trunc,
+            "observed_grid_points": observed, "triangles": n_tri,
+            "tsdf": {"ms": t_ms, "bytes": t_bytes, "achieved_GBs": t_bytes / t_ms / 1e6,
+                     "frac": t_bytes / t_ms / 1e6 / HBM_PEAK_GBS},
+            "marching_cubes": {"ms": m_ms, "bytes": m_bytes, "achieved_GBs": m_bytes / m_ms / 1e6,
+                               "frac": m_bytes / m_ms / 1e6 / HBM_PEAK_GBS}}
+
+
 def large_scene_run(log):
     """~8M voxels (max level 14), 16 views at 1920x1080, K = 1, fwd+bwd of all
     16 views in one batched graph (16x16 tiles, one launch per stage), plus
@@ -294,6 +362,9 @@ def main():
     ap.add_argument("--main-only", action="store_true",
                     help="time only the headline frames (profiled runs: every launch of the "
                          "headline kernels then belongs to the headline workload)")
+    ap.add_argument("--mesh-only", action="store_true",
+                    help="run only the mesh extraction (TSDF fusion + marching cubes) timing and "
+                         "print its JSON object")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the 24-camera batched comparison")
@@ -321,6 +392,10 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.mesh_only:
+        cams = S.orbit_cameras_1297x840(n=args.views)
+        print(json.dumps({"mesh": mesh_run(cams, 2, 8, args.steps, log)}), flush=True)
+        return
     t0 = time.time()
     scene = S.spheres_background_scene()
     cams = S.orbit_cameras_1297x840(n=args.views)
@@ -553,6 +628,7 @@ def main():
     }
     if not args.main_only:
         out["supersampled"] = supersampled_run(ds, cams, K, tile, grad, min(args.steps, 24), log)
+        out["mesh"] = mesh_run(cams, K, tile, 20, log)
     if not (args.no_batched or args.main_only):
         out["batched"] = batched_comparison(ds, K, log)
     if args.large and not args.main_only:

@@ -317,8 +317,9 @@ int svr_downsample_bwd(const float* grad_out, int w_out, int h_out, float* grad_
  * sdf >= -trunc adds min(sdf / trunc, 1) with weight 1.  tsdf[m] is the mean
  * of the added values (1 when none), weight[m] their count.
  * grid_pos: device float [3][n_grid] (x row, y row, z row); cams: host
- * [n_cams], any number >= 1 (one launch per SVR_MAX_CAMERAS of them, tsdf
- * holding running sums in between); depth: device float, the cameras'
+ * [n_cams], any number >= 1 (one launch per group of consecutive cameras,
+ * at most SVR_MAX_CAMERAS whose images take at most 96 MB, tsdf holding
+ * running sums in between); depth: device float, the cameras'
  * [H][W] images concatenated in
  * camera order.  rgba: NULL (depth holds distances), or the frame's rgba
  * [P][4] with depth as svr_render_fwd writes it (the composited sum): then

@@ -678,6 +678,9 @@ int svr_downsample_bwd(const float* grad_out, int w_out, int h_out, float* grad_
   return SVR_OK;
 }
 
+// Image bytes per TSDF fusion launch (the MALL holds 256 MB).
+constexpr int64_t kFuseGroupBytes = (int64_t)96 << 20;
+
 int svr_tsdf_fuse(const float* grid_pos, int64_t n_grid, const svr_camera* cams, int n_cams,
                   const float* depth, const float* rgba, float min_alpha, float trunc, float* tsdf,
                   float* weight, void* stream) {
@@ -686,20 +689,28 @@ int svr_tsdf_fuse(const float* grid_pos, int64_t n_grid, const svr_camera* cams,
   if (!(trunc > 0.f) || !isfinite(trunc)) return fail(SVR_E_INVALID, "trunc must be finite and > 0");
   if (!isfinite(min_alpha)) return fail(SVR_E_INVALID, "min_alpha must be finite");
   if (!cams || n_cams < 1) return fail(SVR_E_INVALID, "need at least one camera");
-  // cameras in groups of SVR_MAX_CAMERAS, one launch each; the depth images
-  // stay one concatenated array
-  const int n_groups = (n_cams + SVR_MAX_CAMERAS - 1) / SVR_MAX_CAMERAS;
-  std::vector<FuseCamSet> groups((size_t)n_groups);
+  // consecutive cameras in groups of at most SVR_MAX_CAMERAS whose images
+  // (depth, plus rgba when given) stay within kFuseGroupBytes, one launch
+  // each, so that a launch's pixel gathers stay resident in the caches; the
+  // images stay one concatenated array
+  std::vector<FuseCamSet> groups;
   int64_t pix_base = 0;
-  for (int gi = 0; gi < n_groups; ++gi) {
-    const int c0 = gi * SVR_MAX_CAMERAS;
-    const int nc = std::min(SVR_MAX_CAMERAS, n_cams - c0);
+  for (int c0 = 0; c0 < n_cams;) {
+    int nc = 0;
+    int64_t bytes = 0;
+    while (c0 + nc < n_cams && nc < SVR_MAX_CAMERAS) {
+      const int64_t b = (int64_t)cams[c0 + nc].width * cams[c0 + nc].height * (rgba ? 20 : 4);
+      if (nc > 0 && bytes + b > kFuseGroupBytes) break;
+      bytes += b;
+      ++nc;
+    }
     CamSet cs;  // validation, centres and pixel offsets
     memset(&cs, 0, sizeof(cs));
     int64_t T = 0, P = 0, sat = 0;
     int st = fill_cams(cams + c0, nc, SVR_TILE, &cs, &T, &P, &sat);
     if (st != SVR_OK) return st;
-    FuseCamSet& fs = groups[(size_t)gi];
+    groups.emplace_back();
+    FuseCamSet& fs = groups.back();
     memset(&fs, 0, sizeof(fs));
     fs.n = nc;
     for (int i = 0; i < nc; ++i) {
@@ -715,7 +726,9 @@ int svr_tsdf_fuse(const float* grid_pos, int64_t n_grid, const svr_camera* cams,
       f.pix_off = pix_base + cs.c[i].pix_off;
     }
     pix_base += P;
+    c0 += nc;
   }
+  const int n_groups = (int)groups.size();
   if (n_grid == 0) return SVR_OK;
   if (!grid_pos || !depth || !tsdf || !weight) return fail(SVR_E_INVALID, "null array");
   for (int gi = 0; gi < n_groups; ++gi)

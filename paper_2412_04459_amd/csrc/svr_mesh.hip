@@ -14,8 +14,8 @@
 //                  selects up to kMaxCellTris triangles from a table built at
 //                  compile time; each vertex sits on a cell edge, is keyed by
 //                  that edge's two grid points (so neighbouring cells share
-//                  it) and placed by linear interpolation.  A wave reserves
-//                  its triangles with one atomic.
+//                  it) and placed by linear interpolation.  A workgroup
+//                  reserves the triangles of its voxels with one atomic.
 //
 // The table follows one rule per cell: on each face the crossing edges are
 // paired (two crossings: one segment; four: two segments, each cutting off
@@ -155,7 +155,7 @@ __global__ __launch_bounds__(kBlock) void k_tsdf_fuse(int64_t M, const float* __
     if (!(fu >= 0.0 && fu < (double)c.W && fv >= 0.0 && fv < (double)c.H)) continue;
     const int64_t pix = c.pix_off + (int64_t)fv * c.W + (int64_t)fu;
     float d = depth[pix];
-    if (rgba) {
+    if (rgba && d > 0.f) {  // d <= 0 gives no depth either way
       const float a = rgba[4 * pix + 3];
       d = (a >= min_alpha && a > 0.f) ? d / a : 0.f;
     }
@@ -170,64 +170,101 @@ __global__ __launch_bounds__(kBlock) void k_tsdf_fuse(int64_t M, const float* __
   weight[m] = w;
 }
 
+// Voxels per thread of the cell kernel: a workgroup covers kBlock * kCellsPer
+// consecutive voxels and reserves their triangles with one atomic.
+constexpr int kCellsPer = 4;
+
+__device__ __forceinline__ int cell_case(int64_t v, int64_t N, const int32_t* __restrict__ vox_grid,
+                                         const float* __restrict__ field,
+                                         const float* __restrict__ weight, float iso, int* g,
+                                         float* f, uint32_t& cs) {
+  cs = 0;
+  if (v >= N) return 0;
+  const int4* vg = reinterpret_cast<const int4*>(vox_grid + v * 8);
+  const int4 ga = vg[0], gb = vg[1];
+  g[0] = ga.x; g[1] = ga.y; g[2] = ga.z; g[3] = ga.w;
+  g[4] = gb.x; g[5] = gb.y; g[6] = gb.z; g[7] = gb.w;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) {
+    f[c] = field[g[c]];
+    cs |= (f[c] > iso ? 1u : 0u) << c;
+  }
+  const int n = (int)kMesh.n[cs];
+  if (n == 0 || !weight) return n;
+  // weights only matter where the surface crosses the cell
+  bool ok = true;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) ok &= weight[g[c]] != 0.f;
+  return ok ? n : 0;
+}
+
 __global__ __launch_bounds__(kBlock) void k_mesh_cells(
     int64_t N, const float* __restrict__ center, const float* __restrict__ size,
     const int32_t* __restrict__ vox_grid, const float* __restrict__ field,
     const float* __restrict__ weight, float iso, int64_t max_tris, int32_t* __restrict__ keys,
     float* __restrict__ pos, unsigned long long* __restrict__ count) {
-  const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-  const int lane = threadIdx.x & 63;
-  int g[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  float f[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
-  uint32_t cs = 0;
-  int nt = 0;
-  if (v < N) {
-    const int4* vg = reinterpret_cast<const int4*>(vox_grid + v * 8);
-    const int4 ga = vg[0], gb = vg[1];
-    g[0] = ga.x; g[1] = ga.y; g[2] = ga.z; g[3] = ga.w;
-    g[4] = gb.x; g[5] = gb.y; g[6] = gb.z; g[7] = gb.w;
-    bool ok = true;
+  __shared__ int s_wave[kBlock / 64];
+  __shared__ unsigned long long s_base;
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  const int64_t v0 = (int64_t)blockIdx.x * kBlock * kCellsPer + threadIdx.x;
+  int g[kCellsPer][8];
+  float f[kCellsPer][8];
+  uint32_t cs[kCellsPer];
+  int nt[kCellsPer];
+  int mine = 0;
 #pragma unroll
-    for (int c = 0; c < 8; ++c) {
-      f[c] = field[g[c]];
-      if (weight && weight[g[c]] == 0.f) ok = false;
-      cs |= (f[c] > iso ? 1u : 0u) << c;
-    }
-    nt = ok ? (int)kMesh.n[cs] : 0;
+  for (int r = 0; r < kCellsPer; ++r) {
+    nt[r] = cell_case(v0 + (int64_t)r * kBlock, N, vox_grid, field, weight, iso, g[r], f[r], cs[r]);
+    mine += nt[r];
   }
-  // one reservation per wave
-  int incl = nt;
+  // workgroup exclusive scan of the per-thread triangle counts
+  int incl = mine;
 #pragma unroll
   for (int o = 1; o < 64; o <<= 1) {
     const int q = __shfl_up(incl, o, 64);
     if (lane >= o) incl += q;
   }
-  const int total = __shfl(incl, 63, 64);
-  if (total == 0) return;
-  unsigned long long base = 0;
-  if (lane == 0) base = atomicAdd(count, (unsigned long long)total);
-  base = __shfl(base, 0, 64);
-  if (nt == 0) return;
-  const unsigned long long first = base + (unsigned long long)(incl - nt);
-  if (first + (unsigned long long)nt > (unsigned long long)max_tris) return;  // caller sees count
-  const float s = size[v];
-  const float ox = center[v] - 0.5f * s, oy = center[N + v] - 0.5f * s, oz = center[2 * N + v] - 0.5f * s;
-  for (int k = 0; k < nt; ++k) {
-    const int64_t tri = (int64_t)(first + (unsigned long long)k);
+  if (lane == 63) s_wave[wid] = incl;
+  __syncthreads();
+  int before = 0, total = 0;
 #pragma unroll
-    for (int j = 0; j < 3; ++j) {
-      const int code = kMesh.v[cs][3 * k + j];
-      const int a = code >> 3, b = code & 7;
-      const float t = (iso - f[a]) / (f[b] - f[a]);
-      const float ax = ox + s * (float)((a >> 2) & 1), ay = oy + s * (float)((a >> 1) & 1),
-                  az = oz + s * (float)(a & 1);
-      const float bx = ox + s * (float)((b >> 2) & 1), by = oy + s * (float)((b >> 1) & 1),
-                  bz = oz + s * (float)(b & 1);
-      pos[tri * 9 + 3 * j + 0] = ax + t * (bx - ax);
-      pos[tri * 9 + 3 * j + 1] = ay + t * (by - ay);
-      pos[tri * 9 + 3 * j + 2] = az + t * (bz - az);
-      keys[tri * 6 + 2 * j + 0] = min(g[a], g[b]);
-      keys[tri * 6 + 2 * j + 1] = max(g[a], g[b]);
+  for (int w = 0; w < kBlock / 64; ++w) {
+    const int t = s_wave[w];
+    before += w < wid ? t : 0;
+    total += t;
+  }
+  if (total == 0) return;  // uniform over the workgroup
+  if (threadIdx.x == 0) s_base = atomicAdd(count, (unsigned long long)total);
+  __syncthreads();
+  unsigned long long first = s_base + (unsigned long long)(before + incl - mine);
+#pragma unroll
+  for (int r = 0; r < kCellsPer; ++r) {
+    const int n = nt[r];
+    if (n == 0) continue;
+    const unsigned long long at = first;
+    first += (unsigned long long)n;
+    if (at + (unsigned long long)n > (unsigned long long)max_tris) continue;  // caller sees count
+    const int64_t v = v0 + (int64_t)r * kBlock;
+    const float s = size[v];
+    const float ox = center[v] - 0.5f * s, oy = center[N + v] - 0.5f * s,
+                oz = center[2 * N + v] - 0.5f * s;
+    for (int k = 0; k < n; ++k) {
+      const int64_t tri = (int64_t)(at + (unsigned long long)k);
+#pragma unroll
+      for (int j = 0; j < 3; ++j) {
+        const int code = kMesh.v[cs[r]][3 * k + j];
+        const int a = code >> 3, b = code & 7;
+        const float t = (iso - f[r][a]) / (f[r][b] - f[r][a]);
+        const float ax = ox + s * (float)((a >> 2) & 1), ay = oy + s * (float)((a >> 1) & 1),
+                    az = oz + s * (float)(a & 1);
+        const float bx = ox + s * (float)((b >> 2) & 1), by = oy + s * (float)((b >> 1) & 1),
+                    bz = oz + s * (float)(b & 1);
+        pos[tri * 9 + 3 * j + 0] = ax + t * (bx - ax);
+        pos[tri * 9 + 3 * j + 1] = ay + t * (by - ay);
+        pos[tri * 9 + 3 * j + 2] = az + t * (bz - az);
+        keys[tri * 6 + 2 * j + 0] = min(g[r][a], g[r][b]);
+        keys[tri * 6 + 2 * j + 1] = max(g[r][a], g[r][b]);
+      }
     }
   }
 }
@@ -247,7 +284,8 @@ hipError_t launch_mesh_cells(const svr_scene& sc, const float* field, const floa
                              hipStream_t s) {
   hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(count), 0u, 2, s);
   if (e != hipSuccess || sc.n_voxels == 0) return e;
-  SVR_LAUNCH("mesh_cells", k_mesh_cells, dim3((unsigned)((sc.n_voxels + kBlock - 1) / kBlock)),
+  const int64_t per = (int64_t)kBlock * kCellsPer;
+  SVR_LAUNCH("mesh_cells", k_mesh_cells, dim3((unsigned)((sc.n_voxels + per - 1) / per)),
              dim3(kBlock), 0, s, sc.n_voxels, sc.center, sc.size, sc.vox_grid, field, weight, iso,
              max_tris, keys, pos, count);
   return hipGetLastError();

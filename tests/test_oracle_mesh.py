@@ -141,3 +141,12 @@ def test_tsdf_of_a_plane_along_pixel_rays_in_closed_form():
     # pixels without depth are not integrated
     val3, w3 = mesh.tsdf_fuse(pts, [cam], [np.zeros_like(depth)], trunc)
     assert np.all(w3 == 0) and np.all(val3 == 1.0)
+    # the renderer's composited depth with opacity A: the sum D A divided by
+    # A where A >= min_alpha gives the same distances; below it, no depth
+    A = rng.uniform(0.55, 1.0, size=depth.shape).astype(np.float32)
+    comp = (depth * A).astype(np.float32)
+    val4, w4 = mesh.tsdf_fuse(pts, [cam], [comp], trunc, alphas=[A], min_alpha=0.5)
+    assert np.array_equal(w4, w)
+    assert np.allclose(val4, val, atol=2e-6 / trunc)
+    val5, w5 = mesh.tsdf_fuse(pts, [cam], [comp], trunc, alphas=[A * 0.5], min_alpha=0.5)
+    assert np.all(w5 == 0) and np.all(val5 == 1.0)
