@@ -138,7 +138,10 @@ __global__ __launch_bounds__(kBlock) void k_tsdf_fuse(int64_t M, const float* __
                                                       float* __restrict__ tsdf,
                                                       float* __restrict__ weight, int first,
                                                       int last) {
-  const int64_t m = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  // contiguous grid points per XCD: they are spatial neighbours, whose
+  // projections fall on the same image lines, read once per L2
+  const int64_t nb = (M + kBlock - 1) / kBlock;
+  const int64_t m = xcd_block(blockIdx.x, nb) * kBlock + threadIdx.x;
   if (m >= M) return;
   const double px = gp[m], py = gp[M + m], pz = gp[2 * M + m];
   // between camera groups tsdf holds the running sum of the added values
@@ -273,7 +276,8 @@ hipError_t launch_tsdf_fuse(const float* grid_pos, int64_t M, const FuseCamSet& 
                             const float* rgba, float min_alpha, float trunc, float* tsdf,
                             float* weight, bool first, bool last, hipStream_t s) {
   if (M <= 0) return hipSuccess;
-  SVR_LAUNCH("tsdf_fuse", k_tsdf_fuse, dim3((unsigned)((M + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
+  const int64_t nb = (M + kBlock - 1) / kBlock;
+  SVR_LAUNCH("tsdf_fuse", k_tsdf_fuse, dim3((unsigned)(((nb + 7) >> 3) << 3)), dim3(kBlock), 0, s,
              M, grid_pos, cams, depth, rgba, min_alpha, trunc, tsdf, weight, first ? 1 : 0,
              last ? 1 : 0);
   return hipGetLastError();
