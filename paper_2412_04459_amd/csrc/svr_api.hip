@@ -83,7 +83,7 @@ int bits_for(int64_t x) {  // bits needed to hold values 0..x
 // Device camera records (fp64 centre, rotation, intrinsics, tile and pixel
 // offsets of the concatenated images) for n_cams host cameras.
 int fill_cams(const svr_camera* cams, int n_cams, int tile, CamSet* cs, int64_t* T_out,
-              int64_t* P_out, int64_t* sat_out) {
+              int64_t* P_out, int64_t* sat_out, int first_index = 0) {
   if (!cams) return fail(SVR_E_INVALID, "null camera pointer");
   if (n_cams < 1 || n_cams > SVR_MAX_CAMERAS)
     return fail(SVR_E_INVALID, "n_cams=%d outside 1..%d", n_cams, SVR_MAX_CAMERAS);
@@ -95,11 +95,13 @@ int fill_cams(const svr_camera* cams, int n_cams, int tile, CamSet* cs, int64_t*
   for (int i = 0; i < n_cams; ++i) {
     const svr_camera& c = cams[i];
     if (c.width < 1 || c.height < 1 || c.width > 16384 || c.height > 16384)
-      return fail(SVR_E_INVALID, "camera %d: size %dx%d outside 1..16384", i, c.width, c.height);
+      return fail(SVR_E_INVALID, "camera %d: size %dx%d outside 1..16384", first_index + i,
+                  c.width, c.height);
     if (!(c.fx > 0.f) || !(c.fy > 0.f) || !isfinite(c.cx) || !isfinite(c.cy))
-      return fail(SVR_E_INVALID, "camera %d: bad intrinsics", i);
+      return fail(SVR_E_INVALID, "camera %d: bad intrinsics", first_index + i);
     for (int k = 0; k < 12; ++k)
-      if (!isfinite(c.w2c[k])) return fail(SVR_E_INVALID, "camera %d: non-finite pose", i);
+      if (!isfinite(c.w2c[k]))
+        return fail(SVR_E_INVALID, "camera %d: non-finite pose", first_index + i);
     DevCam& d = cs->c[i];
     for (int r = 0; r < 3; ++r)
       for (int j = 0; j < 3; ++j) d.r[3 * r + j] = c.w2c[4 * r + j];
@@ -707,7 +709,7 @@ int svr_tsdf_fuse(const float* grid_pos, int64_t n_grid, const svr_camera* cams,
     CamSet cs;  // validation, centres and pixel offsets
     memset(&cs, 0, sizeof(cs));
     int64_t T = 0, P = 0, sat = 0;
-    int st = fill_cams(cams + c0, nc, SVR_TILE, &cs, &T, &P, &sat);
+    int st = fill_cams(cams + c0, nc, SVR_TILE, &cs, &T, &P, &sat, c0);
     if (st != SVR_OK) return st;
     groups.emplace_back();
     FuseCamSet& fs = groups.back();

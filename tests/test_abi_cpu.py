@@ -214,3 +214,21 @@ def test_mesh_entry_points_check_arguments():
     assert _abi.svr_marching_cubes(sc, None, None, 0.0, 10, p, p, p, None) == _abi.SVR_E_INVALID
     sc.n_grid = 1 << 31
     assert _abi.svr_marching_cubes(sc, p, None, 0.0, 10, p, p, p, None) == _abi.SVR_E_INVALID
+
+
+def test_tsdf_fusion_checks_every_camera_beyond_one_group():
+    """More cameras than one launch takes: each is still validated, and the
+    error names its index in the caller's array."""
+    _lib()
+    n = 40
+    cams = (_abi.svr_camera * n)()
+    for c in cams:
+        c.width, c.height = 32, 24
+        c.fx = c.fy = 30.0
+        c.cx, c.cy = 16.0, 12.0
+        for k, v in enumerate([1, 0, 0, 0, 0, 1, 0, 0, 0, 0, 1, 3]):
+            c.w2c[k] = v
+    p = ctypes.c_void_p(0x100000)
+    cams[35].fx = -1.0
+    assert _abi.svr_tsdf_fuse(p, 10, cams, n, p, None, 0.5, 0.1, p, p, None) == _abi.SVR_E_INVALID
+    assert "camera 35" in _abi.svr_last_error()

@@ -282,3 +282,44 @@ def test_mesh_at_the_orbit_scene_size(torch_dev):
         q = got.get(tuple(r))
         assert q is not None, "oracle triangle %s missing" % (tuple(r),)
         assert np.abs(q - p).max() <= POS_REL * sc.world_size
+
+
+def test_rendered_depths_fuse_into_the_sphere_surface(torch_dev):
+    """The extraction pipeline as the paper runs it: render depth and opacity
+    of an opaque scene from several views, fuse them at the grid points, and
+    extract the zero level set.  The scene is a level-6 shell of the sphere
+    |p| = 0.5 (finest voxel h = 1/64): the mesh vertices must lie on that
+    sphere within a voxel (the opacity builds up over the outermost voxel
+    layer, so the rendered surface sits a fraction of a voxel outside)."""
+    torch = torch_dev
+    from paper_2412_04459_amd.render import DeviceScene, Rasterizer, marching_cubes, tsdf_fuse
+    sc = S.sphere_shell_scene(opaque=True)
+    h = sc.world_size / 2 ** sc.max_level
+    rng = np.random.default_rng(31)
+    cams = []
+    for _ in range(12):
+        d = np.abs(S.random_direction(rng)) + 0.2
+        d /= np.linalg.norm(d)
+        cams.append(S.look_at(96, 96, 45.0, 1.8 * d, target=(0.3, 0.3, 0.3)))
+    ds = DeviceScene(sc)
+    rast = Rasterizer(ds, [cams[0]], K=2)
+    P = sum(c.W * c.H for c in cams)
+    rgba = torch.empty((P, 4), dtype=torch.float32, device="cuda")
+    dep = torch.empty(P, dtype=torch.float32, device="cuda")
+    off = 0
+    for c in cams:
+        n = c.W * c.H
+        rast.set_cameras([c])
+        rast.forward(out=rgba[off:off + n], depth=dep[off:off + n])
+        off += n
+    tsdf, w = tsdf_fuse(ds.grid_pos, cams, dep, 3.0 * h, rgba, 0.5)
+    keys, pos = marching_cubes(ds, tsdf, 0.0, w)
+    torch.cuda.synchronize()
+    p = pos.cpu().numpy().reshape(-1, 3).astype(np.float64)
+    _say("pipeline: %d triangles, %d observed grid points" % (keys.shape[0], int((w > 0).sum())))
+    assert keys.shape[0] > 500
+    err = np.abs(np.linalg.norm(p, axis=1) - 0.5) / h
+    _say("vertex distance to the sphere in voxels: median %.3f, p95 %.3f, max %.3f"
+         % (np.median(err), np.quantile(err, 0.95), err.max()))
+    assert np.median(err) < 0.5
+    assert np.quantile(err, 0.95) < 1.0
