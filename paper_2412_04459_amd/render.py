@@ -551,7 +551,9 @@ def tsdf_fuse(grid_pos: torch.Tensor, cams: Sequence, depth: torch.Tensor, trunc
     [3, M]; depth [sum H*W] of the cameras in order (with ``rgba``: the
     renderer's composited depth, divided by the opacity where it reaches
     ``min_alpha``).  Returns (tsdf [M], weight [M])."""
-    M = grid_pos.shape[-1]
+    if grid_pos.dim() != 2 or grid_pos.shape[0] != 3:
+        raise ValueError("grid_pos must be [3, M] (x row, y row, z row)")
+    M = grid_pos.shape[1]
     _f32_dev(grid_pos, "grid_pos", 3 * M)
     P = int(sum(c.W * c.H for c in cams))
     _f32_dev(depth, "depth", P)
