@@ -196,7 +196,7 @@ def mesh_run(cams, K, tile, reps, log):
     import torch
     from paper_2412_04459_amd import scenes as S
     from paper_2412_04459_amd.render import (DeviceScene, Rasterizer, marching_cubes,
-                                             marching_cubes_into, tsdf_fuse)
+                                             marching_cubes_into, morton_order, tsdf_fuse)
     scene = S.spheres_background_scene(opaque=True)
     ds = DeviceScene(scene)
     rast = Rasterizer(ds, [cams[0]], K=K, tile=tile)
@@ -211,8 +211,11 @@ def mesh_run(cams, K, tile, reps, log):
         off += n
     torch.cuda.synchronize()
     trunc = 4.0 * scene.world_size / 2 ** scene.max_level
-    tsdf, w = tsdf_fuse(ds.grid_pos, cams, dep, trunc, rgba, 0.5)
-    keys, pos = marching_cubes(ds, tsdf, 0.0, w)
+    # Z-curve visit orders of the grid points and voxels (once per scene)
+    g_order = morton_order(ds.grid_pos, ds.world_lo, ds.world_size)
+    v_order = morton_order(ds.center, ds.world_lo, ds.world_size)
+    tsdf, w = tsdf_fuse(ds.grid_pos, cams, dep, trunc, rgba, 0.5, order=g_order)
+    keys, pos = marching_cubes(ds, tsdf, 0.0, w, order=v_order)
     n_tri = keys.shape[0]
     cap = n_tri + 1024
     keys = torch.empty((cap, 3, 2), dtype=torch.int32, device="cuda")
@@ -231,20 +234,25 @@ def mesh_run(cams, K, tile, reps, log):
         torch.cuda.synchronize()
         return e0.elapsed_time(e1) / reps
 
-    t_ms = timed(lambda: tsdf_fuse(ds.grid_pos, cams, dep, trunc, rgba, 0.5, tsdf, w))
-    m_ms = timed(lambda: marching_cubes_into(ds, tsdf, keys, pos, count, 0.0, w))
+    t_ms = timed(lambda: tsdf_fuse(ds.grid_pos, cams, dep, trunc, rgba, 0.5, tsdf, w,
+                                   order=g_order))
+    m_ms = timed(lambda: marching_cubes_into(ds, tsdf, keys, pos, count, 0.0, w, order=v_order))
+    t_ms_own = timed(lambda: tsdf_fuse(ds.grid_pos, cams, dep, trunc, rgba, 0.5, tsdf, w))
+    m_ms_own = timed(lambda: marching_cubes_into(ds, tsdf, keys, pos, count, 0.0, w))
     assert int(count.item()) == n_tri
     M, N = scene.n_grid, scene.n_voxels
     obs = float(w.double().sum().item())
     t_bytes = 20.0 * M + 8.0 * obs
     m_bytes = 48.0 * N + 8.0 * M + 60.0 * n_tri
     observed = int((w > 0).sum().item())
-    log("mesh: tsdf %.3f ms (%d views, %d grid points), marching cubes %.3f ms, %d triangles"
-        % (t_ms, len(cams), M, m_ms, n_tri))
+    log("mesh: tsdf %.3f ms (%d views, %d grid points), marching cubes %.3f ms, %d triangles "
+        "(own order: %.3f / %.3f ms)" % (t_ms, len(cams), M, m_ms, n_tri, t_ms_own, m_ms_own))
     del rast, ds
     return {"scene": "orbit scene, opaque surfaces", "views": len(cams), "grid_points": M,
             "voxels": N, "trunc": trunc,
             "observed_grid_points": observed, "triangles": n_tri,
+            "visit_order": "Z-curve of grid points / voxel centres (svr_morton_keys)",
+            "tsdf_ms_own_order": t_ms_own, "marching_cubes_ms_own_order": m_ms_own,
             "tsdf": {"ms": t_ms, "bytes": t_bytes, "achieved_GBs": t_bytes / t_ms / 1e6,
                      "frac": t_bytes / t_ms / 1e6 / HBM_PEAK_GBS},
             "marching_cubes": {"ms": m_ms, "bytes": m_bytes, "achieved_GBs": m_bytes / m_ms / 1e6,

@@ -317,9 +317,10 @@ int svr_downsample_bwd(const float* grad_out, int w_out, int h_out, float* grad_
  * sdf >= -trunc adds min(sdf / trunc, 1) with weight 1.  tsdf[m] is the mean
  * of the added values (1 when none), weight[m] their count.
  * grid_pos: device float [3][n_grid] (x row, y row, z row); cams: host
- * [n_cams], any number >= 1 (one launch per group of consecutive cameras,
- * at most SVR_MAX_CAMERAS whose images take at most 96 MB, tsdf holding
- * running sums in between); depth: device float, the cameras'
+ * [n_cams], any number >= 1 (one launch per group of consecutive cameras:
+ * SVR_MAX_CAMERAS, or with order NULL as many as keep the images within
+ * 96 MB; tsdf holds running sums in between); depth: device float, the
+ * cameras'
  * [H][W] images concatenated in
  * camera order.  rgba: NULL (depth holds distances), or the frame's rgba
  * [P][4] with depth as svr_render_fwd writes it (the composited sum): then
@@ -352,10 +353,24 @@ int svr_downsample_bwd(const float* grad_out, int w_out, int h_out, float* grad_
  * Errors: SVR_E_INVALID (sizes, non-finite iso, null arrays), SVR_E_HIP.   */
 int svr_tsdf_fuse(const float* grid_pos, int64_t n_grid, const svr_camera* cams, int n_cams,
                   const float* depth, const float* rgba, float min_alpha, float trunc, float* tsdf,
-                  float* weight, void* stream);
+                  float* weight, const uint32_t* order, void* stream);
 int svr_marching_cubes(const svr_scene* scene, const float* field, const float* weight, float iso,
                        int64_t max_triangles, int32_t* tri_keys, float* tri_pos,
-                       unsigned long long* n_triangles, void* stream);
+                       unsigned long long* n_triangles, const uint32_t* order, void* stream);
+/* Visit order of the two calls above (`order`: NULL, or a device uint32
+ * permutation of the grid points, resp. of the voxels, that the threads visit
+ * in that order; results do not depend on it, speed does: points in
+ * arbitrary order scatter the pixel and corner gathers).  svr_morton_keys
+ * writes the Z-curve key of every point of pos (device float [3][n], x, y, z
+ * rows) quantised to 1024 cells per axis of the cube [lo, lo + extent)
+ * (lo: host float[3]; coordinates outside clamp to the border cells) into
+ * keys (device uint64 [n], 30 bits) and 0..n-1 into values (device uint32
+ * [n]); svr_radix_sort_pairs(keys, values, ..., bits = 30) then leaves the
+ * order in values.  Entries of `order` outside [0, n) are skipped; a
+ * permutation is not checked.  Errors: SVR_E_INVALID (n outside
+ * [0, 2^32), non-finite lo, extent not finite > 0, null arrays), SVR_E_HIP. */
+int svr_morton_keys(const float* pos, int64_t n, const float* lo, float extent, uint64_t* keys,
+                    uint32_t* values, void* stream);
 /* The cell table svr_marching_cubes uses (host memory, no GPU needed):
  * counts[case] triangles for case = sum over above corners c of 2^c;
  * verts[case][3 t + j] vertex j of triangle t as its corner pair a << 3 | b

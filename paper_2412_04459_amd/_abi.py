@@ -79,8 +79,9 @@ _SIGS = {
                                           ctypes.c_int, P, P]),
     "svr_graph_destroy": (ctypes.c_int, [P]),
     "svr_tsdf_fuse": (ctypes.c_int, [P, I64, P, ctypes.c_int, P, P, ctypes.c_float, ctypes.c_float,
-                                     P, P, P]),
-    "svr_marching_cubes": (ctypes.c_int, [P, P, P, ctypes.c_float, I64, P, P, P, P]),
+                                     P, P, P, P]),
+    "svr_marching_cubes": (ctypes.c_int, [P, P, P, ctypes.c_float, I64, P, P, P, P, P]),
+    "svr_morton_keys": (ctypes.c_int, [P, I64, P, ctypes.c_float, P, P, P]),
     "svr_mesh_case_table": (ctypes.c_int, [P, P]),
     "svr_grid_adjacency_scratch_bytes": (ctypes.c_size_t, [I64, I64]),
     "svr_build_grid_adjacency": (ctypes.c_int, [P, I64, I64, P, P, P, ctypes.c_size_t, P]),
@@ -279,16 +280,19 @@ def svr_build_order_ranks(octpath, n_voxels, max_level, rank, scratch, scratch_b
 
 
 def svr_tsdf_fuse(grid_pos, n_grid, cams, n_cams, depth, rgba, min_alpha, trunc, tsdf, weight,
-                  stream):
+                  order, stream):
     return load().svr_tsdf_fuse(grid_pos, n_grid, cams, n_cams, depth, rgba, min_alpha, trunc,
-                                tsdf, weight, stream)
+                                tsdf, weight, order, stream)
 
 
 def svr_marching_cubes(scene, field, weight, iso, max_triangles, tri_keys, tri_pos, n_triangles,
-                       stream):
+                       order, stream):
     return load().svr_marching_cubes(_ref(scene), field, weight, iso, max_triangles, tri_keys,
-                                     tri_pos,
-                                     n_triangles, stream)
+                                     tri_pos, n_triangles, order, stream)
+
+
+def svr_morton_keys(pos, n, lo, extent, keys, values, stream):
+    return load().svr_morton_keys(pos, n, lo, extent, keys, values, stream)
 
 
 def svr_mesh_case_table(counts, verts):

@@ -685,7 +685,7 @@ constexpr int64_t kFuseGroupBytes = (int64_t)96 << 20;
 
 int svr_tsdf_fuse(const float* grid_pos, int64_t n_grid, const svr_camera* cams, int n_cams,
                   const float* depth, const float* rgba, float min_alpha, float trunc, float* tsdf,
-                  float* weight, void* stream) {
+                  float* weight, const uint32_t* order, void* stream) {
   if (n_grid < 0 || n_grid >= ((int64_t)1 << 31))
     return fail(SVR_E_INVALID, "n_grid=%lld outside [0, 2^31)", (long long)n_grid);
   if (!(trunc > 0.f) || !isfinite(trunc)) return fail(SVR_E_INVALID, "trunc must be finite and > 0");
@@ -702,7 +702,9 @@ int svr_tsdf_fuse(const float* grid_pos, int64_t n_grid, const svr_camera* cams,
     int64_t bytes = 0;
     while (c0 + nc < n_cams && nc < SVR_MAX_CAMERAS) {
       const int64_t b = (int64_t)cams[c0 + nc].width * cams[c0 + nc].height * (rgba ? 20 : 4);
-      if (nc > 0 && bytes + b > kFuseGroupBytes) break;
+      // a Morton visit order keeps the gathers local at any footprint; it makes
+      // the running sums' round trips between launches scattered instead
+      if (nc > 0 && !order && bytes + b > kFuseGroupBytes) break;
       bytes += b;
       ++nc;
     }
@@ -735,7 +737,7 @@ int svr_tsdf_fuse(const float* grid_pos, int64_t n_grid, const svr_camera* cams,
   if (!grid_pos || !depth || !tsdf || !weight) return fail(SVR_E_INVALID, "null array");
   for (int gi = 0; gi < n_groups; ++gi)
     SVR_HIP(launch_tsdf_fuse(grid_pos, n_grid, groups[(size_t)gi], depth, rgba, min_alpha, trunc,
-                             tsdf, weight, gi == 0, gi == n_groups - 1,
+                             tsdf, weight, order, gi == 0, gi == n_groups - 1,
                              reinterpret_cast<hipStream_t>(stream)),
             "tsdf fusion");
   return SVR_OK;
@@ -749,7 +751,7 @@ int svr_mesh_case_table(uint8_t* counts, uint8_t* verts) {
 
 int svr_marching_cubes(const svr_scene* scene, const float* field, const float* weight, float iso,
                        int64_t max_triangles, int32_t* tri_keys, float* tri_pos,
-                       unsigned long long* n_triangles, void* stream) {
+                       unsigned long long* n_triangles, const uint32_t* order, void* stream) {
   if (!scene) return fail(SVR_E_INVALID, "null scene");
   if (scene->n_voxels < 0 || scene->n_voxels >= (int64_t)SVR_MAX_VOXELS)
     return fail(SVR_E_INVALID, "n_voxels=%lld outside [0, 2^29)", (long long)scene->n_voxels);
@@ -762,8 +764,21 @@ int svr_marching_cubes(const svr_scene* scene, const float* field, const float* 
   if (scene->n_voxels > 0 && (!scene->center || !scene->size || !scene->vox_grid || !field))
     return fail(SVR_E_INVALID, "null scene array or field");
   SVR_HIP(launch_mesh_cells(*scene, field, weight, iso, max_triangles, tri_keys, tri_pos,
-                            n_triangles, reinterpret_cast<hipStream_t>(stream)),
+                            n_triangles, order, reinterpret_cast<hipStream_t>(stream)),
           "marching cubes");
+  return SVR_OK;
+}
+
+int svr_morton_keys(const float* pos, int64_t n, const float* lo, float extent, uint64_t* keys,
+                    uint32_t* values, void* stream) {
+  if (n < 0 || n >= ((int64_t)1 << 32)) return fail(SVR_E_INVALID, "n outside [0, 2^32)");
+  if (!lo || !isfinite(lo[0]) || !isfinite(lo[1]) || !isfinite(lo[2]))
+    return fail(SVR_E_INVALID, "lo must be 3 finite floats");
+  if (!(extent > 0.f) || !isfinite(extent)) return fail(SVR_E_INVALID, "extent must be finite > 0");
+  if (n == 0) return SVR_OK;
+  if (!pos || !keys || !values) return fail(SVR_E_INVALID, "null array");
+  SVR_HIP(launch_morton_keys(pos, n, lo, extent, keys, values, reinterpret_cast<hipStream_t>(stream)),
+          "morton keys");
   return SVR_OK;
 }
 

@@ -224,10 +224,13 @@ struct FuseCamSet {
 };
 hipError_t launch_tsdf_fuse(const float* grid_pos, int64_t M, const FuseCamSet& cams, const float* depth,
                             const float* rgba, float min_alpha, float trunc, float* tsdf,
-                            float* weight, bool first, bool last, hipStream_t s);
+                            float* weight, const uint32_t* order, bool first, bool last,
+                            hipStream_t s);
 hipError_t launch_mesh_cells(const svr_scene& sc, const float* field, const float* weight, float iso,
                              int64_t max_tris, int32_t* keys, float* pos, unsigned long long* count,
-                             hipStream_t s);
+                             const uint32_t* order, hipStream_t s);
+hipError_t launch_morton_keys(const float* pos, int64_t n, const float* lo, float extent,
+                              uint64_t* keys, uint32_t* vals, hipStream_t s);
 void mesh_case_table(uint8_t* counts, uint8_t* verts);  // [256], [256][36]
 hipError_t launch_render_stats(const svr_scene& sc, const CamSet& cams, const svr_opts& o,
                                const Layout& L, void* ws, const uint32_t* vals, hipStream_t s);

@@ -136,13 +136,17 @@ __global__ __launch_bounds__(kBlock) void k_tsdf_fuse(int64_t M, const float* __
                                                       const float* __restrict__ rgba,
                                                       float min_alpha, float trunc,
                                                       float* __restrict__ tsdf,
-                                                      float* __restrict__ weight, int first,
-                                                      int last) {
-  // contiguous grid points per XCD: they are spatial neighbours, whose
-  // projections fall on the same image lines, read once per L2
+                                                      float* __restrict__ weight,
+                                                      const uint32_t* __restrict__ order,
+                                                      int first, int last) {
+  // contiguous grid points per XCD: spatial neighbours when the visit order
+  // is, whose projections fall on the same image lines, read once per L2
   const int64_t nb = (M + kBlock - 1) / kBlock;
-  const int64_t m = xcd_block(blockIdx.x, nb) * kBlock + threadIdx.x;
-  if (m >= M) return;
+  const int64_t i = xcd_block(blockIdx.x, nb) * kBlock + threadIdx.x;
+  if (i >= M) return;
+  // visit order (a Morton order keeps a wave's projections on few image lines)
+  const int64_t m = order ? (int64_t)order[i] : i;
+  if (m >= M) return;  // not a permutation entry
   const double px = gp[m], py = gp[M + m], pz = gp[2 * M + m];
   // between camera groups tsdf holds the running sum of the added values
   float acc = first ? 0.f : tsdf[m], w = first ? 0.f : weight[m];
@@ -205,7 +209,8 @@ __global__ __launch_bounds__(kBlock) void k_mesh_cells(
     int64_t N, const float* __restrict__ center, const float* __restrict__ size,
     const int32_t* __restrict__ vox_grid, const float* __restrict__ field,
     const float* __restrict__ weight, float iso, int64_t max_tris, int32_t* __restrict__ keys,
-    float* __restrict__ pos, unsigned long long* __restrict__ count) {
+    float* __restrict__ pos, unsigned long long* __restrict__ count,
+    const uint32_t* __restrict__ order) {
   __shared__ int s_wave[kBlock / 64];
   __shared__ unsigned long long s_base;
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
@@ -214,10 +219,13 @@ __global__ __launch_bounds__(kBlock) void k_mesh_cells(
   float f[kCellsPer][8];
   uint32_t cs[kCellsPer];
   int nt[kCellsPer];
+  int64_t vr[kCellsPer];
   int mine = 0;
 #pragma unroll
   for (int r = 0; r < kCellsPer; ++r) {
-    nt[r] = cell_case(v0 + (int64_t)r * kBlock, N, vox_grid, field, weight, iso, g[r], f[r], cs[r]);
+    const int64_t i = v0 + (int64_t)r * kBlock;
+    vr[r] = (order && i < N) ? (int64_t)order[i] : i;  // visit order
+    nt[r] = cell_case(vr[r], N, vox_grid, field, weight, iso, g[r], f[r], cs[r]);
     mine += nt[r];
   }
   // workgroup exclusive scan of the per-thread triangle counts
@@ -247,7 +255,7 @@ __global__ __launch_bounds__(kBlock) void k_mesh_cells(
     const unsigned long long at = first;
     first += (unsigned long long)n;
     if (at + (unsigned long long)n > (unsigned long long)max_tris) continue;  // caller sees count
-    const int64_t v = v0 + (int64_t)r * kBlock;
+    const int64_t v = vr[r];
     const float s = size[v];
     const float ox = center[v] - 0.5f * s, oy = center[N + v] - 0.5f * s,
                 oz = center[2 * N + v] - 0.5f * s;
@@ -272,26 +280,62 @@ __global__ __launch_bounds__(kBlock) void k_mesh_cells(
   }
 }
 
+// 10 bits of a coordinate spread to every third bit
+__device__ __forceinline__ uint64_t spread3(uint32_t x) {
+  uint64_t v = x & 0x3ffu;
+  v = (v | (v << 16)) & 0x30000ffull;
+  v = (v | (v << 8)) & 0x300f00full;
+  v = (v | (v << 4)) & 0x30c30c3ull;
+  v = (v | (v << 2)) & 0x9249249ull;
+  return v;
+}
+
+__global__ __launch_bounds__(kBlock) void k_morton_keys(int64_t n, const float* __restrict__ pos,
+                                                        float lx, float ly, float lz, float inv,
+                                                        uint64_t* __restrict__ keys,
+                                                        uint32_t* __restrict__ vals) {
+  const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+  if (i >= n) return;
+  const float q[3] = {(pos[i] - lx) * inv, (pos[n + i] - ly) * inv, (pos[2 * n + i] - lz) * inv};
+  uint32_t c[3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    const float t = fminf(fmaxf(q[a], 0.f), 1023.f);  // NaN -> 0
+    c[a] = (uint32_t)t;
+  }
+  keys[i] = spread3(c[0]) << 2 | spread3(c[1]) << 1 | spread3(c[2]);
+  vals[i] = (uint32_t)i;
+}
+
+hipError_t launch_morton_keys(const float* pos, int64_t n, const float* lo, float extent,
+                              uint64_t* keys, uint32_t* vals, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  SVR_LAUNCH("morton_keys", k_morton_keys, dim3((unsigned)((n + kBlock - 1) / kBlock)), dim3(kBlock),
+             0, s, n, pos, lo[0], lo[1], lo[2], 1024.f / extent, keys, vals);
+  return hipGetLastError();
+}
+
 hipError_t launch_tsdf_fuse(const float* grid_pos, int64_t M, const FuseCamSet& cams, const float* depth,
                             const float* rgba, float min_alpha, float trunc, float* tsdf,
-                            float* weight, bool first, bool last, hipStream_t s) {
+                            float* weight, const uint32_t* order, bool first, bool last,
+                            hipStream_t s) {
   if (M <= 0) return hipSuccess;
   const int64_t nb = (M + kBlock - 1) / kBlock;
   SVR_LAUNCH("tsdf_fuse", k_tsdf_fuse, dim3((unsigned)(((nb + 7) >> 3) << 3)), dim3(kBlock), 0, s,
-             M, grid_pos, cams, depth, rgba, min_alpha, trunc, tsdf, weight, first ? 1 : 0,
+             M, grid_pos, cams, depth, rgba, min_alpha, trunc, tsdf, weight, order, first ? 1 : 0,
              last ? 1 : 0);
   return hipGetLastError();
 }
 
 hipError_t launch_mesh_cells(const svr_scene& sc, const float* field, const float* weight, float iso,
                              int64_t max_tris, int32_t* keys, float* pos, unsigned long long* count,
-                             hipStream_t s) {
+                             const uint32_t* order, hipStream_t s) {
   hipError_t e = launch_fill_u32(reinterpret_cast<uint32_t*>(count), 0u, 2, s);
   if (e != hipSuccess || sc.n_voxels == 0) return e;
   const int64_t per = (int64_t)kBlock * kCellsPer;
   SVR_LAUNCH("mesh_cells", k_mesh_cells, dim3((unsigned)((sc.n_voxels + per - 1) / per)),
              dim3(kBlock), 0, s, sc.n_voxels, sc.center, sc.size, sc.vox_grid, field, weight, iso,
-             max_tris, keys, pos, count);
+             max_tris, keys, pos, count, order);
   return hipGetLastError();
 }
 

@@ -50,6 +50,9 @@ class DeviceScene:
         dev = torch.device(device)
         self.n_voxels = int(scene.n_voxels)
         self.n_grid = int(scene.n_grid)
+        # bounding cube of the scene (visit orders of the mesh kernels)
+        self.world_lo = [float(x) - 0.5 * float(scene.world_size) for x in scene.world_center]
+        self.world_size = float(scene.world_size)
         self.sh_degree = int(scene.sh_degree)
         self.max_level = int(scene.max_level)
         self.center = torch.from_numpy(np.ascontiguousarray(scene.center, np.float32)).to(dev)
@@ -544,13 +547,33 @@ def _f32_dev(t, name, n=None):
     return t
 
 
+def morton_order(pos: torch.Tensor, lo, extent: float) -> torch.Tensor:
+    """Z-curve visit order (int32 [n]) of the points pos (float32 [3, n]) in
+    the cube [lo, lo + extent): svr_morton_keys, then svr_radix_sort_pairs on
+    the 30 key bits."""
+    if pos.dim() != 2 or pos.shape[0] != 3:
+        raise ValueError("pos must be [3, n]")
+    n = pos.shape[1]
+    _f32_dev(pos, "pos", 3 * n)
+    keys = torch.empty(max(n, 1), dtype=torch.int64, device=pos.device)
+    vals = torch.empty(max(n, 1), dtype=torch.int32, device=pos.device)
+    lo3 = (ctypes.c_float * 3)(*[float(x) for x in lo])
+    check(_abi.svr_morton_keys(_ptr(pos), n, lo3, float(extent), _ptr(keys), _ptr(vals),
+                               _stream()), "svr_morton_keys")
+    radix_sort_pairs(keys[:n], vals[:n], bits=30)
+    return vals[:n]
+
+
 def tsdf_fuse(grid_pos: torch.Tensor, cams: Sequence, depth: torch.Tensor, trunc: float,
               rgba: Optional[torch.Tensor] = None, min_alpha: float = 0.5,
-              tsdf: Optional[torch.Tensor] = None, weight: Optional[torch.Tensor] = None):
+              tsdf: Optional[torch.Tensor] = None, weight: Optional[torch.Tensor] = None,
+              order: Optional[torch.Tensor] = None):
     """Fused truncated signed distances (svr_tsdf_fuse).  grid_pos float32
     [3, M]; depth [sum H*W] of the cameras in order (with ``rgba``: the
     renderer's composited depth, divided by the opacity where it reaches
-    ``min_alpha``).  Returns (tsdf [M], weight [M])."""
+    ``min_alpha``); ``order`` (int32 [M]): visit order of the grid points
+    (``morton_order``), None for their own order.  Returns (tsdf [M],
+    weight [M])."""
     if grid_pos.dim() != 2 or grid_pos.shape[0] != 3:
         raise ValueError("grid_pos must be [3, M] (x row, y row, z row)")
     M = grid_pos.shape[1]
@@ -565,16 +588,27 @@ def tsdf_fuse(grid_pos: torch.Tensor, cams: Sequence, depth: torch.Tensor, trunc
         weight = torch.empty(M, dtype=torch.float32, device=grid_pos.device)
     _f32_dev(tsdf, "tsdf", M)
     _f32_dev(weight, "weight", M)
+    _check_order(order, M, grid_pos.device)
     arr = camera_structs(cams)
     check(_abi.svr_tsdf_fuse(_ptr(grid_pos), M, arr, len(cams), _ptr(depth), _ptr(rgba),
                              float(min_alpha), float(trunc), _ptr(tsdf), _ptr(weight),
-                             _stream()), "svr_tsdf_fuse")
+                             _ptr(order), _stream()), "svr_tsdf_fuse")
     return tsdf, weight
+
+
+def _check_order(order, n, device):
+    if order is None:
+        return
+    if (order.dtype != torch.int32 or order.numel() != n or not order.is_contiguous()
+            or order.device != device):
+        raise ValueError("order must be a contiguous int32 tensor of %d entries on %s"
+                         % (n, device))
 
 
 def marching_cubes_into(ds: DeviceScene, field: torch.Tensor, keys: torch.Tensor,
                         pos: torch.Tensor, count: torch.Tensor, iso: float = 0.0,
-                        weight: Optional[torch.Tensor] = None):
+                        weight: Optional[torch.Tensor] = None,
+                        order: Optional[torch.Tensor] = None):
     """svr_marching_cubes into preallocated keys int32 [cap, 3, 2], pos float32
     [cap, 3, 3] and count int64 [1] (the total, which may exceed cap); no
     host synchronisation."""
@@ -588,13 +622,16 @@ def marching_cubes_into(ds: DeviceScene, field: torch.Tensor, keys: torch.Tensor
         raise ValueError("pos must be a contiguous float32 [cap, 3, 3] tensor")
     if count.dtype != torch.int64 or count.numel() != 1:
         raise ValueError("count must be an int64 tensor of one element")
+    _check_order(order, ds.n_voxels, ds.device)
     st = ds.struct()
     check(_abi.svr_marching_cubes(st, _ptr(field), _ptr(weight), float(iso), cap, _ptr(keys),
-                                  _ptr(pos), _ptr(count), _stream()), "svr_marching_cubes")
+                                  _ptr(pos), _ptr(count), _ptr(order), _stream()),
+          "svr_marching_cubes")
 
 
 def marching_cubes(ds: DeviceScene, field: torch.Tensor, iso: float = 0.0,
-                   weight: Optional[torch.Tensor] = None, capacity: Optional[int] = None):
+                   weight: Optional[torch.Tensor] = None, capacity: Optional[int] = None,
+                   order: Optional[torch.Tensor] = None):
     """Iso-surface triangles over the voxels (svr_marching_cubes): (keys int32
     [n, 3, 2] grid point pairs per vertex, pos float32 [n, 3, 3]).  The
     triangle order is not deterministic."""
@@ -604,7 +641,7 @@ def marching_cubes(ds: DeviceScene, field: torch.Tensor, iso: float = 0.0,
     for _ in range(2):
         keys = torch.empty((cap, 3, 2), dtype=torch.int32, device=dev)
         pos = torch.empty((cap, 3, 3), dtype=torch.float32, device=dev)
-        marching_cubes_into(ds, field, keys, pos, count, iso, weight)
+        marching_cubes_into(ds, field, keys, pos, count, iso, weight, order)
         n = int(count.item())
         if n <= cap:
             return keys[:n], pos[:n]

@@ -196,24 +196,24 @@ def test_mesh_entry_points_check_arguments():
     sc, cams, _ = _host_args()
     p = ctypes.c_void_p(0x100000)
     # TSDF fusion: sizes, truncation, opacity threshold, cameras, null arrays
-    assert _abi.svr_tsdf_fuse(p, -1, cams, 1, p, None, 0.5, 0.1, p, p, None) == _abi.SVR_E_INVALID
-    assert _abi.svr_tsdf_fuse(p, 10, cams, 1, p, None, 0.5, 0.0, p, p, None) == _abi.SVR_E_INVALID
-    assert _abi.svr_tsdf_fuse(p, 10, cams, 1, p, None, float("nan"), 0.1, p, p,
+    assert _abi.svr_tsdf_fuse(p, -1, cams, 1, p, None, 0.5, 0.1, p, p, None, None) == _abi.SVR_E_INVALID
+    assert _abi.svr_tsdf_fuse(p, 10, cams, 1, p, None, 0.5, 0.0, p, p, None, None) == _abi.SVR_E_INVALID
+    assert _abi.svr_tsdf_fuse(p, 10, cams, 1, p, None, float("nan"), 0.1, p, p, None,
                               None) == _abi.SVR_E_INVALID
-    assert _abi.svr_tsdf_fuse(p, 10, cams, 0, p, None, 0.5, 0.1, p, p, None) == _abi.SVR_E_INVALID
-    assert _abi.svr_tsdf_fuse(None, 10, cams, 1, p, None, 0.5, 0.1, p, p,
+    assert _abi.svr_tsdf_fuse(p, 10, cams, 0, p, None, 0.5, 0.1, p, p, None, None) == _abi.SVR_E_INVALID
+    assert _abi.svr_tsdf_fuse(None, 10, cams, 1, p, None, 0.5, 0.1, p, p, None,
                               None) == _abi.SVR_E_INVALID
-    assert _abi.svr_tsdf_fuse(None, 0, cams, 1, None, None, 0.5, 0.1, None, None,
+    assert _abi.svr_tsdf_fuse(None, 0, cams, 1, None, None, 0.5, 0.1, None, None, None,
                               None) == _abi.SVR_OK
     # marching cubes: counter, arrays, iso, sizes
-    assert _abi.svr_marching_cubes(sc, p, None, 0.0, 10, p, p, None, None) == _abi.SVR_E_INVALID
-    assert _abi.svr_marching_cubes(sc, p, None, 0.0, 10, None, p, p, None) == _abi.SVR_E_INVALID
-    assert _abi.svr_marching_cubes(sc, p, None, float("inf"), 10, p, p, p,
+    assert _abi.svr_marching_cubes(sc, p, None, 0.0, 10, p, p, None, None, None) == _abi.SVR_E_INVALID
+    assert _abi.svr_marching_cubes(sc, p, None, 0.0, 10, None, p, p, None, None) == _abi.SVR_E_INVALID
+    assert _abi.svr_marching_cubes(sc, p, None, float("inf"), 10, p, p, p, None,
                                    None) == _abi.SVR_E_INVALID
-    assert _abi.svr_marching_cubes(sc, p, None, 0.0, -1, p, p, p, None) == _abi.SVR_E_INVALID
-    assert _abi.svr_marching_cubes(sc, None, None, 0.0, 10, p, p, p, None) == _abi.SVR_E_INVALID
+    assert _abi.svr_marching_cubes(sc, p, None, 0.0, -1, p, p, p, None, None) == _abi.SVR_E_INVALID
+    assert _abi.svr_marching_cubes(sc, None, None, 0.0, 10, p, p, p, None, None) == _abi.SVR_E_INVALID
     sc.n_grid = 1 << 31
-    assert _abi.svr_marching_cubes(sc, p, None, 0.0, 10, p, p, p, None) == _abi.SVR_E_INVALID
+    assert _abi.svr_marching_cubes(sc, p, None, 0.0, 10, p, p, p, None, None) == _abi.SVR_E_INVALID
 
 
 def test_tsdf_fusion_checks_every_camera_beyond_one_group():
@@ -230,5 +230,18 @@ def test_tsdf_fusion_checks_every_camera_beyond_one_group():
             c.w2c[k] = v
     p = ctypes.c_void_p(0x100000)
     cams[35].fx = -1.0
-    assert _abi.svr_tsdf_fuse(p, 10, cams, n, p, None, 0.5, 0.1, p, p, None) == _abi.SVR_E_INVALID
+    assert _abi.svr_tsdf_fuse(p, 10, cams, n, p, None, 0.5, 0.1, p, p, None, None) == _abi.SVR_E_INVALID
     assert "camera 35" in _abi.svr_last_error()
+
+
+
+def test_morton_keys_check_arguments():
+    _lib()
+    p = ctypes.c_void_p(0x100000)
+    lo = (ctypes.c_float * 3)(0.0, 0.0, 0.0)
+    bad = (ctypes.c_float * 3)(0.0, float("nan"), 0.0)
+    assert _abi.svr_morton_keys(p, -1, lo, 1.0, p, p, None) == _abi.SVR_E_INVALID
+    assert _abi.svr_morton_keys(p, 10, bad, 1.0, p, p, None) == _abi.SVR_E_INVALID
+    assert _abi.svr_morton_keys(p, 10, lo, 0.0, p, p, None) == _abi.SVR_E_INVALID
+    assert _abi.svr_morton_keys(None, 10, lo, 1.0, p, p, None) == _abi.SVR_E_INVALID
+    assert _abi.svr_morton_keys(None, 0, lo, 1.0, None, None, None) == _abi.SVR_OK
