@@ -357,3 +357,39 @@ def test_morton_order_is_a_z_curve_permutation(torch_dev):
     assert np.all(np.diff(c) >= 0)
     same = np.diff(c) == 0
     assert np.all(np.diff(order)[same] > 0)
+
+
+@pytest.mark.parametrize("morton", [False, True])
+def test_tsdf_fusion_with_cameras_of_different_sizes(torch_dev, morton):
+    """37 cameras of assorted resolutions (pixel offsets of the concatenated
+    images differ per camera and the launch groups split inside the list)."""
+    rng = np.random.default_rng(23)
+    pts = rng.uniform(-0.7, 0.7, size=(20000, 3)).astype(np.float32).astype(np.float64)
+    sizes = [(17, 9), (64, 48), (33, 65), (128, 96), (7, 5), (96, 40)]
+    cams = []
+    for i in range(37):
+        W, H = sizes[i % len(sizes)]
+        eye = S.random_direction(rng) * 2.0
+        cams.append(S.look_at(W, H, 50.0, eye, target=tuple(rng.normal(0, 0.05, 3))))
+    depths = S.sphere_depth_images(cams, SPHERES, hole_p=0.05, seed=23)
+    trunc = 0.1
+    gv, gw = _gpu_tsdf(torch_dev, pts, cams, depths, trunc, morton=morton)
+    ov, ow = om.tsdf_fuse(pts, cams, depths, trunc)
+    keep = _tie_free(pts, cams)
+    assert (ow > 0).sum() > 1000
+    _check_tsdf(gv, gw, ov, ow, keep)
+
+
+def test_marching_cubes_with_corner_values_on_the_iso_level(torch_dev):
+    """Values on a coarse lattice so that many corners equal the iso value
+    exactly: such corners count as below on both sides."""
+    sc = S.tiny_random_scene(9, max_level=4, p_sub=0.55)
+    rng = np.random.default_rng(109)
+    field = (0.5 * rng.integers(-2, 3, size=sc.n_grid)).astype(np.float32)
+    assert (field == 0.5).sum() > 30 and (field == 0.0).sum() > 30
+    ds = _device_scene(sc)
+    for iso in (0.0, 0.5):
+        gk, gp = _gpu_mesh(torch_dev, ds, field, iso)
+        ok, op = om.marching_cubes(sc.center, sc.size, sc.vox_grid, field, iso)
+        assert ok.shape[0] > 100
+        _compare_meshes(gk, gp, ok, op, sc.world_size)
