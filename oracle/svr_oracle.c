@@ -136,27 +136,33 @@ void oracle_sh_basis(int degree, const double dir_in[3], double* Y) {
 }
 
 /* ------------------------------------------------------------------------ */
-/* octree path <-> voxel index (Supp. A.1, the Morton bit interleaving)     */
+/* octree path <-> voxel index (Supp. A.1).  A voxel of level lv has integer  */
+/* index (i, j, k) in [0, 2^lv)^3 among the cells of its level.  Descending   */
+/* from the root, the ancestor of level l has index (i, j, k) >> (lv - l),    */
+/* and the child taken at level l is the low bit of that ancestor index on    */
+/* each axis: octant 4x + 2y + z.  The path stores the octant of level l at   */
+/* bits 3(16 - l) .. 3(16 - l) + 2 (coarsest level highest, unused levels 0). */
 /* ------------------------------------------------------------------------ */
 uint64_t oracle_to_octpath(int64_t i, int64_t j, int64_t k, int lv) {
   uint64_t path = 0;
-  for (int n = 0; n < lv; ++n) {
-    uint64_t bits = (uint64_t)(4 * ((i >> n) & 1) + 2 * ((j >> n) & 1) + ((k >> n) & 1));
-    path |= bits << (3 * n);
+  for (int l = 1; l <= lv; ++l) {
+    int sh = lv - l; /* the ancestor of level l drops the sh finest index bits */
+    int ox = (int)((i >> sh) & 1), oy = (int)((j >> sh) & 1), oz = (int)((k >> sh) & 1);
+    uint64_t octant = (uint64_t)(4 * ox + 2 * oy + oz);
+    path |= octant << (3 * (OR_MAX_LEVELS - l));
   }
-  return path << (3 * (OR_MAX_LEVELS - lv));
+  return path;
 }
 
+/* inverse: walk the path from the root, doubling the index at every level   */
+/* and adding the child's bit on each axis                                   */
 void oracle_to_voxel_index(uint64_t path, int lv, int64_t out[3]) {
-  int64_t i = 0, j = 0, k = 0;
-  path >>= 3 * (OR_MAX_LEVELS - lv);
-  for (int n = 0; n < lv; ++n) {
-    i |= (int64_t)((path >> 2) & 1) << n;
-    j |= (int64_t)((path >> 1) & 1) << n;
-    k |= (int64_t)(path & 1) << n;
-    path >>= 3;
+  int64_t idx[3] = {0, 0, 0};
+  for (int l = 1; l <= lv; ++l) {
+    int octant = (int)((path >> (3 * (OR_MAX_LEVELS - l))) & 7);
+    for (int ax = 0; ax < 3; ++ax) idx[ax] = 2 * idx[ax] + ((octant >> (2 - ax)) & 1);
   }
-  out[0] = i; out[1] = j; out[2] = k;
+  out[0] = idx[0]; out[1] = idx[1]; out[2] = idx[2];
 }
 
 /* ------------------------------------------------------------------------ */
@@ -208,20 +214,39 @@ void oracle_keys(int64_t n, const int64_t* tile, const int64_t* vid, const uint8
 }
 
 /* ------------------------------------------------------------------------ */
-/* ray / axis-aligned box (Supp. A.2 listing "ray_aabb")                     */
+/* ray / axis-aligned box (Supp. A.2, the ray-box test): the points o + t d  */
+/* inside the box [c - s/2, c + s/2]^3 form one interval of t, the           */
+/* intersection over the three axes of the interval between that axis'      */
+/* two bounding planes (empty if the ray runs parallel to the planes outside */
+/* them, unbounded if inside).  a is where the ray enters the box, b where   */
+/* it leaves.  The voxel is hit iff the interval is non-empty and starts in  */
+/* front of the camera, a > 0 (so a camera inside a voxel skips it).         */
 /* ------------------------------------------------------------------------ */
 static int ray_aabb(const double c[3], double s, const double o[3], const double d[3],
                     double* a_out, double* b_out) {
-  double a = -INFINITY, b = INFINITY;
+  double enter = -INFINITY, leave = INFINITY;
   for (int ax = 0; ax < 3; ++ax) {
-    double c0 = (c[ax] - 0.5 * s - o[ax]) / d[ax];
-    double c1 = (c[ax] + 0.5 * s - o[ax]) / d[ax];
-    a = fmax(a, fmin(c0, c1));
-    b = fmin(b, fmax(c0, c1));
+    double lo = c[ax] - 0.5 * s, hi = c[ax] + 0.5 * s;
+    double t_lo, t_hi; /* the part of the ray between the planes x_ax = lo and x_ax = hi */
+    if (d[ax] > 0) {
+      t_lo = (lo - o[ax]) / d[ax];
+      t_hi = (hi - o[ax]) / d[ax];
+    } else if (d[ax] < 0) {
+      t_lo = (hi - o[ax]) / d[ax];
+      t_hi = (lo - o[ax]) / d[ax];
+    } else if (o[ax] >= lo && o[ax] <= hi) {
+      t_lo = -INFINITY;
+      t_hi = INFINITY;
+    } else {
+      t_lo = INFINITY;
+      t_hi = -INFINITY;
+    }
+    if (t_lo > enter) enter = t_lo;
+    if (t_hi < leave) leave = t_hi;
   }
-  *a_out = a;
-  *b_out = b;
-  return (a <= b) && (a > 0);
+  *a_out = enter;
+  *b_out = leave;
+  return (enter <= leave) && (enter > 0);
 }
 
 /* trilinear weights of the 8 corners (Supp. A.2 eq. interp; corner index     */

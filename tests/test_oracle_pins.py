@@ -661,3 +661,95 @@ def test_downsample_adjoint_is_the_transpose():
         lhs = np.sum((oracle.downsample(x1, wo, ho, bg) - oracle.downsample(x2, wo, ho, bg)) * y)
         rhs = np.sum((x1 - x2) * oracle.downsample_adjoint(y, wi, hi, bg))
         assert lhs == pytest.approx(rhs, rel=1e-12)
+
+
+# --------------------------------------------------------------------------
+# tile sign masks (Supp. B.2, the ray sign bits; Supp. B.1: an entry per
+# (voxel, tile, sign pattern present among the tile's pixels)).  Cameras whose
+# rotation is a signed permutation make every ray component a known affine
+# function of the pixel centre, so each tile's set of patterns follows from
+# which in-image pixel columns / rows lie on either side of the principal
+# point: no direction is formed in the test.
+# --------------------------------------------------------------------------
+def _perm_camera(W, H, cx, cy, rows):
+    """Camera with w2c = [R | 0], R's rows the camera's right, down and
+    forward axes in world coordinates (a signed permutation), f = 30 px."""
+    R = np.asarray(rows, np.float64)
+    assert np.allclose(R @ R.T, np.eye(3)) and np.isclose(np.linalg.det(R), 1.0)
+    return S.Camera(W=W, H=H, fx=30.0, fy=30.0, cx=cx, cy=cy,
+                    w2c=np.concatenate([R, np.zeros((3, 1))], 1))
+
+
+def _expected_masks(cam, tw, th, rows):
+    """Per tile, OR of 1 << s over in-image pixels, s = 4[d_x<0] + 2[d_y<0] +
+    [d_z<0].  The world direction is R^T (a, b, 1) with a < 0 iff the pixel
+    centre u + 1/2 lies left of cx (b likewise with v, cy), so each world
+    component is +-a, +-b or +-1 and its sign is fixed per pixel column or
+    row.  Centres exactly on cx / cy are excluded by the callers."""
+    R = np.asarray(rows, np.float64)
+    ntx, nty = -(-cam.W // tw), -(-cam.H // th)
+    masks = np.zeros(ntx * nty, np.uint8)
+    for ty in range(nty):
+        v_rows = range(ty * th, min(ty * th + th, cam.H))          # in-image rows only
+        b_signs = {(-1 if v + 0.5 < cam.cy else 1) for v in v_rows}
+        for tx in range(ntx):
+            u_cols = range(tx * tw, min(tx * tw + tw, cam.W))      # in-image columns only
+            a_signs = {(-1 if u + 0.5 < cam.cx else 1) for u in u_cols}
+            m = 0
+            for sa in a_signs:
+                for sb in b_signs:
+                    # world component w = R[0,w] a + R[1,w] b + R[2,w]: one term is nonzero
+                    s = 0
+                    for w in range(3):
+                        sign = R[0, w] * sa + R[1, w] * sb + R[2, w]
+                        if sign < 0:
+                            s |= 4 >> w
+                    m |= 1 << s
+            masks[ty * ntx + tx] = m
+    return masks
+
+
+_ROTS = {
+    "identity": [[1, 0, 0], [0, 1, 0], [0, 0, 1]],
+    # half turn about y: world x and z flip, so bit 0 (d_z < 0) is always set
+    "half_turn_y": [[-1, 0, 0], [0, 1, 0], [0, 0, -1]],
+    # camera looks along world +x, right = +y, down = +z
+    "along_x": [[0, 1, 0], [0, 0, 1], [1, 0, 0]],
+    # camera looks along world -y, right = -z, down = +x
+    "along_minus_y": [[0, 0, -1], [1, 0, 0], [0, -1, 0]],
+}
+
+
+@pytest.mark.parametrize("rot", sorted(_ROTS))
+@pytest.mark.parametrize("W,H,cx,cy,tw,th", [
+    (37, 21, 20.25, 10.75, 8, 8),     # principal point inside a tile: that tile holds both signs
+    (37, 21, 20.25, 10.75, 4, 4),     # pixel 20's centre is right of cx, its left corner is not
+    (37, 21, 38.25, 21.6, 8, 8),      # beyond the image: out-of-image pixels of the partial
+                                      # edge tiles would add the other sign
+    (45, 30, -3.25, 12.25, 16, 16),   # every column on one side
+    (50, 33, 24.75, 16.25, 32, 32),
+])
+def test_tile_masks_hold_exactly_their_pixels_patterns(rot, W, H, cx, cy, tw, th):
+    cam = _perm_camera(W, H, cx, cy, _ROTS[rot])
+    must, may = oracle.tile_masks(cam, tw, th)
+    exp = _expected_masks(cam, tw, th, _ROTS[rot])
+    assert np.array_equal(must, exp)
+    assert np.array_equal(may, exp)
+    assert np.all(must != 0)
+
+
+def test_tile_masks_band_on_a_zero_component():
+    """A pixel centre exactly on the principal point column has d_x = 0: its
+    tile's may mask holds both x signs, must only the patterns of the other
+    pixels; must is always a subset of may."""
+    rows = _ROTS["identity"]
+    cam = _perm_camera(40, 16, 20.5, 4.25, rows)     # column 20 sits on cx
+    must, may = oracle.tile_masks(cam, 4, 16)
+    assert np.all((must & ~may) == 0)
+    # tile 5 holds columns 20..23: column 20 is ambiguous, 21..23 have d_x > 0
+    t = 5
+    y_pats = {0, 2}                                  # rows above and below cy
+    assert must[t] == sum(1 << p for p in y_pats)
+    assert may[t] == sum(1 << p for p in y_pats) | sum(1 << (p | 4) for p in y_pats)
+    # tile 4 (columns 16..19): all left of cx, unaffected
+    assert must[4] == may[4] == sum(1 << (p | 4) for p in y_pats)
