@@ -16,8 +16,10 @@ TSDF fusion (readings, the paper gives the method by reference only):
   never observed keep the value 1 and weight 0.  When the rendered opacity A
   is given with the depth (the renderer's depth is the composited sum
   sum_i T_i d_i), the distance is that sum divided by A where A >= min_alpha
-  and A > 0, taken in float32 as the renderer's images are; other pixels
-  carry no depth.
+  and A > 0 (the images are float32; the quotient is taken in FP64, and the
+  points whose truncation decision lies within a relative 1e-6 of its
+  threshold are reported as ties, where a float32 quotient may decide the
+  other way); other pixels carry no depth.
 
 Marching cubes over the voxels (one cell per voxel, its 8 corner grid
 points; corner c = 4x + 2y + z):
@@ -161,20 +163,28 @@ def marching_cubes(center, size, vox_grid, field, iso=0.0, weight=None):
     return (np.asarray(keys, np.int64).reshape(-1, 3, 2), np.asarray(pos, np.float64).reshape(-1, 3, 3))
 
 
-def tsdf_fuse(grid_pos, cams, depths, trunc, alphas=None, min_alpha=0.5):
+def tsdf_fuse(grid_pos, cams, depths, trunc, alphas=None, min_alpha=0.5, return_ties=False,
+              tie_rel=1e-6):
     """Fused truncated signed distances of the grid points (values, weights).
     grid_pos [M][3]; depths / alphas: per camera [H*W] (alphas None: the
-    depths are distances already)."""
+    depths are distances already; else the depths are composited sums and
+    the distance is their FP64 quotient by the opacity where the opacity
+    reaches min_alpha).  With ``return_ties`` also a mask of the points
+    whose truncation decision (sdf >= -trunc) lies within ``tie_rel`` times
+    the distance of its threshold in some camera: there a float32 quotient
+    may decide the other way."""
     p = np.asarray(grid_pos, np.float64)
     M = p.shape[0]
     acc = np.zeros(M)
     w = np.zeros(M)
+    ties = np.zeros(M, bool)
     for ci, (cam, D) in enumerate(zip(cams, depths)):
         if alphas is not None:
+            # the opacity test compares two float32 values exactly
             A = np.asarray(alphas[ci], np.float32).reshape(-1)
-            D32 = np.asarray(D, np.float32).reshape(-1)
             ok_a = (A >= np.float32(min_alpha)) & (A > 0)
-            D = np.where(ok_a, D32 / np.where(ok_a, A, np.float32(1)), np.float32(0))
+            Dc = np.asarray(D, np.float32).reshape(-1).astype(np.float64)
+            D = np.where(ok_a, Dc / np.where(ok_a, A, np.float32(1)).astype(np.float64), 0.0)
         D = np.asarray(D, np.float64).reshape(cam.H, cam.W)
         R = np.asarray(cam.w2c, np.float64)[:, :3]
         t = np.asarray(cam.w2c, np.float64)[:, 3]
@@ -192,8 +202,11 @@ def tsdf_fuse(grid_pos, cams, depths, trunc, alphas=None, min_alpha=0.5):
         d[ok] = D[iv[ok].astype(np.int64), iu[ok].astype(np.int64)]
         ok &= d > 0
         sdf = d - np.linalg.norm(p - o[None, :], axis=1)
+        ties |= ok & (np.abs(sdf + trunc) <= tie_rel * d)
         ok &= sdf >= -trunc
         acc[ok] += np.minimum(sdf[ok] / trunc, 1.0)
         w[ok] += 1.0
     val = np.where(w > 0, acc / np.maximum(w, 1.0), 1.0)
+    if return_ties:
+        return val, w, ties
     return val, w

@@ -186,6 +186,9 @@ class Rasterizer:
             capacity = max(1 << 16, 2 * dscene.n_voxels * self.n_cams)
         self.sync_count = sync_count
         self.n_entries = -1
+        # bumped by every preprocess: the workspace holds the lists of the
+        # frame with this number
+        self.frame = 0
         self.ws = None
         self.ws_bytes = 0
         self._set_capacity(int(capacity))
@@ -217,6 +220,7 @@ class Rasterizer:
 
     def preprocess(self, grid_raw=None, sh=None):
         st = self.ds.struct(grid_raw, sh)
+        self.frame += 1
         if self.sync_count:
             n = ctypes.c_int64(0)
             rc = _abi.svr_preprocess(st, self.cam_arr, self.n_cams, self.opts, self._ws_ptr(),
@@ -304,6 +308,7 @@ class Rasterizer:
 
     def replay(self, stream: Optional[torch.cuda.Stream] = None):
         s = (stream or torch.cuda.current_stream()).cuda_stream
+        self.frame += 1
         check(_abi.svr_graph_launch(self._graph, ctypes.c_void_p(s)), "svr_graph_launch")
 
     def capture_views(self, cams: Sequence, rgba: torch.Tensor, grad_rgba: torch.Tensor,
@@ -329,6 +334,7 @@ class Rasterizer:
         return len(self._view_graphs)
 
     def replay_view(self, i: int, stream: torch.cuda.Stream):
+        self.frame += 1
         check(_abi.svr_graph_launch(self._view_graphs[i], ctypes.c_void_p(stream.cuda_stream)),
               "svr_graph_launch")
 
@@ -447,7 +453,14 @@ class BatchRenderer:
 
 class SVRasterFunction(torch.autograd.Function):
     """rgba = render(grid_raw, sh) for a fixed rasterizer (scene geometry and
-    cameras); gradients flow to the corner raw densities and SH coefficients."""
+    cameras); gradients flow to the corner raw densities and SH coefficients.
+
+    The adjoint reads the sorted lists and per-pixel state the forward left
+    in the rasterizer's workspace.  When another frame has gone through the
+    same rasterizer since this forward (a second render before backward,
+    activation checkpointing), the backward first renders this frame again
+    from the saved parameters and cameras, so the gradients always belong
+    to the forward they differentiate."""
 
     @staticmethod
     def forward(ctx, grid_raw, sh, rast: Rasterizer):
@@ -455,15 +468,25 @@ class SVRasterFunction(torch.autograd.Function):
         sh = sh.contiguous()
         rgba = rast.forward(grid_raw, sh)
         ctx.rast = rast
+        ctx.frame = rast.frame
+        ctx.cams = list(rast.cams)
         ctx.save_for_backward(grid_raw, sh)
         return rgba
 
     @staticmethod
     def backward(ctx, grad_rgba):
         grid_raw, sh = ctx.saved_tensors
-        gg, gs = ctx.rast.backward(grad_rgba, grid_raw, sh,
-                                   want_grid=ctx.needs_input_grad[0],
-                                   want_sh=ctx.needs_input_grad[1])
+        rast = ctx.rast
+        cams_now = None
+        if rast.frame != ctx.frame:
+            cams_now = list(rast.cams)
+            rast.set_cameras(ctx.cams)
+            rast.forward(grid_raw, sh)
+        gg, gs = rast.backward(grad_rgba, grid_raw, sh,
+                               want_grid=ctx.needs_input_grad[0],
+                               want_sh=ctx.needs_input_grad[1])
+        if cams_now is not None:
+            rast.set_cameras(cams_now)
         return gg, gs, None
 
 

@@ -186,3 +186,76 @@ def test_grid_adjacency_and_gather_path(torch_dev):
     gc, sc = r2.backward(g)
     torch.cuda.synchronize()
     assert _grad_close(ga, gc) and _grad_close(sa, sc)
+
+
+def test_batched_wide_tile_ids_match_oracle(torch_dev):
+    """Six 1920x1080 cameras in one frame at 8x8 tiles: 194,400 global tile
+    ids, so the key's tile field needs 18 bits, beyond the 16 bits of one view
+    (Supp. B.1 key layout).  Each camera's block of the sorted list is checked
+    bit-exact against the oracle's keys with that camera's tile offset; rgba
+    on sampled pixels of every camera and the gradients of an upstream
+    gradient on those pixels against the oracle, in the no-sync graph mode
+    the batched benchmark uses."""
+    torch = torch_dev
+    from paper_2412_04459_amd.render import DeviceScene, Rasterizer
+    from parity_helpers import (check_grad, check_rgba, check_sorted_list, cpu_order_ranks,
+                                key_low_bits)
+    scene = S.sphere_shell_scene(opaque=True)
+    rng = np.random.default_rng(61)
+    cams = [S.look_at(1920, 1080, 50.0, (1.7 + 0.1 * i) * S.random_direction(rng))
+            for i in range(6)]
+    tiles = [((c.W + 7) // 8) * ((c.H + 7) // 8) for c in cams]
+    offs = np.concatenate([[0], np.cumsum(tiles)])
+    assert offs[-1] > 1 << 17
+    _say("batched wide tile ids: %d cameras, %d tiles" % (len(cams), offs[-1]))
+    P = [c.W * c.H for c in cams]
+    poff = np.concatenate([[0], np.cumsum(P)])
+    # sampled pixels per camera, the oracle's rgba and gradients there
+    g = np.zeros((poff[-1], 4), np.float32)
+    gfull = S.upstream_grads(int(poff[-1]), 62)
+    refs, samples = [], []
+    ref_gg = np.zeros(scene.n_grid)
+    ref_gs = np.zeros(scene.sh.shape)
+    for i, c in enumerate(cams):
+        px = np.unique(rng.choice(P[i], 400, replace=False))
+        r0 = oracle.render(scene, c, K=2, pixels=px)
+        gi = gfull[poff[i] + px].copy()
+        gi[r0["flags"] != 0] = 0.0
+        g[poff[i] + px] = gi
+        rg = oracle.render(scene, c, K=2, pixels=px, grad_rgba=gi.astype(np.float64))
+        ref_gg += rg["grad_grid"]
+        ref_gs += rg["grad_sh"]
+        refs.append(r0)
+        samples.append(px)
+    ds = DeviceScene(scene)
+    probe = Rasterizer(ds, cams, K=2, sync_count=True, tile=8)
+    probe.preprocess()
+    cap = int(probe.n_entries * 1.1) + 4096
+    del probe
+    r = Rasterizer(ds, cams, K=2, capacity=cap, sync_count=False, tile=8)
+    rgba = torch.full((int(poff[-1]), 4), -1.0, dtype=torch.float32, device="cuda")
+    gg = torch.full((ds.n_grid,), 7.0, dtype=torch.float32, device="cuda")
+    gs = torch.full_like(ds.sh, 7.0)
+    stream = torch.cuda.Stream()
+    r.capture(rgba, torch.from_numpy(g).cuda(), gg, gs, stream)
+    r.replay(stream)
+    torch.cuda.synchronize()
+    E = r.check_overflow()
+    assert 0 < E <= cap
+    keys, vals = r.sorted_entries(E)
+    gk = keys.cpu().numpy().view(np.uint64)
+    gv = vals.cpu().numpy().view(np.uint32)
+    tid = (gk >> np.uint64(key_low_bits(scene, True))).astype(np.int64)
+    assert tid.max() >= 1 << 16
+    table = cpu_order_ranks(scene)
+    out = rgba.cpu().numpy().astype(np.float64)
+    for i, c in enumerate(cams):
+        sel = (tid >= offs[i]) & (tid < offs[i + 1])
+        assert sel.any()
+        check_sorted_list(scene, c, gk[sel], gv[sel], True, tile=8, tile_offset=int(offs[i]),
+                          rank_table=table)
+        check_rgba(out[poff[i]:poff[i + 1]], refs[i], pixels=samples[i])
+    assert np.count_nonzero((tid < 0) | (tid >= offs[-1])) == 0
+    check_grad(gg.cpu().numpy(), ref_gg, "grad_grid")
+    check_grad(gs.cpu().numpy(), ref_gs, "grad_sh")
+    r.release_graph()

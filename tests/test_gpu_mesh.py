@@ -246,8 +246,10 @@ def test_tsdf_fusion_from_composited_depth_and_opacity(torch_dev):
     comp = [(d * a).astype(np.float32) for d, a in zip(dist, alphas)]
     trunc = 0.1
     gv, gw = _gpu_tsdf(torch_dev, pts, cams, comp, trunc, alphas, 0.4)
-    ov, ow = om.tsdf_fuse(pts, cams, comp, trunc, alphas=alphas, min_alpha=0.4)
-    keep = _tie_free(pts, cams)
+    ov, ow, ties = om.tsdf_fuse(pts, cams, comp, trunc, alphas=alphas, min_alpha=0.4,
+                                return_ties=True)
+    keep = _tie_free(pts, cams) & ~ties
+    assert keep.mean() > 0.99
     assert (ow > 0).sum() > 500
     _check_tsdf(gv, gw, ov, ow, keep)
 

@@ -1,12 +1,6 @@
-"""GPU parity: the HIP path, called through the C ABI, against the FP64 oracle.
-
-Bars: the sorted (key, value) list is bit-exact (every entry's key equals the
-oracle's key of the same (tile, voxel, sign) triple; the list is strictly
-ascending; it contains every entry the oracle requires and nothing outside
-the oracle's tolerance band); RGBA within 1e-4 absolute per channel; gradients
-within 1e-3 relative (with a small absolute floor relative to the largest
-gradient, for entries that are sums of cancelling terms).
-"""
+"""GPU parity: the HIP path, called through the C ABI, against the FP64 oracle
+(bars in parity_helpers: sorted lists bit-exact, RGBA within 1e-4, gradients
+within 1e-3 relative)."""
 import math
 
 import numpy as np
@@ -14,12 +8,11 @@ import pytest
 
 import oracle
 from paper_2412_04459_amd import scenes as S
+from parity_helpers import (GRAD_FLOOR, GRAD_REL, RGBA_TOL, check_grad as _check_grad,
+                            check_rgba as _check_rgba, check_sorted_list,
+                            cpu_order_ranks as _cpu_order_ranks, say as _say)
 
 pytestmark = pytest.mark.gpu
-
-RGBA_TOL = 1e-4
-GRAD_REL = 1e-3
-GRAD_FLOOR = 2e-5
 
 
 @pytest.fixture(scope="module")
@@ -28,10 +21,6 @@ def torch_dev():
     if not torch.cuda.is_available():
         pytest.skip("no GPU")
     return torch
-
-
-def _say(msg):
-    print(msg, flush=True)
 
 
 def _gpu_frame(torch, scene, cams, K, t_stop=1e-4, act=0, grad=None, sync=True, tile=16,
@@ -47,27 +36,6 @@ def _gpu_frame(torch, scene, cams, K, t_stop=1e-4, act=0, grad=None, sync=True, 
         out["grad_sh"] = gs.cpu().numpy().astype(np.float64)
     torch.cuda.synchronize()
     return out
-
-
-def _check_rgba(gpu, ref, pixels=None, tol=RGBA_TOL):
-    g = gpu if pixels is None else gpu[pixels]
-    e1 = np.abs(g - ref["rgba"]).max(1)
-    e2 = np.abs(g - ref["rgba_alt"]).max(1)
-    err = np.minimum(e1, e2)
-    worst = int(np.argmax(err))
-    assert err.max() <= tol, "max |d rgba| = %.3g at sample %d (gpu %s, oracle %s)" % (
-        err.max(), worst, g[worst], ref["rgba"][worst])
-    return float(err.max())
-
-
-def _check_grad(g, r, name):
-    scale = np.abs(r).max()
-    assert scale > 0
-    tol = GRAD_REL * np.abs(r) + GRAD_FLOOR * scale
-    bad = np.abs(g - r) > tol
-    i = int(np.argmax(np.abs(g - r) - tol))
-    assert not bad.any(), "%s: %d of %d entries off; worst %d gpu %.6g oracle %.6g (scale %.3g)" % (
-        name, int(bad.sum()), r.size, i, g.reshape(-1)[i], r.reshape(-1)[i], scale)
 
 
 # ---------------------------------------------------------------------------
@@ -121,44 +89,6 @@ def _dense_cube(level):
     return S.scene_from_voxels((0.5, 0.5, 0.5), 1.0, level, g, np.full(len(g), level))
 
 
-def _cpu_order_ranks(scene):
-    """Rank of every (voxel, sign) pair in the oracle's within-tile key order."""
-    n8 = 8 * scene.n_voxels
-    vid = np.repeat(np.arange(scene.n_voxels, dtype=np.int64), 8)
-    sgn = np.tile(np.arange(8, dtype=np.uint8), scene.n_voxels)
-    _, kc, _ = oracle.keys(np.zeros(n8, np.int64), vid, sgn, scene.octpath, scene.max_level)
-    order = np.argsort(kc, kind="stable")
-    rank = np.empty(n8, np.int64)
-    rank[order] = np.arange(n8)
-    return rank
-
-
-def _check_sorted_list(scene, cam, gk, gv, ranks):
-    """The GPU's sorted list against the oracle: strictly ascending keys; each
-    entry's value and, for its (tile, voxel, s), the oracle's key; those keys
-    strictly ascending too (the list is in the paper's key order); the key's
-    low bits are the order rank (ranks) or the compact key itself (no ranks);
-    every required entry present and none outside the tolerance band."""
-    L = scene.max_level
-    key_low = int(8 * scene.n_voxels - 1).bit_length() if ranks else 3 * L + 3
-    assert np.all(gk[1:] > gk[:-1])
-    tile = (gk >> np.uint64(key_low)).astype(np.int64)
-    vid = (gv & np.uint32((1 << 29) - 1)).astype(np.int64)
-    sgn = (gv >> np.uint32(29)).astype(np.uint8)
-    _, kc, val = oracle.keys(tile, vid, sgn, scene.octpath, L)
-    assert np.array_equal(val, gv)
-    assert np.all(kc[1:] > kc[:-1])
-    if ranks:
-        low = (gk & np.uint64((1 << key_low) - 1)).astype(np.int64)
-        assert np.array_equal(low, _cpu_order_ranks(scene)[vid * 8 + sgn])
-    else:
-        assert np.array_equal(kc, gk)
-    exp = oracle.expected_entries(scene, cam)
-    must_k, _, _ = exp["must"]
-    may_k, _, _ = exp["may"]
-    assert np.all(np.isin(must_k, kc)), "missing %d required entries" % int((~np.isin(must_k, kc)).sum())
-    assert np.all(np.isin(kc, may_k)), "%d entries outside the band" % int((~np.isin(kc, may_k)).sum())
-    assert len(must_k) > 0
 
 
 @pytest.mark.parametrize("name,ranks", [(c[0], True) for c in _key_cases()] + [("shell", False),
@@ -177,7 +107,7 @@ def test_sorted_entries_bit_exact(torch_dev, name, ranks):
     assert rast.check_overflow() == E
     if name == "one_tile":
         assert E > 2048  # the range is sorted by the radix fallback
-    _check_sorted_list(scene, cams[0], keys.cpu().numpy().view(np.uint64),
+    check_sorted_list(scene, cams[0], keys.cpu().numpy().view(np.uint64),
                        vals.cpu().numpy().view(np.uint32), ranks)
 
 
@@ -308,7 +238,9 @@ def test_autograd_function_matches_direct_backward(torch_dev):
 
 # ---------------------------------------------------------------------------
 # the benchmark workload (about 1.07M voxels, 1297x840, K = 2): sampled pixels
-# against the oracle in the same launch configuration the benchmark times
+# against the oracle, both eagerly with the entry count read back and in the
+# configuration the benchmark times (8x8 tiles, no host synchronisation, the
+# sort sized to the capacity, the whole frame replayed from a captured hipGraph)
 # ---------------------------------------------------------------------------
 @pytest.fixture(scope="module")
 def bench_scene(torch_dev):
@@ -317,26 +249,86 @@ def bench_scene(torch_dev):
     return scene, cams
 
 
-def test_bench_scene_sampled_parity(torch_dev, bench_scene):
+@pytest.fixture(scope="module")
+def bench_device_scene(torch_dev, bench_scene):
+    from paper_2412_04459_amd.render import DeviceScene
+    return DeviceScene(bench_scene[0])
+
+
+@pytest.fixture(scope="module")
+def bench_rank_table(bench_scene):
+    return _cpu_order_ranks(bench_scene[0])
+
+
+def _bench_frame(torch, ds, cam, mode, tile, grad):
+    """One fwd+bwd frame of `cam`.  mode 'eager': entry count read back, sort
+    sized to it, eager launches.  mode 'graph': capacity from a counted probe
+    (as the benchmark sizes it), no host synchronisation, the frame captured
+    as one hipGraph and replayed twice (outputs are overwritten per replay).
+    Returns (rasterizer, rgba, grad_grid, grad_sh, entries)."""
+    from paper_2412_04459_amd.render import Rasterizer
+    g = torch.from_numpy(np.ascontiguousarray(grad, np.float32)).cuda()
+    if mode == "eager":
+        r = Rasterizer(ds, [cam], K=2, sync_count=True, tile=tile)
+        rgba = r.forward()
+        gg, gs = r.backward(g)
+        torch.cuda.synchronize()
+        return r, rgba, gg, gs, r.n_entries
+    probe = Rasterizer(ds, [cam], K=2, sync_count=True, tile=tile)
+    probe.preprocess()
+    cap = int(probe.n_entries * 1.1) + 4096
+    del probe
+    r = Rasterizer(ds, [cam], K=2, capacity=cap, sync_count=False, tile=tile)
+    P = cam.W * cam.H
+    rgba = torch.full((P, 4), -1.0, dtype=torch.float32, device="cuda")
+    gg = torch.full((ds.n_grid,), 7.0, dtype=torch.float32, device="cuda")
+    gs = torch.full_like(ds.sh, 7.0)
+    stream = torch.cuda.Stream()
+    assert r.capture_views([cam], rgba, g, gg, gs, stream) == 1
+    for _ in range(2):
+        r.replay_view(0, stream)
+    torch.cuda.synchronize()
+    E = r.check_overflow()
+    assert 0 < E <= cap
+    return r, rgba, gg, gs, E
+
+
+@pytest.fixture(scope="module")
+def bench_sample(torch_dev, bench_scene, bench_device_scene):
+    """A seeded sample of 700 pixels with hits and 100 random pixels of the
+    benchmark view, the oracle's rgba there, and the oracle's gradients for an
+    upstream gradient that is N(0, 1) on the sample (zero on flagged pixels)
+    and zero elsewhere."""
     torch = torch_dev
     scene, cams = bench_scene
     cam = cams[0]
     P = cam.W * cam.H
-    _say("1.07M-voxel scene sampled parity N=%d" % scene.n_voxels)
+    _, rgba, _, _, _ = _bench_frame(torch, bench_device_scene, cam, "eager", 16, np.zeros((P, 4)))
+    hit_px = np.nonzero(rgba[:, 3].cpu().numpy() > 0)[0]
     rng = np.random.default_rng(13)
-    g_full = S.upstream_grads(P, 2)
-    out_f = _gpu_frame(torch, scene, cams, K=2)
-    hit_px = np.nonzero(out_f["rgba"][:, 3] > 0)[0]
-    px = np.concatenate([rng.choice(hit_px, 700, replace=False), rng.choice(P, 100, replace=False)])
+    px = np.unique(np.concatenate([rng.choice(hit_px, 700, replace=False),
+                                   rng.choice(P, 100, replace=False)]))
     ref0 = oracle.render(scene, cam, K=2, pixels=px)
-    _check_rgba(out_f["rgba"], ref0, pixels=px)
-    g = np.zeros_like(g_full)
-    g[px] = g_full[px]
+    g = np.zeros((P, 4), np.float32)
+    g[px] = S.upstream_grads(P, 2)[px]
     g[px[ref0["flags"] != 0]] = 0.0
     ref = oracle.render(scene, cam, K=2, pixels=px, grad_rgba=g[px].astype(np.float64))
-    out = _gpu_frame(torch, scene, cams, K=2, grad=g)
-    _check_grad(out["grad_grid"], ref["grad_grid"], "grad_grid")
-    _check_grad(out["grad_sh"], ref["grad_sh"], "grad_sh")
+    return px, g, ref0, ref
+
+
+@pytest.mark.parametrize("mode,tile", [("eager", 16), ("eager", 8), ("graph", 8), ("graph", 16)])
+def test_bench_scene_sampled_parity(torch_dev, bench_scene, bench_device_scene, bench_sample,
+                                    mode, tile):
+    torch = torch_dev
+    scene, cams = bench_scene
+    px, g, ref0, ref = bench_sample
+    _say("1.07M-voxel scene sampled parity N=%d, %s, tile %d" % (scene.n_voxels, mode, tile))
+    r, rgba, gg, gs, E = _bench_frame(torch, bench_device_scene, cams[0], mode, tile, g)
+    err = _check_rgba(rgba.cpu().numpy().astype(np.float64), ref0, pixels=px)
+    e1 = _check_grad(gg.cpu().numpy(), ref["grad_grid"], "grad_grid")
+    e2 = _check_grad(gs.cpu().numpy(), ref["grad_sh"], "grad_sh")
+    _say("  E=%d rgba err %.2e, grad rel err %.2e / %.2e" % (E, err, e1, e2))
+    r.release_graph()
 
 
 def test_forward_invariant_to_sync_mode(torch_dev, bench_scene):
@@ -349,29 +341,158 @@ def test_forward_invariant_to_sync_mode(torch_dev, bench_scene):
     assert np.array_equal(a, b)
 
 
-def test_bench_scene_sorted_entries_bit_exact(torch_dev, bench_scene):
-    """Sorted list at the benchmark's full size (about 1.1M entries)."""
+@pytest.mark.parametrize("mode,tile", [("eager", 16), ("graph", 8)])
+def test_bench_scene_sorted_entries_bit_exact(torch_dev, bench_scene, bench_device_scene,
+                                              bench_rank_table, mode, tile):
+    """The whole sorted list of the benchmark view (1.1-1.7M entries)."""
     torch = torch_dev
     scene, cams = bench_scene
-    _say("sorted entries, 1.07M-voxel scene")
-    out = _gpu_frame(torch, scene, cams, K=2)
-    rast = out["rast"]
-    keys, vals = rast.sorted_entries(rast.n_entries)
-    _check_sorted_list(scene, cams[0], keys.cpu().numpy().view(np.uint64),
-                       vals.cpu().numpy().view(np.uint32), True)
+    _say("sorted entries, 1.07M-voxel scene, %s, tile %d" % (mode, tile))
+    P = cams[0].W * cams[0].H
+    r, _, _, _, E = _bench_frame(torch, bench_device_scene, cams[0], mode, tile,
+                                 np.zeros((P, 4)))
+    keys, vals = r.sorted_entries(E)
+    check_sorted_list(scene, cams[0], keys.cpu().numpy().view(np.uint64),
+                      vals.cpu().numpy().view(np.uint32), True, tile=tile,
+                      rank_table=bench_rank_table)
+    r.release_graph()
 
 
-def test_autograd_central_differences_bench_scene(torch_dev, bench_scene):
-    """Gradients from torch.autograd through the C ABI against central finite
-    differences of the GPU forward on 64 sampled parameters (32 corner raw
-    densities, 32 SH coefficients) of the 1.07M-voxel scene at 1297x840, K = 2.
-    The forward is deterministic, so the two perturbed renders differ only
-    where the parameter acts; the loss is summed in float64."""
+def _pixel_roi(scene, cam, voxels, margin=1.5):
+    """Pixels whose rays can meet any of `voxels`: the box of the projected
+    corners, widened by `margin` pixels (None when a corner is not in front
+    of the camera)."""
+    R = np.asarray(cam.w2c, np.float64)[:, :3]
+    t = np.asarray(cam.w2c, np.float64)[:, 3]
+    px = []
+    for v in voxels:
+        c = scene.center[:, v].astype(np.float64)
+        h = 0.5 * float(scene.size[v])
+        corners = c + h * np.array([[dx, dy, dz] for dx in (-1, 1) for dy in (-1, 1)
+                                    for dz in (-1, 1)], np.float64)
+        q = corners @ R.T + t
+        if (q[:, 2] <= 1e-3).any():
+            return None
+        u = cam.fx * q[:, 0] / q[:, 2] + cam.cx
+        w = cam.fy * q[:, 1] / q[:, 2] + cam.cy
+        x0, x1 = max(0, int(np.floor(u.min() - margin))), min(cam.W - 1, int(np.floor(u.max() + margin)))
+        y0, y1 = max(0, int(np.floor(w.min() - margin))), min(cam.H - 1, int(np.floor(w.max() + margin)))
+        if x0 > x1 or y0 > y1:
+            continue
+        yy, xx = np.meshgrid(np.arange(y0, y1 + 1), np.arange(x0, x1 + 1), indexing="ij")
+        px.append((yy * cam.W + xx).reshape(-1))
+    return np.unique(np.concatenate(px)) if px else np.zeros(0, np.int64)
+
+
+def test_bench_scene_gradients_against_oracle_central_differences(torch_dev, bench_scene,
+                                                                  bench_device_scene):
+    """64 sampled parameters of the benchmark view (32 corner raw densities, 32
+    SH coefficients; Supp. A.2 gradient of alpha chained through the
+    compositing and colour equations): the GPU gradient through
+    torch.autograd.Function against the oracle's FP64 adjoint within 1e-3
+    relative, and the oracle's adjoint against FP64 central differences of
+    the oracle's own render over the parameter's pixel region within 1e-6
+    relative.  The upstream gradient is N(0, 1) on the union of the regions
+    (zero on pixels the oracle flags) and zero elsewhere, so each sampled
+    parameter's gradient is complete on both sides."""
+    import dataclasses
     torch = torch_dev
-    from paper_2412_04459_amd.render import DeviceScene, Rasterizer, render
+    from paper_2412_04459_amd.render import Rasterizer, render
     scene, cams = bench_scene
-    _say("central differences, 1.07M-voxel scene")
-    ds = DeviceScene(scene)
+    cam = cams[0]
+    P = cam.W * cam.H
+    ds = bench_device_scene
+    _say("oracle central differences, 1.07M-voxel scene")
+    rast = Rasterizer(ds, [cam], K=2, tile=8)
+    # candidates: parameters with a sizeable gradient under a dense upstream
+    # gradient (selection only; the values compared come from the runs below)
+    grid = ds.grid_raw.clone().requires_grad_(True)
+    sh = ds.sh.clone().requires_grad_(True)
+    g0 = torch.from_numpy(S.upstream_grads(P, 21)).cuda()
+    (render(rast, grid, sh) * g0).sum().backward()
+    gg0 = np.abs(grid.grad.cpu().numpy().astype(np.float64))
+    gs0 = np.abs(sh.grad.cpu().numpy().astype(np.float64).reshape(-1))
+    del grid, sh
+    rng = np.random.default_rng(77)
+    vg = scene.vox_grid.reshape(scene.n_voxels, 8)
+    slots = np.argsort(vg.reshape(-1), kind="stable")
+    starts = np.searchsorted(vg.reshape(-1)[slots], np.arange(scene.n_grid + 1))
+    o = cam.position()
+    params = []  # (kind, index, voxels)
+    for m in rng.permutation(np.nonzero(gg0 > np.median(gg0[gg0 > 0]))[0]):
+        vox = slots[starts[m]:starts[m + 1]] // 8
+        if _pixel_roi(scene, cam, vox) is not None:
+            params.append(("grid", int(m), vox))
+        if len(params) == 32:
+            break
+    for e in rng.permutation(np.nonzero(gs0 > np.median(gs0[gs0 > 0]))[0]):
+        v, ch = int(e) // 48, int(e) % 3
+        Yv = oracle.sh_basis(3, scene.center[:, v].astype(np.float64) - o)
+        pre = float(np.dot(Yv, scene.sh[v, :, ch].astype(np.float64)))
+        if abs(pre) > 1e-3 and _pixel_roi(scene, cam, [v]) is not None:
+            params.append(("sh", int(e), np.array([v])))
+        if len(params) == 64:
+            break
+    assert len(params) == 64
+    rois = [_pixel_roi(scene, cam, vox) for _, _, vox in params]
+    union = np.unique(np.concatenate(rois))
+    _say("  %d parameters, %d pixels in their regions" % (len(params), len(union)))
+    g = np.zeros((P, 4), np.float32)
+    g[union] = S.upstream_grads(P, 22)[union]
+    flags = oracle.render(scene, cam, K=2, pixels=union)["flags"]
+    g[union[flags != 0]] = 0.0
+    ref = oracle.render(scene, cam, K=2, pixels=union, grad_rgba=g[union].astype(np.float64))
+    grid = ds.grid_raw.clone().requires_grad_(True)
+    sh = ds.sh.clone().requires_grad_(True)
+    (render(rast, grid, sh) * torch.from_numpy(g).cuda()).sum().backward()
+    torch.cuda.synchronize()
+    gpu_g = grid.grad.cpu().numpy().astype(np.float64)
+    gpu_s = sh.grad.cpu().numpy().astype(np.float64).reshape(-1)
+    ref_s = ref["grad_sh"].reshape(-1)
+    raw64 = scene.grid_raw.astype(np.float64)
+    sh64 = scene.sh.astype(np.float64)
+    e_gpu, e_fd = [], []
+    for (kind, idx, _), roi in zip(params, rois):
+        theta = raw64[idx] if kind == "grid" else sh64.reshape(-1)[idx]
+        h = 1e-4 * max(1.0, abs(theta))
+        loss = []
+        for sgn in (1.0, -1.0):
+            if kind == "grid":
+                p = raw64.copy(); p[idx] += sgn * h
+                sc = dataclasses.replace(scene, grid_raw=p)
+            else:
+                p = sh64.copy().reshape(-1); p[idx] += sgn * h
+                sc = dataclasses.replace(scene, sh=p.reshape(sh64.shape))
+            out = oracle.render(sc, cam, K=2, pixels=roi)
+            loss.append(float((out["rgba"] * g[roi].astype(np.float64)).sum()))
+        fd = (loss[0] - loss[1]) / (2 * h)
+        r_o = ref["grad_grid"][idx] if kind == "grid" else ref_s[idx]
+        r_g = gpu_g[idx] if kind == "grid" else gpu_s[idx]
+        assert r_o != 0.0
+        e_fd.append(abs(fd - r_o) / abs(r_o))
+        e_gpu.append(abs(r_g - r_o) / abs(r_o))
+    e_fd, e_gpu = np.array(e_fd), np.array(e_gpu)
+    _say("  oracle adjoint vs oracle FD: max rel %.2e; GPU vs oracle adjoint: max rel %.2e"
+         % (e_fd.max(), e_gpu.max()))
+    assert e_fd.max() <= 1e-6
+    assert e_gpu.max() <= 1e-3
+
+
+def test_autograd_central_differences_bench_scene(torch_dev, bench_scene, bench_device_scene):
+    """fp32 smoke check of the autograd path: gradients from
+    torch.autograd through the C ABI against central finite differences of
+    the GPU forward on 64 sampled parameters (32 corner raw densities, 32 SH
+    coefficients) of the benchmark view, h = 1e-2 max(1, |theta|): the fp32
+    rendering error of the affected pixels (about 1e-7 of their values)
+    divided by h is the noise of the difference quotient, and at h = 1e-3 it
+    reaches 2e-2 of the smallest sampled gradients.  The forward is
+    deterministic, so the two perturbed renders differ only where the
+    parameter acts; the loss is summed in float64."""
+    torch = torch_dev
+    from paper_2412_04459_amd.render import Rasterizer, render
+    scene, cams = bench_scene
+    _say("GPU central differences, 1.07M-voxel scene")
+    ds = bench_device_scene
     rast = Rasterizer(ds, cams, K=2)
     grid = ds.grid_raw.clone().requires_grad_(True)
     sh = ds.sh.clone().requires_grad_(True)
@@ -393,7 +514,7 @@ def test_autograd_central_differences_bench_scene(torch_dev, bench_scene):
     base_grid = ds.grid_raw.clone()
     errs = []
     for m in pick_g:
-        h = 2e-2 * max(1.0, abs(float(scene.grid_raw[m])))
+        h = 1e-2 * max(1.0, abs(float(scene.grid_raw[m])))
         up = base_grid.clone(); up[m] += h
         dn = base_grid.clone(); dn[m] -= h
         fd = (loss(up, ds.sh) - loss(dn, ds.sh)) / (2 * h)
@@ -412,15 +533,14 @@ def test_autograd_central_differences_bench_scene(torch_dev, bench_scene):
     pick_s = rng.choice(ok, 32, replace=False)
     base_sh = ds.sh.clone().reshape(-1)
     for e in pick_s:
-        h = 1e-2
+        h = 1e-2 * max(1.0, abs(float(base_sh[e])))
         up = base_sh.clone(); up[e] += h
         dn = base_sh.clone(); dn[e] -= h
         fd = (loss(ds.grid_raw, up.reshape(ds.sh.shape)) - loss(ds.grid_raw, dn.reshape(ds.sh.shape))) / (2 * h)
         errs.append(abs(fd - gs[e]) / max(abs(fd), abs(gs[e])))
     errs = np.array(errs)
     _say("  relative FD error: median %.2e max %.2e" % (np.median(errs), errs.max()))
-    assert np.median(errs) < 5e-3
-    assert errs.max() < 3e-2
+    assert errs.max() < 1e-2
 
 
 # ---------------------------------------------------------------------------
@@ -593,3 +713,135 @@ def test_supersampled_render_with_background_matches_oracle(torch_dev):
     ref = oracle.render(scene, hi, K=2, grad_rgba=g_hi.reshape(-1, 4))
     _check_grad(grid.grad.cpu().numpy().astype(np.float64), ref["grad_grid"], "grad_grid")
     _check_grad(sh.grad.cpu().numpy().astype(np.float64), ref["grad_sh"], "grad_sh")
+
+
+def test_autograd_backward_after_a_second_render(torch_dev):
+    """Two renders through the same rasterizer before backward (two loss
+    terms over different densities): each output's gradient equals the
+    gradient of a single forward/backward with its own parameters."""
+    torch = torch_dev
+    from paper_2412_04459_amd.render import DeviceScene, Rasterizer, render
+    scene = S.sphere_shell_scene(opaque=True)
+    cams = [S.sphere_shell_camera()]
+    ds = DeviceScene(scene)
+    rast = Rasterizer(ds, cams, K=2, tile=8)
+    P = cams[0].W * cams[0].H
+    ga = torch.from_numpy(S.upstream_grads(P, 41)).cuda()
+    gb = torch.from_numpy(S.upstream_grads(P, 42)).cuda()
+    raw_b = (ds.grid_raw * 0.5 - 0.3).contiguous()
+    # references: one frame each
+    ref_a = rast.forward(ds.grid_raw, ds.sh).clone()
+    a_gg, a_gs = [t.clone() for t in rast.backward(ga, ds.grid_raw, ds.sh)]
+    rast.forward(raw_b, ds.sh)
+    b_gg, b_gs = [t.clone() for t in rast.backward(gb, raw_b, ds.sh)]
+    # both renders first, then one backward over both loss terms
+    grid_a = ds.grid_raw.clone().requires_grad_(True)
+    grid_b = raw_b.clone().requires_grad_(True)
+    sh = ds.sh.clone().requires_grad_(True)
+    out_a = render(rast, grid_a, sh)
+    out_b = render(rast, grid_b, sh)
+    assert torch.equal(out_a, ref_a)
+    ((out_a * ga).sum() + (out_b * gb).sum()).backward()
+    torch.cuda.synchronize()
+    assert torch.allclose(grid_a.grad, a_gg, rtol=1e-5, atol=1e-7)
+    assert torch.allclose(grid_b.grad, b_gg, rtol=1e-5, atol=1e-7)
+    assert torch.allclose(sh.grad, a_gs + b_gs, rtol=1e-5, atol=1e-6)
+
+
+# ---------------------------------------------------------------------------
+# the large scene (about 8M voxels, max level 14, SH degree 3, K = 1) at one
+# 1920x1080 view of its orbit, 8x8 tiles, no host synchronisation, one
+# captured hipGraph: sampled pixels and gradients against the oracle, and
+# the sorted lists of sampled tiles bit-exact
+# ---------------------------------------------------------------------------
+def test_large_scene_view_sampled_parity(torch_dev):
+    torch = torch_dev
+    from paper_2412_04459_amd.render import DeviceScene
+    scene = S.large_shells_scene()
+    cam = S.orbit_cameras_1080p()[0]
+    P = cam.W * cam.H
+    _say("large scene N=%d, one 1920x1080 view" % scene.n_voxels)
+    ds = DeviceScene(scene)
+    # sample: pixels with hits (from an untimed frame) and random pixels
+    _, rgba0, _, _, _ = _large_frame(torch, ds, cam, np.zeros((P, 4), np.float32))
+    a0 = rgba0[:, 3].cpu().numpy()
+    rng = np.random.default_rng(17)
+    px = np.unique(np.concatenate([rng.choice(np.nonzero(a0 > 0)[0], 300, replace=False),
+                                   rng.choice(P, 60, replace=False)]))
+    ref0 = oracle.render(scene, cam, K=1, pixels=px)
+    g = np.zeros((P, 4), np.float32)
+    g[px] = S.upstream_grads(P, 4)[px]
+    g[px[ref0["flags"] != 0]] = 0.0
+    ref = oracle.render(scene, cam, K=1, pixels=px, grad_rgba=g[px].astype(np.float64))
+    r, rgba, gg, gs, E = _large_frame(torch, ds, cam, g)
+    _check_rgba(rgba.cpu().numpy().astype(np.float64), ref0, pixels=px)
+    _check_grad(gg.cpu().numpy(), ref["grad_grid"], "grad_grid")
+    _check_grad(gs.cpu().numpy(), ref["grad_sh"], "grad_sh")
+    # sorted lists of sampled tiles: every entry's key and value against the
+    # oracle's, each tile's entries strictly ascending in the paper's key
+    # order, and the tile's entry set between the oracle's bounds
+    keys, vals = r.sorted_entries(E)
+    gk = keys.cpu().numpy().view(np.uint64)
+    gv = vals.cpu().numpy().view(np.uint32)
+    key_low = int(8 * scene.n_voxels - 1).bit_length()
+    assert np.all(gk[1:] > gk[:-1])
+    tid = (gk >> np.uint64(key_low)).astype(np.int64)
+    ntile = ((cam.W + 7) // 8) * ((cam.H + 7) // 8)
+    pick = rng.choice(np.unique(tid), 40, replace=False)
+    sel = np.isin(tid, pick)
+    vid = (gv[sel] & np.uint32((1 << 29) - 1)).astype(np.int64)
+    sgn = (gv[sel] >> np.uint32(29)).astype(np.uint8)
+    _, kc, val = oracle.keys(tid[sel], vid, sgn, scene.octpath, scene.max_level)
+    assert np.array_equal(val, gv[sel])
+    for t in pick:
+        kt = kc[tid[sel] == t]
+        assert np.all(kt[1:] > kt[:-1]), "tile %d out of the paper's key order" % t
+    # the low key bits are the rank of (path XOR s, s) among all 8N pairs
+    n8 = 8 * scene.n_voxels
+    all_vid = np.repeat(np.arange(scene.n_voxels, dtype=np.int64), 8)
+    all_sgn = np.tile(np.arange(8, dtype=np.uint8), scene.n_voxels)
+    _, all_kc, _ = oracle.keys(np.zeros(n8, np.int64), all_vid, all_sgn, scene.octpath,
+                               scene.max_level)
+    del all_vid, all_sgn
+    all_kc.sort()
+    _, own, _ = oracle.keys(np.zeros(vid.size, np.int64), vid, sgn, scene.octpath, scene.max_level)
+    rank = np.searchsorted(all_kc, own)
+    del all_kc
+    low = (gk[sel] & np.uint64((1 << key_low) - 1)).astype(np.int64)
+    assert np.array_equal(low, rank)
+    exp = oracle.expected_entries(scene, cam, tile_w=8, tile_h=8)
+    for name, bound in (("must", exp["must"]), ("may", exp["may"])):
+        bk = bound[0]
+        btile = (bk >> np.uint64(3 * scene.max_level + 3)).astype(np.int64)
+        inb = bk[np.isin(btile, pick)]
+        if name == "must":
+            assert np.all(np.isin(inb, kc)), "missing required entries"
+            assert inb.size > 0
+        else:
+            assert np.all(np.isin(kc, inb)), "entries outside the band"
+    assert tid.max() < ntile
+    r.release_graph()
+
+
+def _large_frame(torch, ds, cam, grad):
+    """One fwd+bwd frame of a 1920x1080 view of the large scene, K = 1, in the
+    batched benchmark's configuration (8x8 tiles, capacity from a counted
+    probe, no host synchronisation, captured hipGraph)."""
+    from paper_2412_04459_amd.render import Rasterizer
+    probe = Rasterizer(ds, [cam], K=1, sync_count=True, tile=8)
+    probe.preprocess()
+    cap = int(probe.n_entries * 1.1) + 4096
+    del probe
+    r = Rasterizer(ds, [cam], K=1, capacity=cap, sync_count=False, tile=8)
+    P = cam.W * cam.H
+    g = torch.from_numpy(np.ascontiguousarray(grad, np.float32)).cuda()
+    rgba = torch.empty((P, 4), dtype=torch.float32, device="cuda")
+    gg = torch.empty((ds.n_grid,), dtype=torch.float32, device="cuda")
+    gs = torch.empty_like(ds.sh)
+    stream = torch.cuda.Stream()
+    r.capture(rgba, g, gg, gs, stream)
+    r.replay(stream)
+    torch.cuda.synchronize()
+    E = r.check_overflow()
+    assert 0 < E <= cap
+    return r, rgba, gg, gs, E
