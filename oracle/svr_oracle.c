@@ -424,7 +424,7 @@ static int64_t collect_hits(const scene_t* S, const double o[3], const double d[
       ++n;
     }
   }
-  qsort(*buf, (size_t)n, sizeof(hit_t), hit_cmp);
+  if (n > 1) qsort(*buf, (size_t)n, sizeof(hit_t), hit_cmp);
   return n;
 }
 

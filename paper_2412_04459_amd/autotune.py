@@ -1,8 +1,9 @@
 """Autotuner for the batched forward + backward of many cameras.
 
 The search space is the tile edge (8, 16, 32 pixels), the render scheduling
-(one workgroup per tile, or a persistent grid of n workgroups taking tiles
-from per-XCD counters) and the batch size (cameras per launch: every camera
+(one workgroup per tile, or a persistent grid of n workgroups taking the
+next tile of the heaviest-first order from one global counter) and the batch
+size (cameras per launch: every camera
 of a group goes through one launch per stage and one hipGraph).  A
 coordinate search tries the tile edges first, then the scheduling for the
 best edge, then the batch sizes; every candidate is timed as replays of its
