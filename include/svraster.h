@@ -244,6 +244,26 @@ int svr_radix_sort_pairs(uint64_t* keys, uint32_t* values, uint64_t* keys_tmp,
                          uint32_t* values_tmp, int64_t n, int bits, void* scratch,
                          size_t scratch_bytes, void* stream);
 
+/* svr_radix_sort_pairs for callers that cannot allocate (code under stream
+ * or graph capture, tight serving loops, hosts that forbid allocation): the
+ * same sort with its second key/value buffer, counters, digit histograms
+ * and look-back status in a device array the library holds, one copy per
+ * GPU, SVR_STATIC_SORT_BYTES in size, kept until the process ends.  The
+ * caller passes only the pairs.  Nothing is allocated: no hipMalloc, no
+ * hipFree, no allocating library call.
+ *   keys/values: device [n], sorted in place on bits [0, bits);
+ *   n <= SVR_STATIC_SORT_MAX (larger n: SVR_E_INVALID, nothing launched);
+ *   stream: a stream of the current device.
+ * Every call on one GPU uses that GPU's array and leaves its contents from
+ * the last call (the counters it needs zeroed are cleared by each call):
+ * calls that overlap on one GPU (other streams, other host threads) race
+ * and must be serialised by the caller.
+ * Errors: SVR_E_INVALID, SVR_E_HIP.                                          */
+#define SVR_STATIC_SORT_MAX (1 << 21)
+#define SVR_STATIC_SORT_BYTES ((size_t)26223104)
+int svr_radix_sort_pairs_static(uint64_t* keys, uint32_t* values, int64_t n, int bits,
+                                void* stream);
+
 /* Frame statistics (diagnostics; synchronises `stream`), after svr_sort:
  *   counts[0]  entries E of the sorted list
  *   counts[1]  (pixel, entry) pairs with the pixel's sign pattern that the

@@ -26,6 +26,7 @@ SVR_ACT_EXPLIN = 0
 SVR_ACT_SOFTPLUS = 1
 SVR_MAX_CAMERAS = 32
 SVR_TILE = 16
+SVR_STATIC_SORT_MAX = 1 << 21
 
 P = ctypes.c_void_p
 I64 = ctypes.c_int64
@@ -65,6 +66,7 @@ _SIGS = {
     "svr_copy_sorted": (ctypes.c_int, [P, P, ctypes.c_int, P, P, ctypes.c_size_t, P, P, I64, P]),
     "svr_radix_sort_scratch_bytes": (ctypes.c_size_t, [I64, ctypes.c_int]),
     "svr_radix_sort_pairs": (ctypes.c_int, [P, P, P, P, I64, ctypes.c_int, P, ctypes.c_size_t, P]),
+    "svr_radix_sort_pairs_static": (ctypes.c_int, [P, P, I64, ctypes.c_int, P]),
     "svr_render_stats": (ctypes.c_int, [P, P, ctypes.c_int, P, P, ctypes.c_size_t, P, P]),
     "svr_timing_enable": (ctypes.c_int, [ctypes.c_int]),
     "svr_timing_read": (ctypes.c_int, [P, ctypes.c_int, P, P, ctypes.c_int, P]),
@@ -200,6 +202,10 @@ def svr_radix_sort_pairs(keys, values, keys_tmp, values_tmp, n, bits, scratch, s
                          stream):
     return load().svr_radix_sort_pairs(keys, values, keys_tmp, values_tmp, n, bits, scratch,
                                        scratch_bytes, stream)
+
+
+def svr_radix_sort_pairs_static(keys, values, n, bits, stream):
+    return load().svr_radix_sort_pairs_static(keys, values, n, bits, stream)
 
 
 def svr_render_stats(scene, cams, n_cams, opts, ws, ws_bytes, counts, stream):

@@ -450,6 +450,91 @@ int svr_radix_sort_pairs(uint64_t* keys, uint32_t* values, uint64_t* keys_tmp,
   return SVR_OK;
 }
 
+}  // extern "C"
+
+// ---- the sort with library-held scratch --------------------------------------
+// Layout of the array: [sort counters, histograms, status] [keys_tmp] [values_tmp],
+// each part sized for SVR_STATIC_SORT_MAX pairs.
+namespace svr {
+namespace {
+constexpr int64_t kStaticParts = (SVR_STATIC_SORT_MAX + kSortPart - 1) / kSortPart;
+constexpr size_t kStaticHead =
+    ((size_t)(8 * 256 + 2 * kStaticParts * 256 + 64) * 4 + 256 + 255) / 256 * 256;
+constexpr size_t kStaticKeys = kStaticHead;
+constexpr size_t kStaticVals = kStaticKeys + (size_t)SVR_STATIC_SORT_MAX * 8;
+constexpr size_t kStaticEnd = kStaticVals + (size_t)SVR_STATIC_SORT_MAX * 4;
+static_assert(kStaticEnd == SVR_STATIC_SORT_BYTES, "SVR_STATIC_SORT_BYTES is the array size");
+constexpr int kMaxDevices = 64;
+std::mutex g_static_mu;
+void* g_static_ptr[kMaxDevices] = {};
+}  // namespace
+}  // namespace svr
+
+static __device__ __align__(256) unsigned char scratch[svr::kStaticEnd];
+
+namespace svr {
+namespace {
+// Device address of `scratch` on the current device, looked up once per
+// device (each GPU holds its own copy of the array at its own address).
+int static_scratch(unsigned char** out) {
+  int dev = -1;
+  SVR_HIP(hipGetDevice(&dev), "current device");
+  if (dev < 0 || dev >= kMaxDevices) return fail(SVR_E_INVALID, "device %d outside 0..63", dev);
+  std::lock_guard<std::mutex> lk(g_static_mu);
+  if (!g_static_ptr[dev]) {
+    void* p = nullptr;
+    SVR_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)), "address of the sort scratch array");
+    if (!p) return fail(SVR_E_HIP, "null address of the sort scratch array");
+    g_static_ptr[dev] = p;
+  }
+  *out = static_cast<unsigned char*>(g_static_ptr[dev]);
+  return SVR_OK;
+}
+}  // namespace
+}  // namespace svr
+
+extern "C" {
+
+int svr_radix_sort_pairs_static(uint64_t* keys, uint32_t* values, int64_t n, int bits,
+                                void* stream) {
+  if (n < 0 || n > (int64_t)SVR_STATIC_SORT_MAX)
+    return fail(SVR_E_INVALID, "n=%lld outside [0, %d] (the library-held sort scratch)",
+                (long long)n, SVR_STATIC_SORT_MAX);
+  if (bits < 0 || bits > 64) return fail(SVR_E_INVALID, "bits outside 0..64");
+  if (n == 0) return SVR_OK;
+  if (!keys || !values) return fail(SVR_E_INVALID, "null pointer");
+  int64_t parts = 0;
+  if (align_up(sort_scratch_bytes(n, bits, &parts), 256) > kStaticHead)
+    return fail(SVR_E_INVALID, "sort scratch exceeds the library-held array");
+  unsigned char* ptr = nullptr;
+  int st = static_scratch(&ptr);
+  if (st != SVR_OK) return st;
+  hipStream_t s = reinterpret_cast<hipStream_t>(stream);
+  // [n as u64 | tickets 16 | err | pad] [hist 2048] [status0] [status1], as in
+  // svr_radix_sort_pairs
+  uint32_t* base = reinterpret_cast<uint32_t*>(ptr);
+  auto* n_dev = reinterpret_cast<unsigned long long*>(base);
+  uint32_t* tickets = base + 2;
+  uint32_t* err = base + 18;
+  uint32_t* hist = base + 64;
+  uint32_t* st0 = hist + 8 * 256;
+  uint32_t* st1 = st0 + parts * 256;
+  uint64_t* keys_tmp = reinterpret_cast<uint64_t*>(ptr + kStaticKeys);
+  uint32_t* values_tmp = reinterpret_cast<uint32_t*>(ptr + kStaticVals);
+  SVR_HIP(launch_fill_u32(base, 0u, 64, s), "clear scratch");
+  SVR_HIP(launch_fill_u32(base, (uint32_t)(n & 0xffffffffu), 1, s), "store n");
+  bool in1 = false;
+  SVR_HIP(launch_radix_sort(keys, values, keys_tmp, values_tmp, n_dev, n, bits, 0, hist, st0, st1,
+                            tickets, err, &in1, s),
+          "radix sort");
+  if (in1) {
+    SVR_HIP(hipMemcpyAsync(keys, keys_tmp, (size_t)n * 8, hipMemcpyDeviceToDevice, s), "copy keys");
+    SVR_HIP(hipMemcpyAsync(values, values_tmp, (size_t)n * 4, hipMemcpyDeviceToDevice, s),
+            "copy values");
+  }
+  return SVR_OK;
+}
+
 int svr_render_stats(const svr_scene* scene, const svr_camera* cams, int n_cams,
                      const svr_opts* opts, void* ws, size_t ws_bytes, int64_t* counts,
                      void* stream) {
