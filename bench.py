@@ -38,10 +38,28 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-# algorithmic VALU lane operations of the render kernels (see the design notes)
-OPS_PAIR = 23              # sign test + ray-box slab test per walked (pixel, entry)
-OPS_HIT_FWD = lambda K: 13 + 28 * K
-OPS_HIT_BWD = lambda K: 2 * (13 + 28 * K) + 20 * K + 30
+# Algorithmic VALU lane operations of the render kernels, two counts.
+# "design": the operations the kernels' inner loops perform, counted per
+# walked (pixel, entry) pair and per hit from the code's arithmetic (sign
+# test + fp64 slab test per pair; K samples of local coordinate, trilinear,
+# activation, then alpha and compositing per hit; the backward recomputes the
+# forward's hit and forms the 8 corner weights per sample).
+# "estimate": the coarser per-unit figures of the measurement plan (about 20
+# per pair, 70 + 60 K per forward hit, 2.5 times that per backward hit).
+OPS = {
+    "design": {"pair": 23, "hit_fwd": lambda K: 13 + 28 * K,
+               "hit_bwd": lambda K: 2 * (13 + 28 * K) + 20 * K + 30},
+    "estimate": {"pair": 20, "hit_fwd": lambda K: 70 + 60 * K,
+                 "hit_bwd": lambda K: 2.5 * (70 + 60 * K)},
+}
+OPS_PAIR = OPS["design"]["pair"]
+OPS_HIT_FWD = OPS["design"]["hit_fwd"]
+OPS_HIT_BWD = OPS["design"]["hit_bwd"]
+# the paper's forward rendering rate on its RTX 3090 Ti (Mip-NeRF360 at 1x:
+# 121 FPS at 1-1.6 Mpix per frame), context only
+PAPER_CONTEXT = {"fps": 121, "mpix_s_range": [121, 194], "hardware": "NVIDIA RTX 3090 Ti",
+                 "what": "forward rendering only, trained Mip-NeRF360 scenes at 1x evaluation "
+                         "resolution (Sec. 4 main results)"}
 
 
 def frame_bytes(N, Nv, E, P, S):
@@ -57,6 +75,35 @@ def frame_bytes(N, Nv, E, P, S):
     }
 
 
+STAGES = [("H1 tile masks + summed-area table", ("tile_masks", "tile_sat"), None),
+          ("H2-H3 project + per-view record", ("project",), ("project", "preprocess")),
+          ("H4 scan + emit", ("scan_top", "emit"), ("emit",)),
+          ("H5-H6 sort + tile ranges", ("sort_hist", "sort_hist_scan", "sort_pass", "tile_ranges",
+                                        "tile_order", "tile_sort_small", "tile_sort_big"),
+           ("sort",)),
+          ("H7 render forward", ("render_fwd",), ("render_fwd",)),
+          ("H8 render backward", ("render_bwd",), ("render_bwd",)),
+          ("H9 pre-process adjoint", ("sh_bwd", "grid_gather"), ("sh_bwd",)),
+          ("fills", ("fill",), None)]
+
+
+def stage_rows(per_kernel, N, Nv, E, P, S):
+    """Per stage of the path: time per frame (HIP events), algorithmic bytes,
+    and the HBM rate those bytes imply against the 8 TB/s peak."""
+    fb = frame_bytes(N, Nv, E, P, S)
+    rows = {}
+    for name, kernels, parts in STAGES:
+        ms = sum(per_kernel[k]["ms_per_step"] for k in kernels if k in per_kernel)
+        row = {"kernels": list(kernels), "ms_per_step": ms}
+        if parts:
+            b = float(sum(fb[x] for x in parts))
+            row["bytes"] = b
+            row["achieved_GBs"] = b / (ms / 1e3) / 1e9 if ms > 0 else None
+            row["frac_hbm"] = row["achieved_GBs"] / HBM_PEAK_GBS if ms > 0 else None
+        rows[name] = row
+    return rows
+
+
 def kernel_bytes(name, N, Nv, E, P, S, passes):
     if name == "sort_pass":
         return 24 * E / 1.0  # per pass launch: read + write of the list
@@ -66,14 +113,16 @@ def kernel_bytes(name, N, Nv, E, P, S, passes):
             "sh_bwd": fb["sh_bwd"]}.get(name)
 
 
-def cpu_baseline(scene, cam, K, seconds_target=15.0):
+def cpu_baseline(scene, cam, K, seconds_target=15.0, threads=None):
     import oracle
-    threads = len(os.sched_getaffinity(0))
+    threads = threads or len(os.sched_getaffinity(0))
     rng = np.random.default_rng(99)
     P = cam.W * cam.H
     n = 64
     t_used = 0.0
     done = 0
+    if threads == 1:
+        n = 16
     while t_used < seconds_target and done < 8192:
         px = rng.choice(P, n, replace=False)
         g = np.random.default_rng(done).normal(size=(n, 4))
@@ -81,7 +130,7 @@ def cpu_baseline(scene, cam, K, seconds_target=15.0):
         oracle.render(scene, cam, K=K, pixels=px, grad_rgba=g, nthreads=threads)
         t_used += time.perf_counter() - t0
         done += n
-        n = min(2 * n, 1024)
+        n = min(2 * n, 1024 if threads > 1 else 128)
     model = ""
     try:
         for line in open("/proc/cpuinfo"):
@@ -125,6 +174,137 @@ def measured_traffic(kernel):
             if k == kernel and blk.get("fetch_factor"):
                 return v["bytes_scaled"], os.path.relpath(f, ROOT)
     return None, None
+
+
+def measured_counters(kernel):
+    """Hardware counters per dispatch of one kernel (mean over its dispatches)
+    from a committed rocprofv3 --pmc summary under profiles/ taken on the
+    current HIP sources: {counter: value}, and the summary's path."""
+    import glob
+    import re as _re
+    from paper_2412_04459_amd.profsum import source_hash
+    h = source_hash()
+    out, src = {}, None
+    for f in sorted(glob.glob(os.path.join(ROOT, "profiles", "*.md"))):
+        m = _re.search(r"```json\n(.*?)\n```", open(f).read(), _re.S)
+        if not m:
+            continue
+        blk = json.loads(m.group(1))
+        if blk.get("source_hash") != h:
+            continue
+        c = blk.get("counters", {}).get(kernel)
+        if c:
+            out.update(c)
+            src = os.path.relpath(f, ROOT)
+    return out, src
+
+
+def atomic_probe_run(n_rows, log, n_waves=1 << 18, iters=32, reps=5):
+    """Float atomic adds in the render backward's flush pattern (11 lanes per
+    instruction over a voxel's corner and colour rows, no return) on an array
+    of n_rows voxels: instructions and lane atomics per second, timed with
+    HIP events on the launch stream."""
+    import ctypes
+    import torch
+    from paper_2412_04459_amd import _abi
+    corner = torch.zeros((n_rows, 8), dtype=torch.float32, device="cuda")
+    colour = torch.zeros((n_rows, 3), dtype=torch.float32, device="cuda")
+    st = torch.cuda.current_stream()
+    sp = ctypes.c_void_p(st.cuda_stream)
+
+    def launch():
+        rc = _abi.svr_atomic_probe(ctypes.c_void_p(corner.data_ptr()),
+                                   ctypes.c_void_p(colour.data_ptr()), n_rows, n_waves, iters, sp)
+        _abi.check(rc, "svr_atomic_probe")
+
+    launch()
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(st)
+    for _ in range(reps):
+        launch()
+    e1.record(st)
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    total = float(corner.double().sum().item() + colour.double().sum().item())
+    expect = 11.0 * n_waves * iters * (reps + 1)
+    assert total == expect, "atomic probe lost updates: %r vs %r" % (total, expect)
+    inst = n_waves * iters
+    log("atomic probe: %d instructions (11 lanes) over %d voxels in %.3f ms" % (inst, n_rows, ms))
+    del corner, colour
+    return {"pattern": "11-lane float atomic add, no return, random voxel rows (8 + 3 floats)",
+            "rows": n_rows, "instructions": inst, "ms": ms,
+            "instructions_per_s": inst / (ms / 1e3), "lane_atomics_per_s": 11 * inst / (ms / 1e3)}
+
+
+def small_configs_run(log, no_cpu, cpu_seconds):
+    """The two small workloads: a plain forward render of the ~3.3k-voxel
+    level-6 sphere shell at 64x64 (K = 1, SH degree 0) and fwd+bwd of the
+    ~184k-voxel spheres-and-plane scene at 800x800 (K = 1, SH degree 3), each
+    timed on the GPU (eager launches, median of repeated frames) and, unless
+    no_cpu, the oracle on the host (all threads; cfg0 full frame, the other on
+    a pixel sample)."""
+    import torch
+    from paper_2412_04459_amd import scenes as S
+    from paper_2412_04459_amd.render import DeviceScene, Rasterizer
+    out = {}
+    for name, bwd in (("sphere_shell_3k", False), ("spheres_plane_184k", True)):
+        wl = S.workload(name)
+        cam = wl.cameras[0]
+        P = cam.W * cam.H
+        ds = DeviceScene(wl.scene)
+        probe = Rasterizer(ds, [cam], K=wl.K, sync_count=True, tile=8)
+        probe.preprocess()
+        cap = int(probe.n_entries * 1.1) + 4096
+        del probe
+        r = Rasterizer(ds, [cam], K=wl.K, capacity=cap, sync_count=False, tile=8)
+        g = torch.from_numpy(S.upstream_grads(P, wl.grad_seed)).cuda()
+        rgba = torch.empty((P, 4), dtype=torch.float32, device="cuda")
+        gg = torch.empty(ds.n_grid, dtype=torch.float32, device="cuda")
+        gs = torch.empty_like(ds.sh)
+        # the frame as one captured hipGraph (small frames are launch-bound)
+        r.capture(rgba, g if bwd else None, gg if bwd else None, gs if bwd else None)
+
+        def frame():
+            r.replay()
+
+        for _ in range(3):
+            frame()
+        torch.cuda.synchronize()
+        times = []
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        for _ in range(15):
+            e0.record()
+            for _ in range(4):
+                frame()
+            e1.record()
+            torch.cuda.synchronize()
+            times.append(e0.elapsed_time(e1) / 4)
+        ms = float(np.median(times))
+        assert r.check_overflow() <= cap
+        r.release_graph()
+        row = {"workload": "%s, %dx%d, K=%d, %s, one hipGraph per frame" % (
+                   name, cam.W, cam.H, wl.K, "fwd+bwd" if bwd else "forward only"),
+               "n_voxels": wl.scene.n_voxels, "ms_per_frame": ms,
+               "mpix_s": P / (ms / 1e3) / 1e6, "frames_per_s": 1e3 / ms}
+        if not no_cpu:
+            import oracle
+            threads = len(os.sched_getaffinity(0))
+            if bwd:
+                row["cpu_baseline"] = cpu_baseline(wl.scene, cam, wl.K, cpu_seconds / 3)
+            else:
+                t0 = time.perf_counter()
+                oracle.render(wl.scene, cam, K=wl.K, nthreads=threads)
+                dt = time.perf_counter() - t0
+                row["cpu_baseline"] = {"value": P / dt / 1e6, "unit": "Mpix/s", "cores": threads,
+                                       "kind": "oracle", "sample": "full frame, FP64 forward"}
+        log("%s: %.3f ms per frame (%.0f Mpix/s)" % (name, ms, P / (ms / 1e3) / 1e6))
+        out[name] = row
+        del r, ds, rgba, g, gg, gs
+        torch.cuda.empty_cache()
+    return out
 
 
 def supersampled_run(ds, cams, K, tile, grad, steps, log):
@@ -376,8 +556,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the 24-camera batched comparison")
-    ap.add_argument("--large", action="store_true",
-                    help="also run the ~8M-voxel scene, 16 views at 1920x1080, batched")
+    ap.add_argument("--no-large", action="store_true",
+                    help="skip the ~8M-voxel scene (16 views at 1920x1080, batched)")
+    ap.add_argument("--no-small", action="store_true",
+                    help="skip the two small workloads (3.3k voxels at 64x64, 184k at 800x800)")
     ap.add_argument("--calibrate", action="store_true",
                     help="run a plain 1 GiB device copy first (counter calibration)")
     args = ap.parse_args()
@@ -584,11 +766,19 @@ def main():
     dom = max(ktimes, key=lambda k: ktimes[k][0])
     dom_avg_s = ktimes[dom][0] / 1e3 / ktimes[dom][1]
     if dom in ("render_fwd", "render_bwd"):
-        ops = pairs_mean * OPS_PAIR + hits_mean * (OPS_HIT_FWD(K) if dom == "render_fwd" else OPS_HIT_BWD(K))
+        hk = "hit_fwd" if dom == "render_fwd" else "hit_bwd"
+        counts = {}
+        for nm, c in OPS.items():
+            o = pairs_mean * c["pair"] + hits_mean * c[hk](K)
+            counts[nm] = {"per_pair": c["pair"], "per_hit": c[hk](K), "ops_per_launch": o,
+                          "achieved": o / dom_avg_s / 1e12,
+                          "frac": o / dom_avg_s / 1e12 / VALU_PEAK_TOPS}
+        ops = counts["design"]["ops_per_launch"]
         ach = ops / dom_avg_s / 1e12
         roof = {"kernel": dom, "bound": "alu", "achieved": ach, "peak": VALU_PEAK_TOPS,
                 "unit": "Tops/s", "frac": ach / VALU_PEAK_TOPS, "traffic": None,
-                "ops_per_launch": ops}
+                "ops_per_launch": ops, "op_counts": counts,
+                "units_per_launch": {"pairs": pairs_mean, "hits": hits_mean}}
     else:
         b = kernel_bytes(dom, scene.n_voxels, Nv_mean, E_mean, P, S_floats, None)
         ach = b / dom_avg_s / 1e9
@@ -600,6 +790,30 @@ def main():
     if tb is not None:
         roof["traffic"] = tb
         roof["traffic_source"] = tsrc
+    # counter evidence for the render kernels: VALU issue (VALUBusy: share of
+    # time the SIMDs issue VALU) and lane occupancy (VALUUtilization: active
+    # lanes per issued VALU instruction), LDS, waits and atomics
+    counters = {}
+    for kind in ("render_fwd", "render_bwd"):
+        sym = kernel_symbol(kind, tile, K)
+        c, csrc = measured_counters(sym)
+        if c:
+            counters[kind] = {"symbol": sym, "source": csrc, **c}
+    if counters:
+        roof["counters"] = counters
+    probe = atomic_probe_run(scene.n_voxels, log)
+    c_probe, _ = measured_counters("k_atomic_probe")
+    atomics = {"probe": probe}
+    bw = counters.get("render_bwd", {})
+    if bw.get("TCP_TCC_ATOMIC_WITHOUT_RET_REQ_sum") and c_probe.get("TCP_TCC_ATOMIC_WITHOUT_RET_REQ_sum"):
+        # requests to L2 per second: the backward (its profiled requests per
+        # dispatch over its live duration) against the probe (requests per
+        # dispatch of the same profile over the probe's live duration)
+        rb = bw["TCP_TCC_ATOMIC_WITHOUT_RET_REQ_sum"] / (ktimes["render_bwd"][0] / 1e3 / ktimes["render_bwd"][1])
+        rp = c_probe["TCP_TCC_ATOMIC_WITHOUT_RET_REQ_sum"] / (probe["ms"] / 1e3)
+        atomics["render_bwd"] = {"l2_atomic_requests_per_launch": bw["TCP_TCC_ATOMIC_WITHOUT_RET_REQ_sum"],
+                                 "requests_per_s": rb, "probe_requests_per_s": rp, "frac": rb / rp,
+                                 "source": bw.get("source")}
     fb = frame_bytes(scene.n_voxels, Nv_mean, E_mean, P, S_floats)
     fbytes = sum(fb.values())
     frame_gbs = fbytes / (ms_step / 1e3) / 1e9
@@ -632,20 +846,27 @@ def main():
         "frame_hbm": {"bytes": fbytes, "achieved_GBs": frame_gbs, "peak_GBs": HBM_PEAK_GBS,
                       "frac": frame_gbs / HBM_PEAK_GBS},
         "roofline": roof,
+        "atomics": atomics,
         "kernels": per_kernel,
+        "stages": stage_rows(per_kernel, scene.n_voxels, Nv_mean, E_mean, P, S_floats),
+        "paper_context": PAPER_CONTEXT,
     }
     if not args.main_only:
         out["supersampled"] = supersampled_run(ds, cams, K, tile, grad, min(args.steps, 24), log)
         out["mesh"] = mesh_run(cams, K, tile, 20, log)
     if not (args.no_batched or args.main_only):
         out["batched"] = batched_comparison(ds, K, log)
-    if args.large and not args.main_only:
+    if not (args.no_small or args.main_only):
+        out["small_configs"] = small_configs_run(log, args.no_cpu, args.cpu_seconds)
+    if not (args.no_large or args.main_only):
         del rast
         torch.cuda.empty_cache()
         out["large"] = large_scene_run(log)
     if not (args.no_cpu or args.main_only):
         log("timing the oracle on the host ...")
         out["cpu_baseline"] = cpu_baseline(scene, cams[0], K, args.cpu_seconds)
+        one = cpu_baseline(scene, cams[0], K, args.cpu_seconds / 2, threads=1)
+        out["cpu_baseline"]["single_thread"] = {k: one[k] for k in ("value", "cores", "sample")}
     print(json.dumps(out), flush=True)
 
 

@@ -200,7 +200,9 @@ typedef struct svr_extra {
  * >= t_stop.  Output rgba: [sum_c H_c W_c][4], cameras in order, row-major
  * pixels; premultiplied RGB and A = 1 - T_final (no background).  `extra`
  * may be NULL; its max_weight, depth and normal are written here.
- * Errors: SVR_E_INVALID, SVR_E_WORKSPACE, SVR_E_HIP.                         */
+ * Errors: SVR_E_INVALID, SVR_E_WORKSPACE, SVR_E_HIP.  A failure a kernel
+ * detects on the device is flagged in the workspace header and returned as
+ * SVR_E_DEVICE by the next svr_check_overflow.                              */
 int svr_render_fwd(const svr_scene* scene, const svr_camera* cams, int n_cams,
                    const svr_opts* opts, void* ws, size_t ws_bytes, float* rgba,
                    const svr_extra* extra, void* stream);
@@ -213,7 +215,10 @@ int svr_render_fwd(const svr_scene* scene, const svr_camera* cams, int n_cams,
  *   grad_sh    [N][(D+1)^2][3]     dL/d sh                  (may be NULL)
  * `extra` may be NULL; its grad_depth and grad_normal are read and its
  * priority is accumulated here.
- * Errors: SVR_E_INVALID, SVR_E_WORKSPACE, SVR_E_HIP.                         */
+ * Errors: SVR_E_INVALID, SVR_E_WORKSPACE, SVR_E_HIP.  A failure a kernel
+ * detects on the device (a backward chunk list that would overflow) is
+ * flagged in the workspace header and returned as SVR_E_DEVICE by the next
+ * svr_check_overflow.                                                       */
 int svr_render_bwd(const svr_scene* scene, const svr_camera* cams, int n_cams,
                    const svr_opts* opts, void* ws, size_t ws_bytes, const float* grad_rgba,
                    float* grad_grid, float* grad_sh, const svr_extra* extra,
@@ -263,6 +268,19 @@ int svr_radix_sort_pairs(uint64_t* keys, uint32_t* values, uint64_t* keys_tmp,
 #define SVR_STATIC_SORT_BYTES ((size_t)26223104)
 int svr_radix_sort_pairs_static(uint64_t* keys, uint32_t* values, int64_t n, int bits,
                                 void* stream);
+
+/* Atomic throughput probe (measurement only): n_waves wave64 groups each
+ * issue `iters` float atomic adds without return, in the pattern of the
+ * render backward's gradient flush (Supp. A.2 gradients summed per wave,
+ * then one atomic per value): per instruction, 8 lanes add 1.0 to the 32-byte
+ * corner row and 3 lanes to the 12-byte colour row of a voxel drawn
+ * uniformly from n_rows by a per-wave generator.  corner: device float
+ * [n_rows][8]; colour: device float [n_rows][3]; both accumulated into (the
+ * grand total grows by 11 n_waves iters).  1 <= n_rows < 2^32,
+ * 1 <= n_waves <= 2^26, iters >= 0.
+ * Errors: SVR_E_INVALID, SVR_E_HIP.                                          */
+int svr_atomic_probe(float* corner, float* colour, int64_t n_rows, int64_t n_waves, int iters,
+                     void* stream);
 
 /* Frame statistics (diagnostics; synchronises `stream`), after svr_sort:
  *   counts[0]  entries E of the sorted list

@@ -67,6 +67,7 @@ _SIGS = {
     "svr_radix_sort_scratch_bytes": (ctypes.c_size_t, [I64, ctypes.c_int]),
     "svr_radix_sort_pairs": (ctypes.c_int, [P, P, P, P, I64, ctypes.c_int, P, ctypes.c_size_t, P]),
     "svr_radix_sort_pairs_static": (ctypes.c_int, [P, P, I64, ctypes.c_int, P]),
+    "svr_atomic_probe": (ctypes.c_int, [P, P, I64, I64, ctypes.c_int, P]),
     "svr_render_stats": (ctypes.c_int, [P, P, ctypes.c_int, P, P, ctypes.c_size_t, P, P]),
     "svr_timing_enable": (ctypes.c_int, [ctypes.c_int]),
     "svr_timing_read": (ctypes.c_int, [P, ctypes.c_int, P, P, ctypes.c_int, P]),
@@ -206,6 +207,10 @@ def svr_radix_sort_pairs(keys, values, keys_tmp, values_tmp, n, bits, scratch, s
 
 def svr_radix_sort_pairs_static(keys, values, n, bits, stream):
     return load().svr_radix_sort_pairs_static(keys, values, n, bits, stream)
+
+
+def svr_atomic_probe(corner, colour, n_rows, n_waves, iters, stream):
+    return load().svr_atomic_probe(corner, colour, n_rows, n_waves, iters, stream)
 
 
 def svr_render_stats(scene, cams, n_cams, opts, ws, ws_bytes, counts, stream):

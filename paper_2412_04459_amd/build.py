@@ -18,7 +18,7 @@ BUILD = os.path.join(ROOT, "_build")
 LIB_DIR = os.path.join(PKG, "lib")
 LIB = os.path.join(LIB_DIR, "libsvraster.so")
 SOURCES = ["svr_api.hip", "svr_preprocess.hip", "svr_sort.hip", "svr_render.hip", "svr_image.hip",
-           "svr_mesh.hip"]
+           "svr_mesh.hip", "svr_diag.hip"]
 ARCH = os.environ.get("SVR_OFFLOAD_ARCH", "gfx950")
 
 

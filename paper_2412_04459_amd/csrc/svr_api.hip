@@ -535,6 +535,19 @@ int svr_radix_sort_pairs_static(uint64_t* keys, uint32_t* values, int64_t n, int
   return SVR_OK;
 }
 
+int svr_atomic_probe(float* corner, float* colour, int64_t n_rows, int64_t n_waves, int iters,
+                     void* stream) {
+  if (!corner || !colour) return fail(SVR_E_INVALID, "null pointer");
+  if (n_rows < 1 || n_rows >= ((int64_t)1 << 32)) return fail(SVR_E_INVALID, "n_rows outside [1, 2^32)");
+  if (n_waves < 1 || n_waves > ((int64_t)1 << 26)) return fail(SVR_E_INVALID, "n_waves outside [1, 2^26]");
+  if (iters < 0) return fail(SVR_E_INVALID, "iters < 0");
+  if (iters == 0) return SVR_OK;
+  SVR_HIP(launch_atomic_probe(corner, colour, n_rows, n_waves, iters,
+                              reinterpret_cast<hipStream_t>(stream)),
+          "atomic probe");
+  return SVR_OK;
+}
+
 int svr_render_stats(const svr_scene* scene, const svr_camera* cams, int n_cams,
                      const svr_opts* opts, void* ws, size_t ws_bytes, int64_t* counts,
                      void* stream) {

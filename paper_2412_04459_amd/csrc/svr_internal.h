@@ -202,6 +202,8 @@ void timing_end(int slot, const char* name, hipStream_t s);
   } while (0)
 
 hipError_t launch_count_inview(const Layout& L, void* ws, hipStream_t s);
+hipError_t launch_atomic_probe(float* corner, float* colour, int64_t n_rows, int64_t n_waves,
+                               int iters, hipStream_t s);
 hipError_t launch_downsample(const float* in, int w_in, int h_in, float* out, int w_out,
                              int h_out, const float bg[3], hipStream_t s);
 hipError_t launch_downsample_bwd(const float* gout, int w_out, int h_out, float* gin, int w_in,

@@ -6,6 +6,8 @@
 --trace   output directory of `rocprofv3 --kernel-trace --stats --output-format csv`
 --fetch   output directory of `rocprofv3 --pmc FETCH_SIZE --output-format csv`
 --write   output directory of `rocprofv3 --pmc WRITE_SIZE --output-format csv`
+--pmc     output directory of any other `rocprofv3 --pmc ... --output-format csv`
+          run (repeatable): every counter in it, mean per dispatch per kernel
 
 The counter runs are expected to include the 1 GiB device copy that
 `bench.py --calibrate` performs; the ratio of its known bytes to what the
@@ -78,6 +80,26 @@ def read_counter(d, counter):
     return {k: acc[k] / cnt[k] for k in acc}, dict(mx)
 
 
+def read_all_counters(d):
+    """{kernel: {counter: mean value per dispatch}} of one --pmc run."""
+    rows = list(csv.DictReader(open(_find(d, "*counter_collection.csv"))))
+    acc = defaultdict(float)
+    cnt = defaultdict(int)
+    for r in rows:
+        key = (short_name(r["Kernel_Name"]), r["Counter_Name"])
+        acc[key] += float(r["Counter_Value"])
+        cnt[key] += 1
+    out = defaultdict(dict)
+    for (k, c), v in acc.items():
+        out[k][c] = v / cnt[(k, c)]
+    return dict(out)
+
+
+# kernels whose counters the summary tabulates (all are kept in the JSON block)
+COUNTER_TABLE = ("k_render_fwd", "k_render_bwd", "k_atomic_probe", "k_project", "k_emit",
+                 "k_sort_pass", "k_sh_bwd", "k_grid_gather")
+
+
 def calib_factor(per_kernel_max_kib):
     """Known bytes / counted bytes of the largest single copy dispatch (the
     1 GiB copy of bench.py --calibrate; the same kernel also serves small
@@ -94,6 +116,7 @@ def main():
     ap.add_argument("--trace", required=True)
     ap.add_argument("--fetch")
     ap.add_argument("--write")
+    ap.add_argument("--pmc", action="append", default=[])
     ap.add_argument("--out", required=True)
     ap.add_argument("--cmd", required=True)
     ap.add_argument("--title", default="rocprofv3 summary")
@@ -125,8 +148,24 @@ def main():
             scaled = (f * (ff or 1.0) + w * (wf or 1.0)) * 1024.0
             traffic[k] = {"fetch_kib": f, "write_kib": w, "bytes_scaled": scaled}
             lines.append("| %s | %.0f | %.0f | %.2f |" % (k, f, w, scaled / 1e6))
+    counters = defaultdict(dict)
+    for d in args.pmc:
+        for k, cs in read_all_counters(d).items():
+            counters[k].update(cs)
+    if counters:
+        names = sorted({c for cs in counters.values() for c in cs})
+        lines += ["", "Hardware counters per dispatch (`--pmc`, mean over dispatches; "
+                  "VALUBusy and VALUUtilization in %):", ""]
+        lines += ["| kernel | " + " | ".join(names) + " |",
+                  "|---|" + "---|" * len(names)]
+        for k in sorted(counters):
+            if not k.startswith(COUNTER_TABLE):
+                continue
+            lines.append("| %s | " % k + " | ".join(
+                ("%.4g" % counters[k][c]) if c in counters[k] else "" for c in names) + " |")
     block = {"source_hash": source_hash(), "kernels": stats, "traffic": traffic,
-             "fetch_factor": ff, "write_factor": wf}
+             "fetch_factor": ff, "write_factor": wf,
+             "counters": {k: v for k, v in counters.items() if k.startswith(COUNTER_TABLE)}}
     lines += ["", "```json", json.dumps(block, sort_keys=True), "```", ""]
     os.makedirs(os.path.dirname(os.path.abspath(args.out)), exist_ok=True)
     open(args.out, "w").write("\n".join(lines))
