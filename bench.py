@@ -77,7 +77,7 @@ def frame_bytes(N, Nv, E, P, S):
 
 STAGES = [("H1 tile masks + summed-area table", ("tile_masks", "tile_sat"), None),
           ("H2-H3 project + per-view record", ("project",), ("project", "preprocess")),
-          ("H4 scan + emit", ("scan_top", "emit"), ("emit",)),
+          ("H4 scan + emit", ("scan_top", "emit", "emit_big"), ("emit",)),
           ("H5-H6 sort + tile ranges", ("sort_hist", "sort_hist_scan", "sort_pass", "tile_ranges",
                                         "tile_order", "tile_sort_small", "tile_sort_big"),
            ("sort",)),
@@ -249,11 +249,13 @@ def small_configs_run(log, no_cpu, cpu_seconds):
     from paper_2412_04459_amd import scenes as S
     from paper_2412_04459_amd.render import DeviceScene, Rasterizer
     out = {}
+    from paper_2412_04459_amd.render import zcurve_relabel
     for name, bwd in (("sphere_shell_3k", False), ("spheres_plane_184k", True)):
         wl = S.workload(name)
+        scene, _ = zcurve_relabel(wl.scene)
         cam = wl.cameras[0]
         P = cam.W * cam.H
-        ds = DeviceScene(wl.scene)
+        ds = DeviceScene(scene)
         probe = Rasterizer(ds, [cam], K=wl.K, sync_count=True, tile=8)
         probe.preprocess()
         cap = int(probe.n_entries * 1.1) + 4096
@@ -287,16 +289,16 @@ def small_configs_run(log, no_cpu, cpu_seconds):
         r.release_graph()
         row = {"workload": "%s, %dx%d, K=%d, %s, one hipGraph per frame" % (
                    name, cam.W, cam.H, wl.K, "fwd+bwd" if bwd else "forward only"),
-               "n_voxels": wl.scene.n_voxels, "ms_per_frame": ms,
+               "n_voxels": scene.n_voxels, "ms_per_frame": ms,
                "mpix_s": P / (ms / 1e3) / 1e6, "frames_per_s": 1e3 / ms}
         if not no_cpu:
             import oracle
             threads = len(os.sched_getaffinity(0))
             if bwd:
-                row["cpu_baseline"] = cpu_baseline(wl.scene, cam, wl.K, cpu_seconds / 3)
+                row["cpu_baseline"] = cpu_baseline(scene, cam, wl.K, cpu_seconds / 3)
             else:
                 t0 = time.perf_counter()
-                oracle.render(wl.scene, cam, K=wl.K, nthreads=threads)
+                oracle.render(scene, cam, K=wl.K, nthreads=threads)
                 dt = time.perf_counter() - t0
                 row["cpu_baseline"] = {"value": P / dt / 1e6, "unit": "Mpix/s", "cores": threads,
                                        "kind": "oracle", "sample": "full frame, FP64 forward"}
@@ -448,8 +450,9 @@ def large_scene_run(log):
     from paper_2412_04459_amd.autotune import time_batch
     from paper_2412_04459_amd.render import BatchRenderer, DeviceScene, Rasterizer
 
+    from paper_2412_04459_amd.render import zcurve_relabel
     t0 = time.time()
-    scene = S.large_shells_scene()
+    scene, _ = zcurve_relabel(S.large_shells_scene())
     cams = S.orbit_cameras_1080p()
     log("large scene: %d voxels, %d grid points (%.0fs)" % (scene.n_voxels, scene.n_grid,
                                                           time.time() - t0))
@@ -554,6 +557,9 @@ def main():
                     help="run only the mesh extraction (TSDF fusion + marching cubes) timing and "
                          "print its JSON object")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--tile", type=int, default=0, choices=(0, 8, 16, 32),
+                    help="tile edge of the headline frames (0: the fastest of 8, 16 and 32 by a "
+                         "short measurement)")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the 24-camera batched comparison")
     ap.add_argument("--no-large", action="store_true",
@@ -571,7 +577,7 @@ def main():
     import torch
     from paper_2412_04459_amd import _abi
     from paper_2412_04459_amd import scenes as S
-    from paper_2412_04459_amd.render import DeviceScene, Rasterizer
+    from paper_2412_04459_amd.render import DeviceScene, Rasterizer, zcurve_relabel
 
     assert torch.cuda.is_available(), "bench.py needs a GPU"
     torch.cuda.set_device(0)
@@ -587,7 +593,9 @@ def main():
         print(json.dumps({"mesh": mesh_run(cams, 2, 8, args.steps, log)}), flush=True)
         return
     t0 = time.time()
-    scene = S.spheres_background_scene()
+    # voxels stored in octree-path order (relabeled once at load; the
+    # generator's shuffled order stands for an arbitrary caller order)
+    scene, _ = zcurve_relabel(S.spheres_background_scene())
     cams = S.orbit_cameras_1297x840(n=args.views)
     K = 2
     log("scene: %d voxels, %d grid points (%.1fs)" % (scene.n_voxels, scene.n_grid, time.time() - t0))
@@ -609,7 +617,7 @@ def main():
     # does for batches); the capacity above covers 16x16 tiles, so the other
     # edges get their own counted pass
     tile_ms = {}
-    for tile in (8, 16, 32):
+    for tile in ((8, 16, 32) if args.tile == 0 else (args.tile,)):
         probe = Rasterizer(ds, [cams[0]], K=K, sync_count=True, tile=tile)
         e_t = 0
         for c in cams[:: max(1, len(cams) // 6)]:

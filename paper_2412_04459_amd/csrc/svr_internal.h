@@ -12,6 +12,8 @@
 namespace svr {
 
 constexpr int kBlock = 256;       // threads per workgroup: 4 wave64
+constexpr uint32_t kBigEmit = 64;    // entries above which a voxel is emitted by whole workgroups
+constexpr uint32_t kBigChunk = 2048; // tiles of such a voxel per workgroup item
 constexpr int kScanItems = 16;
 constexpr int kScanTile = kBlock * kScanItems;  // counts per scan block
 constexpr int kSortItems = 16;
@@ -69,7 +71,8 @@ struct WsHeader {
   uint32_t tickets[16];           // sort partition tickets, one per pass
   unsigned long long stats[8];    // render statistics (svr_render_stats)
   uint32_t work[8];               // persistent render: work[0] counts taken positions
-  uint32_t pad[20];
+  uint32_t big_count;             // voxels queued for the whole-grid emission pass
+  uint32_t pad[19];
 };
 static_assert(sizeof(WsHeader) == 256, "header size");
 
@@ -84,6 +87,8 @@ struct Layout {
   size_t hdr, count, rect, rec, scan_part;
   size_t tile_mask, tile_sat, tile_range, tile_order, tile_rank;
   size_t split_base, split_items, ckpt;  // backward chunks of heavy tiles
+  size_t big_list;                       // (view-voxel, first output) of voxels emitted by
+  int64_t max_big;                       // the whole-grid pass; its capacity
   size_t ckpt_aux;                       // the same for depth and normal
   size_t g_nrm;                          // per voxel dL/dn (normal images)
   int64_t max_split;                     // capacity of the chunk list (>= sum of splits)

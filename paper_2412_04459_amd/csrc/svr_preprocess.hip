@@ -10,10 +10,9 @@
 //   k_project      one thread per (voxel, camera): corner projection, culling,
 //                  pixel rectangle, entry count; for counted voxels also the
 //                  64-byte render record (box, 8 corner densities, SH colour)
-//   k_scan_*       exclusive scan of the counts (reduce / top / down-sweep)
-//   k_emit         one thread per counted (voxel, camera): the (key, value)
-//                  entries for every tile of its rectangle and every sign
-//                  pattern present in that tile
+//   k_scan_top     exclusive scan of the per-workgroup entry totals
+//   k_emit         the (key, value) entries for every tile of a voxel's
+//                  rectangle and every sign pattern present in that tile
 #include "svr_internal.h"
 #include "svr_sh.h"
 
@@ -320,6 +319,62 @@ __device__ __forceinline__ unsigned long long block_excl_scan(unsigned long long
   return tot;
 }
 
+// ---------------------------------------------------------------------------
+// key = global tile << (3L + 3) | (top 3L path bits XOR s repeated) << 3 | s
+//       (the direction-dependent Morton order of Supp. B.2 as one XOR)
+// value = s << 29 | voxel id
+// A voxel's entries are its rectangle's tiles in row-major order, each tile
+// with the sign patterns present in it in ascending order.
+
+struct EmitCtx {
+  uint64_t top, rep;
+  int sh;
+  uint32_t vid;
+  bool ranked;    // key low bits from the order ranks (else from the path)
+  uint4 r03, r47;  // the voxel's 8 order ranks, loaded together up front
+};
+
+__device__ __forceinline__ EmitCtx emit_ctx(const uint64_t* __restrict__ octpath,
+                                            const uint32_t* __restrict__ rank, int64_t vid, int L,
+                                            uint64_t rep, int sh) {
+  EmitCtx e;
+  e.top = octpath[vid] >> (3 * (SVR_MAX_LEVELS - L));
+  e.rep = rep;
+  e.sh = sh;
+  e.vid = (uint32_t)vid;
+  e.ranked = rank != nullptr;
+  if (e.ranked) {
+    const uint4* r = reinterpret_cast<const uint4*>(rank + vid * 8);
+    e.r03 = r[0];
+    e.r47 = r[1];
+  } else {
+    e.r03 = e.r47 = make_uint4(0u, 0u, 0u, 0u);
+  }
+  return e;
+}
+
+__device__ __forceinline__ uint32_t rank_of(const EmitCtx& e, int sgn) {
+  const uint4 q = sgn < 4 ? e.r03 : e.r47;
+  const int i = sgn & 3;
+  return i < 2 ? (i == 0 ? q.x : q.y) : (i == 2 ? q.z : q.w);
+}
+
+__device__ __forceinline__ void emit_tile(const EmitCtx& e, int gt, uint32_t m,
+                                          unsigned long long o, int64_t cap,
+                                          uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
+  while (m) {
+    const int sgn = __ffs(m) - 1;
+    m &= m - 1;
+    if (o < (unsigned long long)cap) {
+      const uint64_t low = e.ranked ? (uint64_t)rank_of(e, sgn)
+                                    : ((e.top ^ ((uint64_t)sgn * e.rep)) << 3) | (uint64_t)sgn;
+      keys[o] = ((uint64_t)gt << e.sh) | low;
+      vals[o] = ((uint32_t)sgn << kVidBits) | e.vid;
+    }
+    ++o;
+  }
+}
+
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_project(
     int64_t NV, int n_cams, CamSet cams, const float* __restrict__ center,
@@ -537,6 +592,7 @@ __global__ __launch_bounds__(kBlock) void k_scan_top(unsigned long long* __restr
     hdr->n_entries = carry;
     hdr->overflow = 0;
     hdr->error = 0;  // the frame's sort and tile order report into it
+    hdr->big_count = 0u;
   }
 }
 
@@ -547,99 +603,68 @@ hipError_t launch_scan(const Layout& L, void* ws, hipStream_t s) {
   return hipGetLastError();
 }
 
-// ---------------------------------------------------------------------------
-// key = global tile << (3L + 3) | (top 3L path bits XOR s repeated) << 3 | s
-//       (the direction-dependent Morton order of Supp. B.2 as one XOR)
-// value = s << 29 | voxel id
-// A thread emits the entries of a voxel with few entries; voxels with more
-// than kBigEmit entries are queued in LDS and emitted by the whole workgroup,
-// one tile of the voxel's rectangle per thread, each tile's output offset
-// read from the summed-area table (row-major tiles, ascending s per tile).
-constexpr uint32_t kBigEmit = 64;
 
-struct EmitCtx {
-  uint64_t top, rep;
-  int sh;
-  uint32_t vid;
-  bool ranked;    // key low bits from the order ranks (else from the path)
-  uint4 r03, r47;  // the voxel's 8 order ranks, loaded together up front
-};
-
-__device__ __forceinline__ EmitCtx emit_ctx(const uint64_t* __restrict__ octpath,
-                                            const uint32_t* __restrict__ rank, int64_t vid, int L,
-                                            uint64_t rep, int sh) {
-  EmitCtx e;
-  e.top = octpath[vid] >> (3 * (SVR_MAX_LEVELS - L));
-  e.rep = rep;
-  e.sh = sh;
-  e.vid = (uint32_t)vid;
-  e.ranked = rank != nullptr;
-  if (e.ranked) {
-    const uint4* r = reinterpret_cast<const uint4*>(rank + vid * 8);
-    e.r03 = r[0];
-    e.r47 = r[1];
-  } else {
-    e.r03 = e.r47 = make_uint4(0u, 0u, 0u, 0u);
-  }
-  return e;
-}
-
-__device__ __forceinline__ uint32_t rank_of(const EmitCtx& e, int sgn) {
-  const uint4 q = sgn < 4 ? e.r03 : e.r47;
-  const int i = sgn & 3;
-  return i < 2 ? (i == 0 ? q.x : q.y) : (i == 2 ? q.z : q.w);
-}
-
-__device__ __forceinline__ void emit_tile(const EmitCtx& e, int gt, uint32_t m,
-                                          unsigned long long o, int64_t cap,
-                                          uint64_t* __restrict__ keys, uint32_t* __restrict__ vals) {
-  while (m) {
-    const int sgn = __ffs(m) - 1;
-    m &= m - 1;
-    if (o < (unsigned long long)cap) {
-      const uint64_t low = e.ranked ? (uint64_t)rank_of(e, sgn)
-                                    : ((e.top ^ ((uint64_t)sgn * e.rep)) << 3) | (uint64_t)sgn;
-      keys[o] = ((uint64_t)gt << e.sh) | low;
-      vals[o] = ((uint32_t)sgn << kVidBits) | e.vid;
-    }
-    ++o;
-  }
-}
-
+// The workgroup's entries are written in three ways.  A voxel whose tiles
+// each hold one sign pattern (count = tiles in its rectangle, the common
+// case) has entry j at tile j of its rectangle in row-major order: those
+// entries are spread over the whole workgroup, 256 consecutive output
+// positions per round, each thread finding its voxel by a binary search over
+// the workgroup's offsets in LDS (full lanes, coalesced stores).  The other
+// voxels (tiles that several sign patterns share) are emitted per thread.
+// Voxels of more than kBigEmit entries are queued for k_emit_big, where a
+// whole workgroup takes each one (large voxels cluster in a Z-curve order,
+// and one workgroup taking them one after another would set the kernel's
+// length).
 __global__ __launch_bounds__(kBlock) void k_emit(
     int64_t NV, int n_cams, CamSet cams, const uint64_t* __restrict__ octpath,
     const uint32_t* __restrict__ count, const unsigned long long* __restrict__ part,
     const uint2* __restrict__ rect, const uint8_t* __restrict__ mask,
     const uint32_t* __restrict__ sat, int L, int key_low, const uint32_t* __restrict__ rank,
     int64_t cap, uint64_t* __restrict__ keys, uint32_t* __restrict__ vals,
-    WsHeader* __restrict__ hdr) {
-  __shared__ int s_nbig;
-  __shared__ int64_t s_big[kBlock];
-  __shared__ unsigned long long s_big_off[kBlock];
-  if (threadIdx.x == 0) s_nbig = 0;
+    WsHeader* __restrict__ hdr, ulonglong2* __restrict__ big, int64_t max_big) {
+  __shared__ uint32_t s_off[kBlock + 1];  // offsets in the workgroup, s_off[kBlock] = total
+  __shared__ uint32_t s_rx[kBlock];       // tile rectangle: tx0 | ty0 << 16 (simple voxels)
+  __shared__ uint32_t s_wd[kBlock];       // its width in tiles; 0: not a simple voxel
   const int64_t vv = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const uint32_t cnt = vv < NV ? count[vv] : 0u;
+  const uint2 r = cnt > 0 ? rect[vv] : make_uint2(1u, 0u);
   // first output position: the workgroup's prefix plus the counts before
   // this thread in the workgroup
-  unsigned long long off_vv;
-  block_excl_scan(cnt, off_vv);
-  off_vv += part[blockIdx.x];
+  unsigned long long ex;
+  const unsigned long long wg_tot = block_excl_scan(cnt, ex);
+  const unsigned long long wg_base = part[blockIdx.x];
+  const unsigned long long off_vv = wg_base + ex;
   const int sh = key_low;
   const uint64_t rep = ((1ull << (3 * L)) - 1ull) / 7ull;  // 001 001 ... 001 (L triplets)
-  if (cnt > 0) {
-    if (off_vv + cnt > (unsigned long long)cap) atomicOr(&hdr->overflow, 1u);
-    if (cnt > kBigEmit) {
-      const int q = atomicAdd(&s_nbig, 1);
-      s_big[q] = vv;
-      s_big_off[q] = off_vv;
-    } else {
+  const int tx0 = (int)(r.x & 0xffffu) >> cams.tshift, tx1 = (int)(r.x >> 16) >> cams.tshift;
+  const int ty0 = (int)(r.y & 0xffffu) >> cams.tshift, ty1 = (int)(r.y >> 16) >> cams.tshift;
+  const uint32_t ntiles = cnt > 0 ? (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1)) : 0u;
+  const bool simple = cnt > 0 && cnt == ntiles;
+  if (cnt > 0 && off_vv + cnt > (unsigned long long)cap) atomicOr(&hdr->overflow, 1u);
+  bool queued = false;
+  if (cnt > kBigEmit) {
+    // one item per kBigChunk tiles of the rectangle (a voxel on the near
+    // plane covers every tile); the list holds every item of a frame within
+    // the capacity; past it (an overflowing frame) the voxel is emitted
+    // here, so that every position below the capacity is written
+    const uint32_t nit = (ntiles + kBigChunk - 1) / kBigChunk;
+    const uint32_t q = atomicAdd(&hdr->big_count, nit);
+    queued = (int64_t)q + nit <= max_big;
+    if (queued)
+      for (uint32_t k = 0; k < nit; ++k)
+        big[q + k] = make_ulonglong2((unsigned long long)vv | ((unsigned long long)k << 40),
+                                     off_vv);
+  }
+  s_off[threadIdx.x] = (uint32_t)ex;
+  if (threadIdx.x == kBlock - 1) s_off[kBlock] = (uint32_t)wg_tot;
+  s_rx[threadIdx.x] = (uint32_t)tx0 | ((uint32_t)ty0 << 16);
+  s_wd[threadIdx.x] = simple && !queued ? (uint32_t)(tx1 - tx0 + 1) : 0u;
+  if (cnt > 0 && !simple) {
+    if (!queued) {
       const int64_t vid = vv / n_cams;
       const DevCam& c = cams.c[(int)(vv - vid * n_cams)];
       const EmitCtx e = emit_ctx(octpath, rank, vid, L, rep, sh);
       unsigned long long o = off_vv;
-      const uint2 r = rect[vv];
-      const int tx0 = (int)(r.x & 0xffffu) >> cams.tshift, tx1 = (int)(r.x >> 16) >> cams.tshift;
-      const int ty0 = (int)(r.y & 0xffffu) >> cams.tshift, ty1 = (int)(r.y >> 16) >> cams.tshift;
       for (int ty = ty0; ty <= ty1; ++ty) {
         for (int tx = tx0; tx <= tx1; ++tx) {
           const int gt = c.tile_off + ty * c.ntx + tx;
@@ -651,25 +676,84 @@ __global__ __launch_bounds__(kBlock) void k_emit(
     }
   }
   __syncthreads();
-  const int nbig = s_nbig;
-  for (int b = 0; b < nbig; ++b) {
-    const int64_t bv = s_big[b];
+  // entry-parallel rounds over the workgroup's output range; positions of
+  // voxels that are not simple are skipped (their owners wrote them)
+  const uint32_t total = s_off[kBlock];
+  if (wg_base + total > (unsigned long long)cap && threadIdx.x == 0) atomicOr(&hdr->overflow, 1u);
+  const int64_t vv0 = (int64_t)blockIdx.x * blockDim.x;
+  for (uint32_t k = threadIdx.x; k < total; k += kBlock) {
+    // owner: the last voxel whose offset is <= k
+    int lo = 0;
+#pragma unroll
+    for (int step = kBlock / 2; step > 0; step >>= 1)
+      if (s_off[lo + step] <= k) lo += step;
+    const uint32_t wd = s_wd[lo];
+    if (wd == 0u) continue;
+    const uint64_t o = wg_base + k;
+    if (o >= (unsigned long long)cap) continue;
+    const uint32_t j = k - s_off[lo];
+    const uint32_t row = j / wd;
+    const uint32_t rx = s_rx[lo];
+    const int64_t ov = vv0 + lo;
+    const int64_t vid = ov / n_cams;
+    const DevCam& c = cams.c[(int)(ov - vid * n_cams)];
+    const int gt = c.tile_off + ((int)(rx >> 16) + (int)row) * c.ntx + (int)(rx & 0xffffu) +
+                   (int)(j - row * wd);
+    const int sgn = __ffs((int)mask[gt]) - 1;
+    uint64_t low;
+    if (rank) {
+      low = (uint64_t)rank[vid * 8 + sgn];
+    } else {
+      const uint64_t top = octpath[vid] >> (3 * (SVR_MAX_LEVELS - L));
+      low = ((top ^ ((uint64_t)sgn * rep)) << 3) | (uint64_t)sgn;
+    }
+    keys[o] = ((uint64_t)gt << sh) | low;
+    vals[o] = ((uint32_t)sgn << kVidBits) | (uint32_t)vid;
+  }
+
+}
+
+// the queued voxels: one workgroup per item (kBigChunk tiles of a voxel's
+// rectangle) at a time, one tile per thread, each tile's output offset from
+// the summed-area table (or its position, when every tile holds one sign
+// pattern)
+__global__ __launch_bounds__(kBlock) void k_emit_big(
+    int n_cams, CamSet cams, const uint64_t* __restrict__ octpath, const uint2* __restrict__ rect,
+    const uint8_t* __restrict__ mask, const uint32_t* __restrict__ sat, int L, int key_low,
+    const uint32_t* __restrict__ rank, int64_t cap, uint64_t* __restrict__ keys,
+    uint32_t* __restrict__ vals, const WsHeader* __restrict__ hdr,
+    const ulonglong2* __restrict__ big, int64_t max_big) {
+  const int64_t nq = min((int64_t)hdr->big_count, max_big);
+  const int sh = key_low;
+  const uint64_t rep = ((1ull << (3 * L)) - 1ull) / 7ull;  // 001 001 ... 001 (L triplets)
+  for (int64_t q = blockIdx.x; q < nq; q += gridDim.x) {
+    const ulonglong2 item = big[q];
+    const int64_t bv = (int64_t)(item.x & ((1ull << 40) - 1ull));
+    const int chunk = (int)(item.x >> 40);
     const int64_t vid = bv / n_cams;
     const DevCam& c = cams.c[(int)(bv - vid * n_cams)];
     const EmitCtx e = emit_ctx(octpath, rank, vid, L, rep, sh);
-    const uint2 r = rect[bv];
-    const int tx0 = (int)(r.x & 0xffffu) >> cams.tshift, tx1 = (int)(r.x >> 16) >> cams.tshift;
-    const int ty0 = (int)(r.y & 0xffffu) >> cams.tshift, ty1 = (int)(r.y >> 16) >> cams.tshift;
-    const int wdt = tx1 - tx0 + 1;
-    const int ntiles = wdt * (ty1 - ty0 + 1);
+    const uint2 br = rect[bv];
+    const int bx0 = (int)(br.x & 0xffffu) >> cams.tshift, bx1 = (int)(br.x >> 16) >> cams.tshift;
+    const int by0 = (int)(br.y & 0xffffu) >> cams.tshift, by1 = (int)(br.y >> 16) >> cams.tshift;
+    const int wdt = bx1 - bx0 + 1;
+    const int nt = wdt * (by1 - by0 + 1);
     const uint32_t* S = sat + c.sat_off;
     const int W1 = c.ntx + 1;
-    const unsigned long long o0 = s_big_off[b];
-    for (int jt = threadIdx.x; jt < ntiles; jt += kBlock) {
-      const int tx = tx0 + jt % wdt, ty = ty0 + jt / wdt;
+    const unsigned long long o0 = item.y;
+    // one pattern per tile: entry j is tile j; else each tile's offset comes
+    // from the summed-area table
+    const bool simple = sat_rect(S, W1, bx0, bx1, by0, by1) == (uint32_t)nt;
+    const int jend = min(nt, (chunk + 1) * (int)kBigChunk);
+    for (int jt = chunk * (int)kBigChunk + (int)threadIdx.x; jt < jend; jt += kBlock) {
+      const int tx = bx0 + jt % wdt, ty = by0 + jt / wdt;
       unsigned long long o = o0;
-      if (ty > ty0) o += sat_rect(S, W1, tx0, tx1, ty0, ty - 1);
-      if (tx > tx0) o += sat_rect(S, W1, tx0, tx - 1, ty, ty);
+      if (simple) {
+        o += (unsigned long long)jt;
+      } else {
+        if (ty > by0) o += sat_rect(S, W1, bx0, bx1, by0, ty - 1);
+        if (tx > bx0) o += sat_rect(S, W1, bx0, tx - 1, ty, ty);
+      }
       const int gt = c.tile_off + ty * c.ntx + tx;
       emit_tile(e, gt, mask[gt], o, cap, keys, vals);
     }
@@ -683,9 +767,18 @@ hipError_t launch_emit(const svr_scene& sc, const CamSet& cams, const Layout& L,
              L.NV, L.n_cams, cams, sc.octpath, at<uint32_t>(ws, L.count),
              at<unsigned long long>(ws, L.scan_part), at<uint2>(ws, L.rect),
              at<uint8_t>(ws, L.tile_mask), at<uint32_t>(ws, L.tile_sat), L.L, L.key_low,
-             sc.order_rank, L.cap,
-             at<uint64_t>(ws, L.keys0), at<uint32_t>(ws, L.vals0), at<WsHeader>(ws, L.hdr));
+             sc.order_rank, L.cap, at<uint64_t>(ws, L.keys0), at<uint32_t>(ws, L.vals0),
+             at<WsHeader>(ws, L.hdr), at<ulonglong2>(ws, L.big_list), L.max_big);
+  // the queued voxels, over a grid of fixed size (the count stays on the
+  // device, so the launch can be captured in a graph)
+  const int64_t gb = L.max_big < 1024 ? L.max_big : 1024;
+  SVR_LAUNCH("emit_big", k_emit_big, dim3((unsigned)gb), dim3(kBlock), 0, s, L.n_cams, cams,
+             sc.octpath, at<uint2>(ws, L.rect), at<uint8_t>(ws, L.tile_mask),
+             at<uint32_t>(ws, L.tile_sat), L.L, L.key_low, sc.order_rank, L.cap,
+             at<uint64_t>(ws, L.keys0), at<uint32_t>(ws, L.vals0), at<WsHeader>(ws, L.hdr),
+             at<ulonglong2>(ws, L.big_list), L.max_big);
   return hipGetLastError();
 }
+
 
 }  // namespace svr

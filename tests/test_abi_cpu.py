@@ -245,3 +245,16 @@ def test_morton_keys_check_arguments():
     assert _abi.svr_morton_keys(p, 10, lo, 0.0, p, p, None) == _abi.SVR_E_INVALID
     assert _abi.svr_morton_keys(None, 10, lo, 1.0, p, p, None) == _abi.SVR_E_INVALID
     assert _abi.svr_morton_keys(None, 0, lo, 1.0, None, None, None) == _abi.SVR_OK
+
+
+def test_zcurve_relabel_is_a_relabeling_in_octree_path_order():
+    from paper_2412_04459_amd import scenes as S
+    from paper_2412_04459_amd.render import zcurve_relabel
+    sc = S.tiny_random_scene(5, max_level=4, sh_degree=1)
+    rs, order = zcurve_relabel(sc)
+    assert np.all(rs.octpath[1:] > rs.octpath[:-1])
+    assert np.array_equal(np.sort(order), np.arange(sc.n_voxels))
+    assert np.array_equal(rs.center, sc.center[:, order])
+    assert np.array_equal(rs.vox_grid, sc.vox_grid[order])
+    assert np.array_equal(rs.sh, sc.sh[order])
+    assert np.array_equal(rs.grid_raw, sc.grid_raw)

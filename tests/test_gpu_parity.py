@@ -244,7 +244,9 @@ def test_autograd_function_matches_direct_backward(torch_dev):
 # ---------------------------------------------------------------------------
 @pytest.fixture(scope="module")
 def bench_scene(torch_dev):
-    scene = S.spheres_background_scene()
+    from paper_2412_04459_amd.render import zcurve_relabel
+    # stored in octree-path order, as the benchmark stores it
+    scene, _ = zcurve_relabel(S.spheres_background_scene())
     cams = S.orbit_cameras_1297x840()[:1]
     return scene, cams
 
@@ -756,8 +758,8 @@ def test_autograd_backward_after_a_second_render(torch_dev):
 # ---------------------------------------------------------------------------
 def test_large_scene_view_sampled_parity(torch_dev):
     torch = torch_dev
-    from paper_2412_04459_amd.render import DeviceScene
-    scene = S.large_shells_scene()
+    from paper_2412_04459_amd.render import DeviceScene, zcurve_relabel
+    scene, _ = zcurve_relabel(S.large_shells_scene())
     cam = S.orbit_cameras_1080p()[0]
     P = cam.W * cam.H
     _say("large scene N=%d, one 1920x1080 view" % scene.n_voxels)
