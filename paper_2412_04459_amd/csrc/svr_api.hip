@@ -203,9 +203,10 @@ int make_layout(const svr_scene* sc, const svr_camera* cams, int n_cams, const s
   l.max_split = l.cap / kBwdChunk + 1;
   l.split_base = take((size_t)T * 4);
   l.split_items = take((size_t)l.max_split * 8);
-  // items of voxels of more than kBigEmit entries: within the capacity at
-  // most capacity / kBigEmit voxels, plus one item per kBigChunk tiles
-  l.max_big = l.cap / 32 + 1;
+  // items of the whole-grid emission pass (voxels of more than kBigEmit
+  // entries or on tiles of several sign patterns, one item per kBigChunk
+  // tiles); a frame with more emits the rest per thread
+  l.max_big = l.cap / 16 + 1;
   l.big_list = take((size_t)l.max_big * 16);
   l.keys0 = take((size_t)l.cap * 8);
   l.keys1 = take((size_t)l.cap * 8);

@@ -13,7 +13,7 @@ namespace svr {
 
 constexpr int kBlock = 256;       // threads per workgroup: 4 wave64
 constexpr uint32_t kBigEmit = 64;    // entries above which a voxel is emitted by whole workgroups
-constexpr uint32_t kBigChunk = 2048; // tiles of such a voxel per workgroup item
+constexpr uint32_t kBigChunk = 512;  // tiles of such a voxel per item of the whole-grid pass
 constexpr int kScanItems = 16;
 constexpr int kScanTile = kBlock * kScanItems;  // counts per scan block
 constexpr int kSortItems = 16;

@@ -610,11 +610,11 @@ hipError_t launch_scan(const Layout& L, void* ws, hipStream_t s) {
 // entries are spread over the whole workgroup, 256 consecutive output
 // positions per round, each thread finding its voxel by a binary search over
 // the workgroup's offsets in LDS (full lanes, coalesced stores).  The other
-// voxels (tiles that several sign patterns share) are emitted per thread.
-// Voxels of more than kBigEmit entries are queued for k_emit_big, where a
-// whole workgroup takes each one (large voxels cluster in a Z-curve order,
-// and one workgroup taking them one after another would set the kernel's
-// length).
+// voxels (tiles that several sign patterns share) and the voxels of more
+// than kBigEmit entries are queued for k_emit_big, where the whole grid takes
+// them a wave per item (they cluster in a Z-curve order: near the lines where
+// a ray component changes sign, and in the coarse background levels, and one
+// workgroup taking them one after another would set the kernel's length).
 __global__ __launch_bounds__(kBlock) void k_emit(
     int64_t NV, int n_cams, CamSet cams, const uint64_t* __restrict__ octpath,
     const uint32_t* __restrict__ count, const unsigned long long* __restrict__ part,
@@ -641,15 +641,31 @@ __global__ __launch_bounds__(kBlock) void k_emit(
   const uint32_t ntiles = cnt > 0 ? (uint32_t)((tx1 - tx0 + 1) * (ty1 - ty0 + 1)) : 0u;
   const bool simple = cnt > 0 && cnt == ntiles;
   if (cnt > 0 && off_vv + cnt > (unsigned long long)cap) atomicOr(&hdr->overflow, 1u);
+  // voxels queued for the whole-grid pass: more than kBigEmit entries, or
+  // tiles shared by several sign patterns; one item per kBigChunk tiles of
+  // the rectangle (a voxel on the near plane covers every tile), reserved
+  // with one atomic per wave.  The list holds every item of a frame within
+  // the capacity; past it (an overflowing frame) the voxel is emitted here,
+  // so that every position below the capacity is written
+  const uint32_t nit = (cnt > kBigEmit || (cnt > 0 && !simple))
+                           ? (ntiles + kBigChunk - 1) / kBigChunk : 0u;
   bool queued = false;
-  if (cnt > kBigEmit) {
-    // one item per kBigChunk tiles of the rectangle (a voxel on the near
-    // plane covers every tile); the list holds every item of a frame within
-    // the capacity; past it (an overflowing frame) the voxel is emitted
-    // here, so that every position below the capacity is written
-    const uint32_t nit = (ntiles + kBigChunk - 1) / kBigChunk;
-    const uint32_t q = atomicAdd(&hdr->big_count, nit);
-    queued = (int64_t)q + nit <= max_big;
+  {
+    const int lane = (int)threadIdx.x & 63;
+    uint32_t incl = nit;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+      const uint32_t t = __shfl_up(incl, d, 64);
+      if (lane >= d) incl += t;
+    }
+    const uint32_t wtot = __shfl(incl, 63, 64);
+    uint32_t wbase = 0;
+    if (wtot > 0) {
+      if (lane == 63) wbase = atomicAdd(&hdr->big_count, wtot);
+      wbase = __shfl(wbase, 63, 64);
+    }
+    const int64_t q = (int64_t)wbase + (incl - nit);
+    queued = nit > 0 && q + nit <= max_big;
     if (queued)
       for (uint32_t k = 0; k < nit; ++k)
         big[q + k] = make_ulonglong2((unsigned long long)vv | ((unsigned long long)k << 40),
@@ -713,8 +729,8 @@ __global__ __launch_bounds__(kBlock) void k_emit(
 
 }
 
-// the queued voxels: one workgroup per item (kBigChunk tiles of a voxel's
-// rectangle) at a time, one tile per thread, each tile's output offset from
+// the queued voxels: one wave per item (kBigChunk tiles of a voxel's
+// rectangle) at a time, one tile per lane, each tile's output offset from
 // the summed-area table (or its position, when every tile holds one sign
 // pattern)
 __global__ __launch_bounds__(kBlock) void k_emit_big(
@@ -726,7 +742,9 @@ __global__ __launch_bounds__(kBlock) void k_emit_big(
   const int64_t nq = min((int64_t)hdr->big_count, max_big);
   const int sh = key_low;
   const uint64_t rep = ((1ull << (3 * L)) - 1ull) / 7ull;  // 001 001 ... 001 (L triplets)
-  for (int64_t q = blockIdx.x; q < nq; q += gridDim.x) {
+  const int lane = (int)threadIdx.x & 63;
+  const int64_t nw = (int64_t)gridDim.x * (kBlock / 64);
+  for (int64_t q = ((int64_t)blockIdx.x * kBlock + threadIdx.x) >> 6; q < nq; q += nw) {
     const ulonglong2 item = big[q];
     const int64_t bv = (int64_t)(item.x & ((1ull << 40) - 1ull));
     const int chunk = (int)(item.x >> 40);
@@ -745,7 +763,7 @@ __global__ __launch_bounds__(kBlock) void k_emit_big(
     // from the summed-area table
     const bool simple = sat_rect(S, W1, bx0, bx1, by0, by1) == (uint32_t)nt;
     const int jend = min(nt, (chunk + 1) * (int)kBigChunk);
-    for (int jt = chunk * (int)kBigChunk + (int)threadIdx.x; jt < jend; jt += kBlock) {
+    for (int jt = chunk * (int)kBigChunk + lane; jt < jend; jt += 64) {
       const int tx = bx0 + jt % wdt, ty = by0 + jt / wdt;
       unsigned long long o = o0;
       if (simple) {
