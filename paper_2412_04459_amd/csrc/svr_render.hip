@@ -1174,8 +1174,10 @@ __global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderArgs A) {
 }
 
 // SH and grid adjoint, one thread per voxel.  The (D+1)^2 x 3 SH gradients of
-// the workgroup's 256 voxels are staged in LDS (odd row stride: no bank
-// conflicts) and written out as one contiguous, coalesced block.
+// the workgroup's 256 voxels are staged in LDS and written out as one
+// contiguous, coalesced block: degree 3 in 16-byte pieces (rows of 13
+// float4, so that the 16-byte accesses of 8 consecutive lanes fall in
+// different banks), lower degrees float by float (odd row stride).
 template <int D>
 __global__ __launch_bounds__(kBlock) void k_sh_bwd(
     int64_t N, int n_cams, CamSet cams, const float* __restrict__ center,
@@ -1183,11 +1185,12 @@ __global__ __launch_bounds__(kBlock) void k_sh_bwd(
     const VoxRec* __restrict__ rec, const float* __restrict__ g_rgb,
     float* __restrict__ g_corner, float* __restrict__ grad_grid, float* __restrict__ grad_sh,
     const float* __restrict__ grid_raw, const float* __restrict__ g_nrm, int accumulate,
-    int scatter) {
+    int scatter, int vec_ok) {
   constexpr int NB = (D + 1) * (D + 1);
   constexpr int F = 3 * NB;
-  constexpr int FP = F | 1;
-  __shared__ float stage[kBlock * FP];
+  constexpr bool kVec = F % 4 == 0;  // degree 3: 48 floats, 12 float4 (16-byte aligned output)
+  constexpr int FP = kVec ? F + 4 : (F | 1);
+  __shared__ __align__(16) float stage[kBlock * FP];
   const int64_t base = (int64_t)blockIdx.x * kBlock;
   const int64_t vid = base + threadIdx.x;
   if (grad_sh) {
@@ -1218,19 +1221,39 @@ __global__ __launch_bounds__(kBlock) void k_sh_bwd(
         }
       }
     }
-#pragma unroll
-    for (int j = 0; j < NB; ++j) {
-      stage[threadIdx.x * FP + 3 * j + 0] = acc[j][0];
-      stage[threadIdx.x * FP + 3 * j + 1] = acc[j][1];
-      stage[threadIdx.x * FP + 3 * j + 2] = acc[j][2];
-    }
-    __syncthreads();
     const int nv = (int)min((int64_t)kBlock, N - base);
     float* o = grad_sh + base * F;
-    if (accumulate) {
-      for (int i = threadIdx.x; i < nv * F; i += kBlock) o[i] += stage[(i / F) * FP + (i % F)];
+    if (kVec && vec_ok) {
+      float4* st4 = reinterpret_cast<float4*>(stage + threadIdx.x * FP);
+#pragma unroll
+      for (int q = 0; q < F / 4; ++q)
+        st4[q] = make_float4(acc[(4 * q + 0) / 3][(4 * q + 0) % 3], acc[(4 * q + 1) / 3][(4 * q + 1) % 3],
+                             acc[(4 * q + 2) / 3][(4 * q + 2) % 3], acc[(4 * q + 3) / 3][(4 * q + 3) % 3]);
+      __syncthreads();
+      constexpr int F4 = F / 4, FP4 = FP / 4;
+      const float4* s4 = reinterpret_cast<const float4*>(stage);
+      float4* o4 = reinterpret_cast<float4*>(o);
+      for (int i = threadIdx.x; i < nv * F4; i += kBlock) {
+        float4 v = s4[(i / F4) * FP4 + (i % F4)];
+        if (accumulate) {
+          const float4 p = o4[i];
+          v.x += p.x; v.y += p.y; v.z += p.z; v.w += p.w;
+        }
+        o4[i] = v;
+      }
     } else {
-      for (int i = threadIdx.x; i < nv * F; i += kBlock) o[i] = stage[(i / F) * FP + (i % F)];
+#pragma unroll
+      for (int j = 0; j < NB; ++j) {
+        stage[threadIdx.x * FP + 3 * j + 0] = acc[j][0];
+        stage[threadIdx.x * FP + 3 * j + 1] = acc[j][1];
+        stage[threadIdx.x * FP + 3 * j + 2] = acc[j][2];
+      }
+      __syncthreads();
+      if (accumulate) {
+        for (int i = threadIdx.x; i < nv * F; i += kBlock) o[i] += stage[(i / F) * FP + (i % F)];
+      } else {
+        for (int i = threadIdx.x; i < nv * F; i += kBlock) o[i] = stage[(i / F) * FP + (i % F)];
+      }
     }
   }
   if (g_nrm && vid < N) {
@@ -1472,7 +1495,7 @@ hipError_t launch_sh_bwd(const svr_scene& sc, const CamSet& cams, const Layout& 
              sc.vox_grid, at<uint32_t>(ws, L.count), at<VoxRec>(ws, L.rec),                     \
              at<float>(ws, L.g_rgb), at<float>(ws, L.g_corner), grad_grid, grad_sh,            \
              sc.grid_raw, aux ? at<float>(ws, L.g_nrm) : nullptr, accumulate ? 1 : 0,          \
-             gather ? 0 : 1)
+             gather ? 0 : 1, (reinterpret_cast<uintptr_t>(grad_sh) & 15u) == 0u ? 1 : 0)
     switch (sc.sh_degree) {
       case 0: SVR_SHB(0); break;
       case 1: SVR_SHB(1); break;
