@@ -257,18 +257,18 @@ __device__ __forceinline__ void sh_color3_lds(const float4* __restrict__ s4, flo
                                               float dz, float rgb[3], uint32_t& pos_bits) {
   float Y[16];
   sh_basis<3>(dx, dy, dz, Y);
-  float buf[48];
+  // each 16-byte piece is used as it arrives (coefficient f = 3 j + channel),
+  // so few registers are held; the sums run in the same order as above
+  float acc[3] = {0.f, 0.f, 0.f};
 #pragma unroll
   for (int i = 0; i < 12; ++i) {
     const float4 q = s4[i];
-    buf[4 * i + 0] = q.x; buf[4 * i + 1] = q.y; buf[4 * i + 2] = q.z; buf[4 * i + 3] = q.w;
-  }
-  float acc[3] = {0.f, 0.f, 0.f};
+    const float v[4] = {q.x, q.y, q.z, q.w};
 #pragma unroll
-  for (int j = 0; j < 16; ++j) {
-    acc[0] = __fmaf_rn(buf[3 * j + 0], Y[j], acc[0]);
-    acc[1] = __fmaf_rn(buf[3 * j + 1], Y[j], acc[1]);
-    acc[2] = __fmaf_rn(buf[3 * j + 2], Y[j], acc[2]);
+    for (int c = 0; c < 4; ++c) {
+      const int f = 4 * i + c;
+      acc[f % 3] = __fmaf_rn(v[c], Y[f / 3], acc[f % 3]);
+    }
   }
   pos_bits = 0;
 #pragma unroll
