@@ -78,8 +78,9 @@ def frame_bytes(N, Nv, E, P, S):
 STAGES = [("H1 tile masks + summed-area table", ("tile_masks", "tile_sat"), None),
           ("H2-H3 project + per-view record", ("project",), ("project", "preprocess")),
           ("H4 scan + emit", ("scan_top", "emit", "emit_big"), ("emit",)),
-          ("H5-H6 sort + tile ranges", ("sort_hist", "sort_hist_scan", "sort_pass", "tile_ranges",
-                                        "tile_order", "tile_sort_small", "tile_sort_big"),
+          ("H5-H6 sort + tile ranges", ("sort_hist", "sort_hist_scan", "sort_pass", "tile_count",
+                                        "tile_ranges", "tile_place", "tile_order", "tile_sort_small",
+                                        "tile_sort_big"),
            ("sort",)),
           ("H7 render forward", ("render_fwd",), ("render_fwd",)),
           ("H8 render backward", ("render_bwd",), ("render_bwd",)),

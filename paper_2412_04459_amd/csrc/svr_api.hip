@@ -178,8 +178,12 @@ int make_layout(const svr_scene* sc, const svr_camera* cams, int n_cams, const s
   if (l.key_bits > 64)
     return fail(SVR_E_INVALID, "sort key needs %d bits (> 64): too many tiles for max_level %d",
                 l.key_bits, l.L);
-  // radix passes over the tile bits (the low key bits are sorted per tile)
-  l.passes = (l.key_bits - l.key_low + 7) / 8;
+  // bucketing by tile: a counting sort (one scatter, result in the second
+  // buffer) when the tile histogram fits in LDS and the keys are unique
+  // within a tile (order ranks, or path keys of at most 15 levels), else
+  // radix passes over the tile bits; the low key bits are sorted per tile
+  l.count_sort = (T > 0 && T <= kCountTiles && (sc->order_rank != nullptr || l.L <= 15)) ? 1 : 0;
+  l.passes = l.count_sort ? 1 : (l.key_bits - l.key_low + 7) / 8;
   l.scan_blocks = (l.NV + kBlock - 1) / kBlock;  // one partial per project/emit workgroup
   l.sort_parts = (l.cap + kSortPart - 1) / kSortPart;
   size_t off = 0;
@@ -199,6 +203,7 @@ int make_layout(const svr_scene* sc, const svr_camera* cams, int n_cams, const s
   l.tile_range = take((size_t)T * 8 + (kOrderBuckets + 1) * 4);
   l.tile_order = take((size_t)T * 4);
   l.tile_rank = take((size_t)T * 4);
+  l.tile_count = take((size_t)(l.count_sort ? T : 0) * 4);
   // a tile of n entries adds ceil(n / kBwdChunk) - 1 <= n / kBwdChunk chunks
   l.max_split = l.cap / kBwdChunk + 1;
   l.split_base = take((size_t)T * 4);
@@ -288,7 +293,8 @@ int svr_preprocess(const svr_scene* scene, const svr_camera* cams, int n_cams,
   if (st != SVR_OK) return st;
   if ((st = check_ws(L, ws, ws_bytes)) != SVR_OK) return st;
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
-  SVR_HIP(launch_tile_masks(cs, at<uint8_t>(ws, L.tile_mask), at<uint2>(ws, L.tile_range), s),
+  SVR_HIP(launch_tile_masks(cs, at<uint8_t>(ws, L.tile_mask), at<uint2>(ws, L.tile_range),
+                            L.count_sort ? at<uint32_t>(ws, L.tile_count) : nullptr, s),
           "tile masks");
   SVR_HIP(launch_tile_sat(cs, at<uint8_t>(ws, L.tile_mask), at<uint32_t>(ws, L.tile_sat), s),
           "tile table");
@@ -318,16 +324,20 @@ int svr_sort(const svr_scene* scene, const svr_camera* cams, int n_cams, const s
   hipStream_t s = reinterpret_cast<hipStream_t>(stream);
   const int64_t n_max = (n_entries_hint >= 0 && n_entries_hint < L.cap) ? n_entries_hint : L.cap;
   WsHeader* hdr = at<WsHeader>(ws, L.hdr);
-  bool in1 = false;
-  // radix sort by tile (the key bits above key_low), then each tile's range
+  // bucket by tile (the key bits above key_low), then sort each tile's range
   // by the low bits
-  SVR_HIP(launch_radix_sort(at<uint64_t>(ws, L.keys0), at<uint32_t>(ws, L.vals0),
-                            at<uint64_t>(ws, L.keys1), at<uint32_t>(ws, L.vals1), &hdr->n_entries,
-                            n_max, L.key_bits, L.key_low, at<uint32_t>(ws, L.sort_hist),
-                            at<uint32_t>(ws, L.sort_status0), at<uint32_t>(ws, L.sort_status1),
-                            hdr->tickets, &hdr->error, &in1, s),
-          "radix sort");
-  SVR_HIP(launch_tile_ranges(L, ws, sorted_keys(L, ws), s), "tile ranges");
+  if (L.count_sort) {
+    SVR_HIP(launch_tile_count_sort(L, ws, n_max, s), "tile counting sort");
+  } else {
+    bool in1 = false;
+    SVR_HIP(launch_radix_sort(at<uint64_t>(ws, L.keys0), at<uint32_t>(ws, L.vals0),
+                              at<uint64_t>(ws, L.keys1), at<uint32_t>(ws, L.vals1), &hdr->n_entries,
+                              n_max, L.key_bits, L.key_low, at<uint32_t>(ws, L.sort_hist),
+                              at<uint32_t>(ws, L.sort_status0), at<uint32_t>(ws, L.sort_status1),
+                              hdr->tickets, &hdr->error, &in1, s),
+            "radix sort");
+    SVR_HIP(launch_tile_ranges(L, ws, sorted_keys(L, ws), s), "tile ranges");
+  }
   const bool res1 = (L.passes & 1) != 0;
   SVR_HIP(launch_tile_sort(L, ws, res1 ? at<uint64_t>(ws, L.keys1) : at<uint64_t>(ws, L.keys0),
                            res1 ? at<uint32_t>(ws, L.vals1) : at<uint32_t>(ws, L.vals0),
@@ -387,6 +397,8 @@ int svr_check_overflow(const svr_scene* scene, const svr_camera* cams, int n_cam
   if (required_entries) *required_entries = (int64_t)h.n_entries;
   if (h.error & 1u) return fail(SVR_E_DEVICE, "sort look-back exceeded its spin limit");
   if (h.error & 2u) return fail(SVR_E_DEVICE, "backward chunk list overflow");
+  if (h.error & 4u)
+    return fail(SVR_E_DEVICE, "tile counts disagree with the entry count (sort without its pre-process)");
   if ((int64_t)h.n_entries > L.cap)
     return fail(SVR_E_CAPACITY, "%llu entries exceed capacity %lld", h.n_entries,
                 (long long)L.cap);

@@ -18,6 +18,9 @@ constexpr int kScanItems = 16;
 constexpr int kScanTile = kBlock * kScanItems;  // counts per scan block
 constexpr int kSortItems = 16;
 constexpr int kSortPart = kBlock * kSortItems;  // (key, value) pairs per sort partition
+// frames of at most kCountTiles tiles whose keys are unique within a tile are
+// bucketed by tile with a counting sort (a per-tile histogram in LDS)
+constexpr int kCountTiles = 32768;
 constexpr float kZNear = 1e-4f;   // corners closer than this to the camera plane
                                   // make a voxel cover every tile
 constexpr int kVidBits = 29;
@@ -67,7 +70,8 @@ constexpr int kSplitWgs = 2048;
 struct WsHeader {
   unsigned long long n_entries;   // E (may exceed capacity)
   uint32_t overflow;              // E > capacity seen by the emitter
-  uint32_t error;                 // bit 0: sort look-back spin limit hit; bit 1: chunk list full
+  uint32_t error;                 // bit 0: sort look-back spin limit hit; bit 1: chunk list full;
+                                  // bit 2: tile counts disagree with the entry count
   uint32_t tickets[16];           // sort partition tickets, one per pass
   unsigned long long stats[8];    // render statistics (svr_render_stats)
   uint32_t work[8];               // persistent render: work[0] counts taken positions
@@ -81,11 +85,13 @@ struct Layout {
   int64_t N, NV, cap, P;
   int32_t n_cams, T, sat_total, key_bits, passes, L;
   int32_t key_low;  // bits below the tile id: 3L + 3 (path key) or log2 of the rank range
+  int32_t count_sort;  // 1: entries bucketed by tile with the counting sort, else radix passes
   int32_t tile, tshift, persistent;
   int64_t scan_blocks, sort_parts;
   // byte offsets into the workspace
   size_t hdr, count, rect, rec, scan_part;
   size_t tile_mask, tile_sat, tile_range, tile_order, tile_rank;
+  size_t tile_count;  // per tile: entry count, then the next free position (counting sort)
   size_t split_base, split_items, ckpt;  // backward chunks of heavy tiles
   size_t big_list;                       // (view-voxel, first output) of voxels emitted by
   int64_t max_big;                       // the whole-grid pass; its capacity
@@ -160,7 +166,8 @@ struct FillSet {
   void add(uint32_t* ptr, int64_t count);
 };
 hipError_t launch_zero_u32(const FillSet& f, hipStream_t s);
-hipError_t launch_tile_masks(const CamSet& cams, uint8_t* mask, uint2* range, hipStream_t s);
+hipError_t launch_tile_masks(const CamSet& cams, uint8_t* mask, uint2* range, uint32_t* count,
+                             hipStream_t s);
 hipError_t launch_tile_sat(const CamSet& cams, const uint8_t* mask, uint32_t* sat, hipStream_t s);
 hipError_t launch_project(const svr_scene& sc, const CamSet& cams, const Layout& L, void* ws,
                           hipStream_t s);
@@ -176,6 +183,7 @@ hipError_t launch_radix_sort(uint64_t* k0, uint32_t* v0, uint64_t* k1, uint32_t*
 hipError_t launch_tile_sort(const Layout& L, void* ws, uint64_t* keys, uint32_t* vals, uint64_t* ktmp,
                             uint32_t* vtmp, hipStream_t s);
 hipError_t launch_tile_ranges(const Layout& L, void* ws, const uint64_t* keys, hipStream_t s);
+hipError_t launch_tile_count_sort(const Layout& L, void* ws, int64_t n_max, hipStream_t s);
 size_t order_rank_scratch_bytes(int64_t N, int L);
 hipError_t launch_order_ranks(const uint64_t* octpath, int64_t N, int L, uint32_t* rank,
                               void* scratch, hipStream_t s);

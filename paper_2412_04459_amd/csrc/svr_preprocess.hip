@@ -80,7 +80,8 @@ __device__ __forceinline__ int find_cam(const CamSet& cams, int gtile) {
 // workgroup covers kBlock pixels: 4 tiles of 8x8, one of 16x16, or one of
 // 32x32 with 4 pixels per thread.
 __global__ __launch_bounds__(kBlock) void k_tile_masks(CamSet cams, uint8_t* __restrict__ mask,
-                                                       uint2* __restrict__ range) {
+                                                       uint2* __restrict__ range,
+                                                       uint32_t* __restrict__ count) {
   __shared__ uint32_t m[4];
   const int ts = cams.tile;
   const int tiles_per_wg = ts == 8 ? 4 : 1;
@@ -113,14 +114,16 @@ __global__ __launch_bounds__(kBlock) void k_tile_masks(CamSet cams, uint8_t* __r
     if (gt < cams.total_tiles) {
       mask[gt] = (uint8_t)m[threadIdx.x];
       range[gt] = make_uint2(0u, 0u);  // tiles without entries keep an empty range
+      if (count) count[gt] = 0u;       // entry count of the counting sort
     }
   }
 }
 
-hipError_t launch_tile_masks(const CamSet& cams, uint8_t* mask, uint2* range, hipStream_t s) {
+hipError_t launch_tile_masks(const CamSet& cams, uint8_t* mask, uint2* range, uint32_t* count,
+                             hipStream_t s) {
   const int per = cams.tile == 8 ? 4 : 1;
   SVR_LAUNCH("tile_masks", k_tile_masks, dim3((cams.total_tiles + per - 1) / per), dim3(kBlock), 0,
-             s, cams, mask, range);
+             s, cams, mask, range, count);
   return hipGetLastError();
 }
 

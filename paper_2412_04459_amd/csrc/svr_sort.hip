@@ -324,13 +324,15 @@ __global__ __launch_bounds__(kBlock) void k_tile_bucket(const uint2* __restrict_
                                                         uint32_t* __restrict__ split_base,
                                                         uint2* __restrict__ split_items,
                                                         uint32_t max_split,
-                                                        uint32_t* __restrict__ err) {
+                                                        uint32_t* __restrict__ err,
+                                                        uint32_t* __restrict__ tile_count) {
   __shared__ uint32_t cnt[kOrderBuckets], base[kOrderBuckets];
   const uint32_t t = blockIdx.x * kBlock + threadIdx.x;
   if (threadIdx.x < kOrderBuckets) cnt[threadIdx.x] = 0;
   __syncthreads();
   uint32_t b = 0, local = 0;
   if (t < T) {
+    if (tile_count) tile_count[t] = 0u;  // ready for the next counting sort
     const uint2 r = range[t];
     b = order_bucket(r);
     local = atomicAdd(cnt + b, 1u);
@@ -366,23 +368,212 @@ __global__ __launch_bounds__(kBlock) void k_tile_scatter(const uint2* __restrict
   order[base + rank[t]] = t;
 }
 
+// ---------------------------------------------------------------------------
+// Counting sort by tile (frames of at most kCountTiles tiles whose keys are
+// unique within a tile).  Each workgroup owns a chunk of kCountChunk pairs of
+// the emitted list:
+//   k_tile_count   counts its pairs per tile in an LDS histogram of every
+//                  tile and adds the non-zero counts to the global ones
+//                  (cleared by the tile-mask kernel of the pre-process, and
+//                  again by the tile-order pass after use);
+//   k_tile_offsets (one workgroup) turns the counts into the tile ranges
+//                  (exclusive scan) and leaves each range's start as the
+//                  tile's next free position;
+//   k_tile_place   ranks its pairs per tile in LDS, reserves its run of
+//                  each tile with one atomic on that position and writes
+//                  every pair there.
+// Within a tile the pairs land in no fixed order; the tile-range sort that
+// follows orders them by their low key bits, which are unique within a tile,
+// so the sorted list is the same as after the stable radix passes.  The
+// histograms take T words of dynamic LDS.
+constexpr int kCountBlock = 1024;
+constexpr int kCountPer = 4;  // pairs per thread
+constexpr int kCountChunk = kCountBlock * kCountPer;
+
+__global__ __launch_bounds__(kCountBlock) void k_tile_count(const uint64_t* __restrict__ keys,
+                                                            const unsigned long long* __restrict__ n_dev,
+                                                            int64_t n_max, int shift, uint32_t T,
+                                                            uint32_t* __restrict__ count) {
+  extern __shared__ uint32_t h[];
+  const int64_t n = min((int64_t)*n_dev, n_max);
+  const int64_t c0 = (int64_t)blockIdx.x * kCountChunk;
+  if (c0 >= n) return;
+  uint32_t tt[kCountPer];
+#pragma unroll
+  for (int k = 0; k < kCountPer; ++k) {
+    const int64_t i = c0 + (int64_t)k * kCountBlock + threadIdx.x;
+    tt[k] = i < n ? (uint32_t)(keys[i] >> shift) : 0xffffffffu;
+  }
+  for (uint32_t t = threadIdx.x; t < T; t += kCountBlock) h[t] = 0u;
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kCountPer; ++k)
+    if (tt[k] < T) atomicAdd(&h[tt[k]], 1u);
+  __syncthreads();
+  for (uint32_t t = threadIdx.x; t < T; t += kCountBlock) {
+    const uint32_t c = h[t];
+    if (c) atomicAdd(&count[t], c);
+  }
+}
+
+// one workgroup: range[t] = [o_t, o_t + count_t) with o the exclusive scan of
+// the counts; count[t] becomes o_t.  Also clears the render-order counters
+// (as k_tile_ranges does).  A total other than the entry count (counts left
+// over from another frame) sets error bit 2.
+__global__ __launch_bounds__(kCountBlock) void k_tile_offsets(uint32_t* __restrict__ count, uint32_t T,
+                                                              const unsigned long long* __restrict__ n_dev,
+                                                              int64_t n_max, uint2* __restrict__ range,
+                                                              uint32_t* __restrict__ counters,
+                                                              uint32_t* __restrict__ err) {
+  constexpr int kPerThread = kCountTiles / kCountBlock;
+  __shared__ uint32_t o[kCountTiles + 1];
+  __shared__ uint32_t wsum[kCountBlock / 64];
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  if (tid <= kOrderBuckets) counters[tid] = 0u;
+  {
+    uint32_t c[kPerThread];
+#pragma unroll
+    for (int k = 0; k < kPerThread; ++k) {
+      const uint32_t t = (uint32_t)(k * kCountBlock + tid);
+      c[k] = t < T ? count[t] : 0u;
+    }
+#pragma unroll
+    for (int k = 0; k < kPerThread; ++k) o[k * kCountBlock + tid] = c[k];
+  }
+  __syncthreads();
+  // thread tid scans the run [t0, t1) of consecutive tiles
+  const uint32_t per = (T + kCountBlock - 1) / kCountBlock;
+  const uint32_t t0 = min((uint32_t)tid * per, T), t1 = min(t0 + per, T);
+  uint32_t sum = 0u;
+  for (uint32_t t = t0; t < t1; ++t) sum += o[t];
+  uint32_t inc = sum;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const uint32_t v = __shfl_up(inc, d, 64);
+    if (lane >= d) inc += v;
+  }
+  if (lane == 63) wsum[w] = inc;
+  __syncthreads();
+  uint32_t off = inc - sum;
+  for (int i = 0; i < w; ++i) off += wsum[i];
+  for (uint32_t t = t0; t < t1; ++t) {
+    const uint32_t c = o[t];
+    o[t] = off;
+    off += c;
+  }
+  if (tid == kCountBlock - 1) {
+    o[T] = off;
+    if ((int64_t)off != min((int64_t)*n_dev, n_max)) atomicOr(err, 4u);
+  }
+  __syncthreads();
+  for (uint32_t t = tid; t < T; t += kCountBlock) {
+    const uint32_t a = o[t], b = o[t + 1];
+    range[t] = make_uint2(a, b);
+    count[t] = a;
+  }
+}
+
+__global__ __launch_bounds__(kCountBlock) void k_tile_place(const uint64_t* __restrict__ kin,
+                                                            const uint32_t* __restrict__ vin,
+                                                            uint64_t* __restrict__ kout,
+                                                            uint32_t* __restrict__ vout,
+                                                            const unsigned long long* __restrict__ n_dev,
+                                                            int64_t n_max, int shift, uint32_t T,
+                                                            uint32_t* __restrict__ next,
+                                                            uint32_t* __restrict__ err) {
+  extern __shared__ uint32_t h[];
+  const int64_t n = min((int64_t)*n_dev, n_max);
+  const int64_t c0 = (int64_t)blockIdx.x * kCountChunk;
+  if (c0 >= n) return;
+  uint64_t kk[kCountPer];
+  uint32_t vv[kCountPer], tt[kCountPer], rk[kCountPer];
+#pragma unroll
+  for (int k = 0; k < kCountPer; ++k) {
+    const int64_t i = c0 + (int64_t)k * kCountBlock + threadIdx.x;
+    tt[k] = 0xffffffffu;
+    kk[k] = 0ull;
+    vv[k] = 0u;
+    rk[k] = 0u;
+    if (i < n) {
+      kk[k] = kin[i];
+      vv[k] = vin[i];
+    }
+  }
+  for (uint32_t t = threadIdx.x; t < T; t += kCountBlock) h[t] = 0u;
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < kCountPer; ++k) {
+    const int64_t i = c0 + (int64_t)k * kCountBlock + threadIdx.x;
+    if (i < n) tt[k] = (uint32_t)(kk[k] >> shift);
+    if (tt[k] < T) rk[k] = atomicAdd(&h[tt[k]], 1u);
+  }
+  __syncthreads();
+  for (uint32_t t = threadIdx.x; t < T; t += kCountBlock) {
+    const uint32_t c = h[t];
+    if (c) h[t] = atomicAdd(&next[t], c);
+  }
+  __syncthreads();
+  bool bad = false;
+#pragma unroll
+  for (int k = 0; k < kCountPer; ++k) {
+    if (tt[k] < T) {
+      const uint32_t pos = h[tt[k]] + rk[k];
+      if ((int64_t)pos < n) {
+        kout[pos] = kk[k];
+        vout[pos] = vv[k];
+      } else {
+        bad = true;
+      }
+    }
+  }
+  if (bad) atomicOr(err, 4u);
+}
+
+static hipError_t launch_tile_order(const Layout& L, void* ws, hipStream_t s) {
+  uint2* range = at<uint2>(ws, L.tile_range);
+  uint32_t* counts = at<uint32_t>(ws, L.tile_range) + 2 * (int64_t)L.T;
+  uint32_t* split_count = counts + kOrderBuckets;
+  const dim3 tg((unsigned)((L.T + kBlock - 1) / kBlock));
+  SVR_LAUNCH("tile_order", k_tile_bucket, tg, dim3(kBlock), 0, s, range, (uint32_t)L.T, counts,
+             at<uint32_t>(ws, L.tile_rank), split_count, at<uint32_t>(ws, L.split_base),
+             at<uint2>(ws, L.split_items), (uint32_t)L.max_split, &at<WsHeader>(ws, L.hdr)->error,
+             L.count_sort ? at<uint32_t>(ws, L.tile_count) : nullptr);
+  SVR_LAUNCH("tile_order", k_tile_scatter, tg, dim3(kBlock), 0, s, range, (uint32_t)L.T, counts,
+             at<uint32_t>(ws, L.tile_rank), at<uint32_t>(ws, L.tile_order));
+  return hipGetLastError();
+}
+
 hipError_t launch_tile_ranges(const Layout& L, void* ws, const uint64_t* keys, hipStream_t s) {
   // the ranges start empty (cleared with the tile masks); the bucket and
   // chunk counters behind them are cleared by the first workgroup here
   uint2* range = at<uint2>(ws, L.tile_range);
   uint32_t* counts = at<uint32_t>(ws, L.tile_range) + 2 * (int64_t)L.T;
-  uint32_t* split_count = counts + kOrderBuckets;
   // at least one workgroup: the first one clears the counters
   SVR_LAUNCH("tile_ranges", k_tile_ranges,
              dim3((unsigned)max((L.cap + kBlock - 1) / kBlock, (int64_t)1)), dim3(kBlock), 0, s, keys,
              &at<WsHeader>(ws, L.hdr)->n_entries, L.cap, L.key_low, (uint32_t)L.T, range, counts);
-  const dim3 tg((unsigned)((L.T + kBlock - 1) / kBlock));
-  SVR_LAUNCH("tile_order", k_tile_bucket, tg, dim3(kBlock), 0, s, range, (uint32_t)L.T, counts,
-             at<uint32_t>(ws, L.tile_rank), split_count, at<uint32_t>(ws, L.split_base),
-             at<uint2>(ws, L.split_items), (uint32_t)L.max_split, &at<WsHeader>(ws, L.hdr)->error);
-  SVR_LAUNCH("tile_order", k_tile_scatter, tg, dim3(kBlock), 0, s, range, (uint32_t)L.T, counts,
-             at<uint32_t>(ws, L.tile_rank), at<uint32_t>(ws, L.tile_order));
-  return hipGetLastError();
+  return launch_tile_order(L, ws, s);
+}
+
+hipError_t launch_tile_count_sort(const Layout& L, void* ws, int64_t n_max, hipStream_t s) {
+  // keys0/vals0 (emission order) -> keys1/vals1 bucketed by tile; the counts
+  // start at zero (tile-mask kernel of the pre-process, or the tile-order
+  // pass of the previous sort)
+  if (L.T <= 0 || L.T > kCountTiles) return hipErrorInvalidValue;
+  uint32_t* count = at<uint32_t>(ws, L.tile_count);
+  WsHeader* hdr = at<WsHeader>(ws, L.hdr);
+  const uint32_t T = (uint32_t)L.T;
+  const size_t lds = (size_t)T * 4;
+  const dim3 grid((unsigned)max((n_max + kCountChunk - 1) / kCountChunk, (int64_t)1));
+  SVR_LAUNCH("tile_count", k_tile_count, grid, dim3(kCountBlock), lds, s, at<uint64_t>(ws, L.keys0),
+             &hdr->n_entries, n_max, L.key_low, T, count);
+  SVR_LAUNCH("tile_ranges", k_tile_offsets, dim3(1), dim3(kCountBlock), 0, s, count, T, &hdr->n_entries,
+             n_max, at<uint2>(ws, L.tile_range), at<uint32_t>(ws, L.tile_range) + 2 * (int64_t)L.T,
+             &hdr->error);
+  SVR_LAUNCH("tile_place", k_tile_place, grid, dim3(kCountBlock), lds, s, at<uint64_t>(ws, L.keys0),
+             at<uint32_t>(ws, L.vals0), at<uint64_t>(ws, L.keys1), at<uint32_t>(ws, L.vals1),
+             &hdr->n_entries, n_max, L.key_low, T, count, &hdr->error);
+  return launch_tile_order(L, ws, s);
 }
 
 // ---------------------------------------------------------------------------
