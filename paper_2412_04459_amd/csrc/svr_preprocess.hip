@@ -378,7 +378,9 @@ __device__ __forceinline__ void emit_tile(const EmitCtx& e, int gt, uint32_t m,
   }
 }
 
-template <int D>
+// ONE: a single camera, whose parameters are then wave-uniform (scalar
+// loads) instead of per-lane reads of the camera array
+template <int D, bool ONE>
 __global__ __launch_bounds__(kBlock) void k_project(
     int64_t NV, int n_cams, CamSet cams, const float* __restrict__ center,
     const float* __restrict__ size, const int32_t* __restrict__ vox_grid,
@@ -389,9 +391,15 @@ __global__ __launch_bounds__(kBlock) void k_project(
   const int64_t vv0 = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const bool active = vv0 < NV;
   const int64_t vv = active ? vv0 : NV - 1;  // inactive lanes stay for the wave-wide staging
-  const int64_t vid = vv / n_cams;
-  const int ci = (int)(vv - vid * n_cams);
+  const int64_t vid = ONE ? vv : vv / n_cams;
+  const int ci = ONE ? 0 : (int)(vv - vid * n_cams);
   const DevCam& c = cams.c[ci];
+  // the corner densities are gathered first (also for voxels that turn out
+  // culled), so their reads overlap the projection instead of ending it
+  const int4* vg = reinterpret_cast<const int4*>(vox_grid + vid * 8);
+  const int4 ga = vg[0], gb = vg[1];
+  const float4 q1 = make_float4(grid_raw[ga.x], grid_raw[ga.y], grid_raw[ga.z], grid_raw[ga.w]);
+  const float4 q2 = make_float4(grid_raw[gb.x], grid_raw[gb.y], grid_raw[gb.z], grid_raw[gb.w]);
   const float s = size[vid];
   const float h = 0.5f * s;
   // centre relative to the camera, then camera-space centre Pc = R (centre - o)
@@ -498,12 +506,10 @@ __global__ __launch_bounds__(kBlock) void k_project(
                 bits);
   }
   if (!need) return;
-  const int4* vg = reinterpret_cast<const int4*>(vox_grid + vid * 8);
-  const int4 ga = vg[0], gb = vg[1];
   VoxRec R;
   R.q0 = make_float4(center[vid], center[N + vid], center[2 * N + vid], s);
-  R.q1 = make_float4(grid_raw[ga.x], grid_raw[ga.y], grid_raw[ga.z], grid_raw[ga.w]);
-  R.q2 = make_float4(grid_raw[gb.x], grid_raw[gb.y], grid_raw[gb.z], grid_raw[gb.w]);
+  R.q1 = q1;
+  R.q2 = q2;
   R.q3 = make_float4(rgb[0], rgb[1], rgb[2], __uint_as_float(bits));
   rec[vv] = R;
 }
@@ -548,9 +554,13 @@ hipError_t launch_project(const svr_scene& sc, const CamSet& cams, const Layout&
   auto* rect = at<uint2>(ws, L.rect);
   auto* rec = at<VoxRec>(ws, L.rec);
   auto* part = at<unsigned long long>(ws, L.scan_part);
-#define SVR_PROJ(D)                                                                             \
-  SVR_LAUNCH("project", k_project<D>, grid, dim3(kBlock), 0, s, L.NV, L.n_cams, cams, sc.center, \
-                     sc.size, sc.vox_grid, sc.grid_raw, sc.sh, L.N, sat, count, rect, rec, part)
+#define SVR_PROJ(D)                                                                              \
+  if (L.n_cams == 1)                                                                             \
+    SVR_LAUNCH("project", (k_project<D, true>), grid, dim3(kBlock), 0, s, L.NV, L.n_cams, cams,  \
+               sc.center, sc.size, sc.vox_grid, sc.grid_raw, sc.sh, L.N, sat, count, rect, rec, part); \
+  else                                                                                           \
+    SVR_LAUNCH("project", (k_project<D, false>), grid, dim3(kBlock), 0, s, L.NV, L.n_cams, cams, \
+               sc.center, sc.size, sc.vox_grid, sc.grid_raw, sc.sh, L.N, sat, count, rect, rec, part)
   switch (sc.sh_degree) {
     case 0: SVR_PROJ(0); break;
     case 1: SVR_PROJ(1); break;
@@ -618,6 +628,8 @@ hipError_t launch_scan(const Layout& L, void* ws, hipStream_t s) {
 // them a wave per item (they cluster in a Z-curve order: near the lines where
 // a ray component changes sign, and in the coarse background levels, and one
 // workgroup taking them one after another would set the kernel's length).
+// ONE: a single camera (wave-uniform camera parameters).
+template <bool ONE>
 __global__ __launch_bounds__(kBlock) void k_emit(
     int64_t NV, int n_cams, CamSet cams, const uint64_t* __restrict__ octpath,
     const uint32_t* __restrict__ count, const unsigned long long* __restrict__ part,
@@ -680,8 +692,8 @@ __global__ __launch_bounds__(kBlock) void k_emit(
   s_wd[threadIdx.x] = simple && !queued ? (uint32_t)(tx1 - tx0 + 1) : 0u;
   if (cnt > 0 && !simple) {
     if (!queued) {
-      const int64_t vid = vv / n_cams;
-      const DevCam& c = cams.c[(int)(vv - vid * n_cams)];
+      const int64_t vid = ONE ? vv : vv / n_cams;
+      const DevCam& c = cams.c[ONE ? 0 : (int)(vv - vid * n_cams)];
       const EmitCtx e = emit_ctx(octpath, rank, vid, L, rep, sh);
       unsigned long long o = off_vv;
       for (int ty = ty0; ty <= ty1; ++ty) {
@@ -714,15 +726,28 @@ __global__ __launch_bounds__(kBlock) void k_emit(
     const uint32_t row = j / wd;
     const uint32_t rx = s_rx[lo];
     const int64_t ov = vv0 + lo;
-    const int64_t vid = ov / n_cams;
-    const DevCam& c = cams.c[(int)(ov - vid * n_cams)];
+    const int64_t vid = ONE ? ov : ov / n_cams;
+    const DevCam& c = cams.c[ONE ? 0 : (int)(ov - vid * n_cams)];
     const int gt = c.tile_off + ((int)(rx >> 16) + (int)row) * c.ntx + (int)(rx & 0xffffu) +
                    (int)(j - row * wd);
-    const int sgn = __ffs((int)mask[gt]) - 1;
     uint64_t low;
+    int sgn;
     if (rank) {
-      low = (uint64_t)rank[vid * 8 + sgn];
+      // the voxel's 8 order ranks are read beside the tile's mask (one round
+      // trip instead of two), then the one of the tile's pattern is taken
+      const uint4* rp = reinterpret_cast<const uint4*>(rank + vid * 8);
+      const uint4 r03 = rp[0], r47 = rp[1];
+      const uint32_t mk = mask[gt];
+      // all nine values before any is used: the compiler would otherwise
+      // read only the needed rank, after the mask
+      asm volatile("" ::"v"(r03.x), "v"(r03.y), "v"(r03.z), "v"(r03.w), "v"(r47.x), "v"(r47.y),
+                   "v"(r47.z), "v"(r47.w), "v"(mk));
+      sgn = __ffs((int)mk) - 1;
+      const uint4 q = sgn < 4 ? r03 : r47;
+      const int i = sgn & 3;
+      low = (uint64_t)(i < 2 ? (i == 0 ? q.x : q.y) : (i == 2 ? q.z : q.w));
     } else {
+      sgn = __ffs((int)mask[gt]) - 1;
       const uint64_t top = octpath[vid] >> (3 * (SVR_MAX_LEVELS - L));
       low = ((top ^ ((uint64_t)sgn * rep)) << 3) | (uint64_t)sgn;
     }
@@ -736,6 +761,7 @@ __global__ __launch_bounds__(kBlock) void k_emit(
 // rectangle) at a time, one tile per lane, each tile's output offset from
 // the summed-area table (or its position, when every tile holds one sign
 // pattern)
+template <bool ONE>
 __global__ __launch_bounds__(kBlock) void k_emit_big(
     int n_cams, CamSet cams, const uint64_t* __restrict__ octpath, const uint2* __restrict__ rect,
     const uint8_t* __restrict__ mask, const uint32_t* __restrict__ sat, int L, int key_low,
@@ -751,8 +777,8 @@ __global__ __launch_bounds__(kBlock) void k_emit_big(
     const ulonglong2 item = big[q];
     const int64_t bv = (int64_t)(item.x & ((1ull << 40) - 1ull));
     const int chunk = (int)(item.x >> 40);
-    const int64_t vid = bv / n_cams;
-    const DevCam& c = cams.c[(int)(bv - vid * n_cams)];
+    const int64_t vid = ONE ? bv : bv / n_cams;
+    const DevCam& c = cams.c[ONE ? 0 : (int)(bv - vid * n_cams)];
     const EmitCtx e = emit_ctx(octpath, rank, vid, L, rep, sh);
     const uint2 br = rect[bv];
     const int bx0 = (int)(br.x & 0xffffu) >> cams.tshift, bx1 = (int)(br.x >> 16) >> cams.tshift;
@@ -784,17 +810,18 @@ __global__ __launch_bounds__(kBlock) void k_emit_big(
 hipError_t launch_emit(const svr_scene& sc, const CamSet& cams, const Layout& L, void* ws,
                        hipStream_t s) {
   if (L.NV == 0) return hipSuccess;
-  SVR_LAUNCH("emit", k_emit, dim3((unsigned)((L.NV + kBlock - 1) / kBlock)), dim3(kBlock), 0, s,
-             L.NV, L.n_cams, cams, sc.octpath, at<uint32_t>(ws, L.count),
-             at<unsigned long long>(ws, L.scan_part), at<uint2>(ws, L.rect),
-             at<uint8_t>(ws, L.tile_mask), at<uint32_t>(ws, L.tile_sat), L.L, L.key_low,
-             sc.order_rank, L.cap, at<uint64_t>(ws, L.keys0), at<uint32_t>(ws, L.vals0),
+  const bool one = L.n_cams == 1;
+  SVR_LAUNCH("emit", one ? k_emit<true> : k_emit<false>,
+             dim3((unsigned)((L.NV + kBlock - 1) / kBlock)), dim3(kBlock), 0, s, L.NV, L.n_cams, cams,
+             sc.octpath, at<uint32_t>(ws, L.count), at<unsigned long long>(ws, L.scan_part),
+             at<uint2>(ws, L.rect), at<uint8_t>(ws, L.tile_mask), at<uint32_t>(ws, L.tile_sat), L.L,
+             L.key_low, sc.order_rank, L.cap, at<uint64_t>(ws, L.keys0), at<uint32_t>(ws, L.vals0),
              at<WsHeader>(ws, L.hdr), at<ulonglong2>(ws, L.big_list), L.max_big);
   // the queued voxels, over a grid of fixed size (the count stays on the
   // device, so the launch can be captured in a graph)
   const int64_t gb = L.max_big < 1024 ? L.max_big : 1024;
-  SVR_LAUNCH("emit_big", k_emit_big, dim3((unsigned)gb), dim3(kBlock), 0, s, L.n_cams, cams,
-             sc.octpath, at<uint2>(ws, L.rect), at<uint8_t>(ws, L.tile_mask),
+  SVR_LAUNCH("emit_big", one ? k_emit_big<true> : k_emit_big<false>, dim3((unsigned)gb), dim3(kBlock),
+             0, s, L.n_cams, cams, sc.octpath, at<uint2>(ws, L.rect), at<uint8_t>(ws, L.tile_mask),
              at<uint32_t>(ws, L.tile_sat), L.L, L.key_low, sc.order_rank, L.cap,
              at<uint64_t>(ws, L.keys0), at<uint32_t>(ws, L.vals0), at<WsHeader>(ws, L.hdr),
              at<ulonglong2>(ws, L.big_list), L.max_big);

@@ -111,6 +111,27 @@ def test_sorted_entries_bit_exact(torch_dev, name, ranks):
                        vals.cpu().numpy().view(np.uint32), ranks)
 
 
+def test_second_sort_after_one_preprocess(torch_dev):
+    """The per-tile counts of the counting sort start at zero for a second
+    sort of the same emitted list (the tile-order pass clears them), so the
+    list and the header check come out unchanged."""
+    torch = torch_dev
+    from paper_2412_04459_amd.render import DeviceScene, Rasterizer
+    scene, cams = S.spheres_plane_scene(), [S.spheres_plane_camera()]
+    _say("second sort: spheres_plane N=%d" % scene.n_voxels)
+    rast = Rasterizer(DeviceScene(scene), cams, K=1, sync_count=True, tile=8)
+    rast.preprocess()
+    rast.sort()
+    E = rast.n_entries
+    k1, v1 = [t.cpu().numpy() for t in rast.sorted_entries(E)]
+    assert rast.check_overflow() == E
+    rast.sort()
+    k2, v2 = [t.cpu().numpy() for t in rast.sorted_entries(E)]
+    assert rast.check_overflow() == E
+    assert np.array_equal(k1, k2) and np.array_equal(v1, v2)
+    check_sorted_list(scene, cams[0], k2.view(np.uint64), v2.view(np.uint32), True, tile=8)
+
+
 # ---------------------------------------------------------------------------
 # forward RGBA
 # ---------------------------------------------------------------------------
