@@ -419,7 +419,8 @@ __global__ __launch_bounds__(kCountBlock) void k_tile_count(const uint64_t* __re
 // one workgroup: range[t] = [o_t, o_t + count_t) with o the exclusive scan of
 // the counts; count[t] becomes o_t.  Also clears the render-order counters
 // (as k_tile_ranges does).  A total other than the entry count (counts left
-// over from another frame) sets error bit 2.
+// over from another frame) sets error bit 2 and leaves every range empty, so
+// that no later pass reads positions the placement did not write.
 __global__ __launch_bounds__(kCountBlock) void k_tile_offsets(uint32_t* __restrict__ count, uint32_t T,
                                                               const unsigned long long* __restrict__ n_dev,
                                                               int64_t n_max, uint2* __restrict__ range,
@@ -428,6 +429,7 @@ __global__ __launch_bounds__(kCountBlock) void k_tile_offsets(uint32_t* __restri
   constexpr int kPerThread = kCountTiles / kCountBlock;
   __shared__ uint32_t o[kCountTiles + 1];
   __shared__ uint32_t wsum[kCountBlock / 64];
+  __shared__ int s_bad;
   const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
   if (tid <= kOrderBuckets) counters[tid] = 0u;
   {
@@ -463,12 +465,14 @@ __global__ __launch_bounds__(kCountBlock) void k_tile_offsets(uint32_t* __restri
   }
   if (tid == kCountBlock - 1) {
     o[T] = off;
-    if ((int64_t)off != min((int64_t)*n_dev, n_max)) atomicOr(err, 4u);
+    s_bad = (int64_t)off != min((int64_t)*n_dev, n_max);
+    if (s_bad) atomicOr(err, 4u);
   }
   __syncthreads();
+  const bool bad = s_bad != 0;
   for (uint32_t t = tid; t < T; t += kCountBlock) {
     const uint32_t a = o[t], b = o[t + 1];
-    range[t] = make_uint2(a, b);
+    range[t] = bad ? make_uint2(0u, 0u) : make_uint2(a, b);
     count[t] = a;
   }
 }

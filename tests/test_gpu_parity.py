@@ -132,6 +132,39 @@ def test_second_sort_after_one_preprocess(torch_dev):
     check_sorted_list(scene, cams[0], k2.view(np.uint64), v2.view(np.uint32), True, tile=8)
 
 
+@pytest.mark.parametrize("graph", [False, True])
+def test_view_without_entries(torch_dev, graph):
+    """A camera facing away from the scene: every voxel is culled, E = 0, the
+    counting sort sees an empty list, and the image and the gradients are
+    zero, as the oracle's."""
+    torch = torch_dev
+    from paper_2412_04459_amd.render import DeviceScene, Rasterizer
+    scene = S.sphere_shell_scene()
+    cam = S.look_at(48, 40, 60.0, [3.0, 0.0, 0.0], target=(6.0, 0.0, 0.0))
+    _say("view without entries: graph=%d" % graph)
+    ref = oracle.render(scene, cam, K=1, grad_rgba=np.ones((cam.W * cam.H, 4)))
+    assert np.all(ref["rgba"] == 0.0)
+    ds = DeviceScene(scene)
+    rast = Rasterizer(ds, [cam], K=1, sync_count=not graph, tile=8)
+    g = torch.ones((cam.W * cam.H, 4), dtype=torch.float32, device="cuda")
+    if graph:
+        # outputs start as garbage: the replays must overwrite them
+        rgba = torch.full((cam.W * cam.H, 4), -1.0, dtype=torch.float32, device="cuda")
+        gg = torch.full((ds.n_grid,), 7.0, dtype=torch.float32, device="cuda")
+        gs = torch.full_like(ds.sh, 7.0)
+        stream = torch.cuda.Stream()
+        assert rast.capture_views([cam], rgba, g, gg, gs, stream) == 1
+        for _ in range(2):
+            rast.replay_view(0, stream)
+    else:
+        rgba = rast.forward()
+        gg, gs = rast.backward(g)
+    torch.cuda.synchronize()
+    assert rast.check_overflow() == 0
+    assert float(rgba.abs().max()) == 0.0
+    assert float(gg.abs().max()) == 0.0 and float(gs.abs().max()) == 0.0
+
+
 # ---------------------------------------------------------------------------
 # forward RGBA
 # ---------------------------------------------------------------------------
