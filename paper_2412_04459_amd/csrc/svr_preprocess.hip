@@ -488,15 +488,32 @@ __global__ __launch_bounds__(kBlock) void k_project(
     const int64_t vhi = __shfl(vid, 63, 64);
     const float4* sh4 = reinterpret_cast<const float4*>(sh);
     float4* S = shs[w];
-    for (int64_t vb = vlo; vb <= vhi; vb += kShStageVox) {
+    // one round stages kShStageVox voxels, kPer float4 per lane; the next
+    // round's reads are issued before the current round is evaluated
+    constexpr int kPer = kShStageVox * 12 / 64;
+    float4 buf[kPer];
+    auto round_reads = [&](int64_t vb) {
       const int nv = (int)min((int64_t)kShStageVox, vhi - vb + 1);
       // with one camera, lane L holds voxel vlo + L: rows of voxels that
       // emit nothing are not read
-      const unsigned long long rows =
-          n_cams == 1 ? (needm >> (vb - vlo)) : ~0ull;
-      for (int q = lane; q < nv * 12; q += 64)
-        if ((rows >> (q / 12)) & 1ull) S[(q / 12) * kShRow + q % 12] = sh4[vb * 12 + q];
+      const unsigned long long rows = n_cams == 1 ? (needm >> (vb - vlo)) : ~0ull;
+#pragma unroll
+      for (int i = 0; i < kPer; ++i) {
+        const int q = lane + 64 * i;
+        buf[i] = (q < nv * 12 && ((rows >> (q / 12)) & 1ull)) ? sh4[vb * 12 + q]
+                                                              : make_float4(0.f, 0.f, 0.f, 0.f);
+      }
+    };
+    round_reads(vlo);
+    for (int64_t vb = vlo; vb <= vhi; vb += kShStageVox) {
+      const int nv = (int)min((int64_t)kShStageVox, vhi - vb + 1);
+#pragma unroll
+      for (int i = 0; i < kPer; ++i) {
+        const int q = lane + 64 * i;
+        if (q < nv * 12) S[(q / 12) * kShRow + q % 12] = buf[i];
+      }
       wave_sync_lds();
+      if (vb + kShStageVox <= vhi) round_reads(vb + kShStageVox);
       if (need && vid >= vb && vid < vb + nv)
         sh_color3_lds(S + (vid - vb) * kShRow, rx * rn, ry * rn, rz * rn, rgb, bits);
       wave_sync_lds();
