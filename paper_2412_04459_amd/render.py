@@ -8,6 +8,7 @@ and the built library every entry point raises.
 from __future__ import annotations
 
 import ctypes
+import dataclasses
 from typing import List, Optional, Sequence
 
 import numpy as np
@@ -40,17 +41,42 @@ def _stream():
     return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
 
 
-def zcurve_relabel(scene):
+def grid_zcurve_order(scene) -> np.ndarray:
+    """Permutation of the grid points along the Z-curve of their integer
+    positions at the finest level (x, y, z bits interleaved from the top, x
+    first, as in the octree path's child index 4x + 2y + z)."""
+    L = int(scene.max_level)
+    lo = np.asarray(scene.world_center, np.float64) - 0.5 * float(scene.world_size)
+    step = float(scene.world_size) / float(1 << L)
+    g = np.rint((np.asarray(scene.grid_pos, np.float64) - lo[None, :]) / step).astype(np.uint64)
+    code = np.zeros(g.shape[0], np.uint64)
+    for b in range(L, -1, -1):
+        for a in range(3):
+            code = (code << np.uint64(1)) | ((g[:, a] >> np.uint64(b)) & np.uint64(1))
+    return np.argsort(code, kind="stable")
+
+
+def zcurve_relabel(scene, grid_points: bool = True):
     """The scene with its voxels stored in octree-path order (a depth-first,
-    Z-curve walk of the leaves), and the permutation: stored voxel i is voxel
-    order[i] of the given scene.  Only the voxels' labels change (grid
-    points, geometry and parameters are the same), so every output is the
-    given scene's, relabeled.  Neighbouring voxels then sit near each other
+    Z-curve walk of the leaves) and, with ``grid_points``, its grid points
+    stored along the same curve; and the voxel permutation: stored voxel i is
+    voxel order[i] of the given scene.  Only labels change (geometry and
+    parameters are the same), so every output is the given scene's,
+    relabeled.  Neighbouring voxels and grid points then sit near each other
     in memory: the corner gathers of the projection and of the grid gradient
     hit the same cache lines, and a tile's entries (sorted in a Z-curve
     order) read neighbouring records."""
     order = np.argsort(np.asarray(scene.octpath, np.uint64), kind="stable")
-    return scene.subset(order), order
+    out = scene.subset(order)
+    if grid_points:
+        gorder = grid_zcurve_order(out)
+        inv = np.empty_like(gorder)
+        inv[gorder] = np.arange(gorder.shape[0], dtype=gorder.dtype)
+        out = dataclasses.replace(
+            out, vox_grid=np.ascontiguousarray(inv[out.vox_grid].astype(np.int32)),
+            grid_pos=np.ascontiguousarray(out.grid_pos[gorder]),
+            grid_raw=np.ascontiguousarray(out.grid_raw[gorder]))
+    return out, order
 
 
 class DeviceScene:

@@ -255,6 +255,25 @@ def test_zcurve_relabel_is_a_relabeling_in_octree_path_order():
     assert np.all(rs.octpath[1:] > rs.octpath[:-1])
     assert np.array_equal(np.sort(order), np.arange(sc.n_voxels))
     assert np.array_equal(rs.center, sc.center[:, order])
-    assert np.array_equal(rs.vox_grid, sc.vox_grid[order])
     assert np.array_equal(rs.sh, sc.sh[order])
-    assert np.array_equal(rs.grid_raw, sc.grid_raw)
+    # grid points relabeled along the Z-curve: every voxel keeps its corner
+    # positions and densities, and the stored positions follow the curve
+    assert np.array_equal(rs.grid_raw[rs.vox_grid], sc.grid_raw[sc.vox_grid[order]])
+    assert np.array_equal(rs.grid_pos[rs.vox_grid], sc.grid_pos[sc.vox_grid[order]])
+    assert np.array_equal(np.sort(rs.grid_raw), np.sort(sc.grid_raw))
+    L = sc.max_level
+    lo = np.asarray(sc.world_center) - 0.5 * sc.world_size
+    g = np.rint((rs.grid_pos - lo) / (sc.world_size / 2 ** L)).astype(np.int64)
+
+    def morton(p):
+        code = 0
+        for b in range(L, -1, -1):
+            for a in range(3):
+                code = (code << 1) | ((int(p[a]) >> b) & 1)
+        return code
+
+    codes = [morton(p) for p in g]
+    assert all(codes[i] < codes[i + 1] for i in range(len(codes) - 1))
+    rv, _ = zcurve_relabel(sc, grid_points=False)
+    assert np.array_equal(rv.vox_grid, sc.vox_grid[order])
+    assert np.array_equal(rv.grid_raw, sc.grid_raw)
