@@ -96,7 +96,6 @@ struct LdsBatch {
   float V[8][NB];                      // corner raw densities
   uint32_t meta[NB];                   // sign bits | block mask << 3
   uint32_t rx[NB], ry[NB];             // pixel rectangle: u0 | u1 << 16, v0 | v1 << 16
-  uint32_t mw[NB];                     // max blending weight in this tile (float bits)
 };
 
 // arguments shared by the render kernels
@@ -153,8 +152,7 @@ template <int TS, int NB>
 __device__ __forceinline__ void stage_entry(LdsBatch<NB>& B, int slot, uint32_t val, int ci,
                                             int n_cams, const DevCam& c,
                                             const VoxRec* __restrict__ rec,
-                                            const uint2* __restrict__ rect, int qu0, int qv0,
-                                            double (*hi)[NB] = nullptr) {
+                                            const uint2* __restrict__ rect, int qu0, int qv0) {
   using G = TileGeom<TS>;
   const uint32_t vid = val & kVidMask;
   const int64_t vv = (int64_t)vid * n_cams + ci;
@@ -176,12 +174,6 @@ __device__ __forceinline__ void stage_entry(LdsBatch<NB>& B, int slot, uint32_t 
   B.lo[1][slot] = ly;
   B.lo[2][slot] = lz;
   B.edge[slot] = R.q0.w;
-  if (hi) {
-    const double e = (double)R.q0.w;
-    hi[0][slot] = lx + e;
-    hi[1][slot] = ly + e;
-    hi[2][slot] = lz + e;
-  }
   B.isz[slot] = 1.f / R.q0.w;
   B.V[0][slot] = R.q1.x; B.V[1][slot] = R.q1.y; B.V[2][slot] = R.q1.z; B.V[3][slot] = R.q1.w;
   B.V[4][slot] = R.q2.x; B.V[5][slot] = R.q2.y; B.V[6][slot] = R.q2.z; B.V[7][slot] = R.q2.w;
@@ -189,7 +181,6 @@ __device__ __forceinline__ void stage_entry(LdsBatch<NB>& B, int slot, uint32_t 
   B.meta[slot] = (val >> kVidBits) | (qm << 3);
   B.rx[slot] = rc.x;
   B.ry[slot] = rc.y;
-  B.mw[slot] = 0u;
 }
 
 // Ray-box slab test (Supp. A.2 listing "ray_aabb") against staged entry j, in
@@ -202,19 +193,6 @@ __device__ __forceinline__ bool slab(const LdsBatch<NB>& B, int j, double idx, d
   const double t0x = lx * idx, t1x = (lx + e) * idx;
   const double t0y = ly * idy, t1y = (ly + e) * idy;
   const double t0z = lz * idz, t1z = (lz + e) * idz;
-  a = fmax(fmax(fmin(t0x, t1x), fmin(t0y, t1y)), fmin(t0z, t1z));
-  b = fmin(fmin(fmax(t0x, t1x), fmax(t0y, t1y)), fmax(t0z, t1z));
-  return (a <= b) && (a > 0.0);
-}
-
-// the same test with the box max staged as well (min + edge, formed as in
-// slab, so both passes take the same decisions)
-template <int NB>
-__device__ __forceinline__ bool slab_hi(const LdsBatch<NB>& B, const double (&hi)[3][NB], int j,
-                                        double idx, double idy, double idz, double& a, double& b) {
-  const double t0x = B.lo[0][j] * idx, t1x = hi[0][j] * idx;
-  const double t0y = B.lo[1][j] * idy, t1y = hi[1][j] * idy;
-  const double t0z = B.lo[2][j] * idz, t1z = hi[2][j] * idz;
   a = fmax(fmax(fmin(t0x, t1x), fmin(t0y, t1y)), fmin(t0z, t1z));
   b = fmin(fmin(fmax(t0x, t1x), fmax(t0y, t1y)), fmax(t0z, t1z));
   return (a <= b) && (a > 0.0);
@@ -536,6 +514,7 @@ __device__ __forceinline__ void block_rect_mask(uint32_t rx, uint32_t ry, int bu
 template <int TS, int KT, int ACT, bool STATS, bool AUX>
 __device__ __forceinline__ void render_tile_fwd(const RenderArgs& A, int g,
                                                 LdsBatch<TileGeom<TS>::kBatch>& B,
+                                                uint32_t* mw,  // per staged entry: max blending weight (float bits)
                                                 WaveLists<DenseCfg<TS, AUX>::kListCap, AUX, TileGeom<TS>::kBatch>* WLs) {
   using G = TileGeom<TS>;
   constexpr int NB = G::kBatch;
@@ -566,7 +545,10 @@ __device__ __forceinline__ void render_tile_fwd(const RenderArgs& A, int g,
 
   for (uint32_t b0 = start; b0 < end; b0 += NB) {
     const uint32_t i = b0 + tid;
-    if (tid < NB && i < end) stage_entry<TS>(B, tid, A.vals[i], ci, A.n_cams, c, A.rec, A.rect, qu0, qv0);
+    if (tid < NB && i < end) {
+      stage_entry<TS>(B, tid, A.vals[i], ci, A.n_cams, c, A.rec, A.rect, qu0, qv0);
+      mw[tid] = 0u;
+    }
     __syncthreads();
     const int n = (int)min((uint32_t)NB, end - b0);
     int cnt = 0;    // this lane's list length
@@ -622,7 +604,7 @@ __device__ __forceinline__ void render_tile_fwd(const RenderArgs& A, int g,
           if (x >= 0.f) {
             const int j = (int)((jw[k >> 2] >> (8 * (k & 3))) & (uint32_t)(NB - 1));
             const float wgt = Tr * alpha_of(x);
-            if (A.max_weight) atomicMax(&B.mw[j], __float_as_uint(wgt));
+            if (A.max_weight) atomicMax(&mw[j], __float_as_uint(wgt));
             C0 = __fmaf_rn(wgt, cc[k].x, C0);
             C1 = __fmaf_rn(wgt, cc[k].y, C1);
             C2 = __fmaf_rn(wgt, cc[k].z, C2);
@@ -694,8 +676,8 @@ __device__ __forceinline__ void render_tile_fwd(const RenderArgs& A, int g,
     }
     const bool all_done = __syncthreads_and(done);
     // the batch's maxima, one global atomic per entry with a composited hit
-    if (!STATS && A.max_weight && tid < n && B.mw[tid] != 0u)
-      atomicMax(A.max_weight + __float_as_uint(B.col[tid].w), B.mw[tid]);
+    if (!STATS && A.max_weight && tid < n && mw[tid] != 0u)
+      atomicMax(A.max_weight + __float_as_uint(B.col[tid].w), mw[tid]);
     if (all_done) break;
   }
   // the backward wants the colour still to come: final minus so far
@@ -739,10 +721,11 @@ __device__ __forceinline__ void render_tile_fwd(const RenderArgs& A, int g,
 template <int TS, int KT, int ACT, bool STATS, bool AUX>
 __global__ __launch_bounds__(TS * TS) void k_render_fwd(RenderArgs A) {
   __shared__ LdsBatch<TileGeom<TS>::kBatch> B;
+  __shared__ uint32_t mw[TileGeom<TS>::kBatch];
   __shared__ WaveLists<DenseCfg<TS, AUX>::kListCap, AUX, TileGeom<TS>::kBatch> WL[TileGeom<TS>::kWaves];
   __shared__ int s_tile;
   if (!A.persistent) {
-    if ((int)blockIdx.x < A.T) render_tile_fwd<TS, KT, ACT, STATS, AUX>(A, A.order[blockIdx.x], B, WL);
+    if ((int)blockIdx.x < A.T) render_tile_fwd<TS, KT, ACT, STATS, AUX>(A, A.order[blockIdx.x], B, mw, WL);
     return;
   }
   while (true) {
@@ -751,7 +734,7 @@ __global__ __launch_bounds__(TS * TS) void k_render_fwd(RenderArgs A) {
     const int p = s_tile;
     if (p < 0) break;
     const int g = A.order[p];
-    render_tile_fwd<TS, KT, ACT, STATS, AUX>(A, g, B, WL);
+    render_tile_fwd<TS, KT, ACT, STATS, AUX>(A, g, B, mw, WL);
     __syncthreads();
   }
 }
@@ -864,7 +847,6 @@ template <int TS, int KT, int ACT, bool AUX>
 __device__ __forceinline__ void render_tile_bwd(const RenderArgs& A, int g, uint32_t m_lo,
                                                 uint32_t m_hi,
                                                 LdsBatch<TileGeom<TS>::kBatch>& B,
-                                                double (&hi)[3][TileGeom<TS>::kBatch],
                                                 uint32_t& s_lmax) {
   using G = TileGeom<TS>;
   constexpr int NB = G::kBatch;
@@ -937,7 +919,7 @@ __device__ __forceinline__ void render_tile_bwd(const RenderArgs& A, int g, uint
     const int n = (int)(bend - b0);
     bend = b0;
     if (tid < n)
-      stage_entry<TS>(B, tid, A.vals[b0 + tid], ci, A.n_cams, c, A.rec, A.rect, qu0, qv0, hi);
+      stage_entry<TS>(B, tid, A.vals[b0 + tid], ci, A.n_cams, c, A.rec, A.rect, qu0, qv0);
     __syncthreads();
     // one hit: step the pixel's reverse state over staged entry j (hit on
     // [a, bb]) and write its gradients into gv[0..14]
@@ -1026,7 +1008,7 @@ __device__ __forceinline__ void render_tile_bwd(const RenderArgs& A, int g, uint
         if (!((meta >> (3 + w)) & 1u)) continue;
         double a = 0.0, bb = 0.0;
         bool hit = (b0 + (uint32_t)j < last) && ((meta & 7u) == r.spat);
-        if (hit) hit = slab_hi(B, hi, j, r.idx, r.idy, r.idz, a, bb);
+        if (hit) hit = slab(B, j, r.idx, r.idy, r.idz, a, bb);
         if (__ballot(hit) == 0ull) continue;
         float gv[16];
 #pragma unroll
@@ -1079,7 +1061,7 @@ __device__ __forceinline__ void render_tile_bwd(const RenderArgs& A, int g, uint
           bool hit = false;
           if (my >= 0) {
             hit = (b0 + (uint32_t)j < last) && ((B.meta[j] & 7u) == r.spat);
-            if (hit) hit = slab_hi(B, hi, j, r.idx, r.idy, r.idz, a, bb);
+            if (hit) hit = slab(B, j, r.idx, r.idy, r.idz, a, bb);
           }
           if (__ballot(hit) == 0ull) continue;
           float gv[16];
@@ -1111,32 +1093,37 @@ __device__ __forceinline__ void render_tile_bwd(const RenderArgs& A, int g, uint
 template <int TS, int KT, int ACT, bool AUX>
 __device__ __forceinline__ void bwd_split_item(const RenderArgs& A, uint32_t k,
                                                LdsBatch<TileGeom<TS>::kBatch>& B,
-                                               double (&hi)[3][TileGeom<TS>::kBatch],
                                                uint32_t& s_lmax) {
   const uint2 it = A.split_items[k];
   if (it.x >= (uint32_t)A.T || A.split_base[it.x] == kNoSplit) return;
   const uint2 rg = A.range[it.x];
   const uint32_t nch = (rg.y - rg.x + kBwdChunk - 1) / kBwdChunk;
   if (it.y + 1 >= nch) return;
-  render_tile_bwd<TS, KT, ACT, AUX>(A, (int)it.x, it.y, it.y + 1, B, hi, s_lmax);
+  render_tile_bwd<TS, KT, ACT, AUX>(A, (int)it.x, it.y, it.y + 1, B, s_lmax);
 }
 
 // a tile's whole range, or its last chunk when the others are chunk items
 template <int TS, int KT, int ACT, bool AUX>
 __device__ __forceinline__ void bwd_tile_rest(const RenderArgs& A, int g,
                                               LdsBatch<TileGeom<TS>::kBatch>& B,
-                                              double (&hi)[3][TileGeom<TS>::kBatch],
                                               uint32_t& s_lmax) {
   const uint2 rg = A.range[g];
   const uint32_t nch = (rg.y - rg.x + kBwdChunk - 1) / kBwdChunk;
   const uint32_t m_lo = (A.split_base[g] == kNoSplit || nch == 0) ? 0u : nch - 1;
-  render_tile_bwd<TS, KT, ACT, AUX>(A, g, m_lo, nch, B, hi, s_lmax);
+  render_tile_bwd<TS, KT, ACT, AUX>(A, g, m_lo, nch, B, s_lmax);
+}
+
+// 6 waves per SIMD for the 8x8 backward where its registers fit 80 without
+// spilling (K = 1, or K = 2 with explin, no depth or normal images); its
+// LDS (5.9 KB per wave) allows 6 as well
+template <int TS, int KT, int ACT, bool AUX>
+constexpr int bwd_min_waves() {
+  return (TS == 8 && !AUX && (KT == 1 || (KT == 2 && ACT == SVR_ACT_EXPLIN))) ? 6 : 1;
 }
 
 template <int TS, int KT, int ACT, bool AUX>
-__global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderArgs A) {
+__global__ __launch_bounds__(TS * TS, (bwd_min_waves<TS, KT, ACT, AUX>())) void k_render_bwd(RenderArgs A) {
   __shared__ LdsBatch<TileGeom<TS>::kBatch> B;
-  __shared__ double hi[3][TileGeom<TS>::kBatch];  // staged box max
   __shared__ uint32_t s_lmax;
   __shared__ int s_tile;
   const uint32_t ns = min(*A.split_count, (uint32_t)A.max_split);
@@ -1146,11 +1133,11 @@ __global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderArgs A) {
     const int b = (int)blockIdx.x;
     if (b < A.split_wgs) {
       for (uint32_t k = (uint32_t)b; k < ns; k += (uint32_t)A.split_wgs) {
-        bwd_split_item<TS, KT, ACT, AUX>(A, k, B, hi, s_lmax);
+        bwd_split_item<TS, KT, ACT, AUX>(A, k, B, s_lmax);
         __syncthreads();
       }
     } else if (b - A.split_wgs < A.T) {
-      bwd_tile_rest<TS, KT, ACT, AUX>(A, (int)A.order[b - A.split_wgs], B, hi, s_lmax);
+      bwd_tile_rest<TS, KT, ACT, AUX>(A, (int)A.order[b - A.split_wgs], B, s_lmax);
     }
     return;
   }
@@ -1159,7 +1146,7 @@ __global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderArgs A) {
     __syncthreads();
     const int k = s_tile;
     if (k < 0) break;
-    bwd_split_item<TS, KT, ACT, AUX>(A, (uint32_t)k, B, hi, s_lmax);
+    bwd_split_item<TS, KT, ACT, AUX>(A, (uint32_t)k, B, s_lmax);
     __syncthreads();
   }
   __syncthreads();  // every thread has read the last s_tile before it is reused
@@ -1168,7 +1155,7 @@ __global__ __launch_bounds__(TS * TS) void k_render_bwd(RenderArgs A) {
     __syncthreads();
     const int p = s_tile;
     if (p < 0) break;
-    bwd_tile_rest<TS, KT, ACT, AUX>(A, (int)A.order[p], B, hi, s_lmax);
+    bwd_tile_rest<TS, KT, ACT, AUX>(A, (int)A.order[p], B, s_lmax);
     __syncthreads();
   }
 }
