@@ -744,9 +744,34 @@ def main():
         aux_ms_step = ev0.elapsed_time(ev1) / args.steps
         del dep, nrm, gdep, gnrm
 
-        return stats_ms_step, aux_ms_step
+        # the same steps through torch.autograd.Function (render(), then
+        # backward of the rgba with the same upstream gradient): the GPU work
+        # is the eager step's, the difference is the autograd host path
+        from paper_2412_04459_amd.render import render as svr_render_fn
+        gp = ds.grid_raw.detach().clone().requires_grad_(True)
+        sp = ds.sh.detach().clone().requires_grad_(True)
 
-    stats_ms_step, aux_ms_step = (None, None) if args.main_only else optional_timings()
+        def step_ag(i):
+            rast.set_cameras([cams[i % len(cams)]])
+            rgba = svr_render_fn(rast, gp, sp)
+            rgba.backward(grad)
+            gp.grad = None
+            sp.grad = None
+
+        for i in range(2):
+            step_ag(i)
+        torch.cuda.synchronize()
+        ev0.record()
+        for i in range(args.steps):
+            step_ag(i)
+        ev1.record()
+        torch.cuda.synchronize()
+        ag_ms_step = ev0.elapsed_time(ev1) / args.steps
+        del gp, sp
+
+        return stats_ms_step, aux_ms_step, ag_ms_step
+
+    stats_ms_step, aux_ms_step, ag_ms_step = (None, None, None) if args.main_only else optional_timings()
 
     # the same frames replayed from one captured hipGraph per view (no host
     # launch overhead); this is the headline number
@@ -852,6 +877,9 @@ def main():
             "ms_per_step": stats_ms_step, "overhead": stats_ms_step / eager_ms_step - 1.0},
         "with_depth_normal": None if aux_ms_step is None else {
             "ms_per_step": aux_ms_step, "overhead": aux_ms_step / eager_ms_step - 1.0},
+        "autograd": None if ag_ms_step is None else {
+            "ms_per_step": ag_ms_step, "overhead": ag_ms_step / eager_ms_step - 1.0,
+            "path": "torch.autograd.Function (render(), rgba.backward), eager launches"},
         "frame_hbm": {"bytes": fbytes, "achieved_GBs": frame_gbs, "peak_GBs": HBM_PEAK_GBS,
                       "frac": frame_gbs / HBM_PEAK_GBS},
         "roofline": roof,
