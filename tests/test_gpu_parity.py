@@ -132,6 +132,26 @@ def test_second_sort_after_one_preprocess(torch_dev):
     check_sorted_list(scene, cams[0], k2.view(np.uint64), v2.view(np.uint32), True, tile=8)
 
 
+def test_counting_sort_at_its_tile_limit(torch_dev):
+    """A 1920x1080 view at 8x8 tiles has 32,400 tiles, just under the counting
+    sort's 32,768 (its per-tile histogram then takes ~127 KB of LDS): the
+    sorted list is still the oracle's."""
+    torch = torch_dev
+    from paper_2412_04459_amd.render import DeviceScene, Rasterizer
+    scene = S.spheres_plane_scene()
+    cam = S.look_at(1920, 1080, 60.0, [1.5, 1.2, 1.0])
+    assert ((cam.W + 7) // 8) * ((cam.H + 7) // 8) == 32400
+    _say("counting sort at 32400 tiles: N=%d" % scene.n_voxels)
+    rast = Rasterizer(DeviceScene(scene), [cam], K=1, sync_count=True, tile=8)
+    rast.preprocess()
+    rast.sort()
+    E = rast.n_entries
+    keys, vals = rast.sorted_entries(E)
+    assert rast.check_overflow() == E
+    check_sorted_list(scene, cam, keys.cpu().numpy().view(np.uint64),
+                      vals.cpu().numpy().view(np.uint32), True, tile=8)
+
+
 @pytest.mark.parametrize("graph", [False, True])
 def test_view_without_entries(torch_dev, graph):
     """A camera facing away from the scene: every voxel is culled, E = 0, the
