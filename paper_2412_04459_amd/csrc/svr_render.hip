@@ -93,7 +93,7 @@ struct LdsBatch {
   float4 col[NB];                      // colour rgb, voxel id (bits) in w
   float edge[NB];                      // box edge (box max = min + edge)
   float isz[NB];                       // 1 / edge
-  float V[8][NB];                      // corner raw densities
+  float V[8][NB];                      // trilinear coefficients of the corner raw densities
   uint32_t meta[NB];                   // sign bits | block mask << 3
   uint32_t rx[NB], ry[NB];             // pixel rectangle: u0 | u1 << 16, v0 | v1 << 16
 };
@@ -175,8 +175,19 @@ __device__ __forceinline__ void stage_entry(LdsBatch<NB>& B, int slot, uint32_t 
   B.lo[2][slot] = lz;
   B.edge[slot] = R.q0.w;
   B.isz[slot] = 1.f / R.q0.w;
-  B.V[0][slot] = R.q1.x; B.V[1][slot] = R.q1.y; B.V[2][slot] = R.q1.z; B.V[3][slot] = R.q1.w;
-  B.V[4][slot] = R.q2.x; B.V[5][slot] = R.q2.y; B.V[6][slot] = R.q2.z; B.V[7][slot] = R.q2.w;
+  // the field over the voxel as c0 + c1 x + c2 y + c3 z + c4 xy + c5 xz +
+  // c6 yz + c7 xyz (corner c = 4x + 2y + z), so that an interpolation is 7
+  // fused multiply-adds
+  const float d0 = R.q1.x, d1 = R.q1.y, d2 = R.q1.z, d3 = R.q1.w;
+  const float d4 = R.q2.x, d5 = R.q2.y, d6 = R.q2.z, d7 = R.q2.w;
+  B.V[0][slot] = d0;
+  B.V[1][slot] = d4 - d0;
+  B.V[2][slot] = d2 - d0;
+  B.V[3][slot] = d1 - d0;
+  B.V[4][slot] = (d6 - d4) - (d2 - d0);
+  B.V[5][slot] = (d5 - d4) - (d1 - d0);
+  B.V[6][slot] = (d3 - d2) - (d1 - d0);
+  B.V[7][slot] = ((d7 - d6) - (d5 - d4)) - ((d3 - d2) - (d1 - d0));
   B.col[slot] = make_float4(R.q3.x, R.q3.y, R.q3.z, __uint_as_float(vid));
   B.meta[slot] = (val >> kVidBits) | (qm << 3);
   B.rx[slot] = rc.x;
@@ -210,18 +221,16 @@ __device__ __forceinline__ void local_coord(const LdsBatch<NB>& B, int j, double
   qz = (float)fma(t, dz, -B.lo[2][j]) * is;
 }
 
-// trilinear interpolation of the staged corners at local coordinate q
-// (corner c = 4x + 2y + z, Supp. A.2 eq. interp)
+// trilinear interpolation of the staged field at local coordinate q
+// (Supp. A.2 eq. interp), from its coefficients
 template <int NB>
 __device__ __forceinline__ float trilerp(const LdsBatch<NB>& B, int j, float qx, float qy,
                                          float qz) {
-  const float v00 = __fmaf_rn(qz, B.V[1][j] - B.V[0][j], B.V[0][j]);
-  const float v01 = __fmaf_rn(qz, B.V[3][j] - B.V[2][j], B.V[2][j]);
-  const float v10 = __fmaf_rn(qz, B.V[5][j] - B.V[4][j], B.V[4][j]);
-  const float v11 = __fmaf_rn(qz, B.V[7][j] - B.V[6][j], B.V[6][j]);
-  const float v0 = __fmaf_rn(qy, v01 - v00, v00);
-  const float v1 = __fmaf_rn(qy, v11 - v10, v10);
-  return __fmaf_rn(qx, v1 - v0, v0);
+  const float a = __fmaf_rn(B.V[3][j], qz, B.V[0][j]);  // c0 + c3 z
+  const float b = __fmaf_rn(B.V[6][j], qz, B.V[2][j]);  // c2 + c6 z
+  const float c = __fmaf_rn(B.V[5][j], qz, B.V[1][j]);  // c1 + c5 z
+  const float d = __fmaf_rn(B.V[7][j], qz, B.V[4][j]);  // c4 + c7 z
+  return __fmaf_rn(__fmaf_rn(d, qy, c), qx, __fmaf_rn(b, qy, a));
 }
 
 struct PixelRay {
@@ -331,10 +340,12 @@ __device__ __forceinline__ void centre_gradient(const float V[8], float g[3]) {
 
 template <int NB>
 __device__ __forceinline__ void staged_normal(const LdsBatch<NB>& B, int j, float n[3]) {
-  float V[8], g[3];
-#pragma unroll
-  for (int m = 0; m < 8; ++m) V[m] = B.V[m][j];
-  centre_gradient(V, g);
+  // the centre gradient from the staged coefficients (the derivative of the
+  // field at q = (1/2, 1/2, 1/2))
+  float g[3];
+  g[0] = B.V[1][j] + 0.5f * (B.V[4][j] + B.V[5][j]) + 0.25f * B.V[7][j];
+  g[1] = B.V[2][j] + 0.5f * (B.V[4][j] + B.V[6][j]) + 0.25f * B.V[7][j];
+  g[2] = B.V[3][j] + 0.5f * (B.V[5][j] + B.V[6][j]) + 0.25f * B.V[7][j];
   const float g2 = g[0] * g[0] + g[1] * g[1] + g[2] * g[2];
   const float r = g2 > 0.f ? rsqrtf(g2) : 0.f;
   n[0] = g[0] * r; n[1] = g[1] * r; n[2] = g[2] * r;
