@@ -112,8 +112,9 @@ size_t svr_workspace_bytes(const svr_scene* scene, const svr_camera* cams, int n
 
 /* The same workspace split by purpose, in bytes (alignment padding included),
  * written to parts[0 .. min(n_parts, SVR_WS_PARTS) - 1]:
- *   [0] header, tile masks, tile summed-area table, tile ranges, render order
- *       and the backward chunk list of heavy tiles
+ *   [0] header, tile masks, tile summed-area table, tile ranges, render order,
+ *       per-tile entry counts (counting sort) and the backward chunk list of
+ *       heavy tiles
  *   [1] per (voxel, camera): count, tile rectangle and render record
  *   [2] scan partial sums
  *   [3] sort keys and values, both buffers of the double-buffered sort
@@ -151,11 +152,17 @@ int svr_preprocess(const svr_scene* scene, const svr_camera* cams, int n_cams,
 
 /* Sort the duplicated list by key (ascending; keys are unique whenever
  * max_level <= 15, so the order is fully determined) (Sec. 3.1.2 "Sorting
- * voxels"): an LSD radix sort over the key's tile bits (entries of one tile
- * keep their emission order), each tile's [start, end) range, then every
- * range sorted by the key's low bits (the direction-dependent order).  `n_entries_hint` is E when known (it sizes
- * the launches) or -1 to size them by capacity; the device-side count is
- * authoritative either way.
+ * voxels"): the entries are first bucketed by tile, then every tile's
+ * [start, end) range is sorted by the key's low bits (the
+ * direction-dependent order).  The bucketing is a counting sort (per-tile
+ * counts, their scan, one placement pass) when the frame has at most 32768
+ * tiles and the keys are unique within a tile (order ranks, or max_level <=
+ * 15), else an LSD radix sort over the key's tile bits; both give the same
+ * list.  Must follow svr_preprocess on the same workspace (which clears the
+ * per-tile counts); tile counts that disagree with the entry count leave
+ * every range empty and make svr_check_overflow return SVR_E_DEVICE.
+ * `n_entries_hint` is E when known (it sizes the launches) or -1 to size
+ * them by capacity; the device-side count is authoritative either way.
  * Errors: SVR_E_INVALID, SVR_E_WORKSPACE, SVR_E_HIP.                         */
 int svr_sort(const svr_scene* scene, const svr_camera* cams, int n_cams, const svr_opts* opts,
              void* ws, size_t ws_bytes, int64_t n_entries_hint, void* stream);
